@@ -1,0 +1,25 @@
+"""CPU FP64 oracle for singular value thresholding (SVT) matrix completion.
+
+TEST INFRASTRUCTURE.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this package.  It shares no code with the HIP
+library: the only module both sides use is ``workload``, which draws inputs.
+
+Contents (each function cites the passage of the paper it writes out):
+
+* ``jacobi_svd``       dense full SVD by one-sided Jacobi (C, ``jacobi.c``)
+* ``shrink``           the singular value shrinkage operator D_tau, eq. (2.2)
+* ``top_triplets_dense`` the largest singular triplets of a dense matrix
+* ``k0_kick``          the number of skipped initial steps, eq. (5.3)
+* ``apply_sparse``     Y x and Y^T x for Y supported on Omega (Section 2.2)
+* ``sampled_entries``  X_ij = sum_l U_il V_jl on Omega
+* ``svt_dense``        Algorithm 1 (Section 5.1.5), tier A: dense Y, full SVD
+"""
+from .svt import (  # noqa: F401
+    jacobi_svd,
+    shrink,
+    k0_kick,
+    apply_sparse,
+    sampled_entries,
+    svt_dense,
+    top_triplets_dense,
+)

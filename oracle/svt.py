@@ -1,0 +1,217 @@
+"""Plain FP64 CPU implementation of the SVT iteration (tier A: dense iterate).
+
+TEST INFRASTRUCTURE: only the tests, the smoke check and the benchmark's
+CPU-baseline leg may use this module.  It shares no code with the HIP library.
+
+Notation follows the paper: the unknown matrix is n1 x n2 (here m x n), the
+observed set is Omega, P_Omega keeps the entries in Omega and zeroes the rest,
+D_tau is the singular value shrinkage operator (Section 2.1, eq. (2.2)).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
+_lib = None
+
+# Jacobi settings: pair-orthogonality threshold and sweep cap.
+JACOBI_TOL = 1e-15
+JACOBI_MAX_SWEEPS = 60
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _build
+            _build.build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.oracle_jacobi_svd.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp,
+                                          ctypes.c_double, ctypes.c_int]
+        lib.oracle_jacobi_svd.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def jacobi_svd(A: np.ndarray, tol: float = JACOBI_TOL,
+               max_sweeps: int = JACOBI_MAX_SWEEPS):
+    """Full SVD A = U diag(s) V^T by one-sided Jacobi (see ``jacobi.c``).
+
+    Returns (U, s, V) with k = min(m, n) columns, s descending.  A wide matrix
+    is handled through its transpose.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    if m < n:
+        Vt, s, Ut = jacobi_svd(A.T, tol, max_sweeps)
+        return Ut, s, Vt
+    work = np.array(A, dtype=np.float64, order="F", copy=True)
+    V = np.zeros((n, n), dtype=np.float64, order="F")
+    s = np.zeros(n, dtype=np.float64)
+    sweeps = _load().oracle_jacobi_svd(m, n, _ptr(work), _ptr(V), _ptr(s),
+                                       tol, max_sweeps)
+    if sweeps < 0:
+        raise RuntimeError(f"one-sided Jacobi did not converge (code {sweeps})")
+    return work, s, V
+
+
+def shrink(Y: np.ndarray, tau: float):
+    """Singular value shrinkage D_tau(Y) (Section 2.1, eq. (2.2)).
+
+    D_tau(Y) = U diag((sigma_i - tau)_+) V^T on the SVD of Y.  Returns
+    (U_r, w, V_r, sigma): the r singular vectors with sigma_i > tau, the weights
+    w_i = sigma_i - tau, and all singular values of Y, so that
+    D_tau(Y) = U_r diag(w) V_r^T.
+    """
+    U, s, V = jacobi_svd(Y)
+    r = int(np.count_nonzero(s > tau))
+    return U[:, :r], s[:r] - tau, V[:, :r], s
+
+
+def top_triplets_dense(Y: np.ndarray, count: int):
+    """The ``count`` largest singular triplets of a dense matrix (full SVD)."""
+    U, s, V = jacobi_svd(Y)
+    return U[:, :count], s[:count], V[:, :count]
+
+
+def k0_kick(tau: float, delta: float, sigma1: float) -> int:
+    """k0 with tau / (delta ||P_Omega M||_2) in (k0 - 1, k0]  (Section 5.1.3, eq. (5.3)).
+
+    Since Y^0 = 0, X^k = 0 and Y^k = k delta P_Omega(M) for k <= k0, so the
+    iteration may start from Y^{k0}.
+    """
+    q = tau / (delta * sigma1)
+    return max(1, int(math.ceil(q)))
+
+
+def apply_sparse(m: int, n: int, rows, cols, yvals, x, trans: bool = False):
+    """Y x (or Y^T x) for Y supported on Omega (Section 2.2, sparsity property).
+
+    Plain definition: (Y x)_i = sum over (i, j) in Omega of Y_ij x_j.
+    """
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    yvals = np.asarray(yvals, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64)
+    if not trans:
+        out = np.zeros(m, dtype=np.float64)
+        np.add.at(out, rows, yvals * x[cols])
+    else:
+        out = np.zeros(n, dtype=np.float64)
+        np.add.at(out, cols, yvals * x[rows])
+    return out
+
+
+def sampled_entries(U: np.ndarray, V: np.ndarray, rows, cols):
+    """X_ij = sum_l U_il V_jl for (i, j) in Omega: P_Omega of a factored X."""
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    out = np.zeros(rows.shape[0], dtype=np.float64)
+    for l in range(U.shape[1]):
+        out += U[rows, l] * V[cols, l]
+    return out
+
+
+def _fro(vec) -> float:
+    """Euclidean norm with an exactly rounded sum of squares (math.fsum)."""
+    v = np.asarray(vec, dtype=np.float64)
+    return math.sqrt(math.fsum((v * v).tolist()))
+
+
+def svt_dense(m: int, n: int, rows, cols, vals, tau: float, delta: float,
+              eps: float, maxiter: int, incr: int, kick: bool = True,
+              k0: int | None = None, stop: str = "relres", noise_sigma: float = 0.0,
+              keep_iterates: bool = False):
+    """Algorithm 1 (Section 5.1.5) with a dense iterate and a full Jacobi SVD.
+
+    Steps, in the paper's order:
+      * Y^0 = k0 delta P_Omega(M), k0 from eq. (5.3) (skipped when kick=False:
+        then Y^0 = 0 and k0 = 0);
+      * for k = 1..k_max:
+          - s_k = r_{k-1} + 1, and s_k grows by ell while the s_k-th singular
+            value of Y^{k-1} is above tau (Section 5.1.1).  With the full SVD at
+            hand this only records s_k; X^k does not depend on it;
+          - r_k = max{j : sigma_j > tau};
+          - X^k = sum_{j <= r_k} (sigma_j - tau) u_j v_j^T;
+          - stop when ||P_Omega(X^k - M)||_F / ||P_Omega M||_F <= eps
+            (eq. (5.5)); with stop="noisy", when
+            ||P_Omega(X^k - B)||_F^2 <= (1 + eps) |Omega| sigma^2 (eq. (5.10));
+          - Y^k = Y^{k-1} + delta P_Omega(M - X^k)  (eq. (2.7)).
+    Returns a dict with the iteration count (Algorithm 1's loop counter at the
+    break, not counting the k0 skipped steps), k0, and the histories of s_k,
+    r_k and the relative residual, and X^opt as factors (U scaled by the
+    weights sigma_j - tau, and V).
+    """
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    vals = np.asarray(vals, dtype=np.float64)
+    nnz = rows.shape[0]
+    norm_pm = _fro(vals)
+    cap = min(m, n)
+
+    Y = np.zeros((m, n), dtype=np.float64)
+    sigma1 = None
+    if kick:
+        PM = np.zeros((m, n), dtype=np.float64)
+        PM[rows, cols] = vals
+        sigma1 = float(jacobi_svd(PM)[1][0])
+        if k0 is None:
+            k0 = k0_kick(tau, delta, sigma1)
+        Y[rows, cols] = k0 * delta * vals
+    else:
+        k0 = 0
+
+    ranks, s_hist, res_hist = [], [], []
+    iterates = []
+    y_hist = [Y[rows, cols].copy()] if keep_iterates else None
+    r_prev = 0
+    status = "not_converged"
+    Uw = np.zeros((m, 0))
+    Vr = np.zeros((n, 0))
+    w = np.zeros(0)
+    k = 0
+    for k in range(1, maxiter + 1):
+        U, s, V = jacobi_svd(Y)
+        s_k = min(r_prev + 1, cap)
+        while s[s_k - 1] > tau and s_k < cap:
+            s_k = min(s_k + incr, cap)
+        r_k = int(np.count_nonzero(s > tau))
+        w = s[:r_k] - tau
+        Uw = U[:, :r_k] * w
+        Vr = V[:, :r_k]
+        e = vals - sampled_entries(Uw, Vr, rows, cols)
+        res = _fro(e) / norm_pm
+        ranks.append(r_k)
+        s_hist.append(s_k)
+        res_hist.append(res)
+        if keep_iterates:
+            iterates.append((Uw.copy(), Vr.copy()))
+        if stop == "noisy":
+            done = _fro(e) ** 2 <= (1.0 + eps) * nnz * noise_sigma ** 2
+        else:
+            done = res <= eps
+        if done:
+            status = "ok"
+            break
+        Y[rows, cols] += delta * e
+        if keep_iterates:
+            y_hist.append(Y[rows, cols].copy())
+        r_prev = r_k
+    out = dict(iters=k, k0=k0, sigma1=sigma1, ranks=ranks, s_hist=s_hist,
+               residuals=res_hist, U=Uw, w=w, V=Vr, status=status,
+               norm_pm=norm_pm)
+    if keep_iterates:
+        out["iterates"] = iterates
+        out["y_hist"] = y_hist
+        out["Y"] = Y
+    return out
