@@ -1,0 +1,204 @@
+/*
+ * svt.h -- C ABI of the MI355X (gfx950) singular value thresholding library.
+ *
+ * The library solves the matrix completion problem of Cai, Candes and Shen,
+ * "A Singular Value Thresholding Algorithm for Matrix Completion" (2008), by
+ * Algorithm 1 of Section 5.1.5:
+ *
+ *     Y^{k0} = k0 delta P_Omega(M)                       (Section 5.1.3, eq. (5.3))
+ *     X^k    = D_tau(Y^{k-1})                            (Section 2.1, eq. (2.2))
+ *     stop when ||P_Omega(X^k - M)||_F / ||P_Omega M||_F <= eps   (eq. (5.5))
+ *     Y^k    = Y^{k-1} + delta P_Omega(M - X^k)          (Section 2.2, eq. (2.7))
+ *
+ * D_tau is evaluated from the singular triplets of the sparse iterate above
+ * tau, found by Golub-Kahan-Lanczos bidiagonalisation (Section 5.1.1); X^k is
+ * kept as factors and evaluated only on Omega.
+ *
+ * Conventions for every entry point:
+ *   - indices are 0-based; the unknown matrix is m x n ("n1 x n2" in the
+ *     paper) and nnz = |Omega| (the paper's "m");
+ *   - all pointers are HOST pointers unless stated otherwise; the library
+ *     copies what it needs, so the caller keeps ownership of its buffers;
+ *   - every function returns an svt_status (negative = error) and never lets a
+ *     C++ exception escape; after an error svt_last_error(h) describes it;
+ *   - a handle may be used by one thread at a time.
+ */
+#ifndef SVT_H
+#define SVT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SVT_OK = 0,
+  SVT_NOT_CONVERGED = 1, /* maxiter reached; the result is the last iterate  */
+  SVT_EINVAL = -1,       /* invalid argument (checked before any device work) */
+  SVT_ENOMEM = -2,       /* host or device allocation failed                   */
+  SVT_EDEVICE = -3,      /* a HIP runtime call failed                          */
+  SVT_ESTATE = -4,       /* call not valid in the handle's current state       */
+  SVT_EDIVERGED = -5,    /* residual became non-finite                         */
+  SVT_EBUSY = -6,        /* serving: no capacity, request stays queued         */
+  SVT_ELANCZOS = -7      /* partial SVD did not converge within its step cap   */
+} svt_status;
+
+typedef enum { SVT_FP64 = 0, SVT_MIXED = 1 } svt_precision;
+typedef enum { SVT_COO = 0, SVT_CSR = 1 } svt_index_format;
+typedef enum { SVT_STOP_RELRES = 0, SVT_STOP_NOISY = 1 } svt_stop_rule;
+
+/*
+ * Solver parameters.  svt_params_default() fills the paper's choices:
+ *   tau    = 5 sqrt(m n)           (Section 5.2.1: tau = 5n for n x n)
+ *   delta  = 1.2 m n / nnz         (Section 5.1.2, eq. (5.1))
+ *   eps    = 1e-4                  (Section 5.1.4, eq. (5.5))
+ *   maxiter= 500, incr (ell) = 5   (Section 5.1.1)
+ *   kick   = 1                     (Section 5.1.3)
+ */
+typedef struct {
+  double tau;            /* shrinkage threshold, > 0                          */
+  double delta;          /* step size, > 0 (the paper uses 1.2 / p)            */
+  double eps;            /* stopping tolerance, >= 0 (0 = run to maxiter)      */
+  int32_t maxiter;       /* k_max, >= 1                                       */
+  int32_t incr;          /* ell: increment of s_k, >= 1                       */
+  int32_t kick;          /* 1: start from Y^{k0} (eq. (5.3)); 0: from Y^0 = 0  */
+  int32_t k0_override;   /* > 0: use this k0 instead of computing it          */
+  int32_t precision;     /* svt_precision                                     */
+  int32_t stop_rule;     /* svt_stop_rule; NOISY is eq. (5.10)                 */
+  double noise_sigma;    /* sigma of eq. (5.10); used with SVT_STOP_NOISY     */
+  double lanczos_tol;    /* Ritz residual bound, relative to the largest Ritz
+                            value; 0 = automatic: 1e-12 FP64, 1e-6 MIXED       */
+  int32_t lanczos_maxsteps; /* cap on bidiagonalisation steps per SVT step
+                               (0 = min(m, n))                                 */
+  int32_t reorth_passes; /* 0: classical Gram-Schmidt with a second pass only
+                            when the first cancels (DGKS test); 2: always two */
+  double decide_margin;  /* the rank decision accepts an unconverged Ritz value
+                            below tau only if value + residual <= tau (1 -
+                            margin); otherwise it waits for convergence.
+                            Default 0.05; >= 1 always waits                  */
+  uint64_t seed;         /* start vectors of the bidiagonalisation            */
+  int32_t profile;       /* 1: time kernel classes with HIP events            */
+  int32_t reserved0;
+  void *stream;          /* hipStream_t to run on; NULL = library-owned stream */
+} svt_params;
+
+typedef struct {
+  int32_t iters;         /* Algorithm 1's loop counter at the break (excludes k0) */
+  int32_t k0;            /* skipped initial steps (0 when kick = 0)            */
+  int32_t rank;          /* r of the returned X                                */
+  int32_t status;        /* svt_status of the solve                            */
+  double rel_residual;   /* ||P_Omega(X - M)||_F / ||P_Omega M||_F              */
+  double sigma1;         /* ||P_Omega M||_2 found for the kick (0 if no kick)  */
+  double norm_pm;        /* ||P_Omega M||_F                                    */
+  double t_setup_s;      /* svt_create: validation, index build, upload       */
+  double t_kick_s;       /* kick: ||P_Omega M||_2 and Y^{k0}                   */
+  double t_solve_s;      /* SVT loop wall time                                 */
+  int64_t gkl_steps;     /* bidiagonalisation steps over the whole solve      */
+} svt_info;
+
+typedef struct svt_problem svt_problem;
+
+/* Fill *out with the defaults above for an m x n problem with nnz samples.
+   Errors: EINVAL if out is NULL or m, n, nnz < 1. */
+svt_status svt_params_default(int64_t m, int64_t n, int64_t nnz, svt_params *out);
+
+/*
+ * Create a problem: Omega and P_Omega(M) (Algorithm 1's inputs, Section 5.1.5).
+ *   fmt == SVT_COO: idx0 = const int32_t rows[nnz], idx1 = const int32_t cols[nnz]
+ *   fmt == SVT_CSR: idx0 = const int64_t rowptr[m+1], idx1 = const int32_t cols[nnz]
+ *   vals: const double[nnz], the observed M_ij in the same order.
+ * The triplets may come in any order.  The library builds row- and
+ * column-compressed copies of Omega (int32) and uploads them with the values.
+ * Errors (all checked before any device work): EINVAL if m, n < 1,
+ * nnz < 1 or nnz > m n, nnz >= 2^31, m or n >= 2^31, an index is out of range,
+ * a position repeats (Omega is a set), a value or parameter is not finite,
+ * tau <= 0, delta <= 0, eps < 0, maxiter < 1, incr < 1, or all values are 0.
+ * ENOMEM / EDEVICE on allocation or HIP failures.  *out is NULL on error.
+ */
+svt_status svt_create(int64_t m, int64_t n, int64_t nnz, int32_t fmt,
+                      const void *idx0, const int32_t *idx1, const double *vals,
+                      const svt_params *params, svt_problem **out);
+
+/* Run Algorithm 1 from the kick (each call starts over).  Returns SVT_OK,
+   SVT_NOT_CONVERGED (maxiter reached; the factors hold X^{maxiter}), or an
+   error.  info may be NULL. */
+svt_status svt_solve(svt_problem *h, svt_info *info);
+
+/* Per-iteration record of the last solve, k = 1..len: rank r_k, the number
+   s_k of triplets Algorithm 1 computes, the relative residual, and the
+   bidiagonalisation steps.  Any output pointer may be NULL; at most cap
+   entries are written; *len_out receives the full length. */
+svt_status svt_history(const svt_problem *h, int32_t cap, int32_t *ranks,
+                       int32_t *s_hist, double *residuals, int32_t *gkl_steps,
+                       int32_t *len_out);
+
+/* X^opt = U diag(w) V^T as factors (Algorithm 1's output): U is m x r
+   row-major and already multiplied by w (w_j = sigma_j - tau), V is n x r
+   row-major with orthonormal columns.  Pass U = w = V = NULL to query r
+   first; buffers are caller-owned and at least m r, r, n r doubles. */
+svt_status svt_factors(const svt_problem *h, int32_t *rank_out, double *U,
+                       double *w, double *V);
+
+/* X^opt at q arbitrary positions (rows[i], cols[i]) -> out[i]. */
+svt_status svt_predict(const svt_problem *h, int64_t q, const int32_t *rows,
+                       const int32_t *cols, double *out);
+
+/* Release the handle and its device memory.  NULL is ignored. */
+void svt_destroy(svt_problem *h);
+
+const char *svt_status_string(int32_t status);
+
+/* Message for the last error on this handle (NULL handle: the last error of
+   svt_create on this thread).  Never NULL. */
+const char *svt_last_error(const svt_problem *h);
+
+/* ---------------------------------------------------------------------
+ * Single steps of the hot path, for checking each one against the oracle.
+ * They act on the handle's current iterate Y (values on Omega).
+ * ------------------------------------------------------------------ */
+
+/* Set / read the iterate's values, given in the order of the triplets passed
+   to svt_create.  which = 0 reads the row-compressed copy, 1 the
+   column-compressed copy (they must agree exactly). */
+svt_status svt_set_iterate(svt_problem *h, const double *y);
+svt_status svt_get_iterate(const svt_problem *h, int32_t which, double *y);
+
+/* out = Y x (trans = 0; x has n entries, out m) or Y^T x (trans = 1): the
+   sparse products that drive the bidiagonalisation (Section 2.2). */
+svt_status svt_apply(svt_problem *h, int32_t trans, const double *x, double *out);
+
+/* The `count` largest singular triplets of the current Y by Golub-Kahan-
+   Lanczos bidiagonalisation (Section 5.1.1), each converged to the handle's
+   lanczos_tol: sigma[count], U m x count row-major, V n x count row-major
+   (U or V may be NULL).  *steps_out (may be NULL) gets the number of steps. */
+svt_status svt_partial_svd(svt_problem *h, int32_t count, double *sigma,
+                           double *U, double *V, int32_t *steps_out);
+
+/* One fused pass of Algorithm 1's last two lines on the current Y with a
+   caller-given X = U V^T (U m x r, V n x r, row-major): returns
+   ||P_Omega(M - X)||_F^2 in *res2 and applies Y += delta P_Omega(M - X). */
+svt_status svt_sample_update(svt_problem *h, int32_t r, const double *U,
+                             const double *V, double delta, double *res2);
+
+/* The kick alone: sets Y = k0 delta P_Omega(M) with k0 from eq. (5.3) (or
+   k0_override), returning sigma1 = ||P_Omega M||_2 and k0. */
+svt_status svt_kick(svt_problem *h, double *sigma1, int32_t *k0);
+
+/* Kernel timing of the last solve when params.profile = 1: for kernel class
+   `kind` (0 sparse product, 1 Gram-Schmidt update and optional second pass,
+   2 normalisation, 3 Ritz vectors, 4 sampled update and residual, 5 first
+   Gram-Schmidt dot products), the number of launches, their summed duration
+   in milliseconds
+   (HIP events on the solve's stream) and their summed algorithmic bytes:
+   the index, value and vector traffic each launch must move at least once.
+   Any output pointer may be NULL. */
+svt_status svt_kernel_stats(const svt_problem *h, int32_t kind, int64_t *launches,
+                            double *total_ms, double *total_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SVT_H */

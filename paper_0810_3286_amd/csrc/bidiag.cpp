@@ -1,0 +1,215 @@
+// Host SVD of an upper-bidiagonal matrix by implicit-shift QR.
+//
+// Invariant kept throughout: B_input = P * B_current * Q^T.  A rotation G
+// applied to rows (a, b) of B_current is undone by P <- P G^T; a rotation H
+// applied to columns (a, b) is undone by Q <- Q H.  When B_current is
+// diagonal, its (sign-corrected) diagonal holds the singular values.
+//
+// The QR sweep is the Golub-Kahan step: a shift mu from the trailing 2 x 2 of
+// B^T B (the eigenvalue nearer its last diagonal entry), a first right
+// rotation chosen from (d0^2 - mu, d0 e0), and a bulge chased to the bottom by
+// alternating left and right rotations.  A zero diagonal entry splits the
+// problem after rotating its superdiagonal neighbour away.
+#include "bidiag.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace svt {
+
+namespace {
+
+constexpr double kEps = 2.220446049250313e-16;
+
+struct Rot {
+  double c, s, r;
+};
+
+// c, s with -s*a + c*b = 0 and c*a + s*b = r >= 0 (r = hypot(a, b)).
+inline Rot make_rot(double a, double b) {
+  if (b == 0.0) return {a >= 0.0 ? 1.0 : -1.0, 0.0, std::fabs(a)};
+  const double r = std::hypot(a, b);
+  return {a / r, b / r, r};
+}
+
+struct Acc {
+  int k;
+  bool full;
+  std::vector<double> *P, *Q;  // column-major k x k
+  std::vector<double> *plast;  // last row of P
+
+  // P <- P G^T for G acting on rows (a, b): new_a = c a + s b, new_b = -s a + c b.
+  void left(int a, int b, double c, double s) {
+    if (full) {
+      double *pa = P->data() + (size_t)a * k, *pb = P->data() + (size_t)b * k;
+      for (int i = 0; i < k; ++i) {
+        const double x = pa[i], y = pb[i];
+        pa[i] = c * x + s * y;
+        pb[i] = -s * x + c * y;
+      }
+    }
+    double &x = (*plast)[a], &y = (*plast)[b];
+    const double xa = x, yb = y;
+    x = c * xa + s * yb;
+    y = -s * xa + c * yb;
+  }
+  // Q <- Q H for H acting on columns (a, b): new_a = c a + s b, new_b = -s a + c b.
+  void right(int a, int b, double c, double s) {
+    if (!full) return;
+    double *qa = Q->data() + (size_t)a * k, *qb = Q->data() + (size_t)b * k;
+    for (int i = 0; i < k; ++i) {
+      const double x = qa[i], y = qb[i];
+      qa[i] = c * x + s * y;
+      qb[i] = -s * x + c * y;
+    }
+  }
+};
+
+}  // namespace
+
+bool bidiag_svd(const std::vector<double> &d_in, const std::vector<double> &e_in, bool vectors,
+                BidiagSVD &out) {
+  const int k = (int)d_in.size();
+  out.sigma.assign(k, 0.0);
+  out.p_last.assign(k, 0.0);
+  out.P.clear();
+  out.Q.clear();
+  if (k == 0) return true;
+  std::vector<double> d(d_in), e(k > 1 ? k - 1 : 0, 0.0);
+  for (int i = 0; i + 1 < k; ++i) e[i] = e_in[i];
+  if (vectors) {
+    out.P.assign((size_t)k * k, 0.0);
+    out.Q.assign((size_t)k * k, 0.0);
+    for (int i = 0; i < k; ++i) out.P[(size_t)i * k + i] = out.Q[(size_t)i * k + i] = 1.0;
+  }
+  out.p_last[k - 1] = 1.0;
+  Acc acc{k, vectors, &out.P, &out.Q, &out.p_last};
+
+  double bnorm = 0.0;
+  for (int i = 0; i < k; ++i) bnorm = std::max(bnorm, std::fabs(d[i]));
+  for (int i = 0; i + 1 < k; ++i) bnorm = std::max(bnorm, std::fabs(e[i]));
+  const double abs_tol = kEps * bnorm;
+
+  const long max_sweeps = 40L * k * k + 100;
+  long sweeps = 0;
+  int hi = k - 1;
+  while (hi > 0) {
+    // deflate negligible superdiagonals
+    for (int i = 0; i < hi; ++i)
+      if (std::fabs(e[i]) <= kEps * (std::fabs(d[i]) + std::fabs(d[i + 1])) || std::fabs(e[i]) <= abs_tol)
+        e[i] = 0.0;
+    while (hi > 0 && e[hi - 1] == 0.0) --hi;
+    if (hi == 0) break;
+    int lo = hi - 1;
+    while (lo > 0 && e[lo - 1] != 0.0) --lo;
+    if (++sweeps > max_sweeps) return false;
+
+    // a (numerically) zero diagonal entry in the block: rotate its
+    // superdiagonal neighbour out and split
+    int zero_at = -1;
+    for (int i = lo; i <= hi; ++i)
+      if (std::fabs(d[i]) <= abs_tol) { zero_at = i; break; }
+    if (zero_at >= 0) {
+      const int i = zero_at;
+      d[i] = 0.0;
+      if (i < hi) {
+        // chase B[i][j] along row i with left rotations on rows (i, j)
+        double f = e[i];
+        e[i] = 0.0;
+        for (int j = i + 1; j <= hi; ++j) {
+          const Rot g = make_rot(d[j], f);  // new_j = c row_j + s row_i, new_i = c row_i - s row_j
+          d[j] = g.r;
+          // rows (j, i): new_j = c j + s i ; new_i = -s j + c i
+          acc.left(j, i, g.c, g.s);
+          if (j < hi) {
+            f = -g.s * e[j];
+            e[j] = g.c * e[j];
+          }
+        }
+      } else {
+        // last diagonal zero: chase B[j][hi] up column hi with right rotations
+        double f = e[hi - 1];
+        e[hi - 1] = 0.0;
+        for (int j = hi - 1; j >= lo; --j) {
+          const Rot g = make_rot(d[j], f);  // cols (j, hi): new_j = c j + s hi ; new_hi = -s j + c hi
+          d[j] = g.r;
+          acc.right(j, hi, g.c, g.s);
+          if (j > lo) {
+            f = -g.s * e[j - 1];
+            e[j - 1] = g.c * e[j - 1];
+          }
+        }
+      }
+      continue;
+    }
+
+    // Golub-Kahan step on d[lo..hi], e[lo..hi-1]
+    const double dm = d[hi - 1], dn = d[hi], em = e[hi - 1];
+    const double fm = (hi - 1 > lo) ? e[hi - 2] : 0.0;
+    const double t11 = dm * dm + fm * fm, t12 = dm * em, t22 = dn * dn + em * em;
+    const double half = 0.5 * (t11 - t22);
+    const double root = std::hypot(half, t12);
+    const double mu = t22 - t12 * t12 / (half + (half >= 0.0 ? root : -root) + (root == 0.0 ? 1.0 : 0.0));
+    double y = d[lo] * d[lo] - mu;
+    double z = d[lo] * e[lo];
+    for (int c = lo; c < hi; ++c) {
+      // right rotation on columns (c, c+1) zeroing z against y
+      Rot h = make_rot(y, z);
+      if (c > lo) e[c - 1] = h.r;
+      {
+        const double dc = d[c], ec = e[c], dn1 = d[c + 1];
+        d[c] = h.c * dc + h.s * ec;
+        e[c] = -h.s * dc + h.c * ec;
+        z = h.s * dn1;           // bulge B[c+1][c]
+        d[c + 1] = h.c * dn1;
+      }
+      acc.right(c, c + 1, h.c, h.s);
+      // left rotation on rows (c, c+1) zeroing the bulge against d[c]
+      Rot g = make_rot(d[c], z);
+      d[c] = g.r;
+      {
+        const double ec = e[c], dn1 = d[c + 1];
+        e[c] = g.c * ec + g.s * dn1;
+        d[c + 1] = -g.s * ec + g.c * dn1;
+        if (c + 1 < hi) {
+          const double en = e[c + 1];
+          z = g.s * en;          // bulge B[c][c+2]
+          e[c + 1] = g.c * en;
+        }
+      }
+      acc.left(c, c + 1, g.c, g.s);
+      y = e[c];
+    }
+  }
+
+  // signs and order
+  for (int i = 0; i < k; ++i) {
+    if (d[i] < 0.0) {
+      d[i] = -d[i];
+      if (vectors)
+        for (int t = 0; t < k; ++t) out.Q[(size_t)i * k + t] = -out.Q[(size_t)i * k + t];
+    }
+  }
+  std::vector<int> ord(k);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return d[a] > d[b]; });
+  std::vector<double> pl(k);
+  for (int i = 0; i < k; ++i) {
+    out.sigma[i] = d[ord[i]];
+    pl[i] = out.p_last[ord[i]];
+  }
+  out.p_last.swap(pl);
+  if (vectors) {
+    std::vector<double> P2((size_t)k * k), Q2((size_t)k * k);
+    for (int i = 0; i < k; ++i) {
+      std::copy_n(out.P.data() + (size_t)ord[i] * k, k, P2.data() + (size_t)i * k);
+      std::copy_n(out.Q.data() + (size_t)ord[i] * k, k, Q2.data() + (size_t)i * k);
+    }
+    out.P.swap(P2);
+    out.Q.swap(Q2);
+  }
+  return true;
+}
+
+}  // namespace svt

@@ -1,0 +1,1076 @@
+// Host driver of the SVT iteration and the C ABI (include/svt.h).
+//
+// Algorithm 1 of Cai, Candes and Shen (Section 5.1.5) on one GPU:
+//   a1  setup: Omega in row- and column-compressed form (int32), values and
+//       P_Omega(M) uploaded once (Section 2.2, sparsity property);
+//   a2  kick: ||P_Omega M||_2 by bidiagonalisation, k0 from eq. (5.3),
+//       Y = k0 delta P_Omega(M);
+//   a3  Golub-Kahan-Lanczos bidiagonalisation of the sparse iterate with full
+//       reorthogonalisation (Section 5.1.1 computes the partial SVD this way);
+//   a4  s_k = r_{k-1} + 1, grown by ell while the s_k-th value is above tau;
+//       the bidiagonalisation is extended, never restarted (Section 5.1.1);
+//   a5  shrink: r_k = #{sigma_j > tau}, w_j = sigma_j - tau (eq. (2.2));
+//   a6  Ritz vectors U diag(w), V from the bases (dense, small);
+//   a7/a8 sampled product, residual and the update of Y in one pass per
+//       compressed copy, stop test of eq. (5.5) (or eq. (5.10)).
+//
+// Orientation: the bidiagonalisation runs on A = Y when m >= n and on A = Y^T
+// otherwise, so its right-hand basis spans the smaller dimension and can be
+// completed exactly when every singular value is needed.
+#include "../../include/svt.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "bidiag.h"
+#include "svt_kernels.h"
+
+namespace svt {
+
+// ---------------------------------------------------------------------------
+// errors
+
+struct Error : std::runtime_error {
+  svt_status code;
+  Error(svt_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIP_CHECK(expr)                                                                          \
+  do {                                                                                           \
+    hipError_t _e = (expr);                                                                      \
+    if (_e != hipSuccess)                                                                        \
+      throw Error(_e == hipErrorOutOfMemory ? SVT_ENOMEM : SVT_EDEVICE,                          \
+                  std::string(#expr) + ": " + hipGetErrorString(_e));                            \
+  } while (0)
+
+static thread_local std::string g_create_error = "";
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ---------------------------------------------------------------------------
+// device memory
+
+struct DevMem {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevMem() = default;
+  DevMem(const DevMem &) = delete;
+  DevMem &operator=(const DevMem &) = delete;
+  ~DevMem() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t b) {
+    release();
+    if (b == 0) b = 8;
+    HIP_CHECK(hipMalloc(&p, b));
+    bytes = b;
+  }
+  template <typename T>
+  T *as() const { return static_cast<T *>(p); }
+};
+
+// ---------------------------------------------------------------------------
+// kernel-class timing with HIP events (params.profile = 1)
+
+enum KernelKind { kSpmv = 0, kOrth = 1, kNorm = 2, kRitz = 3, kSample = 4, kDots = 5, kKinds = 6 };
+
+struct Profiler {
+  bool on = false;
+  hipStream_t stream = nullptr;
+  struct Pending { hipEvent_t a, b; int kind; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  int64_t launches[kKinds] = {};
+  double ms[kKinds] = {};
+  double bytes[kKinds] = {};
+  hipEvent_t cur_a = nullptr;
+
+  hipEvent_t get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e;
+    HIP_CHECK(hipEventCreate(&e));
+    return e;
+  }
+  void begin() {
+    if (!on) return;
+    cur_a = get();
+    HIP_CHECK(hipEventRecord(cur_a, stream));
+  }
+  void end(int kind, double nbytes) {
+    if (!on) return;
+    hipEvent_t b = get();
+    HIP_CHECK(hipEventRecord(b, stream));
+    pending.push_back({cur_a, b, kind});
+    launches[kind] += 1;
+    bytes[kind] += nbytes;
+  }
+  // Resolve recorded pairs (the stream must be synchronised).
+  void flush() {
+    for (auto &p : pending) {
+      float t = 0.f;
+      HIP_CHECK(hipEventElapsedTime(&t, p.a, p.b));
+      ms[p.kind] += t;
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+  void reset() {
+    for (int i = 0; i < kKinds; ++i) { launches[i] = 0; ms[i] = 0; bytes[i] = 0; }
+  }
+  ~Profiler() {
+    for (auto &p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// host-side index build (a1)
+
+struct Index {
+  int64_t m = 0, n = 0, nnz = 0;
+  std::vector<int32_t> rowptr, colidx;   // CSR
+  std::vector<int32_t> colptr, rowidx;   // CSC
+  std::vector<int32_t> csr_of_input;     // input position -> CSR position
+  std::vector<int32_t> csc_of_csr;       // CSR position -> CSC position
+  std::vector<double> vals_csr;
+};
+
+static void build_index(int64_t m, int64_t n, int64_t nnz, const int32_t *rows, const int32_t *cols,
+                        const double *vals, Index &ix) {
+  ix.m = m; ix.n = n; ix.nnz = nnz;
+  // counting sort by row (stable), then sort each row by column
+  ix.rowptr.assign((size_t)m + 1, 0);
+  for (int64_t t = 0; t < nnz; ++t) ix.rowptr[(size_t)rows[t] + 1]++;
+  for (int64_t i = 0; i < m; ++i) ix.rowptr[i + 1] += ix.rowptr[i];
+  std::vector<int32_t> order((size_t)nnz);
+  {
+    std::vector<int32_t> fill(ix.rowptr.begin(), ix.rowptr.end() - 1);
+    for (int64_t t = 0; t < nnz; ++t) order[(size_t)fill[rows[t]]++] = (int32_t)t;
+  }
+  for (int64_t i = 0; i < m; ++i) {
+    auto b = order.begin() + ix.rowptr[i], e = order.begin() + ix.rowptr[i + 1];
+    std::sort(b, e, [&](int32_t a, int32_t c) { return cols[a] < cols[c]; });
+  }
+  ix.colidx.resize((size_t)nnz);
+  ix.vals_csr.resize((size_t)nnz);
+  ix.csr_of_input.resize((size_t)nnz);
+  for (int64_t t = 0; t < nnz; ++t) {
+    const int32_t src = order[(size_t)t];
+    ix.colidx[(size_t)t] = cols[src];
+    ix.vals_csr[(size_t)t] = vals[src];
+    ix.csr_of_input[(size_t)src] = (int32_t)t;
+  }
+  for (int64_t i = 0; i < m; ++i)
+    for (int32_t t = ix.rowptr[i] + 1; t < ix.rowptr[i + 1]; ++t)
+      if (ix.colidx[(size_t)t] == ix.colidx[(size_t)t - 1])
+        throw Error(SVT_EINVAL, "duplicate position (" + std::to_string(i) + ", " +
+                                    std::to_string(ix.colidx[(size_t)t]) + ") in Omega");
+  // CSC by a stable counting sort of the CSR entries on the column
+  ix.colptr.assign((size_t)n + 1, 0);
+  for (int64_t t = 0; t < nnz; ++t) ix.colptr[(size_t)ix.colidx[(size_t)t] + 1]++;
+  for (int64_t j = 0; j < n; ++j) ix.colptr[j + 1] += ix.colptr[j];
+  ix.rowidx.resize((size_t)nnz);
+  ix.csc_of_csr.resize((size_t)nnz);
+  std::vector<int32_t> fill(ix.colptr.begin(), ix.colptr.end() - 1);
+  for (int64_t i = 0; i < m; ++i)
+    for (int32_t t = ix.rowptr[i]; t < ix.rowptr[i + 1]; ++t) {
+      const int32_t pos = fill[ix.colidx[(size_t)t]]++;
+      ix.rowidx[(size_t)pos] = (int32_t)i;
+      ix.csc_of_csr[(size_t)t] = pos;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the solver state for one problem, templated on the bulk value type
+
+struct Record {
+  int32_t rank, s, steps;
+  double res;
+};
+
+struct ProblemBase {
+  virtual ~ProblemBase() = default;
+  svt_params prm{};
+  Index ix;
+  double norm_pm = 0.0;
+  std::string last_error;
+  double t_setup = 0.0;
+  virtual svt_status solve(svt_info *info) = 0;
+  virtual void factors(int32_t *rank, double *U, double *w, double *V) const = 0;
+  virtual void set_iterate(const double *y) = 0;
+  virtual void get_iterate(int which, double *y) const = 0;
+  virtual void apply(int trans, const double *x, double *out) = 0;
+  virtual int partial_svd(int count, double *sigma, double *U, double *V) = 0;
+  virtual double sample_update(int r, const double *U, const double *V, double delta) = 0;
+  virtual void kick(double *sigma1, int32_t *k0) = 0;
+  std::vector<Record> history;
+  Profiler prof;
+};
+
+template <typename T>
+struct Problem final : ProblemBase {
+  // dimensions of the bidiagonalised orientation A
+  int64_t arows = 0, acols = 0;
+  bool a_is_y = true;
+  int lanes_r = 32, lanes_c = 32;  // lanes per row of the CSR / CSC kernels
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+
+  DevMem rowptr, colidx, colptr, rowidx, csc_of_csr;
+  DevMem Mr, Mc, Yr, Yc;          // values, T
+  DevMem Ub, Vb;                  // bases, T, column-major
+  int kcap = 0;                   // columns available in Ub (Vb has kcap + 1)
+  DevMem pbuf;                    // working vector, T, max(m, n)
+  DevMem coef;                    // alpha[0..], beta[0..], double, 2 (kcap + 2)
+  DevMem red_partial, red_h1, red_h2, red_scal, red_counters;
+  ReduceScratch rs{};
+  DevMem Pd, Qd, wd;              // Ritz combination (double)
+  DevMem Fu, Fv;                  // factors of X, T, row-major with stride fstride
+  int fstride = 0, fcap = 0;
+  int rank = 0;
+  std::vector<double> w;          // sigma - tau
+  uint64_t rng_ctr = 0;
+  int k_hint = 0;
+  int log_level = 0;
+  int64_t steps_total = 0;
+
+  // ----------------------------------------------------------------- setup
+  void setup(const svt_params &p) {
+    prm = p;
+    if (const char *lv = std::getenv("SVT_LOG")) log_level = std::atoi(lv);
+    HIP_CHECK(hipGetDevice(&device));
+    if (p.stream) {
+      stream = static_cast<hipStream_t>(p.stream);
+    } else {
+      HIP_CHECK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+      own_stream = true;
+    }
+    prof.on = p.profile != 0;
+    prof.stream = stream;
+    const int64_t m = ix.m, n = ix.n, nnz = ix.nnz;
+    a_is_y = (m >= n);
+    arows = std::max(m, n);
+    acols = std::min(m, n);
+    lanes_r = lanes_for((double)nnz / (double)m);
+    lanes_c = lanes_for((double)nnz / (double)n);
+
+    rowptr.alloc(sizeof(int32_t) * (m + 1));
+    colidx.alloc(sizeof(int32_t) * nnz);
+    colptr.alloc(sizeof(int32_t) * (n + 1));
+    rowidx.alloc(sizeof(int32_t) * nnz);
+    csc_of_csr.alloc(sizeof(int32_t) * nnz);
+    Mr.alloc(sizeof(T) * nnz);
+    Mc.alloc(sizeof(T) * nnz);
+    Yr.alloc(sizeof(T) * nnz);
+    Yc.alloc(sizeof(T) * nnz);
+    pbuf.alloc(sizeof(T) * arows);
+    HIP_CHECK(hipMemcpyAsync(rowptr.p, ix.rowptr.data(), sizeof(int32_t) * (m + 1), hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(colidx.p, ix.colidx.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(colptr.p, ix.colptr.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(rowidx.p, ix.rowidx.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(csc_of_csr.p, ix.csc_of_csr.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, stream));
+    upload_values(ix.vals_csr.data(), Mr.as<T>(), Mc.as<T>());
+    HIP_CHECK(hipMemsetAsync(Yr.p, 0, sizeof(T) * nnz, stream));
+    HIP_CHECK(hipMemsetAsync(Yc.p, 0, sizeof(T) * nnz, stream));
+
+    const int max_blocks = 1100;
+    rs.max_blocks = max_blocks;
+    red_h1.alloc(sizeof(double) * 8);
+    red_h2.alloc(sizeof(double) * 8);
+    red_scal.alloc(sizeof(double) * 8);
+    red_counters.alloc(sizeof(unsigned) * kNumCounters);
+    HIP_CHECK(hipMemsetAsync(red_counters.p, 0, sizeof(unsigned) * kNumCounters, stream));
+    HIP_CHECK(hipMemsetAsync(red_scal.p, 0, sizeof(double) * 8, stream));
+    ensure_basis(std::min<int64_t>(acols, 64));
+    HIP_CHECK(hipStreamSynchronize(stream));
+  }
+
+  // values given in CSR order (double, host) -> row and column copies (T, device)
+  void upload_values(const double *csr_vals, T *dr, T *dc) {
+    const int64_t nnz = ix.nnz;
+    std::vector<T> tr((size_t)nnz), tc((size_t)nnz);
+    for (int64_t t = 0; t < nnz; ++t) {
+      tr[(size_t)t] = (T)csr_vals[t];
+      tc[(size_t)ix.csc_of_csr[(size_t)t]] = (T)csr_vals[t];
+    }
+    HIP_CHECK(hipMemcpyAsync(dr, tr.data(), sizeof(T) * nnz, hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(dc, tc.data(), sizeof(T) * nnz, hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipStreamSynchronize(stream));
+  }
+
+  // Bases with room for `cap` bidiagonalisation steps (grown geometrically).
+  void ensure_basis(int cap) {
+    if (cap <= kcap) return;
+    int newcap = std::max(cap, std::min<int>((int)acols, std::max(kcap * 2, 16)));
+    newcap = (int)std::min<int64_t>(newcap, acols);
+    DevMem nU, nV, ncoef, npart, nh1, nh2;
+    nU.alloc(sizeof(T) * (size_t)arows * (size_t)(newcap + 1));
+    nV.alloc(sizeof(T) * (size_t)acols * (size_t)(newcap + 2));
+    ncoef.alloc(sizeof(double) * 2 * (size_t)(newcap + 4));
+    npart.alloc(sizeof(double) * (size_t)(newcap + 4) * rs.max_blocks);
+    nh1.alloc(sizeof(double) * (size_t)(newcap + 4));
+    nh2.alloc(sizeof(double) * (size_t)(newcap + 4));
+    HIP_CHECK(hipMemsetAsync(ncoef.p, 0, ncoef.bytes, stream));
+    if (kcap > 0) {
+      HIP_CHECK(hipMemcpyAsync(nU.p, Ub.p, sizeof(T) * (size_t)arows * (size_t)(kcap + 1), hipMemcpyDeviceToDevice, stream));
+      HIP_CHECK(hipMemcpyAsync(nV.p, Vb.p, sizeof(T) * (size_t)acols * (size_t)(kcap + 2), hipMemcpyDeviceToDevice, stream));
+      HIP_CHECK(hipMemcpyAsync(ncoef.as<double>(), coef.as<double>(), sizeof(double) * (kcap + 4), hipMemcpyDeviceToDevice, stream));
+      HIP_CHECK(hipMemcpyAsync(ncoef.as<double>() + (newcap + 4), coef.as<double>() + (kcap + 4),
+                               sizeof(double) * (kcap + 4), hipMemcpyDeviceToDevice, stream));
+      HIP_CHECK(hipStreamSynchronize(stream));
+    }
+    std::swap(Ub.p, nU.p); std::swap(Ub.bytes, nU.bytes);
+    std::swap(Vb.p, nV.p); std::swap(Vb.bytes, nV.bytes);
+    std::swap(coef.p, ncoef.p); std::swap(coef.bytes, ncoef.bytes);
+    std::swap(red_partial.p, npart.p); std::swap(red_partial.bytes, npart.bytes);
+    std::swap(red_h1.p, nh1.p); std::swap(red_h1.bytes, nh1.bytes);
+    std::swap(red_h2.p, nh2.p); std::swap(red_h2.bytes, nh2.bytes);
+    kcap = newcap;
+    rs.partial = red_partial.as<double>();
+    rs.h1 = red_h1.as<double>();
+    rs.h2 = red_h2.as<double>();
+    rs.scal = red_scal.as<double>();
+    rs.counters = red_counters.as<unsigned>();
+  }
+
+  double *alpha_d() { return coef.as<double>(); }                 // alpha_{i+1} at [i]
+  double *beta_d() { return coef.as<double>() + (kcap + 4); }     // beta_{i+1} at [i]
+  T *ucol(int i) { return Ub.as<T>() + (size_t)i * (size_t)arows; }
+  T *vcol(int i) { return Vb.as<T>() + (size_t)i * (size_t)acols; }
+
+  // Room for rank-r factors (row stride even, zero padded) and the k x r
+  // combination matrices.
+  void ensure_factors(int r, int k) {
+    if (r > fcap) {
+      const int cap = std::max(r, fcap * 2);
+      fstride = std::max(2, (cap + 1) & ~1);
+      fcap = cap;
+      Fu.alloc(sizeof(T) * (size_t)ix.m * fstride);
+      Fv.alloc(sizeof(T) * (size_t)ix.n * fstride);
+      wd.alloc(sizeof(double) * cap);
+    }
+    const size_t need = sizeof(double) * (size_t)std::max(k, 1) * (size_t)std::max(r, 1);
+    if (Pd.bytes < need) {
+      Pd.alloc(need * 2);
+      Qd.alloc(need * 2);
+    }
+  }
+
+  // --------------------------------------------------------- sparse products
+  // orientation helpers: A's row-compressed and column-compressed structures
+  struct Csx { const int32_t *ptr, *idx; int nrows; int lanes; };
+  Csx a_rows_struct() {
+    if (a_is_y) return {rowptr.as<int32_t>(), colidx.as<int32_t>(), (int)ix.m, lanes_r};
+    return {colptr.as<int32_t>(), rowidx.as<int32_t>(), (int)ix.n, lanes_c};
+  }
+  Csx a_cols_struct() {
+    if (a_is_y) return {colptr.as<int32_t>(), rowidx.as<int32_t>(), (int)ix.n, lanes_c};
+    return {rowptr.as<int32_t>(), colidx.as<int32_t>(), (int)ix.m, lanes_r};
+  }
+
+  // Algorithmic bytes: index and value of every stored entry, the gathered
+  // vector once, the previous vector and the result.
+  double spmv_bytes(const Csx &c, int ncols_x, bool has_prev) const {
+    const double vb = sizeof(T);
+    return (double)ix.nnz * (vb + 4.0) + 4.0 * (c.nrows + 1) + vb * ncols_x + vb * c.nrows +
+           (has_prev ? vb * c.nrows : 0.0);
+  }
+
+  // One half-step: out_col = normalise(orth(S x - coef prev)), norm -> norm_out.
+  void half_step(const Csx &c, const T *vals, const T *x, int ncols_x, const T *prev,
+                 const double *coefp, T *Q, int64_t ldq, int nq, double *norm_out, T *out_col) {
+    T *p = pbuf.as<T>();
+    const double vb = sizeof(T);
+    prof.begin();
+    HIP_CHECK(launch_spmv<T>(stream, c.lanes, c.ptr, c.idx, vals, x, prev, coefp, p, c.nrows));
+    prof.end(kSpmv, spmv_bytes(c, ncols_x, prev != nullptr));
+    prof.begin();
+    HIP_CHECK(launch_dots<T>(stream, p, c.nrows, Q, ldq, nq, rs, norm_out));
+    prof.end(kDots, vb * (double)c.nrows * (nq + 1.0));
+    if (nq > 0) {
+      prof.begin();
+      HIP_CHECK(launch_cgs_update<T>(stream, p, c.nrows, Q, ldq, nq, rs, norm_out,
+                                     prm.reorth_passes == 2 ? 1 : 0));
+      HIP_CHECK(launch_cgs_finish<T>(stream, p, c.nrows, Q, ldq, nq, rs, norm_out));
+      prof.end(kOrth, vb * (double)c.nrows * (nq + 2.0));
+    }
+    prof.begin();
+    HIP_CHECK(launch_scale<T>(stream, p, norm_out, out_col, c.nrows));
+    prof.end(kNorm, vb * (double)c.nrows * 2.0);
+  }
+
+  // ------------------------------------------------- bidiagonalisation (a3)
+  struct Gkl {
+    int k = 0;                // completed steps: u_1..u_k, v_1..v_{k+1}, beta_{k+1}
+    std::vector<double> alpha, beta;  // host copies, alpha[i] = alpha_{i+1}, beta[i] = beta_{i+1}
+  };
+
+  // Start: v_1 random unit, u_1 = A v_1 / alpha_1, then v_2, beta_2.
+  void gkl_start(const T *vr, const T *vc, Gkl &g) {
+    ensure_basis(std::min<int64_t>(acols, 8));
+    const Csx R = a_rows_struct(), C = a_cols_struct();
+    T *p = pbuf.as<T>();
+    HIP_CHECK(launch_randn<T>(stream, p, (int)acols, prm.seed, rng_ctr++));
+    // normalise the start vector: an orthogonalisation against no columns
+    HIP_CHECK(launch_cgs_update<T>(stream, p, (int)acols, vcol(0), acols, 0, rs, beta_d(), 0));
+    HIP_CHECK(launch_scale<T>(stream, p, beta_d(), vcol(0), (int)acols));
+    half_step(R, vr, vcol(0), (int)acols, nullptr, nullptr, Ub.as<T>(), arows, 0, alpha_d(), ucol(0));
+    g.k = 1;
+    // v_2: A^T u_1 - alpha_1 v_1, orthogonal to v_1
+    half_step(C, vc, ucol(0), (int)arows, vcol(0), alpha_d(), Vb.as<T>(), acols, 1, beta_d() + 1, vcol(1));
+    steps_total += 1;
+  }
+
+  // One more step: u_{k+1}, alpha_{k+1}, v_{k+2}, beta_{k+2}.
+  void gkl_step(const T *vr, const T *vc, Gkl &g) {
+    const int k = g.k;
+    ensure_basis(k + 1);
+    const Csx R = a_rows_struct(), C = a_cols_struct();
+    // u_{k+1} = A v_{k+1} - beta_{k+1} u_k, orthogonal to u_1..u_k
+    half_step(R, vr, vcol(k), (int)acols, ucol(k - 1), beta_d() + k, Ub.as<T>(), arows, k,
+              alpha_d() + k, ucol(k));
+    // v_{k+2} = A^T u_{k+1} - alpha_{k+1} v_{k+1}, orthogonal to v_1..v_{k+1}
+    half_step(C, vc, ucol(k), (int)arows, vcol(k), alpha_d() + k, Vb.as<T>(), acols, k + 1,
+              beta_d() + k + 1, vcol(k + 1));
+    g.k = k + 1;
+    steps_total += 1;
+  }
+
+  void gkl_fetch(Gkl &g) {
+    const int k = g.k;
+    g.alpha.resize(k);
+    g.beta.resize(k + 1);
+    HIP_CHECK(hipMemcpyAsync(g.alpha.data(), alpha_d(), sizeof(double) * k, hipMemcpyDeviceToHost, stream));
+    HIP_CHECK(hipMemcpyAsync(g.beta.data(), beta_d(), sizeof(double) * (k + 1), hipMemcpyDeviceToHost, stream));
+    HIP_CHECK(hipStreamSynchronize(stream));
+  }
+
+  // SVD of B_k and residual bounds res_i = beta_{k+1} |P_{k,i}|.
+  void gkl_ritz(const Gkl &g, bool vectors, BidiagSVD &out, std::vector<double> &res) {
+    const int k = g.k;
+    std::vector<double> d(g.alpha.begin(), g.alpha.begin() + k), e(k > 1 ? k - 1 : 0);
+    for (int i = 0; i + 1 < k; ++i) e[i] = g.beta[i + 1];
+    if (!bidiag_svd(d, e, vectors, out)) throw Error(SVT_ELANCZOS, "bidiagonal SVD did not converge");
+    const double bk1 = (k >= acols) ? 0.0 : std::fabs(g.beta[k]);
+    res.resize(k);
+    for (int i = 0; i < k; ++i) res[i] = bk1 * std::fabs(out.p_last[i]);
+  }
+
+  int step_cap() const {
+    int cap = (int)acols;
+    if (prm.lanczos_maxsteps > 0) cap = std::min(cap, (int)prm.lanczos_maxsteps);
+    return cap;
+  }
+
+  // Run the bidiagonalisation until the decision of Algorithm 1's inner loop
+  // is certain.  mode 0 (SVT step): every Ritz value above tau converged and
+  // the first one at or below tau is either converged or certainly below tau
+  // (value + residual <= tau).  mode 1 (fixed count): the `count` largest
+  // triplets converged.  Returns k and fills the final SVD with vectors.
+  int gkl_run(const T *vr, const T *vc, int mode, int count, double tau, Gkl &g, BidiagSVD &sv,
+              int &r_out) {
+    const double tol = prm.lanczos_tol;
+    const int cap = step_cap();
+    gkl_start(vr, vc, g);
+    int next_check = std::max(std::min(cap, mode == 1 ? count + 2 : 3), std::min(cap, k_hint - 2));
+    next_check = std::max(next_check, 1);
+    std::vector<double> res;
+    for (;;) {
+      while (g.k < next_check && g.k < cap) gkl_step(vr, vc, g);
+      gkl_fetch(g);
+      BidiagSVD chk;
+      gkl_ritz(g, false, chk, res);
+      const int k = g.k;
+      const double top = chk.sigma.empty() ? 0.0 : chk.sigma[0];
+      const double atol = tol * std::max(top, 1e-300);
+      bool done = false;
+      int r = 0;
+      if (k >= acols) {
+        done = true;  // the bases span the whole smaller dimension: exact
+        if (mode == 0)
+          while (r < k && chk.sigma[r] > tau) ++r;
+      } else if (mode == 0) {
+        while (r < k && chk.sigma[r] > tau) ++r;
+        bool ok = true;
+        for (int i = 0; i < r && ok; ++i) ok = res[i] <= atol;
+        // The first value at or below tau decides r.  It must be converged,
+        // unless even its residual interval lies well below tau: a Ritz value
+        // can sit between two close singular values before it converges, and
+        // its residual bound then certifies the lower one, not the one above
+        // tau (Ritz values only approach the singular values from below).
+        if (ok && r < k)
+          ok = (res[r] <= atol) || (chk.sigma[r] + res[r] <= tau * (1.0 - prm.decide_margin));
+        if (ok && r == k) ok = false;  // no value below tau seen yet: extend (s_k += ell)
+        done = ok;
+      } else {
+        const int c = std::min(count, k);
+        bool ok = (k >= count);
+        for (int i = 0; i < c && ok; ++i) ok = res[i] <= atol;
+        done = ok;
+      }
+      if (done) {
+        r_out = r;
+        if (log_level > 0) {
+          std::fprintf(stderr, "[svt] gkl mode %d k %d r %d top %.6e", mode, k, r, top);
+          for (int i = std::max(0, r - 1); i < std::min(k, r + 2); ++i)
+            std::fprintf(stderr, " | s%d %.10e res %.2e", i + 1, chk.sigma[i], res[i]);
+          std::fprintf(stderr, " | tau %.10e\n", tau);
+        }
+        gkl_ritz(g, true, sv, res);
+        return k;
+      }
+      if (g.k >= cap) {
+        throw Error(SVT_ELANCZOS, "bidiagonalisation reached its step cap (" + std::to_string(cap) +
+                                      ") before the Ritz triplets converged");
+      }
+      next_check = std::min(cap, g.k + std::max(1, std::min(8, g.k / 4)));
+    }
+  }
+
+  // Ritz vectors for the first r triplets; ws scales the left factor of Y.
+  void form_factors(const Gkl &g, const BidiagSVD &sv, int r, const double *ws) {
+    const int k = g.k;
+    ensure_factors(std::max(r, 1), k);
+    if (r == 0) { rank = 0; return; }
+    // P (u side) and Q (v side) restricted to the first r columns, k x r row-major
+    std::vector<double> Ph((size_t)k * r), Qh((size_t)k * r);
+    for (int c = 0; c < k; ++c)
+      for (int l = 0; l < r; ++l) {
+        Ph[(size_t)c * r + l] = sv.P[(size_t)l * k + c];
+        Qh[(size_t)c * r + l] = sv.Q[(size_t)l * k + c];
+      }
+    HIP_CHECK(hipMemcpyAsync(Pd.p, Ph.data(), sizeof(double) * Ph.size(), hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(Qd.p, Qh.data(), sizeof(double) * Qh.size(), hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(wd.p, ws, sizeof(double) * r, hipMemcpyHostToDevice, stream));
+    // Y's left factor (rows m) takes the weights
+    T *u_out = a_is_y ? Fu.as<T>() : Fv.as<T>();   // A-rows side
+    T *v_out = a_is_y ? Fv.as<T>() : Fu.as<T>();   // A-cols side
+    const double *wu = a_is_y ? wd.as<double>() : nullptr;
+    const double *wv = a_is_y ? nullptr : wd.as<double>();
+    prof.begin();
+    HIP_CHECK(launch_ritz<T>(stream, Ub.as<T>(), arows, (int)arows, k, Pd.as<double>(), wu, r, u_out, fstride));
+    HIP_CHECK(launch_ritz<T>(stream, Vb.as<T>(), acols, (int)acols, k, Qd.as<double>(), wv, r, v_out, fstride));
+    prof.end(kRitz, (double)sizeof(T) * ((double)(arows + acols) * (k + fstride)));
+    rank = r;
+  }
+
+  // Sampled product + residual + update on both copies; returns residual^2.
+  double sample_pass(int r, double delta, bool want_res) {
+    double *res2 = rs.scal + 2;
+    const double vb = sizeof(T);
+    prof.begin();
+    HIP_CHECK(launch_sample_update<T>(stream, lanes_r, rowptr.as<int32_t>(), colidx.as<int32_t>(), Mr.as<T>(),
+                                      Yr.as<T>(), (int)ix.m, Fu.as<T>(), Fv.as<T>(), r, fstride, true, delta, rs,
+                                      want_res ? res2 : nullptr));
+    HIP_CHECK(launch_sample_update<T>(stream, lanes_c, colptr.as<int32_t>(), rowidx.as<int32_t>(), Mc.as<T>(),
+                                      Yc.as<T>(), (int)ix.n, Fu.as<T>(), Fv.as<T>(), r, fstride, false, delta, rs,
+                                      nullptr));
+    prof.end(kSample, 2.0 * ((double)ix.nnz * (4.0 + 3.0 * vb)) + 4.0 * (ix.m + ix.n + 2) +
+                          vb * (double)(ix.m + ix.n) * r * 2.0);
+    if (!want_res) return 0.0;
+    double h = 0.0;
+    HIP_CHECK(hipMemcpyAsync(&h, res2, sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIP_CHECK(hipStreamSynchronize(stream));
+    return h;
+  }
+
+  // --------------------------------------------------------------- kick (a2)
+  void do_kick(double *sigma1, int32_t *k0_out) {
+    Gkl g;
+    BidiagSVD sv;
+    int r = 0;
+    const int saved_hint = k_hint;
+    k_hint = 0;
+    const T *mr = a_is_y ? Mr.as<T>() : Mc.as<T>();
+    const T *mc = a_is_y ? Mc.as<T>() : Mr.as<T>();
+    gkl_run(mr, mc, 1, 1, 0.0, g, sv, r);
+    k_hint = saved_hint;
+    const double s1 = sv.sigma.empty() ? 0.0 : sv.sigma[0];
+    if (!(s1 > 0.0)) throw Error(SVT_EINVAL, "||P_Omega M||_2 is zero");
+    int32_t k0 = prm.k0_override > 0 ? prm.k0_override
+                                     : (int32_t)std::max(1.0, std::ceil(prm.tau / (prm.delta * s1)));
+    const double a = (double)k0 * prm.delta;
+    HIP_CHECK(launch_axpby<T>(stream, Mr.as<T>(), Yr.as<T>(), ix.nnz, a));
+    HIP_CHECK(launch_axpby<T>(stream, Mc.as<T>(), Yc.as<T>(), ix.nnz, a));
+    HIP_CHECK(hipStreamSynchronize(stream));
+    *sigma1 = s1;
+    *k0_out = k0;
+  }
+
+  // -------------------------------------------------------------- solve
+  svt_status solve(svt_info *info) override {
+    history.clear();
+    prof.reset();
+    steps_total = 0;
+    rng_ctr = 0;
+    k_hint = 0;
+    rank = 0;
+    w.clear();
+    svt_info inf{};
+    inf.norm_pm = norm_pm;
+    inf.t_setup_s = t_setup;
+    const double t0 = now_s();
+    double s1 = 0.0;
+    int32_t k0 = 0;
+    HIP_CHECK(hipMemsetAsync(Yr.p, 0, sizeof(T) * ix.nnz, stream));
+    HIP_CHECK(hipMemsetAsync(Yc.p, 0, sizeof(T) * ix.nnz, stream));
+    if (prm.kick) do_kick(&s1, &k0);
+    HIP_CHECK(hipStreamSynchronize(stream));
+    const double t1 = now_s();
+    inf.t_kick_s = t1 - t0;
+    inf.sigma1 = s1;
+    inf.k0 = k0;
+
+    const T *yr = a_is_y ? Yr.as<T>() : Yc.as<T>();
+    const T *yc = a_is_y ? Yc.as<T>() : Yr.as<T>();
+    int r_prev = 0;
+    svt_status st = SVT_NOT_CONVERGED;
+    int k = 0;
+    double res = 1.0;
+    for (k = 1; k <= prm.maxiter; ++k) {
+      Gkl g;
+      BidiagSVD sv;
+      int r = 0;
+      const int steps = gkl_run(yr, yc, 0, 0, prm.tau, g, sv, r);
+      k_hint = steps;
+      // s_k bookkeeping of Algorithm 1's repeat loop (Section 5.1.1)
+      int s = std::min<int64_t>(r_prev + 1, acols);
+      while (s <= r && s < acols) s = (int)std::min<int64_t>(s + prm.incr, acols);
+      std::vector<double> ws(std::max(r, 1));
+      for (int i = 0; i < r; ++i) ws[i] = sv.sigma[i] - prm.tau;
+      form_factors(g, sv, r, ws.data());
+      w.assign(ws.begin(), ws.begin() + r);
+      const double res2 = sample_pass(r, prm.delta, true);
+      res = std::sqrt(res2) / norm_pm;
+      history.push_back({r, s, steps, res});
+      if (!std::isfinite(res)) { st = SVT_EDIVERGED; break; }
+      bool stop;
+      if (prm.stop_rule == SVT_STOP_NOISY)
+        stop = res2 <= (1.0 + prm.eps) * (double)ix.nnz * prm.noise_sigma * prm.noise_sigma;
+      else
+        stop = res <= prm.eps;
+      if (stop) { st = SVT_OK; break; }
+      r_prev = r;
+    }
+    if (k > prm.maxiter) k = prm.maxiter;
+    HIP_CHECK(hipStreamSynchronize(stream));
+    const double t2 = now_s();
+    prof.flush();
+    inf.t_solve_s = t2 - t1;
+    inf.iters = k;
+    inf.rank = rank;
+    inf.rel_residual = res;
+    inf.status = st;
+    inf.gkl_steps = steps_total;
+    if (info) *info = inf;
+    return st;
+  }
+
+  // ---------------------------------------------------------- outputs
+  void factors(int32_t *rank_out, double *U, double *wout, double *V) const override {
+    if (rank_out) *rank_out = rank;
+    if (rank == 0) return;
+    const int64_t m = ix.m, n = ix.n;
+    std::vector<T> hu((size_t)m * fstride), hv((size_t)n * fstride);
+    HIP_CHECK(hipMemcpyAsync(hu.data(), Fu.p, sizeof(T) * hu.size(), hipMemcpyDeviceToHost, stream));
+    HIP_CHECK(hipMemcpyAsync(hv.data(), Fv.p, sizeof(T) * hv.size(), hipMemcpyDeviceToHost, stream));
+    HIP_CHECK(hipStreamSynchronize(stream));
+    if (U)
+      for (int64_t i = 0; i < m; ++i)
+        for (int l = 0; l < rank; ++l) U[(size_t)i * rank + l] = (double)hu[(size_t)i * fstride + l];
+    if (V)
+      for (int64_t j = 0; j < n; ++j)
+        for (int l = 0; l < rank; ++l) V[(size_t)j * rank + l] = (double)hv[(size_t)j * fstride + l];
+    if (wout)
+      for (int l = 0; l < rank; ++l) wout[l] = w[l];
+  }
+
+  void set_iterate(const double *y) override {
+    std::vector<double> csr((size_t)ix.nnz);
+    for (int64_t t = 0; t < ix.nnz; ++t) csr[(size_t)ix.csr_of_input[(size_t)t]] = y[t];
+    upload_values(csr.data(), Yr.as<T>(), Yc.as<T>());
+  }
+
+  void get_iterate(int which, double *y) const override {
+    std::vector<T> h((size_t)ix.nnz);
+    HIP_CHECK(hipMemcpyAsync(h.data(), which ? Yc.p : Yr.p, sizeof(T) * ix.nnz, hipMemcpyDeviceToHost, stream));
+    HIP_CHECK(hipStreamSynchronize(stream));
+    for (int64_t t = 0; t < ix.nnz; ++t) {
+      const int32_t c = ix.csr_of_input[(size_t)t];
+      y[t] = (double)(which ? h[(size_t)ix.csc_of_csr[(size_t)c]] : h[(size_t)c]);
+    }
+  }
+
+  void apply(int trans, const double *x, double *out) override {
+    // trans = 0: Y x through the row-compressed copy; 1: Y^T x through the column copy
+    const int64_t nin = trans ? ix.m : ix.n, nout = trans ? ix.n : ix.m;
+    std::vector<T> hx((size_t)nin);
+    for (int64_t i = 0; i < nin; ++i) hx[(size_t)i] = (T)x[i];
+    DevMem dx, dout;
+    dx.alloc(sizeof(T) * nin);
+    dout.alloc(sizeof(T) * nout);
+    HIP_CHECK(hipMemcpyAsync(dx.p, hx.data(), sizeof(T) * nin, hipMemcpyHostToDevice, stream));
+    Csx c = trans ? Csx{colptr.as<int32_t>(), rowidx.as<int32_t>(), (int)ix.n, lanes_c}
+                  : Csx{rowptr.as<int32_t>(), colidx.as<int32_t>(), (int)ix.m, lanes_r};
+    HIP_CHECK(launch_spmv<T>(stream, c.lanes, c.ptr, c.idx, trans ? Yc.as<T>() : Yr.as<T>(), dx.as<T>(),
+                             nullptr, nullptr, dout.as<T>(), c.nrows));
+    std::vector<T> ho((size_t)nout);
+    HIP_CHECK(hipMemcpyAsync(ho.data(), dout.p, sizeof(T) * nout, hipMemcpyDeviceToHost, stream));
+    HIP_CHECK(hipStreamSynchronize(stream));
+    for (int64_t i = 0; i < nout; ++i) out[i] = (double)ho[(size_t)i];
+  }
+
+  int partial_svd(int count, double *sigma, double *U, double *V) override {
+    if (count > acols) throw Error(SVT_EINVAL, "count exceeds min(m, n)");
+    Gkl g;
+    BidiagSVD sv;
+    int r = 0;
+    const T *yr = a_is_y ? Yr.as<T>() : Yc.as<T>();
+    const T *yc = a_is_y ? Yc.as<T>() : Yr.as<T>();
+    k_hint = 0;
+    const int steps = gkl_run(yr, yc, 1, count, 0.0, g, sv, r);
+    std::vector<double> ones(count, 1.0);
+    form_factors(g, sv, count, ones.data());
+    for (int i = 0; i < count; ++i) sigma[i] = sv.sigma[i];
+    factors(nullptr, U, nullptr, V);
+    rank = 0;  // the handle's X is not this partial SVD
+    return steps;
+  }
+
+  double sample_update(int r, const double *U, const double *V, double delta) override {
+    ensure_factors(std::max(r, 1), 1);
+    const int64_t m = ix.m, n = ix.n;
+    std::vector<T> hu((size_t)m * fstride, (T)0), hv((size_t)n * fstride, (T)0);
+    for (int64_t i = 0; i < m; ++i)
+      for (int l = 0; l < r; ++l) hu[(size_t)i * fstride + l] = (T)U[(size_t)i * r + l];
+    for (int64_t j = 0; j < n; ++j)
+      for (int l = 0; l < r; ++l) hv[(size_t)j * fstride + l] = (T)V[(size_t)j * r + l];
+    HIP_CHECK(hipMemcpyAsync(Fu.p, hu.data(), sizeof(T) * hu.size(), hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(Fv.p, hv.data(), sizeof(T) * hv.size(), hipMemcpyHostToDevice, stream));
+    rank = 0;
+    return sample_pass(r, delta, true);
+  }
+
+  void kick(double *sigma1, int32_t *k0) override { do_kick(sigma1, k0); }
+
+  ~Problem() override {
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// validation (before any device call)
+
+static void validate_params(const svt_params &p) {
+  auto finite = [](double v) { return std::isfinite(v); };
+  if (!finite(p.tau) || p.tau <= 0) throw Error(SVT_EINVAL, "tau must be finite and > 0");
+  if (!finite(p.delta) || p.delta <= 0) throw Error(SVT_EINVAL, "delta must be finite and > 0");
+  if (!finite(p.eps) || p.eps < 0) throw Error(SVT_EINVAL, "eps must be finite and >= 0");
+  if (p.maxiter < 1) throw Error(SVT_EINVAL, "maxiter must be >= 1");
+  if (p.incr < 1) throw Error(SVT_EINVAL, "incr (ell) must be >= 1");
+  if (p.kick != 0 && p.kick != 1) throw Error(SVT_EINVAL, "kick must be 0 or 1");
+  if (p.k0_override < 0) throw Error(SVT_EINVAL, "k0_override must be >= 0");
+  if (p.precision != SVT_FP64 && p.precision != SVT_MIXED) throw Error(SVT_EINVAL, "unknown precision");
+  if (p.stop_rule != SVT_STOP_RELRES && p.stop_rule != SVT_STOP_NOISY) throw Error(SVT_EINVAL, "unknown stop rule");
+  if (!finite(p.noise_sigma) || p.noise_sigma < 0) throw Error(SVT_EINVAL, "noise_sigma must be finite and >= 0");
+  if (p.stop_rule == SVT_STOP_NOISY && p.noise_sigma <= 0) throw Error(SVT_EINVAL, "the noisy stop rule needs noise_sigma > 0");
+  if (!finite(p.lanczos_tol) || p.lanczos_tol < 0 || p.lanczos_tol >= 1) throw Error(SVT_EINVAL, "lanczos_tol must be in [0, 1)");
+  if (p.lanczos_maxsteps < 0) throw Error(SVT_EINVAL, "lanczos_maxsteps must be >= 0");
+  if (p.reorth_passes != 0 && p.reorth_passes != 2) throw Error(SVT_EINVAL, "reorth_passes must be 0 or 2");
+  if (!finite(p.decide_margin) || p.decide_margin < 0) throw Error(SVT_EINVAL, "decide_margin must be finite and >= 0");
+}
+
+}  // namespace svt
+
+// ===========================================================================
+// C ABI
+
+struct svt_problem {
+  std::unique_ptr<svt::ProblemBase> impl;
+};
+
+using svt::Error;
+
+template <typename F>
+static svt_status guarded(const svt_problem *h, F &&f) {
+  try {
+    return f();
+  } catch (const Error &e) {
+    if (h && h->impl) h->impl->last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    if (h && h->impl) h->impl->last_error = "host allocation failed";
+    return SVT_ENOMEM;
+  } catch (const std::exception &e) {
+    if (h && h->impl) h->impl->last_error = e.what();
+    return SVT_EDEVICE;
+  } catch (...) {
+    if (h && h->impl) h->impl->last_error = "unknown error";
+    return SVT_EDEVICE;
+  }
+}
+
+extern "C" {
+
+svt_status svt_params_default(int64_t m, int64_t n, int64_t nnz, svt_params *out) {
+  if (!out || m < 1 || n < 1 || nnz < 1) return SVT_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  out->tau = 5.0 * std::sqrt((double)m * (double)n);
+  out->delta = 1.2 * (double)m * (double)n / (double)nnz;
+  out->eps = 1e-4;
+  out->maxiter = 500;
+  out->incr = 5;
+  out->kick = 1;
+  out->k0_override = 0;
+  out->precision = SVT_FP64;
+  out->stop_rule = SVT_STOP_RELRES;
+  out->noise_sigma = 0.0;
+  out->lanczos_tol = 0.0;  // auto: 1e-12 (FP64) or 1e-6 (MIXED)
+  out->lanczos_maxsteps = 0;
+  out->reorth_passes = 0;
+  out->decide_margin = 0.05;
+  out->seed = 0x5EEDull;
+  out->profile = 0;
+  out->stream = nullptr;
+  return SVT_OK;
+}
+
+svt_status svt_create(int64_t m, int64_t n, int64_t nnz, int32_t fmt, const void *idx0,
+                      const int32_t *idx1, const double *vals, const svt_params *params,
+                      svt_problem **out) {
+  if (out) *out = nullptr;
+  svt::g_create_error.clear();
+  try {
+    if (!out) throw Error(SVT_EINVAL, "out is NULL");
+    if (m < 1 || n < 1) throw Error(SVT_EINVAL, "m and n must be >= 1");
+    if (m > INT32_MAX - 1 || n > INT32_MAX - 1) throw Error(SVT_EINVAL, "m and n must be < 2^31 - 1");
+    if (nnz < 1) throw Error(SVT_EINVAL, "nnz must be >= 1");
+    if ((double)nnz > (double)m * (double)n || nnz > m * n) throw Error(SVT_EINVAL, "nnz exceeds m*n");
+    if (nnz > INT32_MAX) throw Error(SVT_EINVAL, "nnz must be < 2^31");
+    if (!idx0 || !idx1 || !vals) throw Error(SVT_EINVAL, "index or value pointer is NULL");
+    if (fmt != SVT_COO && fmt != SVT_CSR) throw Error(SVT_EINVAL, "unknown index format");
+    svt_params prm;
+    if (params) prm = *params;
+    else svt_params_default(m, n, nnz, &prm);
+    svt::validate_params(prm);
+    if (prm.lanczos_tol == 0.0) prm.lanczos_tol = (prm.precision == SVT_MIXED) ? 1e-6 : 1e-12;
+    // rows of every entry
+    std::vector<int32_t> rows_buf;
+    const int32_t *rows = nullptr;
+    if (fmt == SVT_COO) {
+      rows = static_cast<const int32_t *>(idx0);
+    } else {
+      const int64_t *rp = static_cast<const int64_t *>(idx0);
+      if (rp[0] != 0 || rp[m] != nnz) throw Error(SVT_EINVAL, "rowptr must start at 0 and end at nnz");
+      rows_buf.resize((size_t)nnz);
+      for (int64_t i = 0; i < m; ++i) {
+        if (rp[i + 1] < rp[i]) throw Error(SVT_EINVAL, "rowptr must be non-decreasing");
+        for (int64_t t = rp[i]; t < rp[i + 1]; ++t) rows_buf[(size_t)t] = (int32_t)i;
+      }
+      rows = rows_buf.data();
+    }
+    bool any_nonzero = false;
+    for (int64_t t = 0; t < nnz; ++t) {
+      if (rows[t] < 0 || rows[t] >= m) throw Error(SVT_EINVAL, "row index out of range at entry " + std::to_string(t));
+      if (idx1[t] < 0 || idx1[t] >= n) throw Error(SVT_EINVAL, "column index out of range at entry " + std::to_string(t));
+      if (!std::isfinite(vals[t])) throw Error(SVT_EINVAL, "non-finite value at entry " + std::to_string(t));
+      any_nonzero |= (vals[t] != 0.0);
+    }
+    if (!any_nonzero) throw Error(SVT_EINVAL, "all observed values are zero: the stop test is undefined");
+
+    const double t0 = svt::now_s();
+    std::unique_ptr<svt::ProblemBase> impl;
+    if (prm.precision == SVT_MIXED) impl.reset(new svt::Problem<float>());
+    else impl.reset(new svt::Problem<double>());
+    svt::build_index(m, n, nnz, rows, idx1, vals, impl->ix);
+    {
+      // ||P_Omega M||_F with a compensated sum
+      double s = 0.0, c = 0.0;
+      for (int64_t t = 0; t < nnz; ++t) {
+        const double y = vals[t] * vals[t] - c;
+        const double tt = s + y;
+        c = (tt - s) - y;
+        s = tt;
+      }
+      impl->norm_pm = std::sqrt(s);
+    }
+    if (prm.precision == SVT_MIXED) static_cast<svt::Problem<float> *>(impl.get())->setup(prm);
+    else static_cast<svt::Problem<double> *>(impl.get())->setup(prm);
+    impl->t_setup = svt::now_s() - t0;
+    svt_problem *h = new svt_problem();
+    h->impl = std::move(impl);
+    *out = h;
+    return SVT_OK;
+  } catch (const Error &e) {
+    svt::g_create_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    svt::g_create_error = "host allocation failed";
+    return SVT_ENOMEM;
+  } catch (const std::exception &e) {
+    svt::g_create_error = e.what();
+    return SVT_EDEVICE;
+  }
+}
+
+svt_status svt_solve(svt_problem *h, svt_info *info) {
+  if (!h || !h->impl) return SVT_EINVAL;
+  return guarded(h, [&] { return h->impl->solve(info); });
+}
+
+svt_status svt_history(const svt_problem *h, int32_t cap, int32_t *ranks, int32_t *s_hist,
+                       double *residuals, int32_t *gkl_steps, int32_t *len_out) {
+  if (!h || !h->impl || cap < 0) return SVT_EINVAL;
+  const auto &hist = h->impl->history;
+  const int32_t len = (int32_t)hist.size();
+  if (len_out) *len_out = len;
+  for (int32_t i = 0; i < std::min(cap, len); ++i) {
+    if (ranks) ranks[i] = hist[i].rank;
+    if (s_hist) s_hist[i] = hist[i].s;
+    if (residuals) residuals[i] = hist[i].res;
+    if (gkl_steps) gkl_steps[i] = hist[i].steps;
+  }
+  return SVT_OK;
+}
+
+svt_status svt_factors(const svt_problem *h, int32_t *rank_out, double *U, double *w, double *V) {
+  if (!h || !h->impl) return SVT_EINVAL;
+  return guarded(h, [&] {
+    h->impl->factors(rank_out, U, w, V);
+    return SVT_OK;
+  });
+}
+
+svt_status svt_predict(const svt_problem *h, int64_t q, const int32_t *rows, const int32_t *cols,
+                       double *out) {
+  if (!h || !h->impl || q < 0 || (q > 0 && (!rows || !cols || !out))) return SVT_EINVAL;
+  return guarded(h, [&] {
+    const auto &ix = h->impl->ix;
+    for (int64_t t = 0; t < q; ++t)
+      if (rows[t] < 0 || rows[t] >= ix.m || cols[t] < 0 || cols[t] >= ix.n)
+        throw Error(SVT_EINVAL, "predict index out of range at " + std::to_string(t));
+    int32_t r = 0;
+    h->impl->factors(&r, nullptr, nullptr, nullptr);
+    std::vector<double> U((size_t)ix.m * std::max(r, 1)), V((size_t)ix.n * std::max(r, 1));
+    if (r > 0) h->impl->factors(&r, U.data(), nullptr, V.data());
+    for (int64_t t = 0; t < q; ++t) {
+      double s = 0.0;
+      for (int l = 0; l < r; ++l) s += U[(size_t)rows[t] * r + l] * V[(size_t)cols[t] * r + l];
+      out[t] = s;
+    }
+    return SVT_OK;
+  });
+}
+
+void svt_destroy(svt_problem *h) { delete h; }
+
+const char *svt_status_string(int32_t s) {
+  switch (s) {
+    case SVT_OK: return "ok";
+    case SVT_NOT_CONVERGED: return "not converged (maxiter reached)";
+    case SVT_EINVAL: return "invalid argument";
+    case SVT_ENOMEM: return "out of memory";
+    case SVT_EDEVICE: return "device error";
+    case SVT_ESTATE: return "invalid state";
+    case SVT_EDIVERGED: return "diverged (non-finite residual)";
+    case SVT_EBUSY: return "busy";
+    case SVT_ELANCZOS: return "partial SVD did not converge";
+    default: return "unknown status";
+  }
+}
+
+const char *svt_last_error(const svt_problem *h) {
+  if (!h || !h->impl) return svt::g_create_error.c_str();
+  return h->impl->last_error.c_str();
+}
+
+svt_status svt_set_iterate(svt_problem *h, const double *y) {
+  if (!h || !h->impl || !y) return SVT_EINVAL;
+  return guarded(h, [&] {
+    for (int64_t t = 0; t < h->impl->ix.nnz; ++t)
+      if (!std::isfinite(y[t])) throw Error(SVT_EINVAL, "non-finite iterate value");
+    h->impl->set_iterate(y);
+    return SVT_OK;
+  });
+}
+
+svt_status svt_get_iterate(const svt_problem *h, int32_t which, double *y) {
+  if (!h || !h->impl || !y || (which != 0 && which != 1)) return SVT_EINVAL;
+  return guarded(h, [&] {
+    h->impl->get_iterate(which, y);
+    return SVT_OK;
+  });
+}
+
+svt_status svt_apply(svt_problem *h, int32_t trans, const double *x, double *out) {
+  if (!h || !h->impl || !x || !out || (trans != 0 && trans != 1)) return SVT_EINVAL;
+  return guarded(h, [&] {
+    h->impl->apply(trans, x, out);
+    return SVT_OK;
+  });
+}
+
+svt_status svt_partial_svd(svt_problem *h, int32_t count, double *sigma, double *U, double *V,
+                           int32_t *steps_out) {
+  if (!h || !h->impl || !sigma || count < 1) return SVT_EINVAL;
+  return guarded(h, [&] {
+    const int steps = h->impl->partial_svd(count, sigma, U, V);
+    if (steps_out) *steps_out = steps;
+    return SVT_OK;
+  });
+}
+
+svt_status svt_sample_update(svt_problem *h, int32_t r, const double *U, const double *V,
+                             double delta, double *res2) {
+  if (!h || !h->impl || r < 0 || (r > 0 && (!U || !V)) || !std::isfinite(delta)) return SVT_EINVAL;
+  return guarded(h, [&] {
+    const double v = h->impl->sample_update(r, U, V, delta);
+    if (res2) *res2 = v;
+    return SVT_OK;
+  });
+}
+
+svt_status svt_kick(svt_problem *h, double *sigma1, int32_t *k0) {
+  if (!h || !h->impl) return SVT_EINVAL;
+  return guarded(h, [&] {
+    double s = 0.0;
+    int32_t k = 0;
+    h->impl->kick(&s, &k);
+    if (sigma1) *sigma1 = s;
+    if (k0) *k0 = k;
+    return SVT_OK;
+  });
+}
+
+svt_status svt_kernel_stats(const svt_problem *h, int32_t kind, int64_t *launches, double *total_ms,
+                            double *total_bytes) {
+  if (!h || !h->impl || kind < 0 || kind >= svt::kKinds) return SVT_EINVAL;
+  const auto &p = h->impl->prof;
+  if (launches) *launches = p.launches[kind];
+  if (total_ms) *total_ms = p.ms[kind];
+  if (total_bytes) *total_bytes = p.bytes[kind];
+  return SVT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,284 @@
+"""ctypes binding of the C ABI in ``include/svt.h`` (argument marshalling only).
+
+Every function here has the name of the C entry point it calls; all numerical
+work happens in the HIP library.  Loading fails loudly when the library has not
+been built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libsvt.so")
+
+SVT_OK = 0
+SVT_NOT_CONVERGED = 1
+SVT_EINVAL = -1
+SVT_ENOMEM = -2
+SVT_EDEVICE = -3
+SVT_ESTATE = -4
+SVT_EDIVERGED = -5
+SVT_EBUSY = -6
+SVT_ELANCZOS = -7
+
+SVT_FP64 = 0
+SVT_MIXED = 1
+SVT_COO = 0
+SVT_CSR = 1
+SVT_STOP_RELRES = 0
+SVT_STOP_NOISY = 1
+
+KERNEL_KINDS = {0: "k_spmv", 1: "k_cgs_update+k_cgs_finish", 2: "k_scale", 3: "k_ritz",
+                4: "k_sample_update", 5: "k_dots"}
+
+
+class svt_params(ctypes.Structure):
+    _fields_ = [
+        ("tau", ctypes.c_double),
+        ("delta", ctypes.c_double),
+        ("eps", ctypes.c_double),
+        ("maxiter", ctypes.c_int32),
+        ("incr", ctypes.c_int32),
+        ("kick", ctypes.c_int32),
+        ("k0_override", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("stop_rule", ctypes.c_int32),
+        ("noise_sigma", ctypes.c_double),
+        ("lanczos_tol", ctypes.c_double),
+        ("lanczos_maxsteps", ctypes.c_int32),
+        ("reorth_passes", ctypes.c_int32),
+        ("decide_margin", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("profile", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class svt_info(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32),
+        ("k0", ctypes.c_int32),
+        ("rank", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("rel_residual", ctypes.c_double),
+        ("sigma1", ctypes.c_double),
+        ("norm_pm", ctypes.c_double),
+        ("t_setup_s", ctypes.c_double),
+        ("t_kick_s", ctypes.c_double),
+        ("t_solve_s", ctypes.c_double),
+        ("gkl_steps", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class SvtError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+_lp = ctypes.POINTER(ctypes.c_int64)
+
+
+def _signatures(lib):
+    h = ctypes.c_void_p
+    sig = {
+        "svt_params_default": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                                ctypes.POINTER(svt_params)]),
+        "svt_create": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                        ctypes.c_void_p, _ip, _dp, ctypes.POINTER(svt_params),
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+        "svt_solve": (ctypes.c_int32, [h, ctypes.POINTER(svt_info)]),
+        "svt_history": (ctypes.c_int32, [h, ctypes.c_int32, _ip, _ip, _dp, _ip, _ip]),
+        "svt_factors": (ctypes.c_int32, [h, _ip, _dp, _dp, _dp]),
+        "svt_predict": (ctypes.c_int32, [h, ctypes.c_int64, _ip, _ip, _dp]),
+        "svt_destroy": (None, [h]),
+        "svt_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+        "svt_last_error": (ctypes.c_char_p, [h]),
+        "svt_set_iterate": (ctypes.c_int32, [h, _dp]),
+        "svt_get_iterate": (ctypes.c_int32, [h, ctypes.c_int32, _dp]),
+        "svt_apply": (ctypes.c_int32, [h, ctypes.c_int32, _dp, _dp]),
+        "svt_partial_svd": (ctypes.c_int32, [h, ctypes.c_int32, _dp, _dp, _dp, _ip]),
+        "svt_sample_update": (ctypes.c_int32, [h, ctypes.c_int32, _dp, _dp, ctypes.c_double, _dp]),
+        "svt_kick": (ctypes.c_int32, [h, _dp, _ip]),
+        "svt_kernel_stats": (ctypes.c_int32, [h, ctypes.c_int32, _lp, _dp, _dp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise ImportError(f"HIP library not built: {path} is missing; run "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+        _lib = _signatures(ctypes.CDLL(path))
+    return _lib
+
+
+def _f64(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and a.shape[0] != n:
+        raise ValueError("length mismatch")
+    return a
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _p(a, t=_dp):
+    return a.ctypes.data_as(t) if a is not None else None
+
+
+def svt_status_string(status: int) -> str:
+    return load().svt_status_string(status).decode()
+
+
+def svt_last_error(h=None) -> str:
+    return load().svt_last_error(h).decode()
+
+
+def _check(status, h=None, allow=(SVT_OK,)):
+    if status not in allow:
+        raise SvtError(status, f"{svt_status_string(status)}: {svt_last_error(h)}")
+    return status
+
+
+def svt_params_default(m: int, n: int, nnz: int) -> svt_params:
+    p = svt_params()
+    _check(load().svt_params_default(m, n, nnz, ctypes.byref(p)))
+    return p
+
+
+def svt_create(m: int, n: int, rows, cols, vals, params: svt_params | None = None,
+               fmt: int = SVT_COO):
+    """Create a problem from COO triplets (or CSR: rows = int64 rowptr[m+1])."""
+    lib = load()
+    cols = _i32(cols)
+    vals = _f64(vals)
+    nnz = cols.shape[0]
+    if fmt == SVT_CSR:
+        idx0 = np.ascontiguousarray(rows, dtype=np.int64)
+    else:
+        idx0 = _i32(rows)
+    if vals.shape[0] != nnz or (fmt == SVT_COO and idx0.shape[0] != nnz):
+        raise ValueError("rows, cols and vals must have the same length")
+    h = ctypes.c_void_p()
+    st = lib.svt_create(m, n, nnz, fmt, idx0.ctypes.data_as(ctypes.c_void_p), _p(cols, _ip), _p(vals),
+                        ctypes.byref(params) if params is not None else None, ctypes.byref(h))
+    _check(st, None)
+    return h
+
+
+def svt_destroy(h) -> None:
+    if h is not None:
+        load().svt_destroy(h)
+
+
+def svt_solve(h):
+    info = svt_info()
+    st = load().svt_solve(h, ctypes.byref(info))
+    _check(st, h, allow=(SVT_OK, SVT_NOT_CONVERGED))
+    return st, info
+
+
+def svt_history(h):
+    lib = load()
+    ln = ctypes.c_int32()
+    _check(lib.svt_history(h, 0, None, None, None, None, ctypes.byref(ln)), h)
+    n = ln.value
+    ranks = np.zeros(n, np.int32)
+    s = np.zeros(n, np.int32)
+    res = np.zeros(n, np.float64)
+    steps = np.zeros(n, np.int32)
+    _check(lib.svt_history(h, n, _p(ranks, _ip), _p(s, _ip), _p(res), _p(steps, _ip),
+                           ctypes.byref(ln)), h)
+    return dict(ranks=ranks, s_hist=s, residuals=res, gkl_steps=steps)
+
+
+def svt_factors(h, m: int, n: int):
+    lib = load()
+    r = ctypes.c_int32()
+    _check(lib.svt_factors(h, ctypes.byref(r), None, None, None), h)
+    r = r.value
+    U = np.zeros((m, r))
+    V = np.zeros((n, r))
+    w = np.zeros(r)
+    if r > 0:
+        rr = ctypes.c_int32()
+        _check(lib.svt_factors(h, ctypes.byref(rr), _p(U), _p(w), _p(V)), h)
+    return U, w, V
+
+
+def svt_predict(h, rows, cols):
+    rows = _i32(rows)
+    cols = _i32(cols)
+    out = np.zeros(rows.shape[0])
+    _check(load().svt_predict(h, rows.shape[0], _p(rows, _ip), _p(cols, _ip), _p(out)), h)
+    return out
+
+
+def svt_set_iterate(h, y):
+    y = _f64(y)
+    _check(load().svt_set_iterate(h, _p(y)), h)
+
+
+def svt_get_iterate(h, nnz: int, which: int = 0):
+    y = np.zeros(nnz)
+    _check(load().svt_get_iterate(h, which, _p(y)), h)
+    return y
+
+
+def svt_apply(h, x, out_len: int, trans: int = 0):
+    x = _f64(x)
+    out = np.zeros(out_len)
+    _check(load().svt_apply(h, trans, _p(x), _p(out)), h)
+    return out
+
+
+def svt_partial_svd(h, count: int, m: int, n: int):
+    sigma = np.zeros(count)
+    U = np.zeros((m, count))
+    V = np.zeros((n, count))
+    steps = ctypes.c_int32()
+    _check(load().svt_partial_svd(h, count, _p(sigma), _p(U), _p(V), ctypes.byref(steps)), h)
+    return sigma, U, V, steps.value
+
+
+def svt_sample_update(h, U, V, delta: float) -> float:
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    r = U.shape[1] if U.ndim == 2 else 0
+    res2 = ctypes.c_double()
+    _check(load().svt_sample_update(h, r, _p(U), _p(V), float(delta), ctypes.byref(res2)), h)
+    return res2.value
+
+
+def svt_kick(h):
+    s = ctypes.c_double()
+    k0 = ctypes.c_int32()
+    _check(load().svt_kick(h, ctypes.byref(s), ctypes.byref(k0)), h)
+    return s.value, k0.value
+
+
+def svt_kernel_stats(h, kind: int):
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    b = ctypes.c_double()
+    _check(load().svt_kernel_stats(h, kind, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(b)), h)
+    return n.value, ms.value, b.value

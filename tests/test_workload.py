@@ -67,3 +67,15 @@ def test_serving_trace_respects_fill_cap():
         assert s["r"] in (5, 10, 20, 50)
         assert s["nnz"] <= 0.6 * s["m"] * s["n"]
         assert 3 * s["r"] * (s["m"] + s["n"] - s["r"]) <= s["nnz"] + 1
+
+
+def test_stored_oracle_result_matches_current_generator():
+    # the stored 400 x 400 oracle run must belong to today's generator: its
+    # first two iterations are recomputed here
+    import oracle
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "oracle_config1.npz"))
+    p = workload.config(1)
+    out = oracle.svt_dense(p.m, p.n, p.rows, p.cols, p.vals, p.tau, p.delta, p.eps, 2, p.incr)
+    assert out["k0"] == int(g["k0"])
+    assert list(out["ranks"]) == list(g["ranks"][:2])
+    np.testing.assert_allclose(out["residuals"], g["residuals"][:2], rtol=1e-12)
