@@ -76,11 +76,14 @@ typedef struct {
                             when the first cancels (DGKS test); 2: always two */
   double decide_margin;  /* the rank decision accepts an unconverged Ritz value
                             below tau only if value + residual <= tau (1 -
-                            margin); otherwise it waits for convergence.
-                            Default 0.05; >= 1 always waits                  */
+                            margin) and a Ritz value above tau has already
+                            converged; otherwise it waits for convergence,
+                            as Algorithm 1 does.  Default 0.05; >= 1 always
+                            waits                                            */
   uint64_t seed;         /* start vectors of the bidiagonalisation            */
   int32_t profile;       /* 1: time kernel classes with HIP events            */
-  int32_t reserved0;
+  int32_t spmv_mode;     /* 0: stage x in LDS when it fits (default);
+                            1: gather x from memory                            */
   void *stream;          /* hipStream_t to run on; NULL = library-owned stream */
 } svt_params;
 
@@ -187,13 +190,12 @@ svt_status svt_sample_update(svt_problem *h, int32_t r, const double *U,
 svt_status svt_kick(svt_problem *h, double *sigma1, int32_t *k0);
 
 /* Kernel timing of the last solve when params.profile = 1: for kernel class
-   `kind` (0 sparse product, 1 Gram-Schmidt update and optional second pass,
-   2 normalisation, 3 Ritz vectors, 4 sampled update and residual, 5 first
-   Gram-Schmidt dot products), the number of launches, their summed duration
-   in milliseconds
-   (HIP events on the solve's stream) and their summed algorithmic bytes:
-   the index, value and vector traffic each launch must move at least once.
-   Any output pointer may be NULL. */
+   `kind` (0 sparse product, 1 Gram-Schmidt orthonormalisation (dot
+   products, two updates, scaling), 3 Ritz vectors, 4 sampled update and
+   residual; 2 is unused), the number of launches, their summed duration in
+   milliseconds (HIP events on the solve's stream) and their summed
+   algorithmic bytes: the index, value and vector traffic each launch must
+   move at least once.  Any output pointer may be NULL. */
 svt_status svt_kernel_stats(const svt_problem *h, int32_t kind, int64_t *launches,
                             double *total_ms, double *total_bytes);
 

@@ -5,13 +5,15 @@
 //     `lanes` (4..64) lanes chosen from the mean row length, so that lanes
 //     stride contiguous index/value runs (coalesced) and a sub-wave shuffle
 //     tree reduces the row;
-//   * the vector-side reductions (Gram-Schmidt coefficients, norms, residual)
-//     are deterministic: each workgroup owns a fixed chunk of rows, writes one
-//     partial per output, and the last workgroup to arrive sums the partials
-//     in a fixed order (no floating-point atomics, so results do not depend on
-//     scheduling);
-//   * the bidiagonalisation coefficients never leave the device inside a
-//     step: kernels read them through pointers.
+//   * no kernel uses a device-scope fence or atomic: on a multi-XCD part a
+//     release fence writes back the L2 and the fences of different
+//     workgroups serialise (tens of microseconds per kernel).  Instead every
+//     reduction is split at a kernel boundary: a kernel writes one partial
+//     per workgroup, and every workgroup of the next kernel sums those
+//     partials itself, in the same fixed order, so all of them hold the same
+//     coefficients and the results do not depend on scheduling;
+//   * reorthogonalisation is classical Gram-Schmidt applied twice (CGS2);
+//     the bidiagonalisation coefficients stay on the device within a step.
 #include "svt_kernels.h"
 
 #include <hip/hip_runtime.h>
@@ -25,59 +27,13 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kWaves = kBlock / kWave;
-// Second Gram-Schmidt pass when |p'| < eta |p| (Daniel-Gragg-Kaufman-Stewart).
-constexpr double kEta2 = 0.5;
+constexpr int kTile = 16;  // Gram-Schmidt columns per pass of a workgroup
 
 template <int W, typename A>
 __device__ __forceinline__ A seg_sum(A v) {
 #pragma unroll
   for (int off = W / 2; off > 0; off >>= 1) v += __shfl_down(v, off, W);
   return v;  // first lane of each W-lane segment holds the sum
-}
-
-__device__ __forceinline__ double ld_acquire(const double *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Returns true in every thread of the last workgroup to finish its partials.
-// Writers publish with a device-scope fence before arriving; the last block
-// fences again before it reads.
-__device__ __forceinline__ bool last_block(unsigned *counter) {
-  __shared__ unsigned s_prev;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) s_prev = atomicAdd(counter, 1u);
-  __syncthreads();
-  const bool last = (s_prev == gridDim.x - 1);
-  if (last) __threadfence();
-  return last;
-}
-
-// As last_block, for `total` arrivals on this counter (e.g. one grid column).
-__device__ __forceinline__ bool last_block_of(unsigned *counter, unsigned total) {
-  __shared__ unsigned s_prev2;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) s_prev2 = atomicAdd(counter, 1u);
-  __syncthreads();
-  const bool last = (s_prev2 == total - 1);
-  if (last) __threadfence();
-  return last;
-}
-
-// Sum of partial[col * nblk + 0..nblk-1] in a fixed order, by one wave.
-__device__ __forceinline__ double reduce_partials(const double *partial, int col, int nblk, int wl) {
-  const double *src = partial + (size_t)col * nblk;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int i = wl;
-  for (; i + 3 * kWave < nblk; i += 4 * kWave) {
-    a0 += src[i];
-    a1 += src[i + kWave];
-    a2 += src[i + 2 * kWave];
-    a3 += src[i + 3 * kWave];
-  }
-  for (; i < nblk; i += kWave) a0 += src[i];
-  return seg_sum<kWave>((a0 + a1) + (a2 + a3));
 }
 
 // Block-wide sum of one double (all threads call; result valid in thread 0).
@@ -95,23 +51,87 @@ __device__ __forceinline__ double block_sum(double v, double *sbuf) {
   return t;
 }
 
-// Dot products of the chunk's p (in LDS, as double) with Q[:, 0..nq-1] and
-// with itself (column nq); one wave per column.
-template <typename T>
-__device__ __forceinline__ void chunk_dots(const double *ps, int r0, int r1, const T *__restrict__ Q,
-                                           int64_t ldq, int nq, double *partial, int nblk) {
-  const int w = threadIdx.x / kWave, wl = threadIdx.x % kWave;
-  for (int col = w; col <= nq; col += kWaves) {
+// hs[c] = sum_i part[c * np + i] for c < C, into LDS, in a fixed order that
+// does not depend on the workgroup: column c is split into G interleaved
+// strands (G = kBlock / min(C, kBlock)), each summed with four accumulators,
+// then the strands are added in strand order.
+__device__ void reduce_columns(const double *__restrict__ part, int np, int C, double *hs,
+                               double *scratch /* kBlock doubles of LDS */) {
+  for (int cb = 0; cb < C; cb += kBlock) {
+    const int Cb = min(kBlock, C - cb);
+    const int G = kBlock / Cb;
+    const int t = threadIdx.x, g = t / Cb, c = t % Cb;
     double acc = 0.0;
-    if (col < nq) {
-      const T *qc = Q + (size_t)col * ldq;
-      for (int row = r0 + wl; row < r1; row += kWave) acc = fma((double)qc[row], ps[row - r0], acc);
-    } else {
-      for (int row = r0 + wl; row < r1; row += kWave) acc = fma(ps[row - r0], ps[row - r0], acc);
+    if (g < G) {
+      const double *src = part + (size_t)(cb + c) * np;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int i = g;
+      for (; i + 3 * G < np; i += 4 * G) {
+        a0 += src[i];
+        a1 += src[i + G];
+        a2 += src[i + 2 * G];
+        a3 += src[i + 3 * G];
+      }
+      for (; i < np; i += G) a0 += src[i];
+      acc = (a0 + a1) + (a2 + a3);
     }
-    acc = seg_sum<kWave>(acc);
-    if (wl == 0) partial[(size_t)col * nblk + blockIdx.x] = acc;
+    scratch[t] = acc;
+    __syncthreads();
+    if (t < Cb) {
+      double sum = 0.0;
+      for (int gg = 0; gg < G; ++gg) sum += scratch[gg * Cb + t];
+      hs[cb + t] = sum;
+    }
+    __syncthreads();
   }
+}
+
+// Partial Gram-Schmidt dot products of one workgroup's rows [r0, r1) with
+// the columns c0 .. c0+kTile-1 of Q (column nq stands for the vector itself):
+// part[c * np + rc] = sum_rows Q[c][row] v(row).  Every thread issues its
+// tile's loads together; the kTile sums reduce as independent shuffle chains.
+template <typename T, typename VF>
+__device__ __forceinline__ void tile_partials(VF v, int r0, int r1, const T *__restrict__ Q, int64_t ldq,
+                                              int nq, int c0, double *__restrict__ part, int np, int rc,
+                                              double (*sred)[kTile]) {
+  double acc[kTile];
+#pragma unroll
+  for (int j = 0; j < kTile; ++j) acc[j] = 0.0;
+  // Branch-free tile: columns past nq - 1 load column nq - 1 (any valid
+  // column) and are masked, so the kTile loads of a row issue back to back.
+  const int last = nq > 0 ? nq - 1 : 0;
+  for (int row = r0 + threadIdx.x; row < r1; row += kBlock) {
+    const double pv = v(row);
+    double q[kTile];
+    if (nq > 0) {
+#pragma unroll
+      for (int j = 0; j < kTile; ++j) q[j] = (double)Q[(size_t)min(c0 + j, last) * ldq + row];
+    } else {
+#pragma unroll
+      for (int j = 0; j < kTile; ++j) q[j] = 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kTile; ++j) {
+      const int c = c0 + j;
+      const double f = (c < nq) ? q[j] : ((c == nq) ? pv : 0.0);
+      acc[j] = fma(f, pv, acc[j]);
+    }
+  }
+  const int w = threadIdx.x / kWave, wl = threadIdx.x % kWave;
+#pragma unroll
+  for (int j = 0; j < kTile; ++j) {
+    const double sv = seg_sum<kWave>(acc[j]);
+    if (wl == 0) sred[w][j] = sv;
+  }
+  __syncthreads();
+  if (threadIdx.x < kTile) {
+    const int c = c0 + threadIdx.x;
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) t += sred[i][threadIdx.x];
+    if (c <= nq) part[(size_t)c * np + rc] = t;
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -127,151 +147,154 @@ __global__ __launch_bounds__(kBlock) void k_spmv(
   if (row >= nrows) return;  // whole sub-wave leaves together
   const int beg = ptr[row], end = ptr[row + 1];
   T acc = (T)0;
-  for (int t = beg + lane; t < end; t += L) acc = fma(val[t], x[idx[t]], acc);
+  int t = beg + lane;
+  // four entries per lane per round: the index loads, then the gathers, issue
+  // together
+  for (; t + 3 * L < end; t += 4 * L) {
+    const int i0 = idx[t], i1 = idx[t + L], i2 = idx[t + 2 * L], i3 = idx[t + 3 * L];
+    const T v0 = val[t], v1 = val[t + L], v2 = val[t + 2 * L], v3 = val[t + 3 * L];
+    const T x0 = x[i0], x1 = x[i1], x2 = x[i2], x3 = x[i3];
+    acc = fma(v0, x0, acc);
+    acc = fma(v1, x1, acc);
+    acc = fma(v2, x2, acc);
+    acc = fma(v3, x3, acc);
+  }
+  for (; t < end; t += L) acc = fma(val[t], x[idx[t]], acc);
   acc = seg_sum<L>(acc);
   if (lane == 0) p[row] = prev ? fma(-(T)(*coef), prev[row], acc) : acc;
 }
 
-constexpr int kTile = 16;  // Gram-Schmidt coefficients per workgroup
+// p = A x - coef prev with x staged in LDS.  A workgroup owns a contiguous
+// range of rows; the columns are split into segments of at most `segcols`
+// entries, each copied once into LDS (coalesced), so the per-entry gathers
+// of x hit LDS instead of L2.  segptr[row * (nseg + 1) + s] is the first
+// entry of segment s of the row (null when nseg == 1: ptr is used).  The
+// same sub-wave handles a row in every segment and accumulates it in LDS.
+template <typename T, int L>
+__global__ __launch_bounds__(kSpmvBlock) void k_spmv_lds(
+    const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx, const T *__restrict__ val,
+    const int32_t *__restrict__ segptr, int nseg, int segcols, const T *__restrict__ x, int ncols,
+    const T *__restrict__ prev, const double *__restrict__ coef, T *__restrict__ p, int nrows,
+    int rows_per_blk) {
+  extern __shared__ double smem_d[];
+  T *xs = reinterpret_cast<T *>(smem_d);  // segcols entries
+  T *racc = xs + segcols;                  // rows_per_blk partial row sums
+  const int r0 = blockIdx.x * rows_per_blk;
+  const int r1 = min(nrows, r0 + rows_per_blk);
+  const int lane = threadIdx.x % L, grp = threadIdx.x / L;
+  constexpr int kGroups = kSpmvBlock / L;
+  const T c = prev ? (T)(*coef) : (T)0;
+  for (int sgm = 0; sgm < nseg; ++sgm) {
+    const int c0 = sgm * segcols;
+    const int cn = min(segcols, ncols - c0);
+    __syncthreads();  // the previous segment's gathers are done
+    for (int i = threadIdx.x; i < cn; i += kSpmvBlock) xs[i] = x[c0 + i];
+    __syncthreads();
+    for (int row = r0 + grp; row < r1; row += kGroups) {
+      int beg, end;
+      if (nseg == 1) {
+        beg = ptr[row];
+        end = ptr[row + 1];
+      } else {
+        beg = segptr[(size_t)row * (nseg + 1) + sgm];
+        end = segptr[(size_t)row * (nseg + 1) + sgm + 1];
+      }
+      T acc = (T)0;
+      int t = beg + lane;
+      for (; t + 3 * L < end; t += 4 * L) {
+        const int i0 = idx[t] - c0, i1 = idx[t + L] - c0, i2 = idx[t + 2 * L] - c0, i3 = idx[t + 3 * L] - c0;
+        const T v0 = val[t], v1 = val[t + L], v2 = val[t + 2 * L], v3 = val[t + 3 * L];
+        acc = fma(v0, xs[i0], acc);
+        acc = fma(v1, xs[i1], acc);
+        acc = fma(v2, xs[i2], acc);
+        acc = fma(v3, xs[i3], acc);
+      }
+      for (; t < end; t += L) acc = fma(val[t], xs[idx[t] - c0], acc);
+      acc = seg_sum<L>(acc);
+      if (lane == 0) {
+        const T tot = (sgm == 0) ? acc : racc[row - r0] + acc;
+        if (sgm + 1 < nseg) racc[row - r0] = tot;
+        else p[row] = prev ? fma(-c, prev[row], tot) : tot;
+      }
+    }
+  }
+}
 
-// h = Q^T p (nq columns) and h[nq] = |p|^2, on a (row chunk, column tile)
-// grid: every thread issues its tile's loads together and the 16 partial sums
-// reduce as independent shuffle chains; the last row chunk to finish a tile
-// sums that tile's partials.  With `flag` non-null the kernel does nothing
-// unless *flag is set (the optional second Gram-Schmidt pass).
+// First Gram-Schmidt pass, dot products: part[c * nrc + rc] over a
+// (row chunk, column tile) grid; column nq holds |p|^2.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_dots(
-    const T *__restrict__ p, int nrows, int rows_per_blk, const T *__restrict__ Q, int64_t ldq,
-    int nq, const double *__restrict__ flag, double *__restrict__ partial, double *__restrict__ h_out,
-    double *__restrict__ norm_out, unsigned *__restrict__ counters) {
-  if (flag && *flag == 0.0) return;  // uniform across the grid
+__global__ __launch_bounds__(kBlock) void k_gs_dots(const T *__restrict__ p, int nrows, int rows_per_blk,
+                                                    const T *__restrict__ Q, int64_t ldq, int nq,
+                                                    double *__restrict__ part) {
   __shared__ double sred[kWaves][kTile];
-  const int rc = blockIdx.x, nrc = gridDim.x;
-  const int c0 = blockIdx.y * kTile;
+  const int rc = blockIdx.x;
   const int r0 = rc * rows_per_blk;
   const int r1 = min(nrows, r0 + rows_per_blk);
-  double acc[kTile];
-#pragma unroll
-  for (int j = 0; j < kTile; ++j) acc[j] = 0.0;
-  for (int row = r0 + threadIdx.x; row < r1; row += kBlock) {
-    const double pv = (double)p[row];
-#pragma unroll
-    for (int j = 0; j < kTile; ++j) {
-      const int c = c0 + j;
-      if (c < nq) acc[j] = fma((double)Q[(size_t)c * ldq + row], pv, acc[j]);
-      else if (c == nq) acc[j] = fma(pv, pv, acc[j]);
-    }
-  }
-  const int w = threadIdx.x / kWave, wl = threadIdx.x % kWave;
-#pragma unroll
-  for (int j = 0; j < kTile; ++j) {
-    const double v = seg_sum<kWave>(acc[j]);
-    if (wl == 0) sred[w][j] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < kTile) {
-    const int c = c0 + threadIdx.x;
-    double t = 0.0;
-#pragma unroll
-    for (int i = 0; i < kWaves; ++i) t += sred[i][threadIdx.x];
-    if (c <= nq) partial[(size_t)c * nrc + rc] = t;
-  }
-  if (last_block_of(counters + blockIdx.y, nrc)) {
-    for (int j = w; j < kTile; j += kWaves) {
-      const int c = c0 + j;
-      if (c > nq) break;
-      const double s = reduce_partials(partial, c, nrc, wl);
-      if (wl == 0) {
-        h_out[c] = s;
-        if (c == nq) *norm_out = sqrt(s);
-      }
-    }
-    if (threadIdx.x == 0) counters[blockIdx.y] = 0u;
-  }
+  tile_partials<T>([&](int row) { return (double)p[row]; }, r0, r1, Q, ldq, nq, blockIdx.y * kTile, part,
+                   gridDim.x, rc, sred);
 }
 
-// p' = p - Q h1 (in place) and |p'|^2.  The last workgroup takes the
-// Daniel-Gragg-Kaufman-Stewart decision: a second pass is flagged in scal[3]
-// when |p'|^2 < eta^2 |p|^2 (or when forced); otherwise norm_out = |p'|.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cgs_update(
-    T *__restrict__ p, int nrows, int rows_per_blk, const T *__restrict__ Q, int64_t ldq, int nq,
-    const double *__restrict__ h1, double *__restrict__ partial, double *__restrict__ scal,
-    double *__restrict__ norm_out, int force_second, unsigned *__restrict__ counter) {
-  extern __shared__ double hs[];  // nq coefficients
+// p <- p - Q h, with h = the column sums of part_in (np_in partials each,
+// reduced by every workgroup).  SECOND = false: then the partial dot products
+// of the new p with Q and itself go to part_out (the second pass's
+// coefficients).  SECOND = true: only |p|^2 partials go to part_out.
+template <typename T, bool SECOND>
+__global__ __launch_bounds__(kBlock) void k_gs_update(T *__restrict__ p, int nrows, int rows_per_blk,
+                                                      const T *__restrict__ Q, int64_t ldq, int nq,
+                                                      const double *__restrict__ part_in, int np_in,
+                                                      double *__restrict__ part_out) {
+  extern __shared__ double smem[];
+  double *hs = smem;                   // nq + 1 coefficients
+  double *scratch = hs + nq + 1;       // kBlock
+  double *pc = scratch + kBlock;       // rows_per_blk values of the updated p
+  __shared__ double sred[kWaves][kTile];
   __shared__ double sbuf[kWaves];
-  for (int c = threadIdx.x; c < nq; c += kBlock) hs[c] = h1[c];
-  __syncthreads();
-  const int r0 = blockIdx.x * rows_per_blk;
+  reduce_columns(part_in, np_in, nq + 1, hs, scratch);
+  const int rc = blockIdx.x;
+  const int r0 = rc * rows_per_blk;
   const int r1 = min(nrows, r0 + rows_per_blk);
   double ss = 0.0;
   for (int row = r0 + threadIdx.x; row < r1; row += kBlock) {
-    double a0 = (double)p[row], a1 = 0.0;
+    // eight independent loads per round, four accumulators
+    double a[4] = {(double)p[row], 0.0, 0.0, 0.0};
     int c = 0;
-    for (; c + 1 < nq; c += 2) {
-      a0 = fma(-(double)Q[(size_t)c * ldq + row], hs[c], a0);
-      a1 = fma(-(double)Q[(size_t)(c + 1) * ldq + row], hs[c + 1], a1);
+    for (; c + 8 <= nq; c += 8) {
+      double q[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) q[j] = (double)Q[(size_t)(c + j) * ldq + row];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) a[j & 3] = fma(-q[j], hs[c + j], a[j & 3]);
     }
-    if (c < nq) a0 = fma(-(double)Q[(size_t)c * ldq + row], hs[c], a0);
-    const T pv = (T)(a0 + a1);
+    for (; c < nq; ++c) a[0] = fma(-(double)Q[(size_t)c * ldq + row], hs[c], a[0]);
+    const T pv = (T)((a[0] + a[1]) + (a[2] + a[3]));
     p[row] = pv;
+    pc[row - r0] = (double)pv;
     ss = fma((double)pv, (double)pv, ss);
   }
-  const double tot = block_sum(ss, sbuf);
-  const int nblk = gridDim.x;
-  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
-  if (last_block(counter)) {
-    if (threadIdx.x < kWave) {
-      const double pp2 = reduce_partials(partial, 0, nblk, threadIdx.x);
-      if (threadIdx.x == 0) {
-        const double pp1 = h1[nq];
-        const bool second = (nq > 0) && (force_second || (pp2 < kEta2 * pp1));
-        scal[3] = second ? 1.0 : 0.0;
-        if (!second) *norm_out = sqrt(pp2);
-      }
-    }
-    if (threadIdx.x == 0) *counter = 0u;
-  }
-}
-
-// Optional second Gram-Schmidt pass and the final norm.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cgs_finish(
-    T *__restrict__ p, int nrows, int rows_per_blk, const T *__restrict__ Q, int64_t ldq, int nq,
-    const double *__restrict__ h2, double *__restrict__ partial, const double *__restrict__ scal,
-    double *__restrict__ norm_out, unsigned *__restrict__ counter) {
-  if (scal[3] == 0.0) return;  // uniform across the grid
-  extern __shared__ double hs[];
-  __shared__ double sbuf[kWaves];
-  for (int c = threadIdx.x; c < nq; c += kBlock) hs[c] = h2[c];
   __syncthreads();
-  const int r0 = blockIdx.x * rows_per_blk;
-  const int r1 = min(nrows, r0 + rows_per_blk);
-  double ss = 0.0;
-  for (int row = r0 + threadIdx.x; row < r1; row += kBlock) {
-    double acc = (double)p[row];
-    for (int c = 0; c < nq; ++c) acc = fma(-(double)Q[(size_t)c * ldq + row], hs[c], acc);
-    const T pv = (T)acc;
-    p[row] = pv;
-    ss = fma((double)pv, (double)pv, ss);
-  }
-  const double tot = block_sum(ss, sbuf);
-  const int nblk = gridDim.x;
-  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
-  if (last_block(counter)) {
-    if (threadIdx.x < kWave) {
-      const double s = reduce_partials(partial, 0, nblk, threadIdx.x);
-      if (threadIdx.x == 0) *norm_out = sqrt(s);
-    }
-    if (threadIdx.x == 0) *counter = 0u;
+  if constexpr (!SECOND) {
+    for (int c0 = 0; c0 <= nq; c0 += kTile)
+      tile_partials<T>([&](int row) { return pc[row - r0]; }, r0, r1, Q, ldq, nq, c0, part_out,
+                       gridDim.x, rc, sred);
+  } else {
+    const double tot = block_sum(ss, sbuf);
+    if (threadIdx.x == 0) part_out[rc] = tot;
   }
 }
 
+// out = p / |p| with |p|^2 = sum of part[0..np) (summed by every workgroup in
+// the same order); workgroup 0 stores |p| in *coef_out.  out = 0 when |p|
+// underflows.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_scale(const T *__restrict__ p, const double *__restrict__ nrm,
-                                                  T *__restrict__ out, int n) {
-  const double v = *nrm;
-  const double inv = (v > 1e-280) ? 1.0 / v : 0.0;
+__global__ __launch_bounds__(kBlock) void k_gs_scale(const T *__restrict__ p, int n,
+                                                     const double *__restrict__ part, int np,
+                                                     T *__restrict__ out, double *__restrict__ coef_out) {
+  __shared__ double hs[1];
+  __shared__ double scratch[kBlock];
+  reduce_columns(part, np, 1, hs, scratch);
+  const double nrm = sqrt(hs[0]);
+  const double inv = (nrm > 1e-280) ? 1.0 / nrm : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *coef_out = nrm;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
     out[i] = (T)((double)p[i] * inv);
 }
@@ -324,7 +347,8 @@ __global__ __launch_bounds__(kBlock) void k_ritz(const T *__restrict__ Q, int64_
 // Sampled product, residual and iterate update in one pass over a compressed
 // orientation of Omega.  The dot product is the same fma chain in either
 // orientation (u-factor entry first), so the row- and column-compressed
-// copies of Y receive bit-identical updates.
+// copies of Y receive bit-identical updates.  Each workgroup writes its
+// (compensated) sum of e^2; the host adds the partials in order.
 template <typename T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };
@@ -342,8 +366,7 @@ template <typename T, int L, int RB>
 __global__ __launch_bounds__(kBlock) void k_sample_update(
     const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx, const T *__restrict__ M,
     T *__restrict__ Y, int nrows, int rows_per_blk, const T *__restrict__ Fu, const T *__restrict__ Fv,
-    int r, int rs, int row_side_is_u, T delta, double *__restrict__ partial,
-    double *__restrict__ res2_out, unsigned *__restrict__ counter) {
+    int r, int rs, int row_side_is_u, T delta, double *__restrict__ part_out) {
   __shared__ double sbuf[kWaves];
   const int r0 = blockIdx.x * rows_per_blk;
   const int r1 = min(nrows, r0 + rows_per_blk);
@@ -390,17 +413,9 @@ __global__ __launch_bounds__(kBlock) void k_sample_update(
       sum = tk;
     }
   }
-  if (res2_out == nullptr) return;  // uniform: no residual wanted
+  if (part_out == nullptr) return;  // uniform: no residual wanted
   const double tot = block_sum((double)sum - (double)comp, sbuf);
-  const int nblk = gridDim.x;
-  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
-  if (last_block(counter)) {
-    if (threadIdx.x < kWave) {
-      const double s = reduce_partials(partial, 0, nblk, threadIdx.x);
-      if (threadIdx.x == 0) *res2_out = s;
-    }
-    if (threadIdx.x == 0) *counter = 0u;
-  }
+  if (threadIdx.x == 0) part_out[blockIdx.x] = tot;
 }
 
 template <typename T>
@@ -425,6 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(const T *__restrict__ x, cons
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
     y[i] = x[map[i]];
 }
+
 
 int grid_for(int64_t n, int cap = 4096) {
   int64_t g = (n + kBlock - 1) / kBlock;
@@ -455,13 +471,19 @@ int lanes_for(double mean) {
   return 64;
 }
 
-// Chunking of the Gram-Schmidt kernels: at most 256 workgroups (so the last
-// one reduces at most 256 partials per coefficient) of at least 256 rows.
-RowChunks vec_chunks(int nrows) {
-  int nblk = (nrows + kBlock - 1) / kBlock;
-  if (nblk > 256) nblk = 256;
-  if (nblk < 1) nblk = 1;
-  return row_chunks(nrows, (nrows + nblk - 1) / nblk);
+GsPlan gs_plan(int nrows) {
+  GsPlan g;
+  const RowChunks a = row_chunks(nrows, std::max(kBlock, (nrows + kGsChunks1 - 1) / kGsChunks1));
+  const RowChunks b = row_chunks(nrows, std::max(kBlock, (nrows + kGsChunks2 - 1) / kGsChunks2));
+  g.nrc1 = a.nblk;
+  g.rpb1 = a.rows_per_blk;
+  g.nrc2 = b.nblk;
+  g.rpb2 = b.rows_per_blk;
+  return g;
+}
+
+size_t gs_update_lds(int nq, int rows_per_blk) {
+  return sizeof(double) * ((size_t)nq + 1 + kBlock + (size_t)rows_per_blk);
 }
 
 template <typename T>
@@ -481,57 +503,72 @@ hipError_t launch_spmv(hipStream_t s, int lanes, const int32_t *ptr, const int32
   return hipGetLastError();
 }
 
+SpmvLdsPlan spmv_lds_plan(int nrows, int ncols, int elem_bytes, int num_cus, int lds_bytes) {
+  SpmvLdsPlan pl{};
+  pl.nblk = std::max(1, std::min(num_cus, (nrows + 7) / 8));
+  pl.rows_per_blk = (nrows + pl.nblk - 1) / pl.nblk;
+  pl.nblk = (nrows + pl.rows_per_blk - 1) / pl.rows_per_blk;
+  const long budget = (long)lds_bytes / elem_bytes - pl.rows_per_blk;
+  long seg = std::min<long>(ncols, budget);
+  if (seg < ncols) seg = (seg / 64) * 64;
+  pl.segcols = (int)std::max<long>(seg, 0);
+  pl.nseg = pl.segcols > 0 ? (ncols + pl.segcols - 1) / pl.segcols : 0;
+  pl.lds = (size_t)elem_bytes * ((size_t)pl.segcols + (size_t)pl.rows_per_blk);
+  pl.ok = pl.segcols >= 1024 && pl.nseg <= 8;
+  return pl;
+}
+
 template <typename T>
-hipError_t launch_dots_into(hipStream_t s, const T *p, int nrows, const T *Q, int64_t ldq, int nq,
-                            const double *flag, double *h_out, unsigned *counters, ReduceScratch &rs,
-                            double *norm_out) {
-  const RowChunks ch = vec_chunks(nrows);
-  if (ch.nblk > rs.max_blocks) return hipErrorInvalidValue;
+hipError_t launch_spmv_lds(hipStream_t s, int lanes, const SpmvLdsPlan &pl, const int32_t *ptr,
+                           const int32_t *idx, const T *val, const int32_t *segptr, const T *x, int ncols,
+                           const T *prev, const double *coef, T *p, int nrows) {
+  if (!pl.ok || (pl.nseg > 1 && segptr == nullptr)) return hipErrorInvalidValue;
+#define SVT_SPMVL(LN)                                                                            \
+  do {                                                                                          \
+    auto kern = k_spmv_lds<T, LN>;                                                              \
+    hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),                   \
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds); \
+    if (ea != hipSuccess) return ea;                                                            \
+    hipLaunchKernelGGL(kern, dim3(pl.nblk), dim3(kSpmvBlock), pl.lds, s, ptr, idx, val, segptr,  \
+                       pl.nseg, pl.segcols, x, ncols, prev, coef, p, nrows, pl.rows_per_blk);    \
+  } while (0)
+  switch (lanes) {
+    case 4: SVT_SPMVL(4); break;
+    case 8: SVT_SPMVL(8); break;
+    case 16: SVT_SPMVL(16); break;
+    case 32: SVT_SPMVL(32); break;
+    default: SVT_SPMVL(64); break;
+  }
+#undef SVT_SPMVL
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_orthonormalize(hipStream_t s, T *p, int nrows, const T *Q, int64_t ldq, int nq,
+                                 const GsScratch &gs, T *out, double *coef_out) {
+  const GsPlan g = gs_plan(nrows);
+  if (g.nrc1 > kGsChunks1 || g.nrc2 > kGsChunks2 || nq + 1 > gs.max_cols) return hipErrorInvalidValue;
   const int ntiles = (nq + 1 + kTile - 1) / kTile;
-  if (ntiles > kMaxTiles) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_dots<T>), dim3(ch.nblk, ntiles), dim3(kBlock), 0, s, p, nrows, ch.rows_per_blk,
-                     Q, ldq, nq, flag, rs.partial, h_out, norm_out, counters);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_dots(hipStream_t s, const T *p, int nrows, const T *Q, int64_t ldq, int nq,
-                       ReduceScratch &rs, double *norm_out) {
-  return launch_dots_into<T>(s, p, nrows, Q, ldq, nq, nullptr, rs.h1, rs.counters + kCounterDots, rs,
-                             norm_out);
-}
-
-template <typename T>
-hipError_t launch_cgs_update(hipStream_t s, T *p, int nrows, const T *Q, int64_t ldq, int nq,
-                             ReduceScratch &rs, double *norm_out, int force_second) {
-  const RowChunks ch = vec_chunks(nrows);
-  if (ch.nblk > rs.max_blocks) return hipErrorInvalidValue;
-  const size_t lds = sizeof(double) * (size_t)nq;
-  if (lds > 60 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_cgs_update<T>), dim3(ch.nblk), dim3(kBlock), lds, s, p, nrows, ch.rows_per_blk,
-                     Q, ldq, nq, rs.h1, rs.partial, rs.scal, norm_out, force_second,
-                     rs.counters + kCounterUpdate);
-  return hipGetLastError();
-}
-
-// Second pass when flagged: h2 = Q^T p', then p'' = p' - Q h2 and its norm.
-template <typename T>
-hipError_t launch_cgs_finish(hipStream_t s, T *p, int nrows, const T *Q, int64_t ldq, int nq,
-                             ReduceScratch &rs, double *norm_out) {
-  hipError_t e = launch_dots_into<T>(s, p, nrows, Q, ldq, nq, rs.scal + 3, rs.h2,
-                                     rs.counters + kCounterDots2, rs, rs.scal + 5);
+  hipLaunchKernelGGL((k_gs_dots<T>), dim3(g.nrc1, ntiles), dim3(kBlock), 0, s, p, nrows, g.rpb1, Q, ldq,
+                     nq, gs.part1);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const RowChunks ch = vec_chunks(nrows);
-  const size_t lds = sizeof(double) * (size_t)nq;
-  if (lds > 60 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_cgs_finish<T>), dim3(ch.nblk), dim3(kBlock), lds, s, p, nrows, ch.rows_per_blk,
-                     Q, ldq, nq, rs.h2, rs.partial, rs.scal, norm_out, rs.counters + kCounterFinish);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_scale(hipStream_t s, const T *p, const double *nrm, T *out, int n) {
-  hipLaunchKernelGGL((k_scale<T>), dim3(grid_for(n, 2048)), dim3(kBlock), 0, s, p, nrm, out, n);
+  const double *norm_part = gs.part1;  // column 0 when nq == 0
+  int norm_np = g.nrc1;
+  if (nq > 0) {
+    const size_t lds = gs_update_lds(nq, g.rpb2);
+    if (lds > 64 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_gs_update<T, false>), dim3(g.nrc2), dim3(kBlock), lds, s, p, nrows, g.rpb2, Q,
+                       ldq, nq, gs.part1, g.nrc1, gs.part2);
+    hipLaunchKernelGGL((k_gs_update<T, true>), dim3(g.nrc2), dim3(kBlock), lds, s, p, nrows, g.rpb2, Q,
+                       ldq, nq, gs.part2, g.nrc2, gs.part3);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    norm_part = gs.part3;
+    norm_np = g.nrc2;
+  }
+  hipLaunchKernelGGL((k_gs_scale<T>), dim3(grid_for(nrows, 1024)), dim3(kBlock), 0, s, p, nrows, norm_part,
+                     norm_np, out, coef_out);
   return hipGetLastError();
 }
 
@@ -550,17 +587,20 @@ hipError_t launch_ritz(hipStream_t s, const T *Q, int64_t ldq, int nrows, int k,
   return hipGetLastError();
 }
 
+int sample_blocks(int nrows, int lanes) {
+  return row_chunks(nrows, std::max((kBlock / lanes) * 4, (nrows + kSampleMaxBlocks - 1) / kSampleMaxBlocks))
+      .nblk;
+}
+
 template <typename T>
 hipError_t launch_sample_update(hipStream_t s, int lanes, const int32_t *ptr, const int32_t *idx,
                                 const T *M, T *Y, int nrows, const T *Fu, const T *Fv, int r, int rs,
-                                bool row_side_is_u, double delta, ReduceScratch &rsc,
-                                double *res2_out) {
-  const RowChunks ch = row_chunks(nrows, std::max((kBlock / lanes) * 4, (nrows + 1023) / 1024));
-  if (res2_out && ch.nblk > rsc.max_blocks) return hipErrorInvalidValue;
+                                bool row_side_is_u, double delta, double *part_out) {
+  const RowChunks ch =
+      row_chunks(nrows, std::max((kBlock / lanes) * 4, (nrows + kSampleMaxBlocks - 1) / kSampleMaxBlocks));
 #define SVT_SU2(LN, RB)                                                                          \
   hipLaunchKernelGGL((k_sample_update<T, LN, RB>), dim3(ch.nblk), dim3(kBlock), 0, s, ptr, idx, M, Y, \
-                     nrows, ch.rows_per_blk, Fu, Fv, r, rs, row_side_is_u ? 1 : 0, (T)delta,          \
-                     rsc.partial, res2_out, rsc.counters + kCounterSample)
+                     nrows, ch.rows_per_blk, Fu, Fv, r, rs, row_side_is_u ? 1 : 0, (T)delta, part_out)
 #define SVT_SU(LN)                         \
   do {                                     \
     if (r <= 8) SVT_SU2(LN, 8);            \
@@ -606,19 +646,17 @@ hipError_t launch_gather(hipStream_t s, const T *x, const int32_t *map, T *y, in
 #define SVT_INSTANTIATE(T)                                                                          \
   template hipError_t launch_spmv<T>(hipStream_t, int, const int32_t *, const int32_t *, const T *,   \
                                      const T *, const T *, const double *, T *, int);              \
-  template hipError_t launch_dots<T>(hipStream_t, const T *, int, const T *, int64_t, int,         \
-                                     ReduceScratch &, double *);                                    \
-  template hipError_t launch_cgs_update<T>(hipStream_t, T *, int, const T *, int64_t, int,         \
-                                           ReduceScratch &, double *, int);                         \
-  template hipError_t launch_cgs_finish<T>(hipStream_t, T *, int, const T *, int64_t, int,         \
-                                           ReduceScratch &, double *);                              \
-  template hipError_t launch_scale<T>(hipStream_t, const T *, const double *, T *, int);           \
+  template hipError_t launch_spmv_lds<T>(hipStream_t, int, const SpmvLdsPlan &, const int32_t *,   \
+                                         const int32_t *, const T *, const int32_t *, const T *, int, \
+                                         const T *, const double *, T *, int);                     \
+  template hipError_t launch_orthonormalize<T>(hipStream_t, T *, int, const T *, int64_t, int,     \
+                                               const GsScratch &, T *, double *);                  \
   template hipError_t launch_randn<T>(hipStream_t, T *, int, uint64_t, uint64_t);                  \
   template hipError_t launch_ritz<T>(hipStream_t, const T *, int64_t, int, int, const double *,    \
                                      const double *, int, T *, int);                                \
   template hipError_t launch_sample_update<T>(hipStream_t, int, const int32_t *, const int32_t *,  \
                                               const T *, T *, int, const T *, const T *, int, int,  \
-                                              bool, double, ReduceScratch &, double *);             \
+                                              bool, double, double *);                              \
   template hipError_t launch_axpby<T>(hipStream_t, const T *, T *, int64_t, double);               \
   template hipError_t launch_gather<T>(hipStream_t, const T *, const int32_t *, T *, int64_t);
 

@@ -90,7 +90,7 @@ struct DevMem {
 // ---------------------------------------------------------------------------
 // kernel-class timing with HIP events (params.profile = 1)
 
-enum KernelKind { kSpmv = 0, kOrth = 1, kNorm = 2, kRitz = 3, kSample = 4, kDots = 5, kKinds = 6 };
+enum KernelKind { kSpmv = 0, kOrth = 1, kRitz = 3, kSample = 4, kKinds = 5 };
 
 struct Profiler {
   bool on = false;
@@ -237,13 +237,17 @@ struct Problem final : ProblemBase {
   int device = 0;
 
   DevMem rowptr, colidx, colptr, rowidx, csc_of_csr;
+  SpmvLdsPlan plan_r{}, plan_c{};     // LDS-staged sparse products (CSR, CSC)
+  DevMem seg_r, seg_c;                // their segment starts (when nseg > 1)
   DevMem Mr, Mc, Yr, Yc;          // values, T
   DevMem Ub, Vb;                  // bases, T, column-major
   int kcap = 0;                   // columns available in Ub (Vb has kcap + 1)
   DevMem pbuf;                    // working vector, T, max(m, n)
-  DevMem coef;                    // alpha[0..], beta[0..], double, 2 (kcap + 2)
-  DevMem red_partial, red_h1, red_h2, red_scal, red_counters;
-  ReduceScratch rs{};
+  DevMem coef;                    // alpha[0..], beta[0..], double, 2 (kcap + 4)
+  DevMem gs1, gs2, gs3;           // Gram-Schmidt partial sums
+  GsScratch gs{};
+  DevMem sample_part;             // residual partials, kSampleMaxBlocks + 8 doubles
+  std::vector<double> sample_host;
   DevMem Pd, Qd, wd;              // Ritz combination (double)
   DevMem Fu, Fv;                  // factors of X, T, row-major with stride fstride
   int fstride = 0, fcap = 0;
@@ -289,18 +293,30 @@ struct Problem final : ProblemBase {
     HIP_CHECK(hipMemcpyAsync(colptr.p, ix.colptr.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, stream));
     HIP_CHECK(hipMemcpyAsync(rowidx.p, ix.rowidx.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, stream));
     HIP_CHECK(hipMemcpyAsync(csc_of_csr.p, ix.csc_of_csr.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, stream));
+    {
+      int cus = 0, lds = 0;
+      HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+      HIP_CHECK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+      lds = std::min(lds, 160 * 1024);
+      plan_r = spmv_lds_plan((int)m, (int)n, (int)sizeof(T), cus, lds);
+      plan_c = spmv_lds_plan((int)n, (int)m, (int)sizeof(T), cus, lds);
+      if (plan_r.ok && plan_r.nseg > 1) {
+        const auto sr = segment_starts(ix.rowptr, ix.colidx, (int)m, plan_r);
+        seg_r.alloc(sizeof(int32_t) * sr.size());
+        HIP_CHECK(hipMemcpy(seg_r.p, sr.data(), sizeof(int32_t) * sr.size(), hipMemcpyHostToDevice));
+      }
+      if (plan_c.ok && plan_c.nseg > 1) {
+        const auto sc = segment_starts(ix.colptr, ix.rowidx, (int)n, plan_c);
+        seg_c.alloc(sizeof(int32_t) * sc.size());
+        HIP_CHECK(hipMemcpy(seg_c.p, sc.data(), sizeof(int32_t) * sc.size(), hipMemcpyHostToDevice));
+      }
+    }
     upload_values(ix.vals_csr.data(), Mr.as<T>(), Mc.as<T>());
     HIP_CHECK(hipMemsetAsync(Yr.p, 0, sizeof(T) * nnz, stream));
     HIP_CHECK(hipMemsetAsync(Yc.p, 0, sizeof(T) * nnz, stream));
 
-    const int max_blocks = 1100;
-    rs.max_blocks = max_blocks;
-    red_h1.alloc(sizeof(double) * 8);
-    red_h2.alloc(sizeof(double) * 8);
-    red_scal.alloc(sizeof(double) * 8);
-    red_counters.alloc(sizeof(unsigned) * kNumCounters);
-    HIP_CHECK(hipMemsetAsync(red_counters.p, 0, sizeof(unsigned) * kNumCounters, stream));
-    HIP_CHECK(hipMemsetAsync(red_scal.p, 0, sizeof(double) * 8, stream));
+    sample_part.alloc(sizeof(double) * (kSampleMaxBlocks + 8));
+    sample_host.resize(kSampleMaxBlocks + 8);
     ensure_basis(std::min<int64_t>(acols, 64));
     HIP_CHECK(hipStreamSynchronize(stream));
   }
@@ -323,13 +339,14 @@ struct Problem final : ProblemBase {
     if (cap <= kcap) return;
     int newcap = std::max(cap, std::min<int>((int)acols, std::max(kcap * 2, 16)));
     newcap = (int)std::min<int64_t>(newcap, acols);
-    DevMem nU, nV, ncoef, npart, nh1, nh2;
+    DevMem nU, nV, ncoef, n1, n2, n3;
     nU.alloc(sizeof(T) * (size_t)arows * (size_t)(newcap + 1));
     nV.alloc(sizeof(T) * (size_t)acols * (size_t)(newcap + 2));
     ncoef.alloc(sizeof(double) * 2 * (size_t)(newcap + 4));
-    npart.alloc(sizeof(double) * (size_t)(newcap + 4) * rs.max_blocks);
-    nh1.alloc(sizeof(double) * (size_t)(newcap + 4));
-    nh2.alloc(sizeof(double) * (size_t)(newcap + 4));
+    const int cols = newcap + 4;
+    n1.alloc(sizeof(double) * (size_t)cols * kGsChunks1);
+    n2.alloc(sizeof(double) * (size_t)cols * kGsChunks2);
+    n3.alloc(sizeof(double) * (size_t)kGsChunks2);
     HIP_CHECK(hipMemsetAsync(ncoef.p, 0, ncoef.bytes, stream));
     if (kcap > 0) {
       HIP_CHECK(hipMemcpyAsync(nU.p, Ub.p, sizeof(T) * (size_t)arows * (size_t)(kcap + 1), hipMemcpyDeviceToDevice, stream));
@@ -337,20 +354,19 @@ struct Problem final : ProblemBase {
       HIP_CHECK(hipMemcpyAsync(ncoef.as<double>(), coef.as<double>(), sizeof(double) * (kcap + 4), hipMemcpyDeviceToDevice, stream));
       HIP_CHECK(hipMemcpyAsync(ncoef.as<double>() + (newcap + 4), coef.as<double>() + (kcap + 4),
                                sizeof(double) * (kcap + 4), hipMemcpyDeviceToDevice, stream));
-      HIP_CHECK(hipStreamSynchronize(stream));
     }
+    HIP_CHECK(hipStreamSynchronize(stream));
     std::swap(Ub.p, nU.p); std::swap(Ub.bytes, nU.bytes);
     std::swap(Vb.p, nV.p); std::swap(Vb.bytes, nV.bytes);
     std::swap(coef.p, ncoef.p); std::swap(coef.bytes, ncoef.bytes);
-    std::swap(red_partial.p, npart.p); std::swap(red_partial.bytes, npart.bytes);
-    std::swap(red_h1.p, nh1.p); std::swap(red_h1.bytes, nh1.bytes);
-    std::swap(red_h2.p, nh2.p); std::swap(red_h2.bytes, nh2.bytes);
+    std::swap(gs1.p, n1.p); std::swap(gs1.bytes, n1.bytes);
+    std::swap(gs2.p, n2.p); std::swap(gs2.bytes, n2.bytes);
+    std::swap(gs3.p, n3.p); std::swap(gs3.bytes, n3.bytes);
     kcap = newcap;
-    rs.partial = red_partial.as<double>();
-    rs.h1 = red_h1.as<double>();
-    rs.h2 = red_h2.as<double>();
-    rs.scal = red_scal.as<double>();
-    rs.counters = red_counters.as<unsigned>();
+    gs.part1 = gs1.as<double>();
+    gs.part2 = gs2.as<double>();
+    gs.part3 = gs3.as<double>();
+    gs.max_cols = cols;
   }
 
   double *alpha_d() { return coef.as<double>(); }                 // alpha_{i+1} at [i]
@@ -378,14 +394,49 @@ struct Problem final : ProblemBase {
 
   // --------------------------------------------------------- sparse products
   // orientation helpers: A's row-compressed and column-compressed structures
-  struct Csx { const int32_t *ptr, *idx; int nrows; int lanes; };
-  Csx a_rows_struct() {
-    if (a_is_y) return {rowptr.as<int32_t>(), colidx.as<int32_t>(), (int)ix.m, lanes_r};
-    return {colptr.as<int32_t>(), rowidx.as<int32_t>(), (int)ix.n, lanes_c};
+  struct Csx {
+    const int32_t *ptr, *idx;
+    int nrows, ncols;
+    int lanes;
+    const SpmvLdsPlan *plan;   // LDS-staged product plan (null: gather kernel)
+    const int32_t *segptr;
+  };
+  Csx csr_struct() {
+    return {rowptr.as<int32_t>(), colidx.as<int32_t>(), (int)ix.m, (int)ix.n, lanes_r,
+            plan_r.ok && prm.spmv_mode == 0 ? &plan_r : nullptr, seg_r.as<int32_t>()};
   }
-  Csx a_cols_struct() {
-    if (a_is_y) return {colptr.as<int32_t>(), rowidx.as<int32_t>(), (int)ix.n, lanes_c};
-    return {rowptr.as<int32_t>(), colidx.as<int32_t>(), (int)ix.m, lanes_r};
+  Csx csc_struct() {
+    return {colptr.as<int32_t>(), rowidx.as<int32_t>(), (int)ix.n, (int)ix.m, lanes_c,
+            plan_c.ok && prm.spmv_mode == 0 ? &plan_c : nullptr, seg_c.as<int32_t>()};
+  }
+  Csx a_rows_struct() { return a_is_y ? csr_struct() : csc_struct(); }
+  Csx a_cols_struct() { return a_is_y ? csc_struct() : csr_struct(); }
+
+  void spmv(const Csx &c, const T *vals, const T *x, const T *prev, const double *coefp, T *out) {
+    if (c.plan) {
+      const hipError_t e = launch_spmv_lds<T>(stream, c.lanes, *c.plan, c.ptr, c.idx, vals, c.segptr, x, c.ncols,
+                                              prev, coefp, out, c.nrows);
+      if (e == hipSuccess) return;
+      // the device refused the LDS size: use the gather kernel from now on
+      (void)hipGetLastError();
+      plan_r.ok = plan_c.ok = false;
+    }
+    HIP_CHECK(launch_spmv<T>(stream, c.lanes, c.ptr, c.idx, vals, x, prev, coefp, out, c.nrows));
+  }
+
+  // Segment starts of every row of a compressed structure for the LDS plan.
+  static std::vector<int32_t> segment_starts(const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx,
+                                             int nrows, const SpmvLdsPlan &pl) {
+    std::vector<int32_t> out((size_t)nrows * (pl.nseg + 1));
+    for (int i = 0; i < nrows; ++i) {
+      const int32_t *b = idx.data() + ptr[i], *e = idx.data() + ptr[i + 1];
+      for (int sg = 0; sg <= pl.nseg; ++sg) {
+        const int32_t bound = (int32_t)std::min<int64_t>((int64_t)sg * pl.segcols, INT32_MAX);
+        out[(size_t)i * (pl.nseg + 1) + sg] =
+            sg == pl.nseg ? ptr[i + 1] : (int32_t)(std::lower_bound(b, e, bound) - idx.data());
+      }
+    }
+    return out;
   }
 
   // Algorithmic bytes: index and value of every stored entry, the gathered
@@ -402,21 +453,13 @@ struct Problem final : ProblemBase {
     T *p = pbuf.as<T>();
     const double vb = sizeof(T);
     prof.begin();
-    HIP_CHECK(launch_spmv<T>(stream, c.lanes, c.ptr, c.idx, vals, x, prev, coefp, p, c.nrows));
+    spmv(c, vals, x, prev, coefp, p);
     prof.end(kSpmv, spmv_bytes(c, ncols_x, prev != nullptr));
     prof.begin();
-    HIP_CHECK(launch_dots<T>(stream, p, c.nrows, Q, ldq, nq, rs, norm_out));
-    prof.end(kDots, vb * (double)c.nrows * (nq + 1.0));
-    if (nq > 0) {
-      prof.begin();
-      HIP_CHECK(launch_cgs_update<T>(stream, p, c.nrows, Q, ldq, nq, rs, norm_out,
-                                     prm.reorth_passes == 2 ? 1 : 0));
-      HIP_CHECK(launch_cgs_finish<T>(stream, p, c.nrows, Q, ldq, nq, rs, norm_out));
-      prof.end(kOrth, vb * (double)c.nrows * (nq + 2.0));
-    }
-    prof.begin();
-    HIP_CHECK(launch_scale<T>(stream, p, norm_out, out_col, c.nrows));
-    prof.end(kNorm, vb * (double)c.nrows * 2.0);
+    HIP_CHECK(launch_orthonormalize<T>(stream, p, c.nrows, Q, ldq, nq, gs, out_col, norm_out));
+    // Q read by both dot-product passes and both updates, p read and written
+    // by each update, the result written once
+    prof.end(kOrth, vb * (double)c.nrows * (nq > 0 ? 4.0 * nq + 7.0 : 2.0));
   }
 
   // ------------------------------------------------- bidiagonalisation (a3)
@@ -431,9 +474,8 @@ struct Problem final : ProblemBase {
     const Csx R = a_rows_struct(), C = a_cols_struct();
     T *p = pbuf.as<T>();
     HIP_CHECK(launch_randn<T>(stream, p, (int)acols, prm.seed, rng_ctr++));
-    // normalise the start vector: an orthogonalisation against no columns
-    HIP_CHECK(launch_cgs_update<T>(stream, p, (int)acols, vcol(0), acols, 0, rs, beta_d(), 0));
-    HIP_CHECK(launch_scale<T>(stream, p, beta_d(), vcol(0), (int)acols));
+    // normalise the start vector: an orthonormalisation against no columns
+    HIP_CHECK(launch_orthonormalize<T>(stream, p, (int)acols, vcol(0), acols, 0, gs, vcol(0), beta_d()));
     half_step(R, vr, vcol(0), (int)acols, nullptr, nullptr, Ub.as<T>(), arows, 0, alpha_d(), ucol(0));
     g.k = 1;
     // v_2: A^T u_1 - alpha_1 v_1, orthogonal to v_1
@@ -514,12 +556,16 @@ struct Problem final : ProblemBase {
         bool ok = true;
         for (int i = 0; i < r && ok; ++i) ok = res[i] <= atol;
         // The first value at or below tau decides r.  It must be converged,
-        // unless even its residual interval lies well below tau: a Ritz value
-        // can sit between two close singular values before it converges, and
-        // its residual bound then certifies the lower one, not the one above
-        // tau (Ritz values only approach the singular values from below).
+        // or else its whole residual interval must lie well below tau, and
+        // only once at least one Ritz value above tau has converged.  A
+        // residual interval certifies a singular value near the Ritz value,
+        // not which one: before the Krylov space has found the leading
+        // singular values (few steps), or while a Ritz value still sits
+        // between two close singular values, the bound alone would miss a
+        // singular value above tau (Ritz values approach from below).
         if (ok && r < k)
-          ok = (res[r] <= atol) || (chk.sigma[r] + res[r] <= tau * (1.0 - prm.decide_margin));
+          ok = (res[r] <= atol) ||
+               (r >= 1 && chk.sigma[r] + res[r] <= tau * (1.0 - prm.decide_margin));
         if (ok && r == k) ok = false;  // no value below tau seen yet: extend (s_k += ell)
         done = ok;
       } else {
@@ -543,7 +589,7 @@ struct Problem final : ProblemBase {
         throw Error(SVT_ELANCZOS, "bidiagonalisation reached its step cap (" + std::to_string(cap) +
                                       ") before the Ritz triplets converged");
       }
-      next_check = std::min(cap, g.k + std::max(1, std::min(8, g.k / 4)));
+      next_check = std::min(cap, g.k + std::max(2, std::min(8, g.k / 16)));
     }
   }
 
@@ -574,24 +620,32 @@ struct Problem final : ProblemBase {
     rank = r;
   }
 
-  // Sampled product + residual + update on both copies; returns residual^2.
+  // Sampled product + residual + update on both copies; returns residual^2
+  // (workgroup partials added on the host in order, compensated).
   double sample_pass(int r, double delta, bool want_res) {
-    double *res2 = rs.scal + 2;
     const double vb = sizeof(T);
     prof.begin();
     HIP_CHECK(launch_sample_update<T>(stream, lanes_r, rowptr.as<int32_t>(), colidx.as<int32_t>(), Mr.as<T>(),
-                                      Yr.as<T>(), (int)ix.m, Fu.as<T>(), Fv.as<T>(), r, fstride, true, delta, rs,
-                                      want_res ? res2 : nullptr));
+                                      Yr.as<T>(), (int)ix.m, Fu.as<T>(), Fv.as<T>(), r, fstride, true, delta,
+                                      want_res ? sample_part.as<double>() : nullptr));
     HIP_CHECK(launch_sample_update<T>(stream, lanes_c, colptr.as<int32_t>(), rowidx.as<int32_t>(), Mc.as<T>(),
-                                      Yc.as<T>(), (int)ix.n, Fu.as<T>(), Fv.as<T>(), r, fstride, false, delta, rs,
+                                      Yc.as<T>(), (int)ix.n, Fu.as<T>(), Fv.as<T>(), r, fstride, false, delta,
                                       nullptr));
+    // per pass: index, M and Y read, Y written; both factors once
     prof.end(kSample, 2.0 * ((double)ix.nnz * (4.0 + 3.0 * vb)) + 4.0 * (ix.m + ix.n + 2) +
                           vb * (double)(ix.m + ix.n) * r * 2.0);
     if (!want_res) return 0.0;
-    double h = 0.0;
-    HIP_CHECK(hipMemcpyAsync(&h, res2, sizeof(double), hipMemcpyDeviceToHost, stream));
+    const int nb = sample_blocks((int)ix.m, lanes_r);
+    HIP_CHECK(hipMemcpyAsync(sample_host.data(), sample_part.p, sizeof(double) * nb, hipMemcpyDeviceToHost, stream));
     HIP_CHECK(hipStreamSynchronize(stream));
-    return h;
+    double sum = 0.0, comp = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      const double y = sample_host[(size_t)b] - comp;
+      const double t = sum + y;
+      comp = (t - sum) - y;
+      sum = t;
+    }
+    return sum;
   }
 
   // --------------------------------------------------------------- kick (a2)
@@ -730,10 +784,8 @@ struct Problem final : ProblemBase {
     dx.alloc(sizeof(T) * nin);
     dout.alloc(sizeof(T) * nout);
     HIP_CHECK(hipMemcpyAsync(dx.p, hx.data(), sizeof(T) * nin, hipMemcpyHostToDevice, stream));
-    Csx c = trans ? Csx{colptr.as<int32_t>(), rowidx.as<int32_t>(), (int)ix.n, lanes_c}
-                  : Csx{rowptr.as<int32_t>(), colidx.as<int32_t>(), (int)ix.m, lanes_r};
-    HIP_CHECK(launch_spmv<T>(stream, c.lanes, c.ptr, c.idx, trans ? Yc.as<T>() : Yr.as<T>(), dx.as<T>(),
-                             nullptr, nullptr, dout.as<T>(), c.nrows));
+    const Csx c = trans ? csc_struct() : csr_struct();
+    spmv(c, trans ? Yc.as<T>() : Yr.as<T>(), dx.as<T>(), nullptr, nullptr, dout.as<T>());
     std::vector<T> ho((size_t)nout);
     HIP_CHECK(hipMemcpyAsync(ho.data(), dout.p, sizeof(T) * nout, hipMemcpyDeviceToHost, stream));
     HIP_CHECK(hipStreamSynchronize(stream));
@@ -799,6 +851,7 @@ static void validate_params(const svt_params &p) {
   if (p.lanczos_maxsteps < 0) throw Error(SVT_EINVAL, "lanczos_maxsteps must be >= 0");
   if (p.reorth_passes != 0 && p.reorth_passes != 2) throw Error(SVT_EINVAL, "reorth_passes must be 0 or 2");
   if (!finite(p.decide_margin) || p.decide_margin < 0) throw Error(SVT_EINVAL, "decide_margin must be finite and >= 0");
+  if (p.spmv_mode != 0 && p.spmv_mode != 1) throw Error(SVT_EINVAL, "spmv_mode must be 0 or 1");
 }
 
 }  // namespace svt

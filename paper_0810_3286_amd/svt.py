@@ -31,8 +31,8 @@ SVT_CSR = 1
 SVT_STOP_RELRES = 0
 SVT_STOP_NOISY = 1
 
-KERNEL_KINDS = {0: "k_spmv", 1: "k_cgs_update+k_cgs_finish", 2: "k_scale", 3: "k_ritz",
-                4: "k_sample_update", 5: "k_dots"}
+KERNEL_KINDS = {0: "k_spmv", 1: "k_gs_dots+k_gs_update+k_gs_scale", 3: "k_ritz",
+                4: "k_sample_update"}
 
 
 class svt_params(ctypes.Structure):
@@ -53,7 +53,7 @@ class svt_params(ctypes.Structure):
         ("decide_margin", ctypes.c_double),
         ("seed", ctypes.c_uint64),
         ("profile", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("spmv_mode", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 

@@ -41,16 +41,17 @@ SMALL = [
 ]
 
 
+@pytest.mark.parametrize("mode", [0, 1])   # 0: x staged in LDS, 1: gathered from memory
 @pytest.mark.parametrize("case", SMALL + [(400, 400, 10, 47400, 0), (1000, 777, 5, 60000, 4)])
-def test_sparse_products(case):
+def test_sparse_products(case, mode):
     m, n, r, nnz, seed = case
-    gpu_case(f"spmv {case}")
+    gpu_case(f"spmv {case} mode {mode}")
     p = workload.gaussian_lowrank(m, n, r, nnz, seed, shuffle=True)
     y = workload.dense_random_iterate(p, seed + 10)
     rng = np.random.default_rng(seed + 20)
     x = rng.standard_normal(n)
     u = rng.standard_normal(m)
-    h = _create(p)
+    h = _create(p, spmv_mode=mode)
     try:
         B.svt_set_iterate(h, y)
         got = B.svt_apply(h, x, m, trans=0)
@@ -65,13 +66,15 @@ def test_sparse_products(case):
     assert np.all(np.abs(gotT - refT) <= 1e-14 * 64 * scaleT + 1e-300)
 
 
-def test_sparse_products_full_size_30000():
-    gpu_case("spmv 30000^2")
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sparse_products_full_size_30000(precision):
+    # FP64: x takes two LDS segments at n = 30000; FP32 (mixed form): one
+    gpu_case(f"spmv 30000^2 precision {precision}")
     p = workload.config(4)
     y = workload.dense_random_iterate(p, 5)
     rng = np.random.default_rng(6)
     x = rng.standard_normal(p.n)
-    h = _create(p)
+    h = _create(p, precision=precision)
     try:
         B.svt_set_iterate(h, y)
         got = B.svt_apply(h, x, p.m, trans=0)
@@ -81,12 +84,18 @@ def test_sparse_products_full_size_30000():
     # rows sampled one by one by the oracle's plain definition
     rows = rng.choice(p.m, 300, replace=False)
     sel = np.isin(p.rows, rows)
+    if precision == 1:  # inputs rounded to FP32, FP32 accumulation
+        y = y.astype(np.float32).astype(np.float64)
+        x = x.astype(np.float32).astype(np.float64)
+    tol = 1e-12 if precision == 0 else 2e-5
     ref = oracle.apply_sparse(p.m, p.n, p.rows[sel], p.cols[sel], y[sel], x)
-    np.testing.assert_allclose(got[rows], ref[rows], rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+    scale = oracle.apply_sparse(p.m, p.n, p.rows[sel], p.cols[sel], np.abs(y[sel]), np.abs(x))
+    assert np.all(np.abs(got[rows] - ref[rows]) <= tol * scale[rows])
     cols = rng.choice(p.n, 300, replace=False)
     selc = np.isin(p.cols, cols)
     refT = oracle.apply_sparse(p.m, p.n, p.rows[selc], p.cols[selc], y[selc], x, trans=True)
-    np.testing.assert_allclose(gotT[cols], refT[cols], rtol=1e-12, atol=1e-12 * np.abs(refT).max())
+    scaleT = oracle.apply_sparse(p.m, p.n, p.rows[selc], p.cols[selc], np.abs(y[selc]), np.abs(x), trans=True)
+    assert np.all(np.abs(gotT[cols] - refT[cols]) <= tol * scaleT[cols])
 
 
 @pytest.mark.parametrize("case", SMALL + [(400, 400, 10, 47400, 0)])
