@@ -109,6 +109,25 @@ def cpu_baseline(p, seconds: float):
     }
 
 
+def copy_calibration(mib: int, reps: int = 3):
+    """Device-to-device copies of a known size through the HIP runtime's copy
+    kernel: under rocprofv3 --pmc its FETCH_SIZE / WRITE_SIZE per dispatch,
+    divided by the bytes copied, calibrate the counters."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    nbytes = mib << 20
+    src, dst = ctypes.c_void_p(), ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(src), ctypes.c_size_t(nbytes)) == 0
+    assert hip.hipMalloc(ctypes.byref(dst), ctypes.c_size_t(nbytes)) == 0
+    assert hip.hipMemset(src, 1, ctypes.c_size_t(nbytes)) == 0
+    for _ in range(reps):
+        assert hip.hipMemcpy(dst, src, ctypes.c_size_t(nbytes), 3) == 0  # device to device
+    assert hip.hipDeviceSynchronize() == 0
+    hip.hipFree(src)
+    hip.hipFree(dst)
+    print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,7 +138,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-steps", type=int, default=1)
+    ap.add_argument("--spmv-mode", type=int, default=0, help="0: x staged in LDS, 1: gathered")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the SVT solve here runs on a single MI355X and "
@@ -140,6 +165,7 @@ def main():
         prm.tau, prm.delta, prm.eps, prm.maxiter, prm.incr = p.tau, p.delta, p.eps, p.maxiter, p.incr
         prm.precision = prec
         prm.profile = 1 if profile else 0
+        prm.spmv_mode = args.spmv_mode
         return B.svt_create(p.m, p.n, p.rows, p.cols, p.vals, prm)
 
     log("[bench] svt_create")

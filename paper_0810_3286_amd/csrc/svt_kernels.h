@@ -44,34 +44,42 @@ size_t gs_update_lds(int nq, int rows_per_blk);
 // Lanes per row for the compressed-row kernels, from the mean row length.
 int lanes_for(double mean_per_row);
 
-// p = A x - coef * prev (prev may be null; coef is read on the device).
-template <typename T>
-hipError_t launch_spmv(hipStream_t s, int lanes, const int32_t *ptr, const int32_t *idx, const T *val,
-                       const T *x, const T *prev, const double *coef, T *p, int nrows);
-
 // LDS-staged sparse product: one workgroup per compute unit owns a row range;
 // x is copied into LDS in nseg column segments of segcols entries.
 struct SpmvLdsPlan {
   int nblk, rows_per_blk, segcols, nseg;
   size_t lds;
-  bool ok;  // false: x segments would be too small; use launch_spmv
+  bool ok;  // false: x segments would be too small; use the gather kernel
 };
 SpmvLdsPlan spmv_lds_plan(int nrows, int ncols, int elem_bytes, int num_cus, int lds_bytes);
 
-// As launch_spmv with x in LDS.  segptr: nrows x (nseg + 1) segment starts
-// (null when nseg == 1).
+// p = A (x / s) - s prev, with s^2 the sum of the xnp partials in xpart
+// (xpart null: s = 1, x already normalised; prev may be null).  With x_out
+// non-null the normalised x is written to x_out (ncols entries) and s to
+// *s_out: the previous half-step's vector joins its basis.  pl non-null:
+// x staged in LDS (segptr: nrows x (nseg + 1) segment starts, null when
+// nseg == 1); null: x gathered from memory.
 template <typename T>
-hipError_t launch_spmv_lds(hipStream_t s, int lanes, const SpmvLdsPlan &pl, const int32_t *ptr,
-                           const int32_t *idx, const T *val, const int32_t *segptr, const T *x, int ncols,
-                           const T *prev, const double *coef, T *p, int nrows);
+hipError_t launch_spmv(hipStream_t s, int lanes, const SpmvLdsPlan *pl, const int32_t *ptr, const int32_t *idx,
+                       const T *val, const int32_t *segptr, const T *x, const double *xpart, int xnp, T *x_out,
+                       double *s_out, int ncols, const T *prev, T *p, int nrows);
 
-// Orthonormalise p (length nrows, overwritten) against the nq orthonormal
-// columns of Q by classical Gram-Schmidt applied twice, then
-// out = p / |p| and *coef_out = |p| (device).  Four kernels (one when
-// nq == 0); coefficients never leave the device.
+// Orthogonalise p (length nrows, overwritten) against the nq orthonormal
+// columns of Q by classical Gram-Schmidt applied twice, leaving the |p|^2
+// partials in gs.part3 (gs_plan(nrows).nrc2 of them) for the consumer's
+// lazy normalisation.  Three kernels (one when nq == 0); the coefficients
+// never leave the device.
 template <typename T>
 hipError_t launch_orthonormalize(hipStream_t s, T *p, int nrows, const T *Q, int64_t ldq, int nq,
-                                 const GsScratch &gs, T *out, double *coef_out);
+                                 const GsScratch &gs);
+
+// |p|^2 partials into gs.part3.
+template <typename T>
+hipError_t launch_sumsq(hipStream_t s, T *p, int nrows, const GsScratch &gs);
+
+// out = p / |p| with |p|^2 from gs.part3; *coef_out = |p|.
+template <typename T>
+hipError_t launch_finalize(hipStream_t s, const T *p, int nrows, const GsScratch &gs, T *out, double *coef_out);
 
 // out[i] = standard normal draw i of stream (seed, ctr); counter-based.
 template <typename T>

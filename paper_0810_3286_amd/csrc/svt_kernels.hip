@@ -100,21 +100,31 @@ __device__ __forceinline__ void tile_partials(VF v, int r0, int r1, const T *__r
   // Branch-free tile: columns past nq - 1 load column nq - 1 (any valid
   // column) and are masked, so the kTile loads of a row issue back to back.
   const int last = nq > 0 ? nq - 1 : 0;
-  for (int row = r0 + threadIdx.x; row < r1; row += kBlock) {
+  // two rows per round: 2 kTile loads in flight per thread
+  for (int row = r0 + threadIdx.x; row < r1; row += 2 * kBlock) {
+    const int row2 = row + kBlock;
+    const bool has2 = row2 < r1;
     const double pv = v(row);
-    double q[kTile];
+    const double pv2 = has2 ? v(row2) : 0.0;
+    double q[kTile], q2[kTile];
     if (nq > 0) {
 #pragma unroll
-      for (int j = 0; j < kTile; ++j) q[j] = (double)Q[(size_t)min(c0 + j, last) * ldq + row];
+      for (int j = 0; j < kTile; ++j) {
+        const size_t off = (size_t)min(c0 + j, last) * ldq;
+        q[j] = (double)Q[off + row];
+        q2[j] = has2 ? (double)Q[off + row2] : 0.0;
+      }
     } else {
 #pragma unroll
-      for (int j = 0; j < kTile; ++j) q[j] = 0.0;
+      for (int j = 0; j < kTile; ++j) q[j] = q2[j] = 0.0;
     }
 #pragma unroll
     for (int j = 0; j < kTile; ++j) {
       const int c = c0 + j;
       const double f = (c < nq) ? q[j] : ((c == nq) ? pv : 0.0);
+      const double f2 = (c < nq) ? q2[j] : ((c == nq) ? pv2 : 0.0);
       acc[j] = fma(f, pv, acc[j]);
+      acc[j] = fma(f2, pv2, acc[j]);
     }
   }
   const int w = threadIdx.x / kWave, wl = threadIdx.x % kWave;
@@ -135,12 +145,48 @@ __device__ __forceinline__ void tile_partials(VF v, int r0, int r1, const T *__r
 }
 
 // ---------------------------------------------------------------------------
-// p = A x - coef prev over a compressed orientation (one sub-wave per row).
+// Lazy normalisation of the input vector of a sparse product: x = x_raw / s
+// with s^2 the sum of the np partials in xpart (every workgroup sums them in
+// the same order).  Returns s (1 when xpart is null: x_raw is normalised).
+__device__ __forceinline__ double input_norm(const double *__restrict__ xpart, int np, double *sh) {
+  if (xpart == nullptr) return 1.0;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) v += xpart[i];
+  v = seg_sum<kWave>(v);
+  const int w = threadIdx.x / kWave, wl = threadIdx.x % kWave, nw = blockDim.x / kWave;
+  if (wl == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < nw; ++i) t += sh[i];
+  __syncthreads();
+  return sqrt(t);
+}
+
+// Workgroup b writes x_raw[i] / s for its slice of [0, ncols) into x_out and
+// workgroup 0 stores s: the normalised vector joins its basis.
+template <typename T>
+__device__ __forceinline__ void write_normalised(const T *__restrict__ x_raw, int ncols, double s,
+                                                 T *__restrict__ x_out, double *__restrict__ s_out) {
+  if (x_out == nullptr) return;
+  const double inv = (s > 1e-280) ? 1.0 / s : 0.0;
+  const int chunk = (ncols + gridDim.x - 1) / gridDim.x;
+  const int i0 = blockIdx.x * chunk, i1 = min(ncols, i0 + chunk);
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) x_out[i] = (T)((double)x_raw[i] * inv);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && s_out) *s_out = s;
+}
+
+// p = A (x_raw / s) - s prev over a compressed orientation (one sub-wave per
+// row), s from xpart (see input_norm); with x_out, the normalised x is also
+// written out (the previous half-step's vector joins its basis).
 template <typename T, int L>
 __global__ __launch_bounds__(kBlock) void k_spmv(
     const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx, const T *__restrict__ val,
-    const T *__restrict__ x, const T *__restrict__ prev, const double *__restrict__ coef,
-    T *__restrict__ p, int nrows) {
+    const T *__restrict__ x, const double *__restrict__ xpart, int xnp, T *__restrict__ x_out,
+    double *__restrict__ s_out, int ncols, const T *__restrict__ prev, T *__restrict__ p, int nrows) {
+  __shared__ double sh[kWaves];
+  const double sn = input_norm(xpart, xnp, sh);
+  write_normalised<T>(x, ncols, sn, x_out, s_out);
+  const T inv = (T)((sn > 1e-280) ? 1.0 / sn : 0.0);
   const int lane = threadIdx.x % L;
   constexpr int kGroups = kBlock / L;
   const int row = blockIdx.x * kGroups + threadIdx.x / L;
@@ -161,29 +207,35 @@ __global__ __launch_bounds__(kBlock) void k_spmv(
   }
   for (; t < end; t += L) acc = fma(val[t], x[idx[t]], acc);
   acc = seg_sum<L>(acc);
-  if (lane == 0) p[row] = prev ? fma(-(T)(*coef), prev[row], acc) : acc;
+  if (lane == 0) {
+    acc = acc * inv;
+    p[row] = prev ? fma(-(T)sn, prev[row], acc) : acc;
+  }
 }
 
-// p = A x - coef prev with x staged in LDS.  A workgroup owns a contiguous
-// range of rows; the columns are split into segments of at most `segcols`
-// entries, each copied once into LDS (coalesced), so the per-entry gathers
-// of x hit LDS instead of L2.  segptr[row * (nseg + 1) + s] is the first
-// entry of segment s of the row (null when nseg == 1: ptr is used).  The
-// same sub-wave handles a row in every segment and accumulates it in LDS.
+// p = A (x_raw / s) - s prev with x staged in LDS.  A workgroup owns a
+// contiguous range of rows; the columns are split into segments of at most
+// `segcols` entries, each copied once into LDS (coalesced), so the per-entry
+// gathers of x hit LDS instead of L2.  segptr[row * (nseg + 1) + s] is the
+// first entry of segment s of the row (null when nseg == 1: ptr is used).
+// The same sub-wave handles a row in every segment and accumulates it in LDS.
 template <typename T, int L>
 __global__ __launch_bounds__(kSpmvBlock) void k_spmv_lds(
     const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx, const T *__restrict__ val,
-    const int32_t *__restrict__ segptr, int nseg, int segcols, const T *__restrict__ x, int ncols,
-    const T *__restrict__ prev, const double *__restrict__ coef, T *__restrict__ p, int nrows,
-    int rows_per_blk) {
+    const int32_t *__restrict__ segptr, int nseg, int segcols, const T *__restrict__ x,
+    const double *__restrict__ xpart, int xnp, T *__restrict__ x_out, double *__restrict__ s_out, int ncols,
+    const T *__restrict__ prev, T *__restrict__ p, int nrows, int rows_per_blk) {
   extern __shared__ double smem_d[];
+  __shared__ double sh[kSpmvBlock / kWave];
   T *xs = reinterpret_cast<T *>(smem_d);  // segcols entries
   T *racc = xs + segcols;                  // rows_per_blk partial row sums
+  const double sn = input_norm(xpart, xnp, sh);
+  write_normalised<T>(x, ncols, sn, x_out, s_out);
+  const T inv = (T)((sn > 1e-280) ? 1.0 / sn : 0.0);
   const int r0 = blockIdx.x * rows_per_blk;
   const int r1 = min(nrows, r0 + rows_per_blk);
   const int lane = threadIdx.x % L, grp = threadIdx.x / L;
   constexpr int kGroups = kSpmvBlock / L;
-  const T c = prev ? (T)(*coef) : (T)0;
   for (int sgm = 0; sgm < nseg; ++sgm) {
     const int c0 = sgm * segcols;
     const int cn = min(segcols, ncols - c0);
@@ -213,8 +265,12 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv_lds(
       acc = seg_sum<L>(acc);
       if (lane == 0) {
         const T tot = (sgm == 0) ? acc : racc[row - r0] + acc;
-        if (sgm + 1 < nseg) racc[row - r0] = tot;
-        else p[row] = prev ? fma(-c, prev[row], tot) : tot;
+        if (sgm + 1 < nseg) {
+          racc[row - r0] = tot;
+        } else {
+          const T y = tot * inv;
+          p[row] = prev ? fma(-(T)sn, prev[row], y) : y;
+        }
       }
     }
   }
@@ -487,11 +543,34 @@ size_t gs_update_lds(int nq, int rows_per_blk) {
 }
 
 template <typename T>
-hipError_t launch_spmv(hipStream_t s, int lanes, const int32_t *ptr, const int32_t *idx, const T *val,
-                       const T *x, const T *prev, const double *coef, T *p, int nrows) {
-#define SVT_SPMV(LN)                                                                            \
-  hipLaunchKernelGGL((k_spmv<T, LN>), dim3((nrows + kBlock / LN - 1) / (kBlock / LN)), dim3(kBlock), \
-                     0, s, ptr, idx, val, x, prev, coef, p, nrows)
+hipError_t launch_spmv(hipStream_t s, int lanes, const SpmvLdsPlan *pl, const int32_t *ptr, const int32_t *idx,
+                       const T *val, const int32_t *segptr, const T *x, const double *xpart, int xnp, T *x_out,
+                       double *s_out, int ncols, const T *prev, T *p, int nrows) {
+  if (pl) {
+    if (!pl->ok || (pl->nseg > 1 && segptr == nullptr)) return hipErrorInvalidValue;
+#define SVT_SPMVL(LN)                                                                              \
+  do {                                                                                            \
+    auto kern = k_spmv_lds<T, LN>;                                                                \
+    hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),                     \
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds); \
+    if (ea != hipSuccess) return ea;                                                              \
+    hipLaunchKernelGGL(kern, dim3(pl->nblk), dim3(kSpmvBlock), pl->lds, s, ptr, idx, val, segptr, \
+                       pl->nseg, pl->segcols, x, xpart, xnp, x_out, s_out, ncols, prev, p, nrows,  \
+                       pl->rows_per_blk);                                                         \
+  } while (0)
+    switch (lanes) {
+      case 4: SVT_SPMVL(4); break;
+      case 8: SVT_SPMVL(8); break;
+      case 16: SVT_SPMVL(16); break;
+      case 32: SVT_SPMVL(32); break;
+      default: SVT_SPMVL(64); break;
+    }
+#undef SVT_SPMVL
+    return hipGetLastError();
+  }
+#define SVT_SPMV(LN)                                                                              \
+  hipLaunchKernelGGL((k_spmv<T, LN>), dim3((nrows + kBlock / LN - 1) / (kBlock / LN)), dim3(kBlock), 0, s, \
+                     ptr, idx, val, x, xpart, xnp, x_out, s_out, ncols, prev, p, nrows)
   switch (lanes) {
     case 4: SVT_SPMV(4); break;
     case 8: SVT_SPMV(8); break;
@@ -508,7 +587,8 @@ SpmvLdsPlan spmv_lds_plan(int nrows, int ncols, int elem_bytes, int num_cus, int
   pl.nblk = std::max(1, std::min(num_cus, (nrows + 7) / 8));
   pl.rows_per_blk = (nrows + pl.nblk - 1) / pl.nblk;
   pl.nblk = (nrows + pl.rows_per_blk - 1) / pl.rows_per_blk;
-  const long budget = (long)lds_bytes / elem_bytes - pl.rows_per_blk;
+  // 1 KiB of headroom for the kernel's static LDS
+  const long budget = ((long)lds_bytes - 1024) / elem_bytes - pl.rows_per_blk;
   long seg = std::min<long>(ncols, budget);
   if (seg < ncols) seg = (seg / 64) * 64;
   pl.segcols = (int)std::max<long>(seg, 0);
@@ -519,56 +599,37 @@ SpmvLdsPlan spmv_lds_plan(int nrows, int ncols, int elem_bytes, int num_cus, int
 }
 
 template <typename T>
-hipError_t launch_spmv_lds(hipStream_t s, int lanes, const SpmvLdsPlan &pl, const int32_t *ptr,
-                           const int32_t *idx, const T *val, const int32_t *segptr, const T *x, int ncols,
-                           const T *prev, const double *coef, T *p, int nrows) {
-  if (!pl.ok || (pl.nseg > 1 && segptr == nullptr)) return hipErrorInvalidValue;
-#define SVT_SPMVL(LN)                                                                            \
-  do {                                                                                          \
-    auto kern = k_spmv_lds<T, LN>;                                                              \
-    hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),                   \
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds); \
-    if (ea != hipSuccess) return ea;                                                            \
-    hipLaunchKernelGGL(kern, dim3(pl.nblk), dim3(kSpmvBlock), pl.lds, s, ptr, idx, val, segptr,  \
-                       pl.nseg, pl.segcols, x, ncols, prev, coef, p, nrows, pl.rows_per_blk);    \
-  } while (0)
-  switch (lanes) {
-    case 4: SVT_SPMVL(4); break;
-    case 8: SVT_SPMVL(8); break;
-    case 16: SVT_SPMVL(16); break;
-    case 32: SVT_SPMVL(32); break;
-    default: SVT_SPMVL(64); break;
-  }
-#undef SVT_SPMVL
+hipError_t launch_sumsq(hipStream_t s, T *p, int nrows, const GsScratch &gs) {
+  const GsPlan g = gs_plan(nrows);
+  hipLaunchKernelGGL((k_gs_update<T, true>), dim3(g.nrc2), dim3(kBlock), gs_update_lds(0, g.rpb2), s, p, nrows,
+                     g.rpb2, (const T *)nullptr, (int64_t)0, 0, gs.part1, 1, gs.part3);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_finalize(hipStream_t s, const T *p, int nrows, const GsScratch &gs, T *out,
+                           double *coef_out) {
+  const GsPlan g = gs_plan(nrows);
+  hipLaunchKernelGGL((k_gs_scale<T>), dim3(grid_for(nrows, 1024)), dim3(kBlock), 0, s, p, nrows, gs.part3, g.nrc2,
+                     out, coef_out);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_orthonormalize(hipStream_t s, T *p, int nrows, const T *Q, int64_t ldq, int nq,
-                                 const GsScratch &gs, T *out, double *coef_out) {
+                                 const GsScratch &gs) {
   const GsPlan g = gs_plan(nrows);
   if (g.nrc1 > kGsChunks1 || g.nrc2 > kGsChunks2 || nq + 1 > gs.max_cols) return hipErrorInvalidValue;
+  if (nq == 0) return launch_sumsq<T>(s, p, nrows, gs);
   const int ntiles = (nq + 1 + kTile - 1) / kTile;
   hipLaunchKernelGGL((k_gs_dots<T>), dim3(g.nrc1, ntiles), dim3(kBlock), 0, s, p, nrows, g.rpb1, Q, ldq,
                      nq, gs.part1);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const double *norm_part = gs.part1;  // column 0 when nq == 0
-  int norm_np = g.nrc1;
-  if (nq > 0) {
-    const size_t lds = gs_update_lds(nq, g.rpb2);
-    if (lds > 64 * 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_gs_update<T, false>), dim3(g.nrc2), dim3(kBlock), lds, s, p, nrows, g.rpb2, Q,
-                       ldq, nq, gs.part1, g.nrc1, gs.part2);
-    hipLaunchKernelGGL((k_gs_update<T, true>), dim3(g.nrc2), dim3(kBlock), lds, s, p, nrows, g.rpb2, Q,
-                       ldq, nq, gs.part2, g.nrc2, gs.part3);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    norm_part = gs.part3;
-    norm_np = g.nrc2;
-  }
-  hipLaunchKernelGGL((k_gs_scale<T>), dim3(grid_for(nrows, 1024)), dim3(kBlock), 0, s, p, nrows, norm_part,
-                     norm_np, out, coef_out);
+  const size_t lds = gs_update_lds(nq, g.rpb2);
+  if (lds > 64 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_gs_update<T, false>), dim3(g.nrc2), dim3(kBlock), lds, s, p, nrows, g.rpb2, Q,
+                     ldq, nq, gs.part1, g.nrc1, gs.part2);
+  hipLaunchKernelGGL((k_gs_update<T, true>), dim3(g.nrc2), dim3(kBlock), lds, s, p, nrows, g.rpb2, Q,
+                     ldq, nq, gs.part2, g.nrc2, gs.part3);
   return hipGetLastError();
 }
 
@@ -644,13 +705,13 @@ hipError_t launch_gather(hipStream_t s, const T *x, const int32_t *map, T *y, in
 }
 
 #define SVT_INSTANTIATE(T)                                                                          \
-  template hipError_t launch_spmv<T>(hipStream_t, int, const int32_t *, const int32_t *, const T *,   \
-                                     const T *, const T *, const double *, T *, int);              \
-  template hipError_t launch_spmv_lds<T>(hipStream_t, int, const SpmvLdsPlan &, const int32_t *,   \
-                                         const int32_t *, const T *, const int32_t *, const T *, int, \
-                                         const T *, const double *, T *, int);                     \
+  template hipError_t launch_spmv<T>(hipStream_t, int, const SpmvLdsPlan *, const int32_t *,          \
+                                     const int32_t *, const T *, const int32_t *, const T *,          \
+                                     const double *, int, T *, double *, int, const T *, T *, int);   \
   template hipError_t launch_orthonormalize<T>(hipStream_t, T *, int, const T *, int64_t, int,     \
-                                               const GsScratch &, T *, double *);                  \
+                                               const GsScratch &);                                  \
+  template hipError_t launch_sumsq<T>(hipStream_t, T *, int, const GsScratch &);                    \
+  template hipError_t launch_finalize<T>(hipStream_t, const T *, int, const GsScratch &, T *, double *); \
   template hipError_t launch_randn<T>(hipStream_t, T *, int, uint64_t, uint64_t);                  \
   template hipError_t launch_ritz<T>(hipStream_t, const T *, int64_t, int, int, const double *,    \
                                      const double *, int, T *, int);                                \

@@ -242,7 +242,7 @@ struct Problem final : ProblemBase {
   DevMem Mr, Mc, Yr, Yc;          // values, T
   DevMem Ub, Vb;                  // bases, T, column-major
   int kcap = 0;                   // columns available in Ub (Vb has kcap + 1)
-  DevMem pbuf;                    // working vector, T, max(m, n)
+  DevMem pbuf_u, pbuf_v;          // unnormalised new vectors of each side, T
   DevMem coef;                    // alpha[0..], beta[0..], double, 2 (kcap + 4)
   DevMem gs1, gs2, gs3;           // Gram-Schmidt partial sums
   GsScratch gs{};
@@ -277,6 +277,10 @@ struct Problem final : ProblemBase {
     acols = std::min(m, n);
     lanes_r = lanes_for((double)nnz / (double)m);
     lanes_c = lanes_for((double)nnz / (double)n);
+    if (const char *lv = std::getenv("SVT_SPMV_LANES")) {  // tuning override: 4, 8, 16, 32 or 64
+      const int l = std::atoi(lv);
+      if (l == 4 || l == 8 || l == 16 || l == 32 || l == 64) lanes_r = lanes_c = l;
+    }
 
     rowptr.alloc(sizeof(int32_t) * (m + 1));
     colidx.alloc(sizeof(int32_t) * nnz);
@@ -287,7 +291,8 @@ struct Problem final : ProblemBase {
     Mc.alloc(sizeof(T) * nnz);
     Yr.alloc(sizeof(T) * nnz);
     Yc.alloc(sizeof(T) * nnz);
-    pbuf.alloc(sizeof(T) * arows);
+    pbuf_u.alloc(sizeof(T) * arows);
+    pbuf_v.alloc(sizeof(T) * acols);
     HIP_CHECK(hipMemcpyAsync(rowptr.p, ix.rowptr.data(), sizeof(int32_t) * (m + 1), hipMemcpyHostToDevice, stream));
     HIP_CHECK(hipMemcpyAsync(colidx.p, ix.colidx.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, stream));
     HIP_CHECK(hipMemcpyAsync(colptr.p, ix.colptr.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, stream));
@@ -401,27 +406,39 @@ struct Problem final : ProblemBase {
     const SpmvLdsPlan *plan;   // LDS-staged product plan (null: gather kernel)
     const int32_t *segptr;
   };
+  // spmv_mode 0: stage x in LDS when it fits in one segment; 1: gather; 2:
+  // stage x in LDS whenever a plan exists (several segments if needed).
+  bool use_lds(const SpmvLdsPlan &pl) const {
+    if (!pl.ok) return false;
+    if (prm.spmv_mode == 1) return false;
+    if (prm.spmv_mode == 2) return true;
+    return pl.nseg == 1;
+  }
   Csx csr_struct() {
     return {rowptr.as<int32_t>(), colidx.as<int32_t>(), (int)ix.m, (int)ix.n, lanes_r,
-            plan_r.ok && prm.spmv_mode == 0 ? &plan_r : nullptr, seg_r.as<int32_t>()};
+            use_lds(plan_r) ? &plan_r : nullptr, seg_r.as<int32_t>()};
   }
   Csx csc_struct() {
     return {colptr.as<int32_t>(), rowidx.as<int32_t>(), (int)ix.n, (int)ix.m, lanes_c,
-            plan_c.ok && prm.spmv_mode == 0 ? &plan_c : nullptr, seg_c.as<int32_t>()};
+            use_lds(plan_c) ? &plan_c : nullptr, seg_c.as<int32_t>()};
   }
   Csx a_rows_struct() { return a_is_y ? csr_struct() : csc_struct(); }
   Csx a_cols_struct() { return a_is_y ? csc_struct() : csr_struct(); }
 
-  void spmv(const Csx &c, const T *vals, const T *x, const T *prev, const double *coefp, T *out) {
+  // out = A (x / s) - s prev with s from the |x|^2 partials xpart (null: x
+  // normalised, s = 1); x_out / s_out receive the normalised x and s.
+  void spmv(const Csx &c, const T *vals, const T *x, const double *xpart, int xnp, T *x_out, double *s_out,
+            const T *prev, T *out) {
     if (c.plan) {
-      const hipError_t e = launch_spmv_lds<T>(stream, c.lanes, *c.plan, c.ptr, c.idx, vals, c.segptr, x, c.ncols,
-                                              prev, coefp, out, c.nrows);
+      const hipError_t e = launch_spmv<T>(stream, c.lanes, c.plan, c.ptr, c.idx, vals, c.segptr, x, xpart, xnp,
+                                          x_out, s_out, c.ncols, prev, out, c.nrows);
       if (e == hipSuccess) return;
       // the device refused the LDS size: use the gather kernel from now on
       (void)hipGetLastError();
       plan_r.ok = plan_c.ok = false;
     }
-    HIP_CHECK(launch_spmv<T>(stream, c.lanes, c.ptr, c.idx, vals, x, prev, coefp, out, c.nrows));
+    HIP_CHECK(launch_spmv<T>(stream, c.lanes, nullptr, c.ptr, c.idx, vals, nullptr, x, xpart, xnp, x_out, s_out,
+                             c.ncols, prev, out, c.nrows));
   }
 
   // Segment starts of every row of a compressed structure for the LDS plan.
@@ -447,59 +464,73 @@ struct Problem final : ProblemBase {
            (has_prev ? vb * c.nrows : 0.0);
   }
 
-  // One half-step: out_col = normalise(orth(S x - coef prev)), norm -> norm_out.
-  void half_step(const Csx &c, const T *vals, const T *x, int ncols_x, const T *prev,
-                 const double *coefp, T *Q, int64_t ldq, int nq, double *norm_out, T *out_col) {
-    T *p = pbuf.as<T>();
+  // One half-step of the bidiagonalisation.  In: the other side's new vector
+  // x_raw (unnormalised) whose |.|^2 partials sit in gs.part3 (xnp of them);
+  // the normalised x goes to x_col and its norm to *x_coef.  Out: this side's
+  // new vector, orthogonalised against the nq columns of Q and left
+  // unnormalised in p with its |.|^2 partials in gs.part3.
+  void half_step(const Csx &c, const T *vals, const T *x_raw, int xnp, T *x_col, double *x_coef,
+                 const T *prev, T *Q, int64_t ldq, int nq, T *p) {
     const double vb = sizeof(T);
     prof.begin();
-    spmv(c, vals, x, prev, coefp, p);
-    prof.end(kSpmv, spmv_bytes(c, ncols_x, prev != nullptr));
+    spmv(c, vals, x_raw, gs.part3, xnp, x_col, x_coef, prev, p);
+    prof.end(kSpmv, spmv_bytes(c, c.ncols, prev != nullptr) + 2.0 * vb * c.ncols);
     prof.begin();
-    HIP_CHECK(launch_orthonormalize<T>(stream, p, c.nrows, Q, ldq, nq, gs, out_col, norm_out));
+    HIP_CHECK(launch_orthonormalize<T>(stream, p, c.nrows, Q, ldq, nq, gs));
     // Q read by both dot-product passes and both updates, p read and written
-    // by each update, the result written once
-    prof.end(kOrth, vb * (double)c.nrows * (nq > 0 ? 4.0 * nq + 7.0 : 2.0));
+    // by each update
+    prof.end(kOrth, vb * (double)c.nrows * (nq > 0 ? 4.0 * nq + 5.0 : 1.0));
   }
 
   // ------------------------------------------------- bidiagonalisation (a3)
   struct Gkl {
-    int k = 0;                // completed steps: u_1..u_k, v_1..v_{k+1}, beta_{k+1}
+    int k = 0;                // completed steps: u_1..u_k, v_1..v_k, raw v_{k+1}
+    bool finalized = false;   // v_{k+1} and beta_{k+1} stored
     std::vector<double> alpha, beta;  // host copies, alpha[i] = alpha_{i+1}, beta[i] = beta_{i+1}
   };
+
+  int xnp_of(int nrows) const { return gs_plan(nrows).nrc2; }
 
   // Start: v_1 random unit, u_1 = A v_1 / alpha_1, then v_2, beta_2.
   void gkl_start(const T *vr, const T *vc, Gkl &g) {
     ensure_basis(std::min<int64_t>(acols, 8));
     const Csx R = a_rows_struct(), C = a_cols_struct();
-    T *p = pbuf.as<T>();
-    HIP_CHECK(launch_randn<T>(stream, p, (int)acols, prm.seed, rng_ctr++));
-    // normalise the start vector: an orthonormalisation against no columns
-    HIP_CHECK(launch_orthonormalize<T>(stream, p, (int)acols, vcol(0), acols, 0, gs, vcol(0), beta_d()));
-    half_step(R, vr, vcol(0), (int)acols, nullptr, nullptr, Ub.as<T>(), arows, 0, alpha_d(), ucol(0));
+    HIP_CHECK(launch_randn<T>(stream, pbuf_v.as<T>(), (int)acols, prm.seed, rng_ctr++));
+    HIP_CHECK(launch_sumsq<T>(stream, pbuf_v.as<T>(), (int)acols, gs));
+    // u_1 = A v_1 / alpha_1 (v_1 = the normalised start vector)
+    half_step(R, vr, pbuf_v.as<T>(), xnp_of((int)acols), vcol(0), beta_d(), nullptr, Ub.as<T>(), arows, 0,
+              pbuf_u.as<T>());
+    // v_2 = A^T u_1 - alpha_1 v_1, orthogonal to v_1
+    half_step(C, vc, pbuf_u.as<T>(), xnp_of((int)arows), ucol(0), alpha_d(), vcol(0), Vb.as<T>(), acols, 1,
+              pbuf_v.as<T>());
     g.k = 1;
-    // v_2: A^T u_1 - alpha_1 v_1, orthogonal to v_1
-    half_step(C, vc, ucol(0), (int)arows, vcol(0), alpha_d(), Vb.as<T>(), acols, 1, beta_d() + 1, vcol(1));
+    g.finalized = false;
     steps_total += 1;
   }
 
-  // One more step: u_{k+1}, alpha_{k+1}, v_{k+2}, beta_{k+2}.
+  // One more step: u_{k+1}, alpha_{k+1}, v_{k+2} (unnormalised).
   void gkl_step(const T *vr, const T *vc, Gkl &g) {
     const int k = g.k;
     ensure_basis(k + 1);
     const Csx R = a_rows_struct(), C = a_cols_struct();
     // u_{k+1} = A v_{k+1} - beta_{k+1} u_k, orthogonal to u_1..u_k
-    half_step(R, vr, vcol(k), (int)acols, ucol(k - 1), beta_d() + k, Ub.as<T>(), arows, k,
-              alpha_d() + k, ucol(k));
+    half_step(R, vr, pbuf_v.as<T>(), xnp_of((int)acols), vcol(k), beta_d() + k, ucol(k - 1), Ub.as<T>(), arows,
+              k, pbuf_u.as<T>());
     // v_{k+2} = A^T u_{k+1} - alpha_{k+1} v_{k+1}, orthogonal to v_1..v_{k+1}
-    half_step(C, vc, ucol(k), (int)arows, vcol(k), alpha_d() + k, Vb.as<T>(), acols, k + 1,
-              beta_d() + k + 1, vcol(k + 1));
+    half_step(C, vc, pbuf_u.as<T>(), xnp_of((int)arows), ucol(k), alpha_d() + k, vcol(k), Vb.as<T>(), acols,
+              k + 1, pbuf_v.as<T>());
     g.k = k + 1;
+    g.finalized = false;
     steps_total += 1;
   }
 
   void gkl_fetch(Gkl &g) {
     const int k = g.k;
+    if (!g.finalized) {
+      // normalise v_{k+1} and store beta_{k+1} (the next step redoes this)
+      HIP_CHECK(launch_finalize<T>(stream, pbuf_v.as<T>(), (int)acols, gs, vcol(k), beta_d() + k));
+      g.finalized = true;
+    }
     g.alpha.resize(k);
     g.beta.resize(k + 1);
     HIP_CHECK(hipMemcpyAsync(g.alpha.data(), alpha_d(), sizeof(double) * k, hipMemcpyDeviceToHost, stream));
@@ -785,7 +816,7 @@ struct Problem final : ProblemBase {
     dout.alloc(sizeof(T) * nout);
     HIP_CHECK(hipMemcpyAsync(dx.p, hx.data(), sizeof(T) * nin, hipMemcpyHostToDevice, stream));
     const Csx c = trans ? csc_struct() : csr_struct();
-    spmv(c, trans ? Yc.as<T>() : Yr.as<T>(), dx.as<T>(), nullptr, nullptr, dout.as<T>());
+    spmv(c, trans ? Yc.as<T>() : Yr.as<T>(), dx.as<T>(), nullptr, 0, nullptr, nullptr, nullptr, dout.as<T>());
     std::vector<T> ho((size_t)nout);
     HIP_CHECK(hipMemcpyAsync(ho.data(), dout.p, sizeof(T) * nout, hipMemcpyDeviceToHost, stream));
     HIP_CHECK(hipStreamSynchronize(stream));
@@ -851,7 +882,7 @@ static void validate_params(const svt_params &p) {
   if (p.lanczos_maxsteps < 0) throw Error(SVT_EINVAL, "lanczos_maxsteps must be >= 0");
   if (p.reorth_passes != 0 && p.reorth_passes != 2) throw Error(SVT_EINVAL, "reorth_passes must be 0 or 2");
   if (!finite(p.decide_margin) || p.decide_margin < 0) throw Error(SVT_EINVAL, "decide_margin must be finite and >= 0");
-  if (p.spmv_mode != 0 && p.spmv_mode != 1) throw Error(SVT_EINVAL, "spmv_mode must be 0 or 1");
+  if (p.spmv_mode < 0 || p.spmv_mode > 2) throw Error(SVT_EINVAL, "spmv_mode must be 0, 1 or 2");
 }
 
 }  // namespace svt

@@ -41,7 +41,7 @@ SMALL = [
 ]
 
 
-@pytest.mark.parametrize("mode", [0, 1])   # 0: x staged in LDS, 1: gathered from memory
+@pytest.mark.parametrize("mode", [1, 2])   # 1: x gathered from memory, 2: staged in LDS
 @pytest.mark.parametrize("case", SMALL + [(400, 400, 10, 47400, 0), (1000, 777, 5, 60000, 4)])
 def test_sparse_products(case, mode):
     m, n, r, nnz, seed = case
@@ -66,15 +66,17 @@ def test_sparse_products(case, mode):
     assert np.all(np.abs(gotT - refT) <= 1e-14 * 64 * scaleT + 1e-300)
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_sparse_products_full_size_30000(precision):
-    # FP64: x takes two LDS segments at n = 30000; FP32 (mixed form): one
-    gpu_case(f"spmv 30000^2 precision {precision}")
+def test_sparse_products_full_size_30000(precision, mode):
+    # staged in LDS (mode 2), FP64 x takes two column segments at n = 30000,
+    # FP32 x (mixed form) one; mode 1 gathers x from memory
+    gpu_case(f"spmv 30000^2 precision {precision} mode {mode}")
     p = workload.config(4)
     y = workload.dense_random_iterate(p, 5)
     rng = np.random.default_rng(6)
     x = rng.standard_normal(p.n)
-    h = _create(p, precision=precision)
+    h = _create(p, precision=precision, spmv_mode=mode)
     try:
         B.svt_set_iterate(h, y)
         got = B.svt_apply(h, x, p.m, trans=0)
