@@ -128,17 +128,106 @@ def copy_calibration(mib: int, reps: int = 3):
     print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}), flush=True)
 
 
+def serving_bench(n_req: int, slots: int, budget_gib: float, precision: int, seed: int = 0,
+                  load_frac: float = 0.7):
+    """Serving form on the mixed-request stream: m, n uniform in [500, 8000],
+    r in {5, 10, 20, 50}, |Omega| = c r (m + n - r) with c uniform in [3, 6],
+    tau = 5 sqrt(m n), delta = 1.2 m n / |Omega|, eps = 1e-4, noise off.
+    Closed loop (all requests at t = 0) gives the capacity C in solves/s; an
+    open loop with Poisson arrivals at load_frac * C gives the latency
+    (arrival to completion) percentiles."""
+    import threading
+    import workload
+    from paper_0810_3286_amd import svt as B
+    trace = workload.serving_trace(2 * n_req, seed=seed, rate=1.0)
+    probs = []
+    for _, sp in trace:
+        probs.append(workload.gaussian_lowrank(sp["m"], sp["n"], sp["r"], sp["nnz"], sp["seed"],
+                                               noise_sigma=sp["noise_sigma"], maxiter=500))
+
+    def params(p):
+        prm = B.svt_params_default(p.m, p.n, p.nnz)
+        prm.tau, prm.delta, prm.eps, prm.maxiter, prm.incr = p.tau, p.delta, p.eps, p.maxiter, p.incr
+        prm.precision = precision
+        return prm
+
+    budget = int(budget_gib * (1 << 30))
+    srv = B.svt_server_create(budget, slots)
+    try:
+        closed = probs[:n_req]
+        t0 = time.perf_counter()
+        tickets = [B.svt_submit(srv, p.m, p.n, p.rows, p.cols, p.vals, params(p)) for p in closed]
+        iters = 0
+        statuses = []
+        for i, t in enumerate(tickets):
+            st, info = B.svt_wait(srv, t)
+            iters += info.iters
+            statuses.append(st)
+            B.svt_release(srv, t)
+            log(f"[bench] serving closed loop: request {i} done (status {st}, {info.iters} iterations)")
+        t_closed = time.perf_counter() - t0
+        capacity = n_req / t_closed
+        log(f"[bench] serving closed loop: {n_req} solves in {t_closed:.2f} s")
+        # open loop: Poisson arrivals at load_frac * capacity
+        rate = load_frac * capacity
+        rng = np.random.default_rng(seed + 1)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+        openp = probs[n_req:2 * n_req]
+        tix = [None] * n_req
+
+        def submitter():
+            base = time.perf_counter()
+            for i, p in enumerate(openp):
+                dt = arrivals[i] - (time.perf_counter() - base)
+                if dt > 0:
+                    time.sleep(dt)
+                tix[i] = B.svt_submit(srv, p.m, p.n, p.rows, p.cols, p.vals, params(p))
+                log(f"[bench] serving open loop: request {i} submitted")
+
+        t1 = time.perf_counter()
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+        lat = []
+        for i, p in enumerate(openp):
+            st, info = B.svt_wait(srv, tix[i])
+            _, _, _, _, times = B.svt_result(srv, tix[i], p.m, p.n)
+            lat.append(times[2] - times[0])
+            B.svt_release(srv, tix[i])
+            log(f"[bench] serving open loop: request {i} done (status {st}, latency {lat[-1]:.2f} s)")
+        t_open = time.perf_counter() - t1
+        stats = B.svt_server_stats(srv)
+    finally:
+        B.svt_server_destroy(srv)
+    lat = np.array(lat)
+    return {
+        "requests_per_run": n_req, "slots": slots, "budget_gib": budget_gib,
+        "precision": "mixed" if precision == B.SVT_MIXED else "fp64",
+        "closed_loop_solves_per_s": capacity,
+        "closed_loop_svt_iters_per_s": iters / t_closed,
+        "closed_loop_ok": int(sum(1 for s_ in statuses if s_ == B.SVT_OK)),
+        "open_loop_rate_per_s": rate, "open_loop_solves_per_s": n_req / t_open,
+        "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+        "max_running": stats["max_running"], "peak_admitted_gib": stats["peak_bytes"] / (1 << 30),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=4)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-steps", type=int, default=1)
-    ap.add_argument("--spmv-mode", type=int, default=0, help="0: x staged in LDS, 1: gathered")
+    ap.add_argument("--spmv-mode", type=int, default=0,
+                    help="0: x in LDS when it fits in one segment, 1: gathered, 2: LDS segments")
+    ap.add_argument("--serving-requests", type=int, default=32)
+    ap.add_argument("--serving-slots", type=int, default=8)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -234,7 +323,7 @@ def main():
                    "tau": p.tau, "delta": p.delta, "eps": p.eps,
                    "precision": args.precision, "parallelism": "single-gpu"},
         "sampled_entries_per_s": iters_per_s * p.nnz,
-        "solves_per_s": args.steps / t_total,
+        "solves_per_s_30k": args.steps / t_total,
         "iters_per_solve": iters / args.steps,
         "loop_iters_per_s": iters / loop_s,
         "kick_s_per_solve": kick_s / args.steps,
@@ -251,6 +340,35 @@ def main():
                      "traffic": traffic, "bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": avg_s * 1e6},
     }
+    if not args.no_fp64 and args.precision == "mixed":
+        # the plain FP64 GPU solver on the same workload, for comparison
+        prm = B.svt_params_default(p.m, p.n, p.nnz)
+        prm.tau, prm.delta, prm.eps, prm.maxiter, prm.incr = p.tau, p.delta, p.eps, p.maxiter, p.incr
+        prm.precision = B.SVT_FP64
+        prm.spmv_mode = args.spmv_mode
+        h64 = B.svt_create(p.m, p.n, p.rows, p.cols, p.vals, prm)
+        try:
+            log("[bench] fp64 comparison solves")
+            B.svt_solve(h64)
+            t0 = time.perf_counter()
+            it64 = 0
+            for _ in range(args.steps):
+                _, inf = B.svt_solve(h64)
+                it64 += inf.iters
+            t64 = time.perf_counter() - t0
+            U64, _, V64 = B.svt_factors(h64, p.m, p.n)
+        finally:
+            B.svt_destroy(h64)
+        out["fp64"] = {"svt_iters_per_s": it64 / t64, "sampled_entries_per_s": it64 / t64 * p.nnz,
+                       "iters_per_solve": it64 / args.steps, "ms_per_step": t64 / args.steps * 1e3,
+                       "rel_error_vs_truth": rel_diff_factored(U64, V64, p.ML, p.MR),
+                       "mixed_vs_fp64_rel_diff": rel_diff_factored(U, V, U64, V64)}
+    if not args.no_serving:
+        log("[bench] serving stream")
+        out["serving"] = serving_bench(args.serving_requests, args.serving_slots, 64.0,
+                                       B.SVT_MIXED if args.precision == "mixed" else B.SVT_FP64)
+        out["solves_per_s"] = out["serving"]["closed_loop_solves_per_s"]
+        out["p99_latency_s"] = out["serving"]["p99_latency_s"]
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)

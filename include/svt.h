@@ -201,6 +201,60 @@ svt_status svt_kick(svt_problem *h, double *sigma1, int32_t *k0);
 svt_status svt_kernel_stats(const svt_problem *h, int32_t kind, int64_t *launches,
                             double *total_ms, double *total_bytes);
 
+/* ---------------------------------------------------------------------
+ * Serving form: continuous batching of completion requests on one GPU.
+ * Not part of the paper's method: a request loop around svt_create /
+ * svt_solve.  Requests are admitted first come, first served, when a slot is
+ * free and their predicted device footprint fits in the remaining budget;
+ * each slot runs its solve on its own HIP stream, so solves admitted at
+ * different times overlap on the device.  Every reduction has a fixed order
+ * and no device buffer is shared between solves: each result is
+ * bit-identical alone and in the mix.  A server may be used from several
+ * threads.
+ * ------------------------------------------------------------------ */
+typedef struct svt_server svt_server;
+
+/* Predicted device bytes of a problem (index structures, values, iterate,
+   bidiagonalisation bases for up to 128 steps, factors, scratch). */
+svt_status svt_footprint(int64_t m, int64_t n, int64_t nnz, int32_t precision, size_t *bytes);
+
+/* hbm_budget_bytes > 0: device memory the admitted solves may hold at once;
+   1 <= max_slots <= 64: solves running at once.  Nothing touches the device
+   until a request is admitted. */
+svt_status svt_server_create(size_t hbm_budget_bytes, int32_t max_slots, svt_server **out);
+
+/* Queue one request (COO triplets in any order, host pointers, copied).
+   params may be NULL (defaults); its stream field is ignored.  Returns
+   EINVAL for invalid indices or values (checked here), ENOMEM if the request
+   could never fit in the budget; *ticket identifies the request. */
+svt_status svt_submit(svt_server *s, int64_t m, int64_t n, int64_t nnz, const int32_t *rows,
+                      const int32_t *cols, const double *vals, const svt_params *params,
+                      uint64_t *ticket);
+
+/* *state: 0 queued, 1 running, 2 done. */
+svt_status svt_poll(svt_server *s, uint64_t ticket, int32_t *state);
+
+/* Block until the request is done; returns its solve status (SVT_OK,
+   SVT_NOT_CONVERGED or the error of svt_create / svt_solve). */
+svt_status svt_wait(svt_server *s, uint64_t ticket, svt_info *info);
+
+/* Copy out a finished request's factors (as svt_factors: U m x r scaled by
+   w, V n x r, row-major; pass NULL buffers to query r) and, if times is not
+   NULL, its submit, start and completion times (seconds, one steady clock).
+   EBUSY while the request is not done. */
+svt_status svt_result(svt_server *s, uint64_t ticket, int32_t *rank_out, double *U, double *w,
+                      double *V, double *times);
+
+/* Forget a finished request (its factors are freed). */
+svt_status svt_release(svt_server *s, uint64_t ticket);
+
+/* Peak admitted footprint, the most solves that ran at once, queue length. */
+svt_status svt_server_stats(svt_server *s, size_t *peak_bytes, int32_t *max_running,
+                            int32_t *queued);
+
+/* Finish queued and running work, then stop the slots and free the server. */
+svt_status svt_server_destroy(svt_server *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,6 +26,7 @@ SOURCES = [
     ("svt_kernels.hip", True),
     ("bidiag.cpp", False),
     ("svt_solver.cpp", False),
+    ("svt_server.cpp", False),
 ]
 
 

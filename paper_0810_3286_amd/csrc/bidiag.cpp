@@ -86,12 +86,17 @@ bool bidiag_svd(const std::vector<double> &d_in, const std::vector<double> &e_in
   out.p_last[k - 1] = 1.0;
   Acc acc{k, vectors, &out.P, &out.Q, &out.p_last};
 
+  for (int i = 0; i < k; ++i)
+    if (!std::isfinite(d[i])) return false;
+  for (int i = 0; i + 1 < k; ++i)
+    if (!std::isfinite(e[i])) return false;
   double bnorm = 0.0;
   for (int i = 0; i < k; ++i) bnorm = std::max(bnorm, std::fabs(d[i]));
   for (int i = 0; i + 1 < k; ++i) bnorm = std::max(bnorm, std::fabs(e[i]));
   const double abs_tol = kEps * bnorm;
 
-  const long max_sweeps = 40L * k * k + 100;
+  // implicit-shift QR needs about two sweeps per singular value
+  const long max_sweeps = 30L * k + 1000;
   long sweeps = 0;
   int hi = k - 1;
   while (hi > 0) {

@@ -20,7 +20,7 @@ struct BidiagSVD {
 // Implicit-shift QR (Golub-Kahan step with a Wilkinson shift, zero-diagonal
 // deflation by Givens chasing).  With vectors = false only sigma and the last
 // row of P are formed (O(k^2) work); with vectors = true the full P and Q.
-// Returns false if the iteration cap (40 k^2 sweeps over 2x2 blocks) is hit.
+// Returns false for non-finite input or if the sweep cap (30 k + 1000) is hit.
 bool bidiag_svd(const std::vector<double> &d, const std::vector<double> &e, bool vectors,
                 BidiagSVD &out);
 

@@ -20,6 +20,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <map>
+#include <mutex>
 
 namespace svt {
 
@@ -542,6 +544,28 @@ size_t gs_update_lds(int nq, int rows_per_blk) {
   return sizeof(double) * ((size_t)nq + 1 + kBlock + (size_t)rows_per_blk);
 }
 
+// The dynamic-LDS limit is a per-kernel attribute shared by every stream and
+// thread: raise it once to the largest size any plan uses (the device's
+// per-workgroup maximum) and never lower it, so concurrent solves with
+// different plans cannot shrink it under each other's launches.
+hipError_t allow_dynamic_lds(const void *kern, size_t bytes) {
+  static std::mutex mu;
+  static std::map<const void *, size_t> raised;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = raised.find(kern);
+  if (it != raised.end() && it->second >= bytes) return hipSuccess;
+  int dev = 0, maxlds = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return e;
+  const size_t want = std::max(bytes, (size_t)std::min(maxlds, 160 * 1024));
+  e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)want);
+  if (e != hipSuccess) return e;
+  raised[kern] = want;
+  return hipSuccess;
+}
+
 template <typename T>
 hipError_t launch_spmv(hipStream_t s, int lanes, const SpmvLdsPlan *pl, const int32_t *ptr, const int32_t *idx,
                        const T *val, const int32_t *segptr, const T *x, const double *xpart, int xnp, T *x_out,
@@ -551,8 +575,7 @@ hipError_t launch_spmv(hipStream_t s, int lanes, const SpmvLdsPlan *pl, const in
 #define SVT_SPMVL(LN)                                                                              \
   do {                                                                                            \
     auto kern = k_spmv_lds<T, LN>;                                                                \
-    hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),                     \
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->lds); \
+    hipError_t ea = allow_dynamic_lds(reinterpret_cast<const void *>(kern), pl->lds);             \
     if (ea != hipSuccess) return ea;                                                              \
     hipLaunchKernelGGL(kern, dim3(pl->nblk), dim3(kSpmvBlock), pl->lds, s, ptr, idx, val, segptr, \
                        pl->nseg, pl->segcols, x, xpart, xnp, x_out, s_out, ncols, prev, p, nrows,  \

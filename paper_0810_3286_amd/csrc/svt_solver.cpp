@@ -543,7 +543,12 @@ struct Problem final : ProblemBase {
     const int k = g.k;
     std::vector<double> d(g.alpha.begin(), g.alpha.begin() + k), e(k > 1 ? k - 1 : 0);
     for (int i = 0; i + 1 < k; ++i) e[i] = g.beta[i + 1];
-    if (!bidiag_svd(d, e, vectors, out)) throw Error(SVT_ELANCZOS, "bidiagonal SVD did not converge");
+    for (int i = 0; i <= k; ++i)
+      if ((i < k && !std::isfinite(g.alpha[i])) || !std::isfinite(g.beta[i]))
+        throw Error(SVT_EDIVERGED, "non-finite bidiagonalisation coefficient at step " + std::to_string(i + 1) +
+                                       " of " + std::to_string(k));
+    if (!bidiag_svd(d, e, vectors, out))
+      throw Error(SVT_ELANCZOS, "bidiagonal SVD did not converge (k = " + std::to_string(k) + ")");
     const double bk1 = (k >= acols) ? 0.0 : std::fabs(g.beta[k]);
     res.resize(k);
     for (int i = 0; i < k; ++i) res[i] = bk1 * std::fabs(out.p_last[i]);

@@ -111,6 +111,17 @@ def _signatures(lib):
         "svt_sample_update": (ctypes.c_int32, [h, ctypes.c_int32, _dp, _dp, ctypes.c_double, _dp]),
         "svt_kick": (ctypes.c_int32, [h, _dp, _ip]),
         "svt_kernel_stats": (ctypes.c_int32, [h, ctypes.c_int32, _lp, _dp, _dp]),
+        "svt_footprint": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_size_t)]),
+        "svt_server_create": (ctypes.c_int32, [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+        "svt_submit": (ctypes.c_int32, [h, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _ip, _ip, _dp,
+                                        ctypes.POINTER(svt_params), ctypes.POINTER(ctypes.c_uint64)]),
+        "svt_poll": (ctypes.c_int32, [h, ctypes.c_uint64, _ip]),
+        "svt_wait": (ctypes.c_int32, [h, ctypes.c_uint64, ctypes.POINTER(svt_info)]),
+        "svt_result": (ctypes.c_int32, [h, ctypes.c_uint64, _ip, _dp, _dp, _dp, _dp]),
+        "svt_release": (ctypes.c_int32, [h, ctypes.c_uint64]),
+        "svt_server_stats": (ctypes.c_int32, [h, ctypes.POINTER(ctypes.c_size_t), _ip, _ip]),
+        "svt_server_destroy": (ctypes.c_int32, [h]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -282,3 +293,77 @@ def svt_kernel_stats(h, kind: int):
     b = ctypes.c_double()
     _check(load().svt_kernel_stats(h, kind, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(b)), h)
     return n.value, ms.value, b.value
+
+
+# ---------------------------------------------------------------- serving
+
+
+def svt_footprint(m: int, n: int, nnz: int, precision: int = SVT_FP64) -> int:
+    b = ctypes.c_size_t()
+    _check(load().svt_footprint(m, n, nnz, precision, ctypes.byref(b)))
+    return b.value
+
+
+def svt_server_create(hbm_budget_bytes: int, max_slots: int):
+    s = ctypes.c_void_p()
+    _check(load().svt_server_create(hbm_budget_bytes, max_slots, ctypes.byref(s)))
+    return s
+
+
+def svt_submit(server, m: int, n: int, rows, cols, vals, params: svt_params | None = None) -> int:
+    rows = _i32(rows)
+    cols = _i32(cols)
+    vals = _f64(vals)
+    if not (rows.shape[0] == cols.shape[0] == vals.shape[0]):
+        raise ValueError("rows, cols and vals must have the same length")
+    t = ctypes.c_uint64()
+    st = load().svt_submit(server, m, n, vals.shape[0], _p(rows, _ip), _p(cols, _ip), _p(vals),
+                           ctypes.byref(params) if params is not None else None, ctypes.byref(t))
+    if st != SVT_OK:
+        raise SvtError(st, svt_status_string(st))
+    return t.value
+
+
+def svt_poll(server, ticket: int) -> int:
+    st = ctypes.c_int32()
+    _check(load().svt_poll(server, ticket, ctypes.byref(st)))
+    return st.value
+
+
+def svt_wait(server, ticket: int):
+    info = svt_info()
+    st = load().svt_wait(server, ticket, ctypes.byref(info))
+    return st, info
+
+
+def svt_result(server, ticket: int, m: int, n: int):
+    lib = load()
+    r = ctypes.c_int32()
+    st = lib.svt_result(server, ticket, ctypes.byref(r), None, None, None, None)
+    if st not in (SVT_OK, SVT_NOT_CONVERGED):
+        raise SvtError(st, svt_status_string(st))
+    r = r.value
+    U = np.zeros((m, r))
+    V = np.zeros((n, r))
+    w = np.zeros(r)
+    times = np.zeros(3)
+    rr = ctypes.c_int32()
+    lib.svt_result(server, ticket, ctypes.byref(rr), _p(U), _p(w), _p(V), _p(times))
+    return st, U, w, V, times
+
+
+def svt_release(server, ticket: int) -> None:
+    _check(load().svt_release(server, ticket))
+
+
+def svt_server_stats(server):
+    b = ctypes.c_size_t()
+    mr = ctypes.c_int32()
+    q = ctypes.c_int32()
+    _check(load().svt_server_stats(server, ctypes.byref(b), ctypes.byref(mr), ctypes.byref(q)))
+    return dict(peak_bytes=b.value, max_running=mr.value, queued=q.value)
+
+
+def svt_server_destroy(server) -> None:
+    if server is not None:
+        load().svt_server_destroy(server)

@@ -1,0 +1,106 @@
+"""Serving form on the GPU: continuous batching of mixed-size requests.
+
+* every result is bit-identical alone (svt_solve) and in the mix (server);
+* admission respects the device-memory budget (a budget that fits one
+  request at a time serialises the solves);
+* a request solved in the mix matches the FP64 oracle (sampled subset).
+The paper has no serving form: parity beyond alone = in the mix and the
+oracle on sampled requests is unpinned."""
+import numpy as np
+import pytest
+
+import oracle
+import workload
+from paper_0810_3286_amd import svt as B
+from tests.helpers import gpu_case, rel_diff_factored
+
+pytestmark = pytest.mark.gpu
+
+REQS = [
+    (150, 150, 4, 7000, 6),
+    (90, 260, 3, 8000, 3),
+    (260, 90, 3, 8000, 5),
+    (400, 400, 10, 47400, 0),
+    (700, 500, 5, 42000, 11),
+    (33, 29, 2, 700, 3),
+]
+
+
+def _prm(p, precision):
+    prm = B.svt_params_default(p.m, p.n, p.nnz)
+    prm.tau, prm.delta, prm.eps, prm.maxiter, prm.incr = p.tau, p.delta, p.eps, 300, p.incr
+    prm.precision = precision
+    return prm
+
+
+def _alone(p, prm):
+    h = B.svt_create(p.m, p.n, p.rows, p.cols, p.vals, prm)
+    try:
+        st, info = B.svt_solve(h)
+        U, w, V = B.svt_factors(h, p.m, p.n)
+    finally:
+        B.svt_destroy(h)
+    return st, info, U, w, V
+
+
+@pytest.mark.parametrize("precision", [B.SVT_FP64, B.SVT_MIXED])
+def test_alone_equals_mix(precision):
+    gpu_case(f"serving alone vs mix precision {precision}")
+    probs = [workload.gaussian_lowrank(*c, shuffle=True) for c in REQS]
+    alone = [_alone(p, _prm(p, precision)) for p in probs]
+    srv = B.svt_server_create(64 << 30, 4)
+    try:
+        tickets = [B.svt_submit(srv, p.m, p.n, p.rows, p.cols, p.vals, _prm(p, precision)) for p in probs]
+        for p, t, a in zip(probs, tickets, alone):
+            st, info = B.svt_wait(srv, t)
+            st2, U, w, V, times = B.svt_result(srv, t, p.m, p.n)
+            assert st == a[0] and info.iters == a[1].iters
+            assert np.array_equal(U, a[2]) and np.array_equal(w, a[3]) and np.array_equal(V, a[4])
+            assert times[0] <= times[1] <= times[2]
+        stats = B.svt_server_stats(srv)
+        assert stats["max_running"] >= 2  # the solves overlapped
+    finally:
+        B.svt_server_destroy(srv)
+
+
+def test_budget_serialises():
+    gpu_case("serving tiny budget")
+    probs = [workload.gaussian_lowrank(*c) for c in REQS[:4]]
+    fps = [B.svt_footprint(p.m, p.n, p.nnz) for p in probs]
+    budget = int(max(fps) * 1.01)
+    srv = B.svt_server_create(budget, 4)
+    try:
+        tickets = [B.svt_submit(srv, p.m, p.n, p.rows, p.cols, p.vals, _prm(p, B.SVT_FP64)) for p in probs]
+        spans = []
+        for p, t in zip(probs, tickets):
+            B.svt_wait(srv, t)
+            spans.append(B.svt_result(srv, t, p.m, p.n)[4])
+        stats = B.svt_server_stats(srv)
+        assert stats["peak_bytes"] <= budget
+        # a pair of requests fits only if both footprints fit
+        for i in range(len(spans)):
+            for j in range(i + 1, len(spans)):
+                overlap = min(spans[i][2], spans[j][2]) > max(spans[i][1], spans[j][1])
+                if fps[i] + fps[j] > budget:
+                    assert not overlap
+        # first come, first served
+        starts = [s[1] for s in spans]
+        assert starts == sorted(starts)
+    finally:
+        B.svt_server_destroy(srv)
+
+
+def test_mix_member_matches_oracle():
+    gpu_case("serving vs oracle")
+    probs = [workload.gaussian_lowrank(*c) for c in REQS[:3]]
+    srv = B.svt_server_create(64 << 30, 3)
+    try:
+        tickets = [B.svt_submit(srv, p.m, p.n, p.rows, p.cols, p.vals, _prm(p, B.SVT_FP64)) for p in probs]
+        for p, t in zip(probs, tickets):
+            st, info = B.svt_wait(srv, t)
+            _, U, w, V, _ = B.svt_result(srv, t, p.m, p.n)
+            o = oracle.svt_dense(p.m, p.n, p.rows, p.cols, p.vals, p.tau, p.delta, p.eps, 300, p.incr)
+            assert info.iters == o["iters"]
+            assert rel_diff_factored(U, V, o["U"], o["V"]) <= 1e-8
+    finally:
+        B.svt_server_destroy(srv)
