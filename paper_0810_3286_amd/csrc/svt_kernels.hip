@@ -147,6 +147,12 @@ __device__ __forceinline__ void tile_partials(VF v, int r0, int r1, const T *__r
 }
 
 // ---------------------------------------------------------------------------
+// Norms at or below this are treated as zero: the reciprocal of a larger one
+// is finite in the value type.
+template <typename T> __device__ __forceinline__ double norm_floor();
+template <> __device__ __forceinline__ double norm_floor<double>() { return 1e-280; }
+template <> __device__ __forceinline__ double norm_floor<float>() { return 1e-30; }
+
 // Lazy normalisation of the input vector of a sparse product: x = x_raw / s
 // with s^2 the sum of the np partials in xpart (every workgroup sums them in
 // the same order).  Returns s (1 when xpart is null: x_raw is normalised).
@@ -170,7 +176,7 @@ template <typename T>
 __device__ __forceinline__ void write_normalised(const T *__restrict__ x_raw, int ncols, double s,
                                                  T *__restrict__ x_out, double *__restrict__ s_out) {
   if (x_out == nullptr) return;
-  const double inv = (s > 1e-280) ? 1.0 / s : 0.0;
+  const double inv = (s > norm_floor<T>()) ? 1.0 / s : 0.0;
   const int chunk = (ncols + gridDim.x - 1) / gridDim.x;
   const int i0 = blockIdx.x * chunk, i1 = min(ncols, i0 + chunk);
   for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) x_out[i] = (T)((double)x_raw[i] * inv);
@@ -188,7 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(
   __shared__ double sh[kWaves];
   const double sn = input_norm(xpart, xnp, sh);
   write_normalised<T>(x, ncols, sn, x_out, s_out);
-  const T inv = (T)((sn > 1e-280) ? 1.0 / sn : 0.0);
+  const T inv = (T)((sn > norm_floor<T>()) ? 1.0 / sn : 0.0);
   const int lane = threadIdx.x % L;
   constexpr int kGroups = kBlock / L;
   const int row = blockIdx.x * kGroups + threadIdx.x / L;
@@ -233,7 +239,7 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv_lds(
   T *racc = xs + segcols;                  // rows_per_blk partial row sums
   const double sn = input_norm(xpart, xnp, sh);
   write_normalised<T>(x, ncols, sn, x_out, s_out);
-  const T inv = (T)((sn > 1e-280) ? 1.0 / sn : 0.0);
+  const T inv = (T)((sn > norm_floor<T>()) ? 1.0 / sn : 0.0);
   const int r0 = blockIdx.x * rows_per_blk;
   const int r1 = min(nrows, r0 + rows_per_blk);
   const int lane = threadIdx.x % L, grp = threadIdx.x / L;
@@ -351,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_gs_scale(const T *__restrict__ p, in
   __shared__ double scratch[kBlock];
   reduce_columns(part, np, 1, hs, scratch);
   const double nrm = sqrt(hs[0]);
-  const double inv = (nrm > 1e-280) ? 1.0 / nrm : 0.0;
+  const double inv = (nrm > norm_floor<T>()) ? 1.0 / nrm : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) *coef_out = nrm;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
     out[i] = (T)((double)p[i] * inv);

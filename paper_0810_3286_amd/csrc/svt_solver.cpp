@@ -354,6 +354,9 @@ struct Problem final : ProblemBase {
     n3.alloc(sizeof(double) * (size_t)kGsChunks2);
     HIP_CHECK(hipMemsetAsync(ncoef.p, 0, ncoef.bytes, stream));
     if (kcap > 0) {
+      // the pending vector's |.|^2 partials (part3) cross the growth: the
+      // next half-step normalises that vector with them
+      HIP_CHECK(hipMemcpyAsync(n3.p, gs3.p, sizeof(double) * (size_t)kGsChunks2, hipMemcpyDeviceToDevice, stream));
       HIP_CHECK(hipMemcpyAsync(nU.p, Ub.p, sizeof(T) * (size_t)arows * (size_t)(kcap + 1), hipMemcpyDeviceToDevice, stream));
       HIP_CHECK(hipMemcpyAsync(nV.p, Vb.p, sizeof(T) * (size_t)acols * (size_t)(kcap + 2), hipMemcpyDeviceToDevice, stream));
       HIP_CHECK(hipMemcpyAsync(ncoef.as<double>(), coef.as<double>(), sizeof(double) * (kcap + 4), hipMemcpyDeviceToDevice, stream));
@@ -543,6 +546,11 @@ struct Problem final : ProblemBase {
     const int k = g.k;
     std::vector<double> d(g.alpha.begin(), g.alpha.begin() + k), e(k > 1 ? k - 1 : 0);
     for (int i = 0; i + 1 < k; ++i) e[i] = g.beta[i + 1];
+    if (log_level > 1) {
+      std::fprintf(stderr, "[svt] coefficients k %d:", k);
+      for (int i = 0; i < k; ++i) std::fprintf(stderr, " a%d %.3e b%d %.3e", i + 1, g.alpha[i], i + 2, g.beta[i + 1]);
+      std::fprintf(stderr, "\n");
+    }
     for (int i = 0; i <= k; ++i)
       if ((i < k && !std::isfinite(g.alpha[i])) || !std::isfinite(g.beta[i]))
         throw Error(SVT_EDIVERGED, "non-finite bidiagonalisation coefficient at step " + std::to_string(i + 1) +

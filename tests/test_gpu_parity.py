@@ -283,3 +283,36 @@ def test_unkicked_solve_matches_oracle():
     o = oracle.svt_dense(p.m, p.n, p.rows, p.cols, p.vals, p.tau, p.delta, p.eps,
                          p.maxiter, p.incr, kick=False)
     _compare_solves(g, o)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_partial_svd_across_basis_growth(precision):
+    # 70 triplets need more than 64 bidiagonalisation steps: the bases grow
+    # mid-run and the pending vector's norm partials must survive the move
+    gpu_case(f"partial_svd growth precision {precision}")
+    p = workload.gaussian_lowrank(300, 250, 5, 30000, 21)
+    y = workload.dense_random_iterate(p, 22)
+    h = _create(p, precision=precision)
+    try:
+        B.svt_set_iterate(h, y)
+        sig, U, V, steps = B.svt_partial_svd(h, 70, p.m, p.n)
+    finally:
+        B.svt_destroy(h)
+    assert steps > 64
+    Yd = np.zeros((p.m, p.n))
+    Yd[p.rows, p.cols] = y
+    so = oracle.top_triplets_dense(Yd, 70)[1]
+    tol = 1e-11 if precision == 0 else 2e-5
+    np.testing.assert_allclose(sig, so, rtol=0, atol=tol * so[0])
+
+
+def test_mixed_hard_request_stays_finite():
+    # a request whose singular values cluster at tau needs long
+    # bidiagonalisations every iteration (it does not converge in 60)
+    gpu_case("mixed 700x500 hard request")
+    p = workload.gaussian_lowrank(700, 500, 5, 30000, 11, shuffle=True)
+    from paper_0810_3286_amd import solve
+    g = solve(p.m, p.n, p.rows, p.cols, p.vals, tau=p.tau, delta=p.delta, eps=p.eps,
+              maxiter=60, incr=p.incr, precision=B.SVT_MIXED)
+    assert g["status"] == B.SVT_NOT_CONVERGED
+    assert np.all(np.isfinite(g["residuals"])) and max(g["gkl_steps"]) > 64
