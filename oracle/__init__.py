@@ -13,6 +13,9 @@ Contents (each function cites the passage of the paper it writes out):
 * ``apply_sparse``     Y x and Y^T x for Y supported on Omega (Section 2.2)
 * ``sampled_entries``  X_ij = sum_l U_il V_jl on Omega
 * ``svt_dense``        Algorithm 1 (Section 5.1.5), tier A: dense Y, full SVD
+* ``gram_triplets``    singular triplets above tau of a sparse Y from its Gram
+                       matrix's eigendecomposition (LAPACK, FP64)
+* ``svt_sparse``       Algorithm 1, tier B: sparse Y, Gram-matrix triplets
 """
 from .svt import (  # noqa: F401
     jacobi_svd,
@@ -22,4 +25,6 @@ from .svt import (  # noqa: F401
     sampled_entries,
     svt_dense,
     top_triplets_dense,
+    gram_triplets,
+    svt_sparse,
 )

@@ -215,3 +215,92 @@ def svt_dense(m: int, n: int, rows, cols, vals, tau: float, delta: float,
         out["y_hist"] = y_hist
         out["Y"] = Y
     return out
+
+
+def gram_triplets(Ys, tau: float):
+    """Singular triplets of a sparse Y with sigma > tau, plus sigma_{r+1}.
+
+    Tier B of the oracle, for sizes where a dense Jacobi SVD per iteration is
+    too slow.  The plain definition via the Gram matrix: on the smaller side,
+    G = Y^T Y (or Y Y^T) = V diag(sigma^2) V^T (LAPACK's symmetric
+    eigensolver, FP64), and u_i = Y v_i / sigma_i.  Singular values are
+    accurate to eps * sigma_1^2 / sigma_i relative, ample for those above tau.
+    Returns (U_r, sigma_r, V_r, all singular values descending).
+    """
+    m, n = Ys.shape
+    if m >= n:
+        G = (Ys.T @ Ys).toarray()
+        lam, W = np.linalg.eigh(G)
+        order = np.argsort(lam)[::-1]
+        lam, W = lam[order], W[:, order]
+        s = np.sqrt(np.maximum(lam, 0.0))
+        r = int(np.count_nonzero(s > tau))
+        V = W[:, :r]
+        U = (Ys @ V) / s[:r] if r > 0 else np.zeros((m, 0))
+    else:
+        G = (Ys @ Ys.T).toarray()
+        lam, W = np.linalg.eigh(G)
+        order = np.argsort(lam)[::-1]
+        lam, W = lam[order], W[:, order]
+        s = np.sqrt(np.maximum(lam, 0.0))
+        r = int(np.count_nonzero(s > tau))
+        U = W[:, :r]
+        V = (Ys.T @ U) / s[:r] if r > 0 else np.zeros((n, 0))
+    return U, s[:r], V, s
+
+
+def svt_sparse(m: int, n: int, rows, cols, vals, tau: float, delta: float,
+               eps: float, maxiter: int, incr: int, kick: bool = True,
+               progress=None):
+    """Algorithm 1 (Section 5.1.5), tier B: sparse Y, triplets from the Gram
+    matrix (``gram_triplets``); otherwise the same steps as ``svt_dense``.
+    ||P_Omega M||_2 for the kick is the largest singular value from the same
+    route."""
+    import scipy.sparse as sp
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    vals = np.asarray(vals, dtype=np.float64)
+    norm_pm = _fro(vals)
+    cap = min(m, n)
+    # CSR pattern fixed; the iterate's values follow Omega's input order
+    order = np.lexsort((cols, rows))
+    rs, cs = rows[order], cols[order]
+
+    def as_sparse(y):
+        return sp.csr_matrix((y[order], (rs, cs)), shape=(m, n))
+
+    sigma1 = None
+    y = np.zeros(vals.shape[0])
+    k0 = 0
+    if kick:
+        sigma1 = float(gram_triplets(as_sparse(vals), 0.0)[3][0])
+        k0 = k0_kick(tau, delta, sigma1)
+        y = k0 * delta * vals
+    ranks, s_hist, res_hist = [], [], []
+    r_prev = 0
+    status = "not_converged"
+    Uw = np.zeros((m, 0)); Vr = np.zeros((n, 0)); w = np.zeros(0)
+    k = 0
+    for k in range(1, maxiter + 1):
+        U, sr, V, s = gram_triplets(as_sparse(y), tau)
+        s_k = min(r_prev + 1, cap)
+        while s[s_k - 1] > tau and s_k < cap:
+            s_k = min(s_k + incr, cap)
+        r_k = sr.shape[0]
+        w = sr - tau
+        Uw = U * w
+        Vr = V
+        e = vals - sampled_entries(Uw, Vr, rows, cols)
+        res = _fro(e) / norm_pm
+        ranks.append(r_k)
+        s_hist.append(s_k)
+        res_hist.append(res)
+        if progress:
+            progress(k, r_k, res)
+        if res <= eps:
+            status = "ok"
+            break
+        y = y + delta * e
+        r_prev = r_k
+    return dict(iters=k, k0=k0, sigma1=sigma1, ranks=ranks, s_hist=s_hist,
+                residuals=res_hist, U=Uw, w=w, V=Vr, status=status, norm_pm=norm_pm)
