@@ -129,36 +129,50 @@ def copy_calibration(mib: int, reps: int = 3):
 
 
 def serving_bench(n_req: int, slots: int, budget_gib: float, precision: int, seed: int = 0,
-                  load_frac: float = 0.7):
-    """Serving form on the mixed-request stream: m, n uniform in [500, 8000],
-    r in {5, 10, 20, 50}, |Omega| = c r (m + n - r) with c uniform in [3, 6],
-    tau = 5 sqrt(m n), delta = 1.2 m n / |Omega|, eps = 1e-4, noise off.
+                  load_frac: float = 0.7, mix: str = "baseline", step_cap: int = 256):
+    """Serving form on a stream of mixed completion requests.
+
+    mix "baseline": m, n uniform in [500, 8000] (rectangular), r in
+    {5, 10, 20, 50}, |Omega| = c r (m + n - r) with c uniform in [3, 6].
+    mix "table1": m, n uniform in [1000, 8000] (aspect ratio at most 1.5),
+    (r, c) drawn from Table 1's pairs (10, 6), (50, 5), (100, 4).
+    Both: tau = 5 sqrt(m n), delta = 1.2 m n / |Omega|, eps = 1e-4, maxiter
+    500, noise off; each request's bidiagonalisation is capped at step_cap
+    steps (a request that needs more ends with SVT_ELANCZOS), so a request
+    outside the method's regime holds its slot for a bounded time.
     Closed loop (all requests at t = 0) gives the capacity C in solves/s; an
     open loop with Poisson arrivals at load_frac * C gives the latency
     (arrival to completion) percentiles."""
     import threading
     import workload
     from paper_0810_3286_amd import svt as B
-    trace = workload.serving_trace(2 * n_req, seed=seed, rate=1.0)
+    if mix == "table1":
+        trace = workload.serving_trace(2 * n_req, seed=seed, rate=1.0, mn_range=(1000, 8000),
+                                       pairs=workload.TABLE1_RANK_OVERSAMPLING, max_aspect=1.5)
+    else:
+        trace = workload.serving_trace(2 * n_req, seed=seed, rate=1.0)
     probs = []
     for _, sp in trace:
         probs.append(workload.gaussian_lowrank(sp["m"], sp["n"], sp["r"], sp["nnz"], sp["seed"],
                                                noise_sigma=sp["noise_sigma"], maxiter=500))
+        log(f"[bench] serving request {len(probs) - 1} generated ({sp['m']} x {sp['n']}, r {sp['r']}, "
+            f"|Omega| {sp['nnz']})")
 
     def params(p):
         prm = B.svt_params_default(p.m, p.n, p.nnz)
         prm.tau, prm.delta, prm.eps, prm.maxiter, prm.incr = p.tau, p.delta, p.eps, p.maxiter, p.incr
         prm.precision = precision
+        prm.lanczos_maxsteps = step_cap
         return prm
 
     budget = int(budget_gib * (1 << 30))
     srv = B.svt_server_create(budget, slots)
+    statuses = []
     try:
         closed = probs[:n_req]
         t0 = time.perf_counter()
         tickets = [B.svt_submit(srv, p.m, p.n, p.rows, p.cols, p.vals, params(p)) for p in closed]
         iters = 0
-        statuses = []
         for i, t in enumerate(tickets):
             st, info = B.svt_wait(srv, t)
             iters += info.iters
@@ -193,6 +207,7 @@ def serving_bench(n_req: int, slots: int, budget_gib: float, precision: int, see
             st, info = B.svt_wait(srv, tix[i])
             _, _, _, _, times = B.svt_result(srv, tix[i], p.m, p.n)
             lat.append(times[2] - times[0])
+            statuses.append(st)
             B.svt_release(srv, tix[i])
             log(f"[bench] serving open loop: request {i} done (status {st}, latency {lat[-1]:.2f} s)")
         t_open = time.perf_counter() - t1
@@ -205,7 +220,9 @@ def serving_bench(n_req: int, slots: int, budget_gib: float, precision: int, see
         "precision": "mixed" if precision == B.SVT_MIXED else "fp64",
         "closed_loop_solves_per_s": capacity,
         "closed_loop_svt_iters_per_s": iters / t_closed,
-        "closed_loop_ok": int(sum(1 for s_ in statuses if s_ == B.SVT_OK)),
+        "mix": mix, "step_cap": step_cap,
+        "status_counts": {B.svt_status_string(k): int(v) for k, v in
+                          zip(*np.unique(np.array(statuses), return_counts=True))},
         "open_loop_rate_per_s": rate, "open_loop_solves_per_s": n_req / t_open,
         "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
         "max_running": stats["max_running"], "peak_admitted_gib": stats["peak_bytes"] / (1 << 30),
@@ -224,9 +241,11 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=1)
     ap.add_argument("--spmv-mode", type=int, default=0,
                     help="0: x in LDS when it fits in one segment, 1: gathered, 2: LDS segments")
-    ap.add_argument("--serving-requests", type=int, default=32)
+    ap.add_argument("--serving-requests", type=int, default=16)
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-mix", choices=["baseline", "table1"], default="baseline")
+    ap.add_argument("--serving-step-cap", type=int, default=256)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration)")
@@ -366,7 +385,8 @@ def main():
     if not args.no_serving:
         log("[bench] serving stream")
         out["serving"] = serving_bench(args.serving_requests, args.serving_slots, 64.0,
-                                       B.SVT_MIXED if args.precision == "mixed" else B.SVT_FP64)
+                                       B.SVT_MIXED if args.precision == "mixed" else B.SVT_FP64,
+                                       mix=args.serving_mix, step_cap=args.serving_step_cap)
         out["solves_per_s"] = out["serving"]["closed_loop_solves_per_s"]
         out["p99_latency_s"] = out["serving"]["p99_latency_s"]
     if not args.no_cpu_baseline:

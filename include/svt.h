@@ -128,7 +128,9 @@ svt_status svt_create(int64_t m, int64_t n, int64_t nnz, int32_t fmt,
 
 /* Run Algorithm 1 from the kick (each call starts over).  Returns SVT_OK,
    SVT_NOT_CONVERGED (maxiter reached; the factors hold X^{maxiter}), or an
-   error.  info may be NULL. */
+   error; after an error raised inside the iteration (e.g. SVT_ELANCZOS when
+   the bidiagonalisation reaches lanczos_maxsteps) info still reports the
+   iterations completed and their last residual.  info may be NULL. */
 svt_status svt_solve(svt_problem *h, svt_info *info);
 
 /* Per-iteration record of the last solve, k = 1..len: rank r_k, the number
@@ -215,7 +217,8 @@ svt_status svt_kernel_stats(const svt_problem *h, int32_t kind, int64_t *launche
 typedef struct svt_server svt_server;
 
 /* Predicted device bytes of a problem (index structures, values, iterate,
-   bidiagonalisation bases for up to 128 steps, factors, scratch). */
+   bidiagonalisation bases for up to 256 steps, factors, scratch).  A
+   request submitted with lanczos_maxsteps > 0 is admitted on its own cap. */
 svt_status svt_footprint(int64_t m, int64_t n, int64_t nnz, int32_t precision, size_t *bytes);
 
 /* hbm_budget_bytes > 0: device memory the admitted solves may hold at once;

@@ -143,22 +143,35 @@ struct svt_server {
   }
 };
 
-extern "C" {
+namespace {
 
-svt_status svt_footprint(int64_t m, int64_t n, int64_t nnz, int32_t precision, size_t *bytes) {
-  if (!bytes || m < 1 || n < 1 || nnz < 1) return SVT_EINVAL;
+// Device bytes of one solve whose bidiagonalisation runs at most kmax steps.
+size_t footprint_bytes(int64_t m, int64_t n, int64_t nnz, int32_t precision, double kmax) {
   const double vb = precision == SVT_MIXED ? 4.0 : 8.0;
   const double big = (double)std::max(m, n), small = (double)std::min(m, n);
-  const double kcap = std::min(small, 128.0);
+  const double kcap = std::min(small, kmax);
   double b = 0.0;
   b += 4.0 * (3.0 * (double)nnz + (double)(m + n + 2));   // colidx, rowidx, csc_of_csr, rowptr, colptr
   b += 4.0 * vb * (double)nnz;                            // M and Y, both orders
   b += vb * (big * (kcap + 1) + small * (kcap + 2));      // Lanczos bases
   b += vb * (big + small);                                // working vectors
-  b += vb * (double)(m + n) * 2.0 * 64.0;                 // factors (rank up to 64, padded)
+  b += vb * (double)(m + n) * 130.0;                      // factors (rank up to 128, padded)
   b += 8.0 * (kcap + 4) * (32 + 256 + 8) + 16.0 * 1024;   // reduction partials
   b += 8.0 * (double)(m + n + 2) * 3.0;                   // LDS plan segment starts (worst case)
-  *bytes = (size_t)(b * 1.05) + (1u << 20);               // margin for allocation granularity
+  return (size_t)(b * 1.05) + (1u << 20);                 // margin for allocation granularity
+}
+
+// Without a step cap in the parameters, admission assumes 256 steps: about
+// 3.5 steps per singular value above tau are typical, so ranks up to ~70.
+constexpr double kDefaultStepCap = 256.0;
+
+}  // namespace
+
+extern "C" {
+
+svt_status svt_footprint(int64_t m, int64_t n, int64_t nnz, int32_t precision, size_t *bytes) {
+  if (!bytes || m < 1 || n < 1 || nnz < 1) return SVT_EINVAL;
+  *bytes = footprint_bytes(m, n, nnz, precision, kDefaultStepCap);
   return SVT_OK;
 }
 
@@ -188,7 +201,8 @@ svt_status svt_submit(svt_server *s, int64_t m, int64_t n, int64_t nnz, const in
   r->m = m; r->n = n; r->nnz = nnz;
   if (params) r->prm = *params;
   else svt_params_default(m, n, nnz, &r->prm);
-  if (svt_footprint(m, n, nnz, r->prm.precision, &r->footprint) != SVT_OK) return SVT_EINVAL;
+  r->footprint = footprint_bytes(m, n, nnz, r->prm.precision,
+                                 r->prm.lanczos_maxsteps > 0 ? (double)r->prm.lanczos_maxsteps : kDefaultStepCap);
   r->rows.assign(rows, rows + nnz);
   r->cols.assign(cols, cols + nnz);
   r->vals.assign(vals, vals + nnz);

@@ -728,59 +728,70 @@ struct Problem final : ProblemBase {
     inf.norm_pm = norm_pm;
     inf.t_setup_s = t_setup;
     const double t0 = now_s();
-    double s1 = 0.0;
-    int32_t k0 = 0;
-    HIP_CHECK(hipMemsetAsync(Yr.p, 0, sizeof(T) * ix.nnz, stream));
-    HIP_CHECK(hipMemsetAsync(Yc.p, 0, sizeof(T) * ix.nnz, stream));
-    if (prm.kick) do_kick(&s1, &k0);
-    HIP_CHECK(hipStreamSynchronize(stream));
-    const double t1 = now_s();
-    inf.t_kick_s = t1 - t0;
-    inf.sigma1 = s1;
-    inf.k0 = k0;
-
+    double t1 = t0;
     const T *yr = a_is_y ? Yr.as<T>() : Yc.as<T>();
     const T *yc = a_is_y ? Yc.as<T>() : Yr.as<T>();
     int r_prev = 0;
     svt_status st = SVT_NOT_CONVERGED;
     int k = 0;
     double res = 1.0;
-    for (k = 1; k <= prm.maxiter; ++k) {
-      Gkl g;
-      BidiagSVD sv;
-      int r = 0;
-      const int steps = gkl_run(yr, yc, 0, 0, prm.tau, g, sv, r);
-      k_hint = steps;
-      // s_k bookkeeping of Algorithm 1's repeat loop (Section 5.1.1)
-      int s = std::min<int64_t>(r_prev + 1, acols);
-      while (s <= r && s < acols) s = (int)std::min<int64_t>(s + prm.incr, acols);
-      std::vector<double> ws(std::max(r, 1));
-      for (int i = 0; i < r; ++i) ws[i] = sv.sigma[i] - prm.tau;
-      form_factors(g, sv, r, ws.data());
-      w.assign(ws.begin(), ws.begin() + r);
-      const double res2 = sample_pass(r, prm.delta, true);
-      res = std::sqrt(res2) / norm_pm;
-      history.push_back({r, s, steps, res});
-      if (!std::isfinite(res)) { st = SVT_EDIVERGED; break; }
-      bool stop;
-      if (prm.stop_rule == SVT_STOP_NOISY)
-        stop = res2 <= (1.0 + prm.eps) * (double)ix.nnz * prm.noise_sigma * prm.noise_sigma;
-      else
-        stop = res <= prm.eps;
-      if (stop) { st = SVT_OK; break; }
-      r_prev = r;
+    // an error in the kick or the loop still reports the iterations completed
+    auto report = [&](int iters, svt_status status) {
+      inf.t_solve_s = now_s() - t1;
+      inf.iters = iters;
+      inf.rank = rank;
+      inf.rel_residual = res;
+      inf.status = status;
+      inf.gkl_steps = steps_total;
+      if (info) *info = inf;
+    };
+    try {
+      double s1 = 0.0;
+      int32_t k0 = 0;
+      HIP_CHECK(hipMemsetAsync(Yr.p, 0, sizeof(T) * ix.nnz, stream));
+      HIP_CHECK(hipMemsetAsync(Yc.p, 0, sizeof(T) * ix.nnz, stream));
+      if (prm.kick) do_kick(&s1, &k0);
+      HIP_CHECK(hipStreamSynchronize(stream));
+      t1 = now_s();
+      inf.t_kick_s = t1 - t0;
+      inf.sigma1 = s1;
+      inf.k0 = k0;
+
+      for (k = 1; k <= prm.maxiter; ++k) {
+        Gkl g;
+        BidiagSVD sv;
+        int r = 0;
+        const int steps = gkl_run(yr, yc, 0, 0, prm.tau, g, sv, r);
+        k_hint = steps;
+        // s_k bookkeeping of Algorithm 1's repeat loop (Section 5.1.1)
+        int s = std::min<int64_t>(r_prev + 1, acols);
+        while (s <= r && s < acols) s = (int)std::min<int64_t>(s + prm.incr, acols);
+        std::vector<double> ws(std::max(r, 1));
+        for (int i = 0; i < r; ++i) ws[i] = sv.sigma[i] - prm.tau;
+        form_factors(g, sv, r, ws.data());
+        w.assign(ws.begin(), ws.begin() + r);
+        const double res2 = sample_pass(r, prm.delta, true);
+        res = std::sqrt(res2) / norm_pm;
+        history.push_back({r, s, steps, res});
+        if (log_level > 0)
+          std::fprintf(stderr, "[svt] iter %d rank %d steps %d res %.3e t %.3f s\n", k, r, steps, res, now_s() - t1);
+        if (!std::isfinite(res)) { st = SVT_EDIVERGED; break; }
+        bool stop;
+        if (prm.stop_rule == SVT_STOP_NOISY)
+          stop = res2 <= (1.0 + prm.eps) * (double)ix.nnz * prm.noise_sigma * prm.noise_sigma;
+        else
+          stop = res <= prm.eps;
+        if (stop) { st = SVT_OK; break; }
+        r_prev = r;
+      }
+    } catch (const Error &e) {
+      report((int)history.size(), e.code);
+      throw;
     }
     if (k > prm.maxiter) k = prm.maxiter;
     HIP_CHECK(hipStreamSynchronize(stream));
-    const double t2 = now_s();
     prof.flush();
-    inf.t_solve_s = t2 - t1;
-    inf.iters = k;
-    inf.rank = rank;
-    inf.rel_residual = res;
-    inf.status = st;
-    inf.gkl_steps = steps_total;
-    if (info) *info = inf;
+    report(k, st);
     return st;
   }
 

@@ -81,6 +81,7 @@ class SvtError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{message} (status {status})")
         self.status = status
+        self.info = None
 
 
 _lib = None
@@ -202,9 +203,15 @@ def svt_destroy(h) -> None:
 
 
 def svt_solve(h):
+    """Returns (status, info) for SVT_OK / SVT_NOT_CONVERGED; raises SvtError
+    otherwise, with the info of the iterations completed as ``.info``."""
     info = svt_info()
     st = load().svt_solve(h, ctypes.byref(info))
-    _check(st, h, allow=(SVT_OK, SVT_NOT_CONVERGED))
+    try:
+        _check(st, h, allow=(SVT_OK, SVT_NOT_CONVERGED))
+    except SvtError as e:
+        e.info = info
+        raise
     return st, info
 
 
@@ -340,9 +347,10 @@ def svt_result(server, ticket: int, m: int, n: int):
     lib = load()
     r = ctypes.c_int32()
     st = lib.svt_result(server, ticket, ctypes.byref(r), None, None, None, None)
-    if st not in (SVT_OK, SVT_NOT_CONVERGED):
+    if st == SVT_EINVAL or st == SVT_EBUSY:
         raise SvtError(st, svt_status_string(st))
-    r = r.value
+    # a failed solve still carries its timestamps (and rank 0)
+    r = r.value if st in (SVT_OK, SVT_NOT_CONVERGED) else 0
     U = np.zeros((m, r))
     V = np.zeros((n, r))
     w = np.zeros(r)

@@ -316,3 +316,23 @@ def test_mixed_hard_request_stays_finite():
               maxiter=60, incr=p.incr, precision=B.SVT_MIXED)
     assert g["status"] == B.SVT_NOT_CONVERGED
     assert np.all(np.isfinite(g["residuals"])) and max(g["gkl_steps"]) > 64
+
+
+def test_step_cap_error_reports_progress():
+    # the hard request needs more than 64 bidiagonalisation steps after a
+    # few iterations: with the cap at 64 the solve fails with SVT_ELANCZOS,
+    # and the info still reports the iterations completed before it
+    gpu_case("step cap 64 on the 700x500 hard request")
+    p = workload.gaussian_lowrank(700, 500, 5, 30000, 11, shuffle=True)
+    h = _create(p, maxiter=60, precision=B.SVT_MIXED, lanczos_maxsteps=64)
+    try:
+        with pytest.raises(B.SvtError) as ei:
+            B.svt_solve(h)
+        hist = B.svt_history(h)
+    finally:
+        B.svt_destroy(h)
+    e = ei.value
+    assert e.status == B.SVT_ELANCZOS and e.info is not None
+    assert e.info.status == B.SVT_ELANCZOS
+    assert e.info.iters == len(hist["ranks"]) >= 1
+    assert np.all(np.isfinite(hist["residuals"])) and max(hist["gkl_steps"]) <= 64

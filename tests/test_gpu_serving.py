@@ -104,3 +104,28 @@ def test_mix_member_matches_oracle():
             assert rel_diff_factored(U, V, o["U"], o["V"]) <= 1e-8
     finally:
         B.svt_server_destroy(srv)
+
+
+def test_failing_request_frees_its_slot():
+    # a request that hits its step cap ends with SVT_ELANCZOS and rank 0;
+    # the request queued behind it on the single slot still completes
+    gpu_case("serving: failing request then a normal one, one slot")
+    hard = workload.gaussian_lowrank(700, 500, 5, 30000, 11, shuffle=True)
+    easy = workload.gaussian_lowrank(*REQS[0], shuffle=True)
+    prm_h = _prm(hard, B.SVT_MIXED)
+    prm_h.maxiter, prm_h.lanczos_maxsteps = 60, 64
+    srv = B.svt_server_create(64 << 30, 1)
+    try:
+        t1 = B.svt_submit(srv, hard.m, hard.n, hard.rows, hard.cols, hard.vals, prm_h)
+        t2 = B.svt_submit(srv, easy.m, easy.n, easy.rows, easy.cols, easy.vals, _prm(easy, B.SVT_MIXED))
+        st1, info1 = B.svt_wait(srv, t1)
+        st1b, U, w, V, times1 = B.svt_result(srv, t1, hard.m, hard.n)
+        st2, info2 = B.svt_wait(srv, t2)
+        _, _, _, _, times2 = B.svt_result(srv, t2, easy.m, easy.n)
+        B.svt_release(srv, t1)
+        B.svt_release(srv, t2)
+    finally:
+        B.svt_server_destroy(srv)
+    assert st1 == st1b == B.SVT_ELANCZOS and info1.iters >= 1 and U.shape == (hard.m, 0)
+    assert st2 == B.SVT_OK
+    assert times1[0] <= times1[1] <= times1[2] <= times2[1] <= times2[2]

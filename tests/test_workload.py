@@ -67,6 +67,16 @@ def test_serving_trace_respects_fill_cap():
         assert s["r"] in (5, 10, 20, 50)
         assert s["nnz"] <= 0.6 * s["m"] * s["n"]
         assert 3 * s["r"] * (s["m"] + s["n"] - s["r"]) <= s["nnz"] + 1
+        assert s["nnz"] <= 6 * s["r"] * (s["m"] + s["n"] - s["r"])
+
+
+def test_serving_trace_table1_pairs():
+    trace = workload.serving_trace(100, seed=2, mn_range=(1000, 8000),
+                                   pairs=workload.TABLE1_RANK_OVERSAMPLING, max_aspect=1.5)
+    for _, s in trace:
+        c = {10: 6, 50: 5, 100: 4}[s["r"]]
+        assert s["nnz"] == int(c * s["r"] * (s["m"] + s["n"] - s["r"]))
+        assert max(s["m"], s["n"]) <= 1.5 * min(s["m"], s["n"])
 
 
 def test_stored_oracle_result_matches_current_generator():

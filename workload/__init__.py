@@ -32,6 +32,7 @@ __all__ = [
     "config",
     "CONFIGS",
     "serving_trace",
+    "TABLE1_RANK_OVERSAMPLING",
     "full_observation",
     "dense_random_iterate",
 ]
@@ -180,19 +181,31 @@ def dense_random_iterate(prob: Problem, seed: int = 1) -> np.ndarray:
     return rng.standard_normal(prob.nnz)
 
 
+# (rank, |Omega| / d_r) pairs of the paper's Table 1 at n >= 5000
+TABLE1_RANK_OVERSAMPLING = ((10, 6.0), (50, 5.0), (100, 4.0))
+
+
 def serving_trace(count: int, seed: int = 0, *, mn_range=(500, 8000),
-                  ranks=(5, 10, 20, 50), c_range=(3.0, 6.0), rate: float = 1.0,
-                  noise_frac: float = 0.0, noise_sigma: float = 0.01,
-                  max_fill: float = 0.6):
+                  ranks=(5, 10, 20, 50), c_range=(3.0, 6.0), pairs=None,
+                  rate: float = 1.0, noise_frac: float = 0.0, noise_sigma: float = 0.01,
+                  max_fill: float = 0.6, max_aspect=None):
     """Poisson stream of mixed completion requests.
 
-    Each request draws m, n uniform integers in ``mn_range``, r from ``ranks``,
-    c uniform in ``c_range`` and |Omega| = floor(c r (m + n - r)); a request
-    whose |Omega| would exceed ``max_fill`` * m n is drawn again.  tau =
-    5 sqrt(m n), delta = 1.2 m n / |Omega|, eps = 1e-4.  Arrival gaps are
-    exponential with mean 1/rate seconds.  Returns a list of
-    (arrival_time_s, spec) where spec is a dict of problem parameters and a
-    per-request seed; ``gaussian_lowrank(**spec)`` materialises it.
+    Each request draws m, n uniform integers in ``mn_range``; r from
+    ``ranks`` and c uniform in ``c_range`` (or, with ``pairs`` given, a
+    (r, c) pair from it, e.g. TABLE1_RANK_OVERSAMPLING); and |Omega| =
+    floor(c r (m + n - r)).  A request whose |Omega| would exceed
+    ``max_fill`` * m n, or whose aspect ratio max(m, n) / min(m, n) exceeds
+    ``max_aspect`` (when given), is drawn again.  tau = 5 sqrt(m n), delta =
+    1.2 m n / |Omega|, eps = 1e-4.  Arrival gaps are exponential with mean
+    1/rate seconds.  Returns a list of (arrival_time_s, spec) where spec is a
+    dict of problem parameters and a per-request seed;
+    ``gaussian_lowrank(**spec)`` materialises it.
+
+    With the default ranges some requests fall outside the regime of Table 1
+    (c near 3 at a sampling density of a few percent, or c near 5 at rank 5
+    or 10): with delta = 1.2 / p Algorithm 1 then oscillates or stalls on
+    them, which a server has to bound.
     """
     rng = np.random.default_rng(seed)
     t = 0.0
@@ -201,14 +214,20 @@ def serving_trace(count: int, seed: int = 0, *, mn_range=(500, 8000),
         while True:
             m = int(rng.integers(mn_range[0], mn_range[1] + 1))
             n = int(rng.integers(mn_range[0], mn_range[1] + 1))
-            r = int(ranks[int(rng.integers(0, len(ranks)))])
-            c = float(rng.uniform(c_range[0], c_range[1]))
+            if pairs is None:
+                r = int(ranks[int(rng.integers(0, len(ranks)))])
+                c = float(rng.uniform(c_range[0], c_range[1]))
+            else:
+                r, c = pairs[int(rng.integers(0, len(pairs)))]
             nnz = int(math.floor(c * degrees_of_freedom(m, n, r)))
-            if nnz <= max_fill * m * n:
-                break
+            if nnz > max_fill * m * n:
+                continue
+            if max_aspect is not None and max(m, n) > max_aspect * min(m, n):
+                continue
+            break
         noisy = bool(rng.uniform() < noise_frac)
         t += float(rng.exponential(1.0 / rate)) if rate > 0 else 0.0
-        spec = dict(m=m, n=n, r=r, nnz=nnz, seed=int(seed * 1000003 + i),
+        spec = dict(m=m, n=n, r=int(r), nnz=nnz, seed=int(seed * 1000003 + i),
                     noise_sigma=noise_sigma if noisy else 0.0,
                     name=f"req{i}")
         out.append((t, spec))
