@@ -29,12 +29,26 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 from paper_0810_3286_amd.svt import KERNEL_KINDS as KIND_NAMES  # noqa: E402
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_0810_3286_amd", "csrc", "svt_kernels.hip")
+# the kernels and the launch configurations the solver picks for them
+KERNEL_SRCS = [os.path.join(ROOT, "paper_0810_3286_amd", "csrc", f)
+               for f in ("svt_kernels.hip", "svt_kernels.h", "svt_solver.cpp")]
+# rocprofv3 kernel names of each timed kind (substring matches)
+ROCPROF_NAMES = {
+    "k_spmv": ("k_spmv",),
+    "k_gs_dots": ("k_gs_dots",),
+    "k_gs_update_pass1": ("k_gs_update<float, false>", "k_gs_update<double, false>"),
+    "k_ritz": ("k_ritz",),
+    "k_sample_update": ("k_sample_update",),
+    "k_gs_update_pass2": ("k_gs_update<float, true>", "k_gs_update<double, true>"),
+}
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def log(msg):
@@ -58,44 +72,51 @@ def measured_traffic(kernel: str, workload: str, precision: str):
 
 
 def cpu_baseline(p, seconds: float):
-    """The oracle's one-sided Jacobi on a slab of the kick iterate, scaled.
+    """The oracle's SVT iteration at this size, timed on column slabs.
 
-    Algorithm 1 in the oracle takes a full Jacobi SVD of the dense m x n
-    iterate each iteration: n(n-1)/2 column pairs per sweep.  The sample
-    times the oracle on the first c columns of Y^{k0} (m x c, the same row
-    length), growing c until the run takes about `seconds`; the per-pair cost
-    and sweeps per SVD then give the oracle's time per SVT iteration at full
-    size (sweeps per SVD taken from the sample itself).
+    At n >= 5000 the oracle takes the singular triplets of each iterate from
+    the Gram matrix (tier B: a sparse product Y^T Y, then LAPACK's symmetric
+    eigensolver, multithreaded BLAS).  Its cost per iteration is a c^2 term
+    (the Gram product and the dense matrix) plus a c^3 term (the
+    eigensolver) in the number c of columns.  The sample runs the oracle's
+    ``gram_triplets`` as it stands on the first c and 2c columns of
+    P_Omega(M) (c doubled until the 2c run takes about seconds / 2), fits
+    t(c) = a c^2 + b c^3 through the two timings, and evaluates it at n;
+    the sampled-entry residual and update (O(|Omega| r)) are left out.
     """
-    import oracle.svt as osvt
-    threads = 1  # the oracle's Jacobi is single-threaded C
+    import scipy.sparse as sp
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i["num_threads"] for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:  # noqa: BLE001
+        threads = int(os.environ.get("OMP_NUM_THREADS", "1"))
     m, n = p.m, p.n
-    # kick iterate columns: Y^{k0} = k0 delta P_Omega(M); k0 from the GPU-free
-    # definition needs sigma_1 of P_Omega M, which is not needed for timing:
-    # the Jacobi cost does not depend on the scale, so take P_Omega(M) itself.
     order = np.argsort(p.cols, kind="stable")
     cols_sorted = p.cols[order]
-    c = 16
-    elapsed = 0.0
-    sweeps = 0
-    while True:
+
+    def run(c):
         hi = np.searchsorted(cols_sorted, c)
         sel = order[:hi]
-        A = np.zeros((m, c), order="F")
-        A[p.rows[sel], p.cols[sel]] = p.vals[sel]
-        V = np.zeros((c, c), order="F")
-        s = np.zeros(c)
+        Ys = sp.csr_matrix((p.vals[sel], (p.rows[sel], p.cols[sel])), shape=(m, c))
         t0 = time.perf_counter()
-        sw = osvt._load().oracle_jacobi_svd(m, c, osvt._ptr(A), osvt._ptr(V), osvt._ptr(s),
-                                            osvt.JACOBI_TOL, osvt.JACOBI_MAX_SWEEPS)
-        elapsed = time.perf_counter() - t0
-        sweeps = max(sw, 1)
-        if elapsed >= seconds / 4 or c >= n:
+        oracle.gram_triplets(Ys, p.tau)
+        return time.perf_counter() - t0
+
+    c = 256
+    while True:
+        t1 = run(c)
+        t2 = run(2 * c)
+        log(f"[bench] cpu baseline: gram_triplets on {c} and {2 * c} columns: {t1:.2f} s, {t2:.2f} s")
+        if t2 >= seconds / 2 or 4 * c > n:
             break
-        c = min(n, c * 2)
-    pairs_sample = c * (c - 1) / 2 * sweeps
-    per_pair = elapsed / pairs_sample
-    per_iter = per_pair * (n * (n - 1) / 2) * sweeps
+        c *= 2
+    # t = a c^2 + b c^3 through (c, t1) and (2c, t2)
+    b = (t2 - 4.0 * t1) / (4.0 * c ** 3)
+    a = (t1 - b * c ** 3) / c ** 2
+    if a < 0 or b < 0:  # timing noise: scale the larger run by the cube alone
+        a, b = 0.0, t2 / (2 * c) ** 3
+    per_iter = a * n ** 2 + b * n ** 3
     iters_per_s = 1.0 / per_iter
     return {
         "value": iters_per_s,
@@ -103,10 +124,88 @@ def cpu_baseline(p, seconds: float):
         "sampled_entries_per_s": iters_per_s * p.nnz,
         "cores": threads,
         "kind": "oracle",
-        "sample": (f"one-sided Jacobi (the oracle's full SVD) on a {m} x {c} column slab of "
-                   f"P_Omega(M): {elapsed:.2f} s, {sweeps} sweeps; scaled by column pairs to the "
-                   f"{m} x {n} iterate, {sweeps} sweeps per SVT iteration"),
+        "sample": (f"the oracle's tier-B triplets (sparse Gram product + LAPACK eigh) on the first {c} and "
+                   f"{2 * c} columns of P_Omega(M) ({m} rows): {t1:.2f} s and {t2:.2f} s; "
+                   f"t(c) = a c^2 + b c^3 fitted through both and evaluated at c = {n}: "
+                   f"{per_iter:.0f} s per SVT iteration"),
     }
+
+
+def _pmc_per_kernel(run_dir: str, counter: str):
+    """Mean counter value (KiB) per dispatch of each kernel name in a
+    rocprofv3 --pmc CSV run directory."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {run_dir}")
+    tot, cnt = {}, {}
+    for f in files:
+        for row in csv.DictReader(open(f)):
+            if row["Counter_Name"] != counter:
+                continue
+            k = row["Kernel_Name"]
+            tot[k] = tot.get(k, 0.0) + float(row["Counter_Value"])
+            cnt[k] = cnt.get(k, 0) + 1
+    return {k: (tot[k] / cnt[k], cnt[k]) for k in tot}
+
+
+def traffic_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_mib, workload, precision,
+                    algorithmic):
+    """HBM bytes per launch of each timed kernel from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE), each scaled by what the same counter reads for
+    the runtime's copy kernel moving copy_mib MiB; writes the committed
+    traffic file and prints a text summary."""
+    nbytes = float(copy_mib << 20)
+    cf = _pmc_per_kernel(copy_fetch_dir, "FETCH_SIZE")
+    cw = _pmc_per_kernel(copy_write_dir, "WRITE_SIZE")
+
+    def copy_mean(d):
+        ent = [v for k, v in d.items() if "copyBuffer" in k]
+        if not ent:
+            raise SystemExit("no copy-kernel dispatch in the calibration run")
+        # the largest mean is the copy of the full buffer
+        return max(e[0] for e in ent)
+    f_fetch = nbytes / (copy_mean(cf) * 1024.0)
+    f_write = nbytes / (copy_mean(cw) * 1024.0)
+    fe = _pmc_per_kernel(fetch_dir, "FETCH_SIZE")
+    wr = _pmc_per_kernel(write_dir, "WRITE_SIZE")
+    out = {"kernel_source_sha256_16": kernel_source_hash(), "copy_mib": copy_mib,
+           "fetch_factor": f_fetch, "write_factor": f_write, "kernels": {}}
+    lines = [f"copy calibration ({copy_mib} MiB): FETCH_SIZE x {f_fetch:.3f}, WRITE_SIZE x {f_write:.3f}",
+             f"{'kernel':<20} {'dispatches':>10} {'fetch MB':>10} {'write MB':>10} {'HBM MB':>10} {'alg MB':>10}"]
+    for kind, pats in ROCPROF_NAMES.items():
+        def agg(d):
+            n_ = sum(v[1] for k, v in d.items() if any(pt in k for pt in pats))
+            s_ = sum(v[0] * v[1] for k, v in d.items() if any(pt in k for pt in pats))
+            return (s_ / n_ if n_ else 0.0), n_
+        fkib, nf = agg(fe)
+        wkib, nw = agg(wr)
+        if nf == 0:
+            continue
+        hbm = fkib * 1024.0 * f_fetch + wkib * 1024.0 * f_write
+        key = f"{workload}/{precision}/{kind}"
+        alg = algorithmic.get(kind)
+        out["kernels"][key] = {"dispatches": nf, "fetch_bytes_per_launch": fkib * 1024.0 * f_fetch,
+                               "write_bytes_per_launch": wkib * 1024.0 * f_write, "bytes_per_launch": hbm,
+                               "algorithmic_bytes_per_launch": alg}
+        lines.append(f"{kind:<20} {nf:>10d} {fkib * 1024 * f_fetch / 1e6:>10.3f} {wkib * 1024 * f_write / 1e6:>10.3f} "
+                     f"{hbm / 1e6:>10.3f} {(alg or 0) / 1e6:>10.3f}")
+    old = {}
+    if os.path.exists(TRAFFIC_FILE):
+        try:
+            old = json.load(open(TRAFFIC_FILE))
+        except ValueError:
+            old = {}
+    if old.get("kernel_source_sha256_16") == out["kernel_source_sha256_16"]:
+        merged = dict(old.get("kernels", {}))
+        merged.update(out["kernels"])
+        out["kernels"] = merged
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+        f.write("\n")
+    print("\n".join(lines))
 
 
 def copy_calibration(mib: int, reps: int = 3):
@@ -249,9 +348,23 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
+                                                         "COPY_WRITE_DIR"),
+                    help="write the HBM traffic file from rocprofv3 --pmc runs of this bench "
+                         "(FETCH_SIZE, WRITE_SIZE) and of --copy-calibration (same two counters); "
+                         "needs --traffic-mib and --traffic-bench-json")
+    ap.add_argument("--traffic-mib", type=int, default=256)
+    ap.add_argument("--traffic-bench-json", help="the JSON line of the counted bench run")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.traffic_summary:
+        line = open(args.traffic_bench_json).read().strip().splitlines()[-1]
+        bj = json.loads(line)
+        alg = {k: v.get("bytes_per_launch") for k, v in bj["kernels"].items()}
+        traffic_summary(*args.traffic_summary, args.traffic_mib, bj["config"]["workload"],
+                        bj["config"]["precision"], alg)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -352,6 +465,7 @@ def main():
         "gkl_steps_per_iter": float(np.mean(hist["gkl_steps"])) if len(hist["gkl_steps"]) else 0.0,
         "kernels": {KIND_NAMES[k]: {"launches": v[0], "ms": v[1],
                                     "avg_us": v[1] * 1e3 / max(v[0], 1),
+                                    "bytes_per_launch": v[2] / max(v[0], 1),
                                     "GBps": (v[2] / (v[1] / 1e3) / 1e9) if v[1] > 0 else 0.0}
                     for k, v in kstats.items()},
         "roofline": {"kernel": KIND_NAMES[dom], "bound": "hbm", "achieved": achieved,

@@ -193,13 +193,19 @@ svt_status svt_sample_update(svt_problem *h, int32_t r, const double *U,
    k0_override), returning sigma1 = ||P_Omega M||_2 and k0. */
 svt_status svt_kick(svt_problem *h, double *sigma1, int32_t *k0);
 
-/* Kernel timing of the last solve when params.profile = 1: for kernel class
-   `kind` (0 sparse product, 1 Gram-Schmidt orthonormalisation (dot
-   products, two updates, scaling), 3 Ritz vectors, 4 sampled update and
-   residual; 2 is unused), the number of launches, their summed duration in
-   milliseconds (HIP events on the solve's stream) and their summed
-   algorithmic bytes: the index, value and vector traffic each launch must
-   move at least once.  Any output pointer may be NULL. */
+/* Kernel timing of the last solve when params.profile = 1.  Each kind is
+   one kernel, and each timed bracket holds exactly one launch of it:
+     0 k_spmv / k_spmv_lds   sparse product of a bidiagonalisation half-step
+     1 k_gs_dots             first Gram-Schmidt pass, dot products
+     2 k_gs_update<false>    first update + second pass's dot products
+     3 k_ritz                Ritz vectors (one launch per side)
+     4 k_sample_update       sampled product, residual and update (one
+                             launch per compressed orientation)
+     5 k_gs_update<true>     second update + |p|^2 partials
+   Outputs: the number of launches, their summed duration in milliseconds
+   (HIP events on the solve's stream) and their summed algorithmic bytes:
+   the index, value and vector traffic each launch must move at least once.
+   Any output pointer may be NULL; EINVAL for a kind outside 0..5. */
 svt_status svt_kernel_stats(const svt_problem *h, int32_t kind, int64_t *launches,
                             double *total_ms, double *total_bytes);
 

@@ -14,6 +14,12 @@
 
 namespace svt {
 
+// Kernel timing: the next kernel this thread launches through the wrappers
+// below records its own start and end in these events (hipExtLaunchKernel),
+// so their elapsed time is the kernel's duration without the gaps around
+// it; the launch clears them.  Null: no timing.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+
 constexpr int kBlock = 256;
 constexpr int kSpmvBlock = 1024;  // workgroup of the LDS-staged sparse product
 constexpr int kGsChunks1 = 32;    // row chunks of the first Gram-Schmidt dot products
@@ -72,6 +78,18 @@ hipError_t launch_spmv(hipStream_t s, int lanes, const SpmvLdsPlan *pl, const in
 template <typename T>
 hipError_t launch_orthonormalize(hipStream_t s, T *p, int nrows, const T *Q, int64_t ldq, int nq,
                                  const GsScratch &gs);
+
+// The three kernels of launch_orthonormalize (nq >= 1), for callers that
+// time them one by one: the first pass's dot products into gs.part1; then
+// the first update with the second pass's dot products into gs.part2
+// (second = false), or the second update with the |p|^2 partials into
+// gs.part3 (second = true).
+template <typename T>
+hipError_t launch_gs_dots(hipStream_t s, const T *p, int nrows, const T *Q, int64_t ldq, int nq,
+                          const GsScratch &gs);
+template <typename T>
+hipError_t launch_gs_update(hipStream_t s, T *p, int nrows, const T *Q, int64_t ldq, int nq,
+                            const GsScratch &gs, bool second);
 
 // |p|^2 partials into gs.part3.
 template <typename T>

@@ -17,6 +17,7 @@
 #include "svt_kernels.h"
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -24,6 +25,29 @@
 #include <mutex>
 
 namespace svt {
+
+namespace {
+
+// Events for the next launch of this thread (set_launch_events): the
+// runtime stamps them with the kernel's own start and end.
+thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+
+}  // namespace
+
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+  t_ev_start = start;
+  t_ev_stop = stop;
+}
+
+// Every launch goes through hipExtLaunchKernelGGL and takes (and clears) the
+// pending timing events, if any.
+#define SVT_LAUNCH(kern, grid, block, lds, stream, ...)                                     \
+  do {                                                                                      \
+    hipEvent_t ev_a_ = t_ev_start, ev_b_ = t_ev_stop;                                       \
+    t_ev_start = t_ev_stop = nullptr;                                                       \
+    hipExtLaunchKernelGGL(kern, grid, block, (std::uint32_t)(lds), stream, ev_a_, ev_b_, 0u, \
+                          __VA_ARGS__);                                                     \
+  } while (0)
 
 namespace {
 
@@ -583,7 +607,7 @@ hipError_t launch_spmv(hipStream_t s, int lanes, const SpmvLdsPlan *pl, const in
     auto kern = k_spmv_lds<T, LN>;                                                                \
     hipError_t ea = allow_dynamic_lds(reinterpret_cast<const void *>(kern), pl->lds);             \
     if (ea != hipSuccess) return ea;                                                              \
-    hipLaunchKernelGGL(kern, dim3(pl->nblk), dim3(kSpmvBlock), pl->lds, s, ptr, idx, val, segptr, \
+    SVT_LAUNCH(kern, dim3(pl->nblk), dim3(kSpmvBlock), pl->lds, s, ptr, idx, val, segptr, \
                        pl->nseg, pl->segcols, x, xpart, xnp, x_out, s_out, ncols, prev, p, nrows,  \
                        pl->rows_per_blk);                                                         \
   } while (0)
@@ -598,7 +622,7 @@ hipError_t launch_spmv(hipStream_t s, int lanes, const SpmvLdsPlan *pl, const in
     return hipGetLastError();
   }
 #define SVT_SPMV(LN)                                                                              \
-  hipLaunchKernelGGL((k_spmv<T, LN>), dim3((nrows + kBlock / LN - 1) / (kBlock / LN)), dim3(kBlock), 0, s, \
+  SVT_LAUNCH((k_spmv<T, LN>), dim3((nrows + kBlock / LN - 1) / (kBlock / LN)), dim3(kBlock), 0, s, \
                      ptr, idx, val, x, xpart, xnp, x_out, s_out, ncols, prev, p, nrows)
   switch (lanes) {
     case 4: SVT_SPMV(4); break;
@@ -630,7 +654,7 @@ SpmvLdsPlan spmv_lds_plan(int nrows, int ncols, int elem_bytes, int num_cus, int
 template <typename T>
 hipError_t launch_sumsq(hipStream_t s, T *p, int nrows, const GsScratch &gs) {
   const GsPlan g = gs_plan(nrows);
-  hipLaunchKernelGGL((k_gs_update<T, true>), dim3(g.nrc2), dim3(kBlock), gs_update_lds(0, g.rpb2), s, p, nrows,
+  SVT_LAUNCH((k_gs_update<T, true>), dim3(g.nrc2), dim3(kBlock), gs_update_lds(0, g.rpb2), s, p, nrows,
                      g.rpb2, (const T *)nullptr, (int64_t)0, 0, gs.part1, 1, gs.part3);
   return hipGetLastError();
 }
@@ -639,32 +663,52 @@ template <typename T>
 hipError_t launch_finalize(hipStream_t s, const T *p, int nrows, const GsScratch &gs, T *out,
                            double *coef_out) {
   const GsPlan g = gs_plan(nrows);
-  hipLaunchKernelGGL((k_gs_scale<T>), dim3(grid_for(nrows, 1024)), dim3(kBlock), 0, s, p, nrows, gs.part3, g.nrc2,
+  SVT_LAUNCH((k_gs_scale<T>), dim3(grid_for(nrows, 1024)), dim3(kBlock), 0, s, p, nrows, gs.part3, g.nrc2,
                      out, coef_out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gs_dots(hipStream_t s, const T *p, int nrows, const T *Q, int64_t ldq, int nq,
+                          const GsScratch &gs) {
+  const GsPlan g = gs_plan(nrows);
+  if (nq < 1 || g.nrc1 > kGsChunks1 || nq + 1 > gs.max_cols) return hipErrorInvalidValue;
+  const int ntiles = (nq + 1 + kTile - 1) / kTile;
+  SVT_LAUNCH((k_gs_dots<T>), dim3(g.nrc1, ntiles), dim3(kBlock), 0, s, p, nrows, g.rpb1, Q, ldq,
+                     nq, gs.part1);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gs_update(hipStream_t s, T *p, int nrows, const T *Q, int64_t ldq, int nq,
+                            const GsScratch &gs, bool second) {
+  const GsPlan g = gs_plan(nrows);
+  if (nq < 1 || g.nrc1 > kGsChunks1 || g.nrc2 > kGsChunks2 || nq + 1 > gs.max_cols) return hipErrorInvalidValue;
+  const size_t lds = gs_update_lds(nq, g.rpb2);
+  if (lds > 64 * 1024) return hipErrorInvalidValue;
+  if (!second)
+    SVT_LAUNCH((k_gs_update<T, false>), dim3(g.nrc2), dim3(kBlock), lds, s, p, nrows, g.rpb2, Q,
+                       ldq, nq, gs.part1, g.nrc1, gs.part2);
+  else
+    SVT_LAUNCH((k_gs_update<T, true>), dim3(g.nrc2), dim3(kBlock), lds, s, p, nrows, g.rpb2, Q,
+                       ldq, nq, gs.part2, g.nrc2, gs.part3);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_orthonormalize(hipStream_t s, T *p, int nrows, const T *Q, int64_t ldq, int nq,
                                  const GsScratch &gs) {
-  const GsPlan g = gs_plan(nrows);
-  if (g.nrc1 > kGsChunks1 || g.nrc2 > kGsChunks2 || nq + 1 > gs.max_cols) return hipErrorInvalidValue;
   if (nq == 0) return launch_sumsq<T>(s, p, nrows, gs);
-  const int ntiles = (nq + 1 + kTile - 1) / kTile;
-  hipLaunchKernelGGL((k_gs_dots<T>), dim3(g.nrc1, ntiles), dim3(kBlock), 0, s, p, nrows, g.rpb1, Q, ldq,
-                     nq, gs.part1);
-  const size_t lds = gs_update_lds(nq, g.rpb2);
-  if (lds > 64 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_gs_update<T, false>), dim3(g.nrc2), dim3(kBlock), lds, s, p, nrows, g.rpb2, Q,
-                     ldq, nq, gs.part1, g.nrc1, gs.part2);
-  hipLaunchKernelGGL((k_gs_update<T, true>), dim3(g.nrc2), dim3(kBlock), lds, s, p, nrows, g.rpb2, Q,
-                     ldq, nq, gs.part2, g.nrc2, gs.part3);
-  return hipGetLastError();
+  hipError_t e = launch_gs_dots<T>(s, p, nrows, Q, ldq, nq, gs);
+  if (e != hipSuccess) return e;
+  e = launch_gs_update<T>(s, p, nrows, Q, ldq, nq, gs, false);
+  if (e != hipSuccess) return e;
+  return launch_gs_update<T>(s, p, nrows, Q, ldq, nq, gs, true);
 }
 
 template <typename T>
 hipError_t launch_randn(hipStream_t s, T *out, int n, uint64_t seed, uint64_t ctr) {
-  hipLaunchKernelGGL((k_randn<T>), dim3(grid_for(n, 2048)), dim3(kBlock), 0, s, out, n, seed, ctr);
+  SVT_LAUNCH((k_randn<T>), dim3(grid_for(n, 2048)), dim3(kBlock), 0, s, out, n, seed, ctr);
   return hipGetLastError();
 }
 
@@ -673,7 +717,7 @@ hipError_t launch_ritz(hipStream_t s, const T *Q, int64_t ldq, int nrows, int k,
                        const double *w, int r, T *out, int rs) {
   if (rs < 1) return hipSuccess;
   dim3 grid((nrows + kBlock - 1) / kBlock, (rs + 3) / 4);
-  hipLaunchKernelGGL((k_ritz<T>), grid, dim3(kBlock), 0, s, Q, ldq, nrows, k, P, w, r, out, rs);
+  SVT_LAUNCH((k_ritz<T>), grid, dim3(kBlock), 0, s, Q, ldq, nrows, k, P, w, r, out, rs);
   return hipGetLastError();
 }
 
@@ -689,7 +733,7 @@ hipError_t launch_sample_update(hipStream_t s, int lanes, const int32_t *ptr, co
   const RowChunks ch =
       row_chunks(nrows, std::max((kBlock / lanes) * 4, (nrows + kSampleMaxBlocks - 1) / kSampleMaxBlocks));
 #define SVT_SU2(LN, RB)                                                                          \
-  hipLaunchKernelGGL((k_sample_update<T, LN, RB>), dim3(ch.nblk), dim3(kBlock), 0, s, ptr, idx, M, Y, \
+  SVT_LAUNCH((k_sample_update<T, LN, RB>), dim3(ch.nblk), dim3(kBlock), 0, s, ptr, idx, M, Y, \
                      nrows, ch.rows_per_blk, Fu, Fv, r, rs, row_side_is_u ? 1 : 0, (T)delta, part_out)
 #define SVT_SU(LN)                         \
   do {                                     \
@@ -713,23 +757,23 @@ hipError_t launch_sample_update(hipStream_t s, int lanes, const int32_t *ptr, co
 
 template <typename T>
 hipError_t launch_axpby(hipStream_t s, const T *x, T *y, int64_t n, double a) {
-  hipLaunchKernelGGL((k_axpby<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, x, y, n, a);
+  SVT_LAUNCH((k_axpby<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, x, y, n, a);
   return hipGetLastError();
 }
 
 hipError_t launch_d2f(hipStream_t s, const double *x, float *y, int64_t n) {
-  hipLaunchKernelGGL(k_d2f, dim3(grid_for(n)), dim3(kBlock), 0, s, x, y, n);
+  SVT_LAUNCH(k_d2f, dim3(grid_for(n)), dim3(kBlock), 0, s, x, y, n);
   return hipGetLastError();
 }
 
 hipError_t launch_f2d(hipStream_t s, const float *x, double *y, int64_t n) {
-  hipLaunchKernelGGL(k_f2d, dim3(grid_for(n)), dim3(kBlock), 0, s, x, y, n);
+  SVT_LAUNCH(k_f2d, dim3(grid_for(n)), dim3(kBlock), 0, s, x, y, n);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_gather(hipStream_t s, const T *x, const int32_t *map, T *y, int64_t n) {
-  hipLaunchKernelGGL((k_gather<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, x, map, y, n);
+  SVT_LAUNCH((k_gather<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, x, map, y, n);
   return hipGetLastError();
 }
 
@@ -739,6 +783,10 @@ hipError_t launch_gather(hipStream_t s, const T *x, const int32_t *map, T *y, in
                                      const double *, int, T *, double *, int, const T *, T *, int);   \
   template hipError_t launch_orthonormalize<T>(hipStream_t, T *, int, const T *, int64_t, int,     \
                                                const GsScratch &);                                  \
+  template hipError_t launch_gs_dots<T>(hipStream_t, const T *, int, const T *, int64_t, int,      \
+                                        const GsScratch &);                                         \
+  template hipError_t launch_gs_update<T>(hipStream_t, T *, int, const T *, int64_t, int,          \
+                                          const GsScratch &, bool);                                 \
   template hipError_t launch_sumsq<T>(hipStream_t, T *, int, const GsScratch &);                    \
   template hipError_t launch_finalize<T>(hipStream_t, const T *, int, const GsScratch &, T *, double *); \
   template hipError_t launch_randn<T>(hipStream_t, T *, int, uint64_t, uint64_t);                  \

@@ -90,7 +90,11 @@ struct DevMem {
 // ---------------------------------------------------------------------------
 // kernel-class timing with HIP events (params.profile = 1)
 
-enum KernelKind { kSpmv = 0, kOrth = 1, kRitz = 3, kSample = 4, kKinds = 5 };
+// One kind per kernel (each bracket times exactly one launch):
+//   0 k_spmv / k_spmv_lds, 1 k_gs_dots, 2 k_gs_update (first pass, with the
+//   second pass's dot products), 3 k_ritz, 4 k_sample_update, 5 k_gs_update
+//   (second pass, with the |p|^2 partials).
+enum KernelKind { kSpmv = 0, kGsDots = 1, kGsUpdate1 = 2, kRitz = 3, kSample = 4, kGsUpdate2 = 5, kKinds = 6 };
 
 struct Profiler {
   bool on = false;
@@ -109,16 +113,19 @@ struct Profiler {
     HIP_CHECK(hipEventCreate(&e));
     return e;
   }
+  hipEvent_t cur_b = nullptr;
+  // The bracketed launch stamps the pair itself (set_launch_events), so the
+  // time is the kernel's own duration.
   void begin() {
     if (!on) return;
     cur_a = get();
-    HIP_CHECK(hipEventRecord(cur_a, stream));
+    cur_b = get();
+    set_launch_events(cur_a, cur_b);
   }
   void end(int kind, double nbytes) {
     if (!on) return;
-    hipEvent_t b = get();
-    HIP_CHECK(hipEventRecord(b, stream));
-    pending.push_back({cur_a, b, kind});
+    set_launch_events(nullptr, nullptr);  // in case the bracket launched nothing
+    pending.push_back({cur_a, cur_b, kind});
     launches[kind] += 1;
     bytes[kind] += nbytes;
   }
@@ -126,8 +133,8 @@ struct Profiler {
   void flush() {
     for (auto &p : pending) {
       float t = 0.f;
-      HIP_CHECK(hipEventElapsedTime(&t, p.a, p.b));
-      ms[p.kind] += t;
+      if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) ms[p.kind] += t;
+      else (void)hipGetLastError();
       pool.push_back(p.a);
       pool.push_back(p.b);
     }
@@ -477,12 +484,25 @@ struct Problem final : ProblemBase {
     const double vb = sizeof(T);
     prof.begin();
     spmv(c, vals, x_raw, gs.part3, xnp, x_col, x_coef, prev, p);
-    prof.end(kSpmv, spmv_bytes(c, c.ncols, prev != nullptr) + 2.0 * vb * c.ncols);
+    // plus the normalised x written to its basis column
+    prof.end(kSpmv, spmv_bytes(c, c.ncols, prev != nullptr) + vb * c.ncols);
+    if (nq == 0) {
+      HIP_CHECK(launch_sumsq<T>(stream, p, c.nrows, gs));
+      return;
+    }
+    // algorithmic bytes: Q and p read by the dot products; Q read once and p
+    // read and written by each update (the fused second-pass dot products
+    // and norms reuse the same rows)
+    const double len = (double)c.nrows;
     prof.begin();
-    HIP_CHECK(launch_orthonormalize<T>(stream, p, c.nrows, Q, ldq, nq, gs));
-    // Q read by both dot-product passes and both updates, p read and written
-    // by each update
-    prof.end(kOrth, vb * (double)c.nrows * (nq > 0 ? 4.0 * nq + 5.0 : 1.0));
+    HIP_CHECK(launch_gs_dots<T>(stream, p, c.nrows, Q, ldq, nq, gs));
+    prof.end(kGsDots, vb * len * (nq + 1.0));
+    prof.begin();
+    HIP_CHECK(launch_gs_update<T>(stream, p, c.nrows, Q, ldq, nq, gs, false));
+    prof.end(kGsUpdate1, vb * len * (nq + 2.0));
+    prof.begin();
+    HIP_CHECK(launch_gs_update<T>(stream, p, c.nrows, Q, ldq, nq, gs, true));
+    prof.end(kGsUpdate2, vb * len * (nq + 2.0));
   }
 
   // ------------------------------------------------- bidiagonalisation (a3)
@@ -657,10 +677,13 @@ struct Problem final : ProblemBase {
     T *v_out = a_is_y ? Fv.as<T>() : Fu.as<T>();   // A-cols side
     const double *wu = a_is_y ? wd.as<double>() : nullptr;
     const double *wv = a_is_y ? nullptr : wd.as<double>();
+    // algorithmic bytes: the basis read once, the factor written
     prof.begin();
     HIP_CHECK(launch_ritz<T>(stream, Ub.as<T>(), arows, (int)arows, k, Pd.as<double>(), wu, r, u_out, fstride));
+    prof.end(kRitz, (double)sizeof(T) * (double)arows * (k + fstride));
+    prof.begin();
     HIP_CHECK(launch_ritz<T>(stream, Vb.as<T>(), acols, (int)acols, k, Qd.as<double>(), wv, r, v_out, fstride));
-    prof.end(kRitz, (double)sizeof(T) * ((double)(arows + acols) * (k + fstride)));
+    prof.end(kRitz, (double)sizeof(T) * (double)acols * (k + fstride));
     rank = r;
   }
 
@@ -668,16 +691,19 @@ struct Problem final : ProblemBase {
   // (workgroup partials added on the host in order, compensated).
   double sample_pass(int r, double delta, bool want_res) {
     const double vb = sizeof(T);
+    // algorithmic bytes per pass: index, M and Y read, Y written, the row
+    // pointers, both factors once
+    const double pass_bytes = (double)ix.nnz * (4.0 + 3.0 * vb) + vb * (double)(ix.m + ix.n) * r;
     prof.begin();
     HIP_CHECK(launch_sample_update<T>(stream, lanes_r, rowptr.as<int32_t>(), colidx.as<int32_t>(), Mr.as<T>(),
                                       Yr.as<T>(), (int)ix.m, Fu.as<T>(), Fv.as<T>(), r, fstride, true, delta,
                                       want_res ? sample_part.as<double>() : nullptr));
+    prof.end(kSample, pass_bytes + 4.0 * (ix.m + 1));
+    prof.begin();
     HIP_CHECK(launch_sample_update<T>(stream, lanes_c, colptr.as<int32_t>(), rowidx.as<int32_t>(), Mc.as<T>(),
                                       Yc.as<T>(), (int)ix.n, Fu.as<T>(), Fv.as<T>(), r, fstride, false, delta,
                                       nullptr));
-    // per pass: index, M and Y read, Y written; both factors once
-    prof.end(kSample, 2.0 * ((double)ix.nnz * (4.0 + 3.0 * vb)) + 4.0 * (ix.m + ix.n + 2) +
-                          vb * (double)(ix.m + ix.n) * r * 2.0);
+    prof.end(kSample, pass_bytes + 4.0 * (ix.n + 1));
     if (!want_res) return 0.0;
     const int nb = sample_blocks((int)ix.m, lanes_r);
     HIP_CHECK(hipMemcpyAsync(sample_host.data(), sample_part.p, sizeof(double) * nb, hipMemcpyDeviceToHost, stream));
