@@ -72,8 +72,9 @@ typedef struct {
                             value; 0 = automatic: 1e-12 FP64, 1e-6 MIXED       */
   int32_t lanczos_maxsteps; /* cap on bidiagonalisation steps per SVT step
                                (0 = min(m, n))                                 */
-  int32_t reorth_passes; /* 0: classical Gram-Schmidt with a second pass only
-                            when the first cancels (DGKS test); 2: always two */
+  int32_t reorth_passes; /* 0 or 2; both run classical Gram-Schmidt twice
+                            (CGS2) on every new basis vector (0 is reserved
+                            for a conditional second pass, not built)        */
   double decide_margin;  /* the rank decision accepts an unconverged Ritz value
                             below tau only if value + residual <= tau (1 -
                             margin) and a Ritz value above tau has already
@@ -192,6 +193,13 @@ svt_status svt_sample_update(svt_problem *h, int32_t r, const double *U,
 /* The kick alone: sets Y = k0 delta P_Omega(M) with k0 from eq. (5.3) (or
    k0_override), returning sigma1 = ||P_Omega M||_2 and k0. */
 svt_status svt_kick(svt_problem *h, double *sigma1, int32_t *k0);
+
+/* Which sparse-product kernel a handle uses: *segments = the number of
+   column segments of x that the row-compressed (which = 0, Y x) or
+   column-compressed (which = 1, Y^T x) product stages in LDS, or 0 when it
+   gathers x from memory (spmv_mode 1, x too large for the plan, or the
+   device refused the LDS size).  EINVAL for a bad handle or which. */
+svt_status svt_spmv_plan(const svt_problem *h, int32_t which, int32_t *segments);
 
 /* Kernel timing of the last solve when params.profile = 1.  Each kind is
    one kernel, and each timed bracket holds exactly one launch of it:

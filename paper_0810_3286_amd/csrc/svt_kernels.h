@@ -54,8 +54,9 @@ int lanes_for(double mean_per_row);
 // x is copied into LDS in nseg column segments of segcols entries.
 struct SpmvLdsPlan {
   int nblk, rows_per_blk, segcols, nseg;
+  int lanes;  // lanes per row (all of a workgroup's rows at once when possible)
   size_t lds;
-  bool ok;  // false: x segments would be too small; use the gather kernel
+  bool ok;  // false: x needs many small segments; use the gather kernel
 };
 SpmvLdsPlan spmv_lds_plan(int nrows, int ncols, int elem_bytes, int num_cus, int lds_bytes);
 

@@ -237,7 +237,16 @@ __global__ __launch_bounds__(kBlock) void k_spmv(
     acc = fma(v2, x2, acc);
     acc = fma(v3, x3, acc);
   }
-  for (; t < end; t += L) acc = fma(val[t], x[idx[t]], acc);
+  if (t < end) {
+    // fewer than four entries left: one masked batch, same order
+    const bool in1 = t + L < end, in2 = t + 2 * L < end;
+    const int i0 = idx[t], i1 = in1 ? idx[t + L] : 0, i2 = in2 ? idx[t + 2 * L] : 0;
+    const T v0 = val[t], v1 = in1 ? val[t + L] : (T)0, v2 = in2 ? val[t + 2 * L] : (T)0;
+    const T x0 = x[i0], x1 = in1 ? x[i1] : (T)0, x2 = in2 ? x[i2] : (T)0;
+    acc = fma(v0, x0, acc);
+    if (in1) acc = fma(v1, x1, acc);
+    if (in2) acc = fma(v2, x2, acc);
+  }
   acc = seg_sum<L>(acc);
   if (lane == 0) {
     acc = acc * inv;
@@ -247,10 +256,16 @@ __global__ __launch_bounds__(kBlock) void k_spmv(
 
 // p = A (x_raw / s) - s prev with x staged in LDS.  A workgroup owns a
 // contiguous range of rows; the columns are split into segments of at most
-// `segcols` entries, each copied once into LDS (coalesced), so the per-entry
-// gathers of x hit LDS instead of L2.  segptr[row * (nseg + 1) + s] is the
-// first entry of segment s of the row (null when nseg == 1: ptr is used).
-// The same sub-wave handles a row in every segment and accumulates it in LDS.
+// `segcols` entries, each copied once into LDS (coalesced, every thread's
+// loads issued before its stores), so the per-entry gathers of x hit LDS
+// instead of L2.  segptr[row * (nseg + 1) + s] is the first entry of segment
+// s of the row (null when nseg == 1: ptr is used).  L lanes take a row (L is
+// chosen so that all of a workgroup's rows run at once) and each lane keeps
+// kSpmvUnroll entries in flight; a lane accumulates its entries in index
+// order, so the result does not depend on the unrolling.
+constexpr int kSpmvUnroll = 16;
+constexpr int kStageUnroll = 16;
+
 template <typename T, int L>
 __global__ __launch_bounds__(kSpmvBlock) void k_spmv_lds(
     const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx, const T *__restrict__ val,
@@ -272,7 +287,19 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv_lds(
     const int c0 = sgm * segcols;
     const int cn = min(segcols, ncols - c0);
     __syncthreads();  // the previous segment's gathers are done
-    for (int i = threadIdx.x; i < cn; i += kSpmvBlock) xs[i] = x[c0 + i];
+    for (int base = threadIdx.x; base < cn; base += kSpmvBlock * kStageUnroll) {
+      T v[kStageUnroll];
+#pragma unroll
+      for (int j = 0; j < kStageUnroll; ++j) {
+        const int i = base + j * kSpmvBlock;
+        v[j] = (i < cn) ? x[c0 + i] : (T)0;
+      }
+#pragma unroll
+      for (int j = 0; j < kStageUnroll; ++j) {
+        const int i = base + j * kSpmvBlock;
+        if (i < cn) xs[i] = v[j];
+      }
+    }
     __syncthreads();
     for (int row = r0 + grp; row < r1; row += kGroups) {
       int beg, end;
@@ -285,15 +312,31 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv_lds(
       }
       T acc = (T)0;
       int t = beg + lane;
-      for (; t + 3 * L < end; t += 4 * L) {
-        const int i0 = idx[t] - c0, i1 = idx[t + L] - c0, i2 = idx[t + 2 * L] - c0, i3 = idx[t + 3 * L] - c0;
-        const T v0 = val[t], v1 = val[t + L], v2 = val[t + 2 * L], v3 = val[t + 3 * L];
-        acc = fma(v0, xs[i0], acc);
-        acc = fma(v1, xs[i1], acc);
-        acc = fma(v2, xs[i2], acc);
-        acc = fma(v3, xs[i3], acc);
+      for (; t + (kSpmvUnroll - 1) * L < end; t += kSpmvUnroll * L) {
+        int ii[kSpmvUnroll];
+        T vv[kSpmvUnroll];
+#pragma unroll
+        for (int j = 0; j < kSpmvUnroll; ++j) {
+          ii[j] = idx[t + j * L];
+          vv[j] = val[t + j * L];
+        }
+#pragma unroll
+        for (int j = 0; j < kSpmvUnroll; ++j) acc = fma(vv[j], xs[ii[j] - c0], acc);
       }
-      for (; t < end; t += L) acc = fma(val[t], xs[idx[t] - c0], acc);
+      if (t < end) {
+        // fewer than kSpmvUnroll entries left: one masked batch, same order
+        int ii[kSpmvUnroll];
+        T vv[kSpmvUnroll];
+#pragma unroll
+        for (int j = 0; j < kSpmvUnroll; ++j) {
+          const bool in = t + j * L < end;
+          ii[j] = in ? idx[t + j * L] : c0;
+          vv[j] = in ? val[t + j * L] : (T)0;
+        }
+#pragma unroll
+        for (int j = 0; j < kSpmvUnroll; ++j)
+          if (t + j * L < end) acc = fma(vv[j], xs[ii[j] - c0], acc);
+      }
       acc = seg_sum<L>(acc);
       if (lane == 0) {
         const T tot = (sgm == 0) ? acc : racc[row - r0] + acc;
@@ -589,10 +632,16 @@ hipError_t allow_dynamic_lds(const void *kern, size_t bytes) {
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   if (e != hipSuccess) return e;
-  const size_t want = std::max(bytes, (size_t)std::min(maxlds, 160 * 1024));
-  e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)want);
+  hipFuncAttributes fa{};
+  e = hipFuncGetAttributes(&fa, kern);
   if (e != hipSuccess) return e;
-  raised[kern] = want;
+  // the dynamic limit plus the kernel's static LDS must fit the device's
+  // per-workgroup maximum
+  const size_t room = (size_t)maxlds > fa.sharedSizeBytes ? (size_t)maxlds - fa.sharedSizeBytes : 0;
+  if (bytes > room) return hipErrorInvalidValue;
+  e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)room);
+  if (e != hipSuccess) return e;
+  raised[kern] = room;
   return hipSuccess;
 }
 
@@ -602,6 +651,7 @@ hipError_t launch_spmv(hipStream_t s, int lanes, const SpmvLdsPlan *pl, const in
                        double *s_out, int ncols, const T *prev, T *p, int nrows) {
   if (pl) {
     if (!pl->ok || (pl->nseg > 1 && segptr == nullptr)) return hipErrorInvalidValue;
+    lanes = pl->lanes;
 #define SVT_SPMVL(LN)                                                                              \
   do {                                                                                            \
     auto kern = k_spmv_lds<T, LN>;                                                                \
@@ -647,7 +697,12 @@ SpmvLdsPlan spmv_lds_plan(int nrows, int ncols, int elem_bytes, int num_cus, int
   pl.segcols = (int)std::max<long>(seg, 0);
   pl.nseg = pl.segcols > 0 ? (ncols + pl.segcols - 1) / pl.segcols : 0;
   pl.lds = (size_t)elem_bytes * ((size_t)pl.segcols + (size_t)pl.rows_per_blk);
-  pl.ok = pl.segcols >= 1024 && pl.nseg <= 8;
+  // lanes per row: the widest power of two that still runs all of a
+  // workgroup's rows at once (4 .. 64)
+  pl.lanes = 64;
+  while (pl.lanes > 4 && (kSpmvBlock / pl.lanes) < pl.rows_per_blk) pl.lanes /= 2;
+  // one segment holding all of x, or a few segments that are not tiny
+  pl.ok = pl.segcols >= 1 && (pl.nseg == 1 || (pl.segcols >= 1024 && pl.nseg <= 8));
   return pl;
 }
 

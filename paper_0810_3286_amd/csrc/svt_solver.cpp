@@ -229,6 +229,9 @@ struct ProblemBase {
   virtual int partial_svd(int count, double *sigma, double *U, double *V) = 0;
   virtual double sample_update(int r, const double *U, const double *V, double delta) = 0;
   virtual void kick(double *sigma1, int32_t *k0) = 0;
+  // x segments staged in LDS by the row- (0) or column-compressed (1)
+  // product; 0 when that product gathers x from memory
+  virtual int spmv_segments(int which) const = 0;
   std::vector<Record> history;
   Profiler prof;
 };
@@ -431,6 +434,10 @@ struct Problem final : ProblemBase {
   Csx csc_struct() {
     return {colptr.as<int32_t>(), rowidx.as<int32_t>(), (int)ix.n, (int)ix.m, lanes_c,
             use_lds(plan_c) ? &plan_c : nullptr, seg_c.as<int32_t>()};
+  }
+  int spmv_segments(int which) const override {
+    const SpmvLdsPlan &pl = which == 0 ? plan_r : plan_c;
+    return use_lds(pl) ? pl.nseg : 0;
   }
   Csx a_rows_struct() { return a_is_y ? csr_struct() : csc_struct(); }
   Csx a_cols_struct() { return a_is_y ? csc_struct() : csr_struct(); }
@@ -1195,6 +1202,12 @@ svt_status svt_kick(svt_problem *h, double *sigma1, int32_t *k0) {
     if (k0) *k0 = k;
     return SVT_OK;
   });
+}
+
+svt_status svt_spmv_plan(const svt_problem *h, int32_t which, int32_t *segments) {
+  if (!h || !h->impl || (which != 0 && which != 1) || !segments) return SVT_EINVAL;
+  *segments = h->impl->spmv_segments(which);
+  return SVT_OK;
 }
 
 svt_status svt_kernel_stats(const svt_problem *h, int32_t kind, int64_t *launches, double *total_ms,

@@ -112,6 +112,7 @@ def _signatures(lib):
         "svt_sample_update": (ctypes.c_int32, [h, ctypes.c_int32, _dp, _dp, ctypes.c_double, _dp]),
         "svt_kick": (ctypes.c_int32, [h, _dp, _ip]),
         "svt_kernel_stats": (ctypes.c_int32, [h, ctypes.c_int32, _lp, _dp, _dp]),
+        "svt_spmv_plan": (ctypes.c_int32, [h, ctypes.c_int32, _ip]),
         "svt_footprint": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                            ctypes.POINTER(ctypes.c_size_t)]),
         "svt_server_create": (ctypes.c_int32, [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
@@ -300,6 +301,14 @@ def svt_kernel_stats(h, kind: int):
     b = ctypes.c_double()
     _check(load().svt_kernel_stats(h, kind, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(b)), h)
     return n.value, ms.value, b.value
+
+
+def svt_spmv_plan(h, which: int) -> int:
+    """Column segments of x staged in LDS by the row- (0) or column-compressed
+    (1) sparse product; 0 when it gathers x from memory."""
+    seg = ctypes.c_int32()
+    _check(load().svt_spmv_plan(h, which, ctypes.byref(seg)), h)
+    return seg.value
 
 
 # ---------------------------------------------------------------- serving

@@ -56,8 +56,11 @@ def test_sparse_products(case, mode):
         B.svt_set_iterate(h, y)
         got = B.svt_apply(h, x, m, trans=0)
         gotT = B.svt_apply(h, u, n, trans=1)
+        plan = (B.svt_spmv_plan(h, 0), B.svt_spmv_plan(h, 1))
     finally:
         B.svt_destroy(h)
+    # FP64 x of these sizes fits LDS whole: mode 2 stages it in one segment
+    assert plan == ((0, 0) if mode == 1 else (1, 1))
     ref = oracle.apply_sparse(m, n, p.rows, p.cols, y, x)
     refT = oracle.apply_sparse(m, n, p.rows, p.cols, y, u, trans=True)
     scale = oracle.apply_sparse(m, n, p.rows, p.cols, np.abs(y), np.abs(x))
@@ -81,8 +84,12 @@ def test_sparse_products_full_size_30000(precision, mode):
         B.svt_set_iterate(h, y)
         got = B.svt_apply(h, x, p.m, trans=0)
         gotT = B.svt_apply(h, x, p.n, trans=1)
+        plan = (B.svt_spmv_plan(h, 0), B.svt_spmv_plan(h, 1))
     finally:
         B.svt_destroy(h)
+    # the kernel asked for is the one that ran (no silent fall-back)
+    want = 0 if mode == 1 else (2 if precision == 0 else 1)
+    assert plan == (want, want)
     # rows sampled one by one by the oracle's plain definition
     rows = rng.choice(p.m, 300, replace=False)
     sel = np.isin(p.rows, rows)
