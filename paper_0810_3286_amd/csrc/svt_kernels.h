@@ -5,7 +5,9 @@
 //   - compressed sparse rows of one orientation of Omega: ptr[nrows+1],
 //     idx[nnz] (int32), values[nnz];
 //   - Lanczos bases: column-major, leading dimension ld (>= vector length);
-//   - Ritz factors: row-major with row stride rs (>= r, even, zero padded).
+//   - Ritz factors: row-major with row stride rs (>= r, even, zero padded);
+//   - reduction partials: column c of a partial array holds one value per
+//     workgroup of the row partition (row_plan), at part[c * nblk + b].
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,18 +22,27 @@ namespace svt {
 // it; the launch clears them.  Null: no timing.
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
 
-constexpr int kBlock = 256;
-constexpr int kSpmvBlock = 1024;  // workgroup of the LDS-staged sparse product
-constexpr int kGsChunks1 = 32;    // row chunks of the first Gram-Schmidt dot products
-constexpr int kGsChunks2 = 256;   // row chunks of the Gram-Schmidt updates
+constexpr int kBlock = 256;            // elementwise and sampled-update kernels
+constexpr int kRowBlock = 1024;        // row-range kernels (sparse product, Gram-Schmidt)
+constexpr int kMaxRowBlocks = 256;     // row ranges per vector: one per compute unit ...
+constexpr int kMaxRowsPerBlock = 2048; // ... unless that would give longer ranges
 constexpr int kSampleMaxBlocks = 1024;
 
-// Partial-sum buffers of the Gram-Schmidt kernels (device memory owned by
-// the solver): part1 >= max_cols * kGsChunks1, part2 >= max_cols *
-// kGsChunks2, part3 >= kGsChunks2 doubles.
+// Partition of a vector of nrows entries into nblk contiguous row ranges of
+// rows_per_blk (the last one shorter), shared by the sparse product, the
+// Gram-Schmidt kernels and the norm kernels: the partial sums they exchange
+// have one entry per range.
+struct RowPlan {
+  int nblk, rows_per_blk;
+};
+RowPlan row_plan(int nrows);
+
+// Partial-sum buffers of the bidiagonalisation (device memory owned by the
+// solver): part1 and part2 hold max_cols columns of max_blocks partials,
+// part3 max_blocks partials.
 struct GsScratch {
   double *part1, *part2, *part3;
-  int max_cols;
+  int max_cols, max_blocks;
 };
 
 struct RowChunks {
@@ -40,65 +51,49 @@ struct RowChunks {
 };
 RowChunks row_chunks(int nrows, int target_rows);
 
-struct GsPlan {
-  int nrc1, rpb1;      // dot-product row chunks and their size
-  int nrc2, rpb2;      // update row chunks and their size
-};
-GsPlan gs_plan(int nrows);
-size_t gs_update_lds(int nq, int rows_per_blk);
-
-// Lanes per row for the compressed-row kernels, from the mean row length.
+// Lanes per row for the sampled-update kernel, from the mean row length.
 int lanes_for(double mean_per_row);
 
-// LDS-staged sparse product: one workgroup per compute unit owns a row range;
-// x is copied into LDS in nseg column segments of segcols entries.
-struct SpmvLdsPlan {
-  int nblk, rows_per_blk, segcols, nseg;
-  int lanes;  // lanes per row (all of a workgroup's rows at once when possible)
-  size_t lds;
-  bool ok;  // false: x needs many small segments; use the gather kernel
+// Sparse product plan: the row partition of row_plan(nrows), lanes per row,
+// and nseg column segments of segcols entries of x staged in LDS (nseg = 0:
+// x gathered from memory).  mode 0 stages x when it fits in one segment,
+// 1 always gathers, 2 also allows up to 8 segments of >= 1024 entries.
+struct SpmvPlan {
+  int nblk, rows_per_blk, lanes, nseg, segcols;
+  size_t lds;  // dynamic LDS bytes of a launch
 };
-SpmvLdsPlan spmv_lds_plan(int nrows, int ncols, int elem_bytes, int num_cus, int lds_bytes);
+SpmvPlan spmv_plan(int nrows, int ncols, int elem_bytes, int lds_bytes, int mode);
 
-// p = A (x / s) - s prev, with s^2 the sum of the xnp partials in xpart
+// p = A (x / s) - s prev with s^2 the sum of the xnp partials in xpart
 // (xpart null: s = 1, x already normalised; prev may be null).  With x_out
 // non-null the normalised x is written to x_out (ncols entries) and s to
-// *s_out: the previous half-step's vector joins its basis.  pl non-null:
-// x staged in LDS (segptr: nrows x (nseg + 1) segment starts, null when
-// nseg == 1); null: x gathered from memory.
+// *s_out: the previous half-step's vector joins its basis.  segptr: nrows x
+// (nseg + 1) segment starts (null unless nseg > 1).  With dots_out non-null
+// the kernel also writes the first Gram-Schmidt pass's partial dot products
+// of p with the nq columns of Q and |p|^2 (column nq): nq + 1 columns.
 template <typename T>
-hipError_t launch_spmv(hipStream_t s, int lanes, const SpmvLdsPlan *pl, const int32_t *ptr, const int32_t *idx,
-                       const T *val, const int32_t *segptr, const T *x, const double *xpart, int xnp, T *x_out,
-                       double *s_out, int ncols, const T *prev, T *p, int nrows);
+hipError_t launch_spmv(hipStream_t s, const SpmvPlan &pl, const int32_t *ptr, const int32_t *idx, const T *val,
+                       const int32_t *segptr, const T *x, const double *xpart, int xnp, T *x_out, double *s_out,
+                       int ncols, const T *prev, T *p, int nrows, const T *Q, int64_t ldq, int nq,
+                       double *dots_out);
 
-// Orthogonalise p (length nrows, overwritten) against the nq orthonormal
-// columns of Q by classical Gram-Schmidt applied twice, leaving the |p|^2
-// partials in gs.part3 (gs_plan(nrows).nrc2 of them) for the consumer's
-// lazy normalisation.  Three kernels (one when nq == 0); the coefficients
-// never leave the device.
-template <typename T>
-hipError_t launch_orthonormalize(hipStream_t s, T *p, int nrows, const T *Q, int64_t ldq, int nq,
-                                 const GsScratch &gs);
-
-// The three kernels of launch_orthonormalize (nq >= 1), for callers that
-// time them one by one: the first pass's dot products into gs.part1; then
-// the first update with the second pass's dot products into gs.part2
-// (second = false), or the second update with the |p|^2 partials into
-// gs.part3 (second = true).
-template <typename T>
-hipError_t launch_gs_dots(hipStream_t s, const T *p, int nrows, const T *Q, int64_t ldq, int nq,
-                          const GsScratch &gs);
+// One classical Gram-Schmidt update of p (length nrows, overwritten)
+// against the nq >= 1 orthonormal columns of Q, with coefficients summed from
+// the nq + 1 columns of part_in.  second = false: part_out receives the next
+// pass's partial dot products (nq + 1 columns); second = true: the |p|^2
+// partials (one column).  Two calls after launch_spmv's dots make CGS2.
 template <typename T>
 hipError_t launch_gs_update(hipStream_t s, T *p, int nrows, const T *Q, int64_t ldq, int nq,
-                            const GsScratch &gs, bool second);
+                            const double *part_in, double *part_out, bool second);
 
-// |p|^2 partials into gs.part3.
+// |p|^2 partials (one column).
 template <typename T>
-hipError_t launch_sumsq(hipStream_t s, T *p, int nrows, const GsScratch &gs);
+hipError_t launch_sumsq(hipStream_t s, const T *p, int nrows, double *part_out);
 
-// out = p / |p| with |p|^2 from gs.part3; *coef_out = |p|.
+// out = p / |p| with |p|^2 the sum of the partials in part; *coef_out = |p|.
 template <typename T>
-hipError_t launch_finalize(hipStream_t s, const T *p, int nrows, const GsScratch &gs, T *out, double *coef_out);
+hipError_t launch_finalize(hipStream_t s, const T *p, int nrows, const double *part, T *out,
+                           double *coef_out);
 
 // out[i] = standard normal draw i of stream (seed, ctr); counter-based.
 template <typename T>

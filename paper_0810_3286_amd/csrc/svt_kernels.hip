@@ -53,7 +53,6 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kWaves = kBlock / kWave;
-constexpr int kTile = 16;  // Gram-Schmidt columns per pass of a workgroup
 
 template <int W, typename A>
 __device__ __forceinline__ A seg_sum(A v) {
@@ -75,99 +74,6 @@ __device__ __forceinline__ double block_sum(double v, double *sbuf) {
   }
   __syncthreads();
   return t;
-}
-
-// hs[c] = sum_i part[c * np + i] for c < C, into LDS, in a fixed order that
-// does not depend on the workgroup: column c is split into G interleaved
-// strands (G = kBlock / min(C, kBlock)), each summed with four accumulators,
-// then the strands are added in strand order.
-__device__ void reduce_columns(const double *__restrict__ part, int np, int C, double *hs,
-                               double *scratch /* kBlock doubles of LDS */) {
-  for (int cb = 0; cb < C; cb += kBlock) {
-    const int Cb = min(kBlock, C - cb);
-    const int G = kBlock / Cb;
-    const int t = threadIdx.x, g = t / Cb, c = t % Cb;
-    double acc = 0.0;
-    if (g < G) {
-      const double *src = part + (size_t)(cb + c) * np;
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      int i = g;
-      for (; i + 3 * G < np; i += 4 * G) {
-        a0 += src[i];
-        a1 += src[i + G];
-        a2 += src[i + 2 * G];
-        a3 += src[i + 3 * G];
-      }
-      for (; i < np; i += G) a0 += src[i];
-      acc = (a0 + a1) + (a2 + a3);
-    }
-    scratch[t] = acc;
-    __syncthreads();
-    if (t < Cb) {
-      double sum = 0.0;
-      for (int gg = 0; gg < G; ++gg) sum += scratch[gg * Cb + t];
-      hs[cb + t] = sum;
-    }
-    __syncthreads();
-  }
-}
-
-// Partial Gram-Schmidt dot products of one workgroup's rows [r0, r1) with
-// the columns c0 .. c0+kTile-1 of Q (column nq stands for the vector itself):
-// part[c * np + rc] = sum_rows Q[c][row] v(row).  Every thread issues its
-// tile's loads together; the kTile sums reduce as independent shuffle chains.
-template <typename T, typename VF>
-__device__ __forceinline__ void tile_partials(VF v, int r0, int r1, const T *__restrict__ Q, int64_t ldq,
-                                              int nq, int c0, double *__restrict__ part, int np, int rc,
-                                              double (*sred)[kTile]) {
-  double acc[kTile];
-#pragma unroll
-  for (int j = 0; j < kTile; ++j) acc[j] = 0.0;
-  // Branch-free tile: columns past nq - 1 load column nq - 1 (any valid
-  // column) and are masked, so the kTile loads of a row issue back to back.
-  const int last = nq > 0 ? nq - 1 : 0;
-  // two rows per round: 2 kTile loads in flight per thread
-  for (int row = r0 + threadIdx.x; row < r1; row += 2 * kBlock) {
-    const int row2 = row + kBlock;
-    const bool has2 = row2 < r1;
-    const double pv = v(row);
-    const double pv2 = has2 ? v(row2) : 0.0;
-    double q[kTile], q2[kTile];
-    if (nq > 0) {
-#pragma unroll
-      for (int j = 0; j < kTile; ++j) {
-        const size_t off = (size_t)min(c0 + j, last) * ldq;
-        q[j] = (double)Q[off + row];
-        q2[j] = has2 ? (double)Q[off + row2] : 0.0;
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < kTile; ++j) q[j] = q2[j] = 0.0;
-    }
-#pragma unroll
-    for (int j = 0; j < kTile; ++j) {
-      const int c = c0 + j;
-      const double f = (c < nq) ? q[j] : ((c == nq) ? pv : 0.0);
-      const double f2 = (c < nq) ? q2[j] : ((c == nq) ? pv2 : 0.0);
-      acc[j] = fma(f, pv, acc[j]);
-      acc[j] = fma(f2, pv2, acc[j]);
-    }
-  }
-  const int w = threadIdx.x / kWave, wl = threadIdx.x % kWave;
-#pragma unroll
-  for (int j = 0; j < kTile; ++j) {
-    const double sv = seg_sum<kWave>(acc[j]);
-    if (wl == 0) sred[w][j] = sv;
-  }
-  __syncthreads();
-  if (threadIdx.x < kTile) {
-    const int c = c0 + threadIdx.x;
-    double t = 0.0;
-#pragma unroll
-    for (int i = 0; i < kWaves; ++i) t += sred[i][threadIdx.x];
-    if (c <= nq) part[(size_t)c * np + rc] = t;
-  }
-  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -207,103 +113,205 @@ __device__ __forceinline__ void write_normalised(const T *__restrict__ x_raw, in
   if (blockIdx.x == 0 && threadIdx.x == 0 && s_out) *s_out = s;
 }
 
-// p = A (x_raw / s) - s prev over a compressed orientation (one sub-wave per
-// row), s from xpart (see input_norm); with x_out, the normalised x is also
-// written out (the previous half-step's vector joins its basis).
-template <typename T, int L>
-__global__ __launch_bounds__(kBlock) void k_spmv(
-    const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx, const T *__restrict__ val,
-    const T *__restrict__ x, const double *__restrict__ xpart, int xnp, T *__restrict__ x_out,
-    double *__restrict__ s_out, int ncols, const T *__restrict__ prev, T *__restrict__ p, int nrows) {
-  __shared__ double sh[kWaves];
-  const double sn = input_norm(xpart, xnp, sh);
-  write_normalised<T>(x, ncols, sn, x_out, s_out);
-  const T inv = (T)((sn > norm_floor<T>()) ? 1.0 / sn : 0.0);
-  const int lane = threadIdx.x % L;
-  constexpr int kGroups = kBlock / L;
-  const int row = blockIdx.x * kGroups + threadIdx.x / L;
-  if (row >= nrows) return;  // whole sub-wave leaves together
-  const int beg = ptr[row], end = ptr[row + 1];
-  T acc = (T)0;
-  int t = beg + lane;
-  // four entries per lane per round: the index loads, then the gathers, issue
-  // together
-  for (; t + 3 * L < end; t += 4 * L) {
-    const int i0 = idx[t], i1 = idx[t + L], i2 = idx[t + 2 * L], i3 = idx[t + 3 * L];
-    const T v0 = val[t], v1 = val[t + L], v2 = val[t + 2 * L], v3 = val[t + 3 * L];
-    const T x0 = x[i0], x1 = x[i1], x2 = x[i2], x3 = x[i3];
-    acc = fma(v0, x0, acc);
-    acc = fma(v1, x1, acc);
-    acc = fma(v2, x2, acc);
-    acc = fma(v3, x3, acc);
-  }
-  if (t < end) {
-    // fewer than four entries left: one masked batch, same order
-    const bool in1 = t + L < end, in2 = t + 2 * L < end;
-    const int i0 = idx[t], i1 = in1 ? idx[t + L] : 0, i2 = in2 ? idx[t + 2 * L] : 0;
-    const T v0 = val[t], v1 = in1 ? val[t + L] : (T)0, v2 = in2 ? val[t + 2 * L] : (T)0;
-    const T x0 = x[i0], x1 = in1 ? x[i1] : (T)0, x2 = in2 ? x[i2] : (T)0;
-    acc = fma(v0, x0, acc);
-    if (in1) acc = fma(v1, x1, acc);
-    if (in2) acc = fma(v2, x2, acc);
-  }
-  acc = seg_sum<L>(acc);
-  if (lane == 0) {
-    acc = acc * inv;
-    p[row] = prev ? fma(-(T)sn, prev[row], acc) : acc;
+// ---------------------------------------------------------------------------
+// Row-range kernels: kRowBlock threads own the rows [r0, r0 + rows_per_blk)
+// of a vector (row_plan); the sparse product and both Gram-Schmidt updates
+// use the same partition, so a workgroup's rows were written by the
+// workgroup of the same index in the kernel before.
+constexpr int kRowWaves = kRowBlock / kWave;   // 16
+constexpr int kRowLanes = 128;                 // row slots of the column-group layout
+constexpr int kColGroups = kRowBlock / kRowLanes;  // 8 column groups
+constexpr int kColsPerPass = 8 * kColGroups;   // 64 columns per pass, 8 per thread
+
+// Block-wide sum of one double over kRowBlock threads (result in thread 0).
+__device__ __forceinline__ double row_block_sum(double v, double *sh /* kRowWaves */) {
+  v = seg_sum<kWave>(v);
+  const int w = threadIdx.x / kWave, wl = threadIdx.x % kWave;
+  if (wl == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kRowWaves; ++i) t += sh[i];
+  __syncthreads();
+  return t;
+}
+
+// Partial dot products of the workgroup's rows: part[c * gridDim.x + b] =
+// sum_rows Q[row, c] v[row - r0] for c < nq and sum_rows v^2 for c = nq.
+// Layout: thread (row slot i, column group g) takes rows r0 + i + 128 t and
+// columns cb + g + 8 j (j < 8) of each 64-column pass; its Q loads are
+// coalesced across the row slots and issued together.  The row sums reduce
+// over the two waves of a column group (shuffles, then LDS), in a fixed order.
+template <typename T, typename VF>
+__device__ __forceinline__ void row_dots(VF v, int r0, int r1, const T *__restrict__ Q, int64_t ldq, int nq,
+                                         double *__restrict__ part, double (*sred)[8]) {
+  const int C = nq + 1;
+  const int i = threadIdx.x % kRowLanes, g = threadIdx.x / kRowLanes;
+  const int w = threadIdx.x / kWave, wl = threadIdx.x % kWave;
+  const int last = nq > 0 ? nq - 1 : 0;
+  for (int cb = 0; cb < C; cb += kColsPerPass) {
+    double acc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] = 0.0;
+    for (int row = r0 + i; row < r1; row += kRowLanes) {
+      const double pv = v(row);
+      T q[8];
+      if (nq > 0) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) q[j] = Q[(size_t)min(cb + g + 8 * j, last) * ldq + row];
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) q[j] = (T)0;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int c = cb + g + 8 * j;
+        const double f = (c < nq) ? (double)q[j] : ((c == nq) ? pv : 0.0);
+        acc[j] = fma(f, pv, acc[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const double sv = seg_sum<kWave>(acc[j]);
+      if (wl == 0) sred[w][j] = sv;
+    }
+    __syncthreads();
+    if (threadIdx.x < kColsPerPass) {
+      const int gg = threadIdx.x / 8, j = threadIdx.x % 8;
+      const int c = cb + gg + 8 * j;
+      if (c < C) part[(size_t)c * gridDim.x + blockIdx.x] = sred[2 * gg][j] + sred[2 * gg + 1][j];
+    }
+    __syncthreads();
   }
 }
 
-// p = A (x_raw / s) - s prev with x staged in LDS.  A workgroup owns a
-// contiguous range of rows; the columns are split into segments of at most
-// `segcols` entries, each copied once into LDS (coalesced, every thread's
-// loads issued before its stores), so the per-entry gathers of x hit LDS
-// instead of L2.  segptr[row * (nseg + 1) + s] is the first entry of segment
-// s of the row (null when nseg == 1: ptr is used).  L lanes take a row (L is
-// chosen so that all of a workgroup's rows run at once) and each lane keeps
-// kSpmvUnroll entries in flight; a lane accumulates its entries in index
-// order, so the result does not depend on the unrolling.
+// Fast path of row_dots when nq < kColsPerPass and the workgroup has at most
+// kRowLanes rows: the thread's eight Q values of its row (q, loaded before)
+// and its row's value v are already in registers.  The 64 column sums over
+// the 128 row slots go through LDS instead of shuffle trees (the double
+// shuffles cost more than the rest of the kernel): each half of the columns
+// writes its products to buf, 32 threads per column add four of them, and
+// one thread per column adds those 32 in order.  buf: kDotsLds bytes.
+constexpr int kDotsLds = sizeof(double) * (4 * kRowBlock + 32 * 32);
+
+template <typename T>
+__device__ __forceinline__ void row_dots_lds(const T (&q)[8], double v, bool valid, int nq,
+                                             double *__restrict__ part, double *buf) {
+  const int C = nq + 1;
+  const int g = threadIdx.x / kRowLanes;
+  double *prod = buf;                  // 4 x kRowBlock products
+  double *mid = buf + 4 * kRowBlock;   // 32 columns x 32 partial sums
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int j = 4 * h + jj;
+      const int c = g + 8 * j;
+      const double f = (c < nq) ? (double)q[j] : ((c == nq) ? v : 0.0);
+      prod[jj * kRowBlock + threadIdx.x] = valid ? f * v : 0.0;
+    }
+    __syncthreads();
+    {
+      // column (gg, jj) = threadIdx.x / 32: its 128 row-slot products are
+      // prod[jj][gg * 128 + 0 .. 127]
+      const int col = threadIdx.x / 32, sidx = threadIdx.x % 32;
+      const int gg = col % 8, jj = col / 8;
+      const double *src = prod + jj * kRowBlock + gg * kRowLanes;
+      mid[col * 32 + sidx] = ((src[sidx] + src[sidx + 32]) + src[sidx + 64]) + src[sidx + 96];
+    }
+    __syncthreads();
+    if (threadIdx.x < 32) {
+      const int col = threadIdx.x, gg = col % 8, jj = col / 8;
+      const int c = gg + 8 * (4 * h + jj);
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < 32; ++k) t += mid[col * 32 + k];
+      if (c < C) part[(size_t)c * gridDim.x + blockIdx.x] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// The thread's eight Q values of row `row` in the column-group layout
+// (columns g + 8 j, clamped to a valid column; masked by the caller).
+template <typename T>
+__device__ __forceinline__ void load_q8(T (&q)[8], const T *__restrict__ Q, int64_t ldq, int nq, int row,
+                                        bool valid) {
+  const int g = threadIdx.x / kRowLanes;
+  const int last = nq > 0 ? nq - 1 : 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) q[j] = (valid && nq > 0) ? Q[(size_t)min(g + 8 * j, last) * ldq + row] : (T)0;
+}
+
+// p = A (x_raw / s) - s prev over one compressed orientation, s from xpart
+// (input_norm); with x_out, the normalised x is also written out (the
+// previous half-step's vector joins its basis).  STAGE: x is copied into LDS
+// in nseg column segments of segcols entries (coalesced, every thread's loads
+// issued before its stores) and the per-entry gathers hit LDS; otherwise they
+// gather x from memory.  segptr[row * (nseg + 1) + s] is the first entry of
+// segment s of the row (null when nseg == 1: ptr is used).  L lanes take a
+// row and each lane keeps kSpmvUnroll entries in flight, accumulating them in
+// index order (the result does not depend on the unrolling).  With part_out,
+// the first Gram-Schmidt pass's partial dot products of p with the nq
+// columns of Q (and |p|^2) follow in the same kernel (row_dots).
 constexpr int kSpmvUnroll = 16;
 constexpr int kStageUnroll = 16;
 
-template <typename T, int L>
-__global__ __launch_bounds__(kSpmvBlock) void k_spmv_lds(
+template <typename T, int L, bool STAGE>
+__global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
     const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx, const T *__restrict__ val,
     const int32_t *__restrict__ segptr, int nseg, int segcols, const T *__restrict__ x,
     const double *__restrict__ xpart, int xnp, T *__restrict__ x_out, double *__restrict__ s_out, int ncols,
-    const T *__restrict__ prev, T *__restrict__ p, int nrows, int rows_per_blk) {
+    const T *__restrict__ prev, T *__restrict__ p, int nrows, int rows_per_blk, const T *__restrict__ Q,
+    int64_t ldq, int nq, double *__restrict__ part_out) {
   extern __shared__ double smem_d[];
-  __shared__ double sh[kSpmvBlock / kWave];
-  T *xs = reinterpret_cast<T *>(smem_d);  // segcols entries
-  T *racc = xs + segcols;                  // rows_per_blk partial row sums
+  __shared__ double sh[kRowWaves];
+  __shared__ double sred[kRowWaves][8];
+  T *racc = reinterpret_cast<T *>(smem_d);  // rows_per_blk row sums, then the rows of p
+  // after racc (16-byte aligned): segcols entries of x (STAGE), reused by the
+  // fused dot products once the product is done
+  char *region = reinterpret_cast<char *>(smem_d) + ((sizeof(T) * rows_per_blk + 15) / 16) * 16;
+  T *xs = reinterpret_cast<T *>(region);
+  // epilogue fast path: this thread's Q values are loaded now and arrive
+  // while the product runs
+  const bool fast = part_out != nullptr && nq < kColsPerPass && rows_per_blk <= kRowLanes;
+  const int frow = blockIdx.x * rows_per_blk + threadIdx.x % kRowLanes;
+  const bool fvalid = fast && threadIdx.x % kRowLanes < rows_per_blk && frow < nrows;
+  T q8[8];
+  load_q8<T>(q8, Q, ldq, nq, frow, fvalid);
   const double sn = input_norm(xpart, xnp, sh);
   write_normalised<T>(x, ncols, sn, x_out, s_out);
   const T inv = (T)((sn > norm_floor<T>()) ? 1.0 / sn : 0.0);
   const int r0 = blockIdx.x * rows_per_blk;
   const int r1 = min(nrows, r0 + rows_per_blk);
   const int lane = threadIdx.x % L, grp = threadIdx.x / L;
-  constexpr int kGroups = kSpmvBlock / L;
-  for (int sgm = 0; sgm < nseg; ++sgm) {
-    const int c0 = sgm * segcols;
-    const int cn = min(segcols, ncols - c0);
-    __syncthreads();  // the previous segment's gathers are done
-    for (int base = threadIdx.x; base < cn; base += kSpmvBlock * kStageUnroll) {
-      T v[kStageUnroll];
+  constexpr int kGroups = kRowBlock / L;
+  const int nsg = STAGE ? nseg : 1;
+  for (int sgm = 0; sgm < nsg; ++sgm) {
+    const int c0 = STAGE ? sgm * segcols : 0;
+    const T *xv = x;
+    if constexpr (STAGE) {
+      const int cn = min(segcols, ncols - c0);
+      __syncthreads();  // the previous segment's gathers are done
+      for (int base = threadIdx.x; base < cn; base += kRowBlock * kStageUnroll) {
+        T v[kStageUnroll];
 #pragma unroll
-      for (int j = 0; j < kStageUnroll; ++j) {
-        const int i = base + j * kSpmvBlock;
-        v[j] = (i < cn) ? x[c0 + i] : (T)0;
-      }
+        for (int j = 0; j < kStageUnroll; ++j) {
+          const int ii = base + j * kRowBlock;
+          v[j] = (ii < cn) ? x[c0 + ii] : (T)0;
+        }
 #pragma unroll
-      for (int j = 0; j < kStageUnroll; ++j) {
-        const int i = base + j * kSpmvBlock;
-        if (i < cn) xs[i] = v[j];
+        for (int j = 0; j < kStageUnroll; ++j) {
+          const int ii = base + j * kRowBlock;
+          if (ii < cn) xs[ii] = v[j];
+        }
       }
+      __syncthreads();
+      xv = xs;
     }
-    __syncthreads();
     for (int row = r0 + grp; row < r1; row += kGroups) {
       int beg, end;
-      if (nseg == 1) {
+      if (!STAGE || nseg == 1) {
         beg = ptr[row];
         end = ptr[row + 1];
       } else {
@@ -321,7 +329,7 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv_lds(
           vv[j] = val[t + j * L];
         }
 #pragma unroll
-        for (int j = 0; j < kSpmvUnroll; ++j) acc = fma(vv[j], xs[ii[j] - c0], acc);
+        for (int j = 0; j < kSpmvUnroll; ++j) acc = fma(vv[j], xv[ii[j] - c0], acc);
       }
       if (t < end) {
         // fewer than kSpmvUnroll entries left: one masked batch, same order
@@ -335,98 +343,193 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv_lds(
         }
 #pragma unroll
         for (int j = 0; j < kSpmvUnroll; ++j)
-          if (t + j * L < end) acc = fma(vv[j], xs[ii[j] - c0], acc);
+          if (t + j * L < end) acc = fma(vv[j], xv[ii[j] - c0], acc);
       }
       acc = seg_sum<L>(acc);
       if (lane == 0) {
         const T tot = (sgm == 0) ? acc : racc[row - r0] + acc;
-        if (sgm + 1 < nseg) {
+        if (sgm + 1 < nsg) {
           racc[row - r0] = tot;
         } else {
           const T y = tot * inv;
-          p[row] = prev ? fma(-(T)sn, prev[row], y) : y;
+          const T pv = prev ? fma(-(T)sn, prev[row], y) : y;
+          p[row] = pv;
+          racc[row - r0] = pv;
         }
       }
     }
   }
+  if (part_out == nullptr) return;  // uniform
+  __syncthreads();
+  if (fast) {
+    row_dots_lds<T>(q8, fvalid ? (double)racc[frow - r0] : 0.0, fvalid, nq, part_out,
+                    reinterpret_cast<double *>(region));
+  } else {
+    row_dots<T>([&](int row) { return (double)racc[row - r0]; }, r0, r1, Q, ldq, nq, part_out, sred);
+  }
 }
 
-// First Gram-Schmidt pass, dot products: part[c * nrc + rc] over a
-// (row chunk, column tile) grid; column nq holds |p|^2.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_gs_dots(const T *__restrict__ p, int nrows, int rows_per_blk,
-                                                    const T *__restrict__ Q, int64_t ldq, int nq,
-                                                    double *__restrict__ part) {
-  __shared__ double sred[kWaves][kTile];
-  const int rc = blockIdx.x;
-  const int r0 = rc * rows_per_blk;
-  const int r1 = min(nrows, r0 + rows_per_blk);
-  tile_partials<T>([&](int row) { return (double)p[row]; }, r0, r1, Q, ldq, nq, blockIdx.y * kTile, part,
-                   gridDim.x, rc, sred);
-}
-
-// p <- p - Q h, with h = the column sums of part_in (np_in partials each,
-// reduced by every workgroup).  SECOND = false: then the partial dot products
-// of the new p with Q and itself go to part_out (the second pass's
-// coefficients).  SECOND = true: only |p|^2 partials go to part_out.
-template <typename T, bool SECOND>
-__global__ __launch_bounds__(kBlock) void k_gs_update(T *__restrict__ p, int nrows, int rows_per_blk,
-                                                      const T *__restrict__ Q, int64_t ldq, int nq,
-                                                      const double *__restrict__ part_in, int np_in,
-                                                      double *__restrict__ part_out) {
-  extern __shared__ double smem[];
-  double *hs = smem;                   // nq + 1 coefficients
-  double *scratch = hs + nq + 1;       // kBlock
-  double *pc = scratch + kBlock;       // rows_per_blk values of the updated p
-  __shared__ double sred[kWaves][kTile];
-  __shared__ double sbuf[kWaves];
-  reduce_columns(part_in, np_in, nq + 1, hs, scratch);
-  const int rc = blockIdx.x;
-  const int r0 = rc * rows_per_blk;
-  const int r1 = min(nrows, r0 + rows_per_blk);
-  double ss = 0.0;
-  for (int row = r0 + threadIdx.x; row < r1; row += kBlock) {
-    // eight independent loads per round, four accumulators
-    double a[4] = {(double)p[row], 0.0, 0.0, 0.0};
-    int c = 0;
-    for (; c + 8 <= nq; c += 8) {
-      double q[8];
+// hs[c] = sum_i part[c * np + i] for c < C, into LDS.  Wave w takes the
+// columns w, w + 16, ... four at a time; its lanes read consecutive partials
+// of a column (coalesced: a column's np partials are contiguous), add their
+// own ones in index order and the 64 lane sums reduce by a shuffle tree.  The
+// order does not depend on the workgroup, so every workgroup holds the same
+// values.
+__device__ void reduce_columns(const double *__restrict__ part, int np, int C, double *hs) {
+  const int w = threadIdx.x / kWave, wl = threadIdx.x % kWave;
+  for (int cb = w; cb < C; cb += 4 * kRowWaves) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i0 = 0; i0 < np; i0 += 4 * kWave) {
+      double v[4][4];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) q[j] = (double)Q[(size_t)(c + j) * ldq + row];
+      for (int k = 0; k < 4; ++k) {
+        const int c = cb + k * kRowWaves;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) a[j & 3] = fma(-q[j], hs[c + j], a[j & 3]);
+        for (int j = 0; j < 4; ++j) {
+          const int ii = i0 + j * kWave + wl;
+          v[k][j] = (c < C && ii < np) ? part[(size_t)c * np + ii] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[k] += v[k][j];
     }
-    for (; c < nq; ++c) a[0] = fma(-(double)Q[(size_t)c * ldq + row], hs[c], a[0]);
-    const T pv = (T)((a[0] + a[1]) + (a[2] + a[3]));
-    p[row] = pv;
-    pc[row - r0] = (double)pv;
-    ss = fma((double)pv, (double)pv, ss);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double t = seg_sum<kWave>(acc[k]);
+      const int c = cb + k * kRowWaves;
+      if (wl == 0 && c < C) hs[c] = t;
+    }
   }
   __syncthreads();
+}
+
+// p <- p - Q h over the workgroup's rows, with h = the column sums of
+// part_in (np_in partials each, reduced by every workgroup).  Each thread
+// takes the 8-column slices of its column group (loads batched), the eight
+// group sums of a row are added in group order.  SECOND = false: the partial
+// dot products of the new p with Q and itself follow (the second pass's
+// coefficients); SECOND = true: only the |p|^2 partials.
+template <typename T, bool SECOND>
+__global__ __launch_bounds__(kRowBlock) void k_gs_update(T *__restrict__ p, int nrows, int rows_per_blk,
+                                                         const T *__restrict__ Q, int64_t ldq, int nq,
+                                                         const double *__restrict__ part_in, int np_in,
+                                                         double *__restrict__ part_out) {
+  extern __shared__ double smem[];
+  double *hs = smem;                       // nq + 1 coefficients
+  double *pc = hs + nq + 1;                // rows_per_blk values of the new p
+  double *upd = pc + rows_per_blk;         // kRowBlock partial updates
+  double *dbuf = upd + kRowBlock;          // kDotsLds bytes for the fused dot products
+  __shared__ double sh[kRowWaves];
+  __shared__ double sred[kRowWaves][8];
+  const int r0 = blockIdx.x * rows_per_blk;
+  const int r1 = min(nrows, r0 + rows_per_blk);
+  const int i = threadIdx.x % kRowLanes, g = threadIdx.x / kRowLanes;
+  if (nq < kColsPerPass && rows_per_blk <= kRowLanes) {
+    // fast path: one row per row slot and at most eight columns per thread;
+    // the Q values and p are loaded before the coefficients are summed, and
+    // the Q values are reused by the fused dot products
+    const int row = r0 + i;
+    const bool valid = row < r1;
+    T q[8];
+    load_q8<T>(q, Q, ldq, nq, row, valid);
+    const double p0 = (valid && g == 0) ? (double)p[row] : 0.0;
+    reduce_columns(part_in, np_in, nq + 1, hs);
+    double a = 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c = g + 8 * j;
+      if (c < nq) a = fma((double)q[j], hs[c], a);
+    }
+    upd[g * kRowLanes + i] = a;
+    __syncthreads();
+    if (g == 0 && valid) {
+      double tot = 0.0;
+#pragma unroll
+      for (int gg = 0; gg < kColGroups; ++gg) tot += upd[gg * kRowLanes + i];
+      const T pv = (T)(p0 - tot);
+      p[row] = pv;
+      pc[i] = (double)pv;
+    }
+    __syncthreads();
+    const double pn = valid ? pc[i] : 0.0;
+    if constexpr (!SECOND) {
+      row_dots_lds<T>(q, pn, valid, nq, part_out, dbuf);
+    } else {
+      const double tot = row_block_sum(g == 0 ? pn * pn : 0.0, sh);
+      if (threadIdx.x == 0) part_out[blockIdx.x] = tot;
+    }
+    return;
+  }
+  reduce_columns(part_in, np_in, nq + 1, hs);
+  const int last = nq - 1;
+  for (int rb = r0; rb < r1; rb += kRowLanes) {
+    const int row = rb + i;
+    const bool valid = row < r1;
+    double a = 0.0;
+    if (valid) {
+      for (int cb = 0; cb < nq; cb += kColsPerPass) {
+        T q[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) q[j] = Q[(size_t)min(cb + g + 8 * j, last) * ldq + row];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int c = cb + g + 8 * j;
+          if (c < nq) a = fma((double)q[j], hs[c], a);
+        }
+      }
+    }
+    upd[g * kRowLanes + i] = a;
+    __syncthreads();
+    if (g == 0 && valid) {
+      double tot = 0.0;
+#pragma unroll
+      for (int gg = 0; gg < kColGroups; ++gg) tot += upd[gg * kRowLanes + i];
+      const T pv = (T)((double)p[row] - tot);
+      p[row] = pv;
+      pc[row - r0] = (double)pv;
+    }
+    __syncthreads();
+  }
   if constexpr (!SECOND) {
-    for (int c0 = 0; c0 <= nq; c0 += kTile)
-      tile_partials<T>([&](int row) { return pc[row - r0]; }, r0, r1, Q, ldq, nq, c0, part_out,
-                       gridDim.x, rc, sred);
+    row_dots<T>([&](int row) { return pc[row - r0]; }, r0, r1, Q, ldq, nq, part_out, sred);
   } else {
-    const double tot = block_sum(ss, sbuf);
-    if (threadIdx.x == 0) part_out[rc] = tot;
+    double ss = 0.0;
+    for (int row = r0 + threadIdx.x; row < r1; row += kRowBlock) ss = fma(pc[row - r0], pc[row - r0], ss);
+    const double tot = row_block_sum(ss, sh);
+    if (threadIdx.x == 0) part_out[blockIdx.x] = tot;
   }
 }
 
-// out = p / |p| with |p|^2 = sum of part[0..np) (summed by every workgroup in
-// the same order); workgroup 0 stores |p| in *coef_out.  out = 0 when |p|
-// underflows.
+// |p|^2 partials of the workgroup's rows (row_plan partition).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_gs_scale(const T *__restrict__ p, int n,
-                                                     const double *__restrict__ part, int np,
-                                                     T *__restrict__ out, double *__restrict__ coef_out) {
-  __shared__ double hs[1];
-  __shared__ double scratch[kBlock];
-  reduce_columns(part, np, 1, hs, scratch);
-  const double nrm = sqrt(hs[0]);
+__global__ __launch_bounds__(kRowBlock) void k_sumsq(const T *__restrict__ p, int nrows, int rows_per_blk,
+                                                     double *__restrict__ part_out) {
+  __shared__ double sh[kRowWaves];
+  const int r0 = blockIdx.x * rows_per_blk;
+  const int r1 = min(nrows, r0 + rows_per_blk);
+  double ss = 0.0;
+  for (int row = r0 + threadIdx.x; row < r1; row += kRowBlock) {
+    const double v = (double)p[row];
+    ss = fma(v, v, ss);
+  }
+  const double tot = row_block_sum(ss, sh);
+  if (threadIdx.x == 0) part_out[blockIdx.x] = tot;
+}
+
+// out = p / |p| with |p|^2 = the sum of part[0..np) (input_norm: the same
+// order as the sparse product that would normalise it); workgroup 0 stores
+// |p| in *coef_out.  out = 0 when |p| underflows.
+template <typename T>
+__global__ __launch_bounds__(kRowBlock) void k_gs_scale(const T *__restrict__ p, int n,
+                                                        const double *__restrict__ part, int np,
+                                                        T *__restrict__ out, double *__restrict__ coef_out) {
+  __shared__ double sh[kRowWaves];
+  const double nrm = input_norm(part, np, sh);
   const double inv = (nrm > norm_floor<T>()) ? 1.0 / nrm : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) *coef_out = nrm;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+  for (int i = blockIdx.x * kRowBlock + threadIdx.x; i < n; i += gridDim.x * kRowBlock)
     out[i] = (T)((double)p[i] * inv);
 }
 
@@ -602,25 +705,21 @@ int lanes_for(double mean) {
   return 64;
 }
 
-GsPlan gs_plan(int nrows) {
-  GsPlan g;
-  const RowChunks a = row_chunks(nrows, std::max(kBlock, (nrows + kGsChunks1 - 1) / kGsChunks1));
-  const RowChunks b = row_chunks(nrows, std::max(kBlock, (nrows + kGsChunks2 - 1) / kGsChunks2));
-  g.nrc1 = a.nblk;
-  g.rpb1 = a.rows_per_blk;
-  g.nrc2 = b.nblk;
-  g.rpb2 = b.rows_per_blk;
-  return g;
-}
-
-size_t gs_update_lds(int nq, int rows_per_blk) {
-  return sizeof(double) * ((size_t)nq + 1 + kBlock + (size_t)rows_per_blk);
+RowPlan row_plan(int nrows) {
+  RowPlan rp;
+  rp.nblk = std::max(1, std::min(kMaxRowBlocks, (nrows + 7) / 8));
+  // very long vectors: more workgroups rather than more rows each
+  rp.nblk = std::max(rp.nblk, (nrows + kMaxRowsPerBlock - 1) / kMaxRowsPerBlock);
+  rp.rows_per_blk = std::max(1, (nrows + rp.nblk - 1) / rp.nblk);
+  rp.nblk = std::max(1, (nrows + rp.rows_per_blk - 1) / rp.rows_per_blk);
+  return rp;
 }
 
 // The dynamic-LDS limit is a per-kernel attribute shared by every stream and
-// thread: raise it once to the largest size any plan uses (the device's
-// per-workgroup maximum) and never lower it, so concurrent solves with
-// different plans cannot shrink it under each other's launches.
+// thread: raise it once to the largest size the kernel can take (the
+// device's per-workgroup maximum less the kernel's static LDS) and never
+// lower it, so concurrent solves with different plans cannot shrink it under
+// each other's launches.
 hipError_t allow_dynamic_lds(const void *kern, size_t bytes) {
   static std::mutex mu;
   static std::map<const void *, size_t> raised;
@@ -635,8 +734,6 @@ hipError_t allow_dynamic_lds(const void *kern, size_t bytes) {
   hipFuncAttributes fa{};
   e = hipFuncGetAttributes(&fa, kern);
   if (e != hipSuccess) return e;
-  // the dynamic limit plus the kernel's static LDS must fit the device's
-  // per-workgroup maximum
   const size_t room = (size_t)maxlds > fa.sharedSizeBytes ? (size_t)maxlds - fa.sharedSizeBytes : 0;
   if (bytes > room) return hipErrorInvalidValue;
   e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)room);
@@ -645,120 +742,113 @@ hipError_t allow_dynamic_lds(const void *kern, size_t bytes) {
   return hipSuccess;
 }
 
-template <typename T>
-hipError_t launch_spmv(hipStream_t s, int lanes, const SpmvLdsPlan *pl, const int32_t *ptr, const int32_t *idx,
-                       const T *val, const int32_t *segptr, const T *x, const double *xpart, int xnp, T *x_out,
-                       double *s_out, int ncols, const T *prev, T *p, int nrows) {
-  if (pl) {
-    if (!pl->ok || (pl->nseg > 1 && segptr == nullptr)) return hipErrorInvalidValue;
-    lanes = pl->lanes;
-#define SVT_SPMVL(LN)                                                                              \
-  do {                                                                                            \
-    auto kern = k_spmv_lds<T, LN>;                                                                \
-    hipError_t ea = allow_dynamic_lds(reinterpret_cast<const void *>(kern), pl->lds);             \
-    if (ea != hipSuccess) return ea;                                                              \
-    SVT_LAUNCH(kern, dim3(pl->nblk), dim3(kSpmvBlock), pl->lds, s, ptr, idx, val, segptr, \
-                       pl->nseg, pl->segcols, x, xpart, xnp, x_out, s_out, ncols, prev, p, nrows,  \
-                       pl->rows_per_blk);                                                         \
-  } while (0)
-    switch (lanes) {
-      case 4: SVT_SPMVL(4); break;
-      case 8: SVT_SPMVL(8); break;
-      case 16: SVT_SPMVL(16); break;
-      case 32: SVT_SPMVL(32); break;
-      default: SVT_SPMVL(64); break;
-    }
-#undef SVT_SPMVL
-    return hipGetLastError();
-  }
-#define SVT_SPMV(LN)                                                                              \
-  SVT_LAUNCH((k_spmv<T, LN>), dim3((nrows + kBlock / LN - 1) / (kBlock / LN)), dim3(kBlock), 0, s, \
-                     ptr, idx, val, x, xpart, xnp, x_out, s_out, ncols, prev, p, nrows)
-  switch (lanes) {
-    case 4: SVT_SPMV(4); break;
-    case 8: SVT_SPMV(8); break;
-    case 16: SVT_SPMV(16); break;
-    case 32: SVT_SPMV(32); break;
-    default: SVT_SPMV(64); break;
-  }
-#undef SVT_SPMV
-  return hipGetLastError();
-}
-
-SpmvLdsPlan spmv_lds_plan(int nrows, int ncols, int elem_bytes, int num_cus, int lds_bytes) {
-  SpmvLdsPlan pl{};
-  pl.nblk = std::max(1, std::min(num_cus, (nrows + 7) / 8));
-  pl.rows_per_blk = (nrows + pl.nblk - 1) / pl.nblk;
-  pl.nblk = (nrows + pl.rows_per_blk - 1) / pl.rows_per_blk;
-  // 1 KiB of headroom for the kernel's static LDS
-  const long budget = ((long)lds_bytes - 1024) / elem_bytes - pl.rows_per_blk;
-  long seg = std::min<long>(ncols, budget);
-  if (seg < ncols) seg = (seg / 64) * 64;
-  pl.segcols = (int)std::max<long>(seg, 0);
-  pl.nseg = pl.segcols > 0 ? (ncols + pl.segcols - 1) / pl.segcols : 0;
-  pl.lds = (size_t)elem_bytes * ((size_t)pl.segcols + (size_t)pl.rows_per_blk);
+SpmvPlan spmv_plan(int nrows, int ncols, int elem_bytes, int lds_bytes, int mode) {
+  SpmvPlan pl{};
+  const RowPlan rp = row_plan(nrows);
+  pl.nblk = rp.nblk;
+  pl.rows_per_blk = rp.rows_per_blk;
   // lanes per row: the widest power of two that still runs all of a
   // workgroup's rows at once (4 .. 64)
   pl.lanes = 64;
-  while (pl.lanes > 4 && (kSpmvBlock / pl.lanes) < pl.rows_per_blk) pl.lanes /= 2;
-  // one segment holding all of x, or a few segments that are not tiny
-  pl.ok = pl.segcols >= 1 && (pl.nseg == 1 || (pl.segcols >= 1024 && pl.nseg <= 8));
+  while (pl.lanes > 4 && (kRowBlock / pl.lanes) < pl.rows_per_blk) pl.lanes /= 2;
+  const long racc = (((long)elem_bytes * pl.rows_per_blk + 15) / 16) * 16;
+  pl.nseg = 0;
+  pl.segcols = 0;
+  if (mode != 1) {
+    // 2 KiB of headroom for the kernel's static LDS
+    const long budget = ((long)lds_bytes - 2048 - racc) / elem_bytes;
+    long seg = std::min<long>(ncols, budget);
+    if (seg < ncols) seg = (seg / 64) * 64;
+    if (seg >= 1) {
+      const int nseg = (int)((ncols + seg - 1) / seg);
+      // one segment holding all of x, or (mode 2) a few segments that are not tiny
+      const bool ok = nseg == 1 || (mode == 2 && seg >= 1024 && nseg <= 8);
+      if (ok) {
+        pl.nseg = nseg;
+        pl.segcols = (int)seg;
+      }
+    }
+  }
+  // the region after racc holds x's segment, then the fused dot products
+  pl.lds = (size_t)racc + std::max((size_t)elem_bytes * (size_t)pl.segcols, (size_t)kDotsLds);
   return pl;
 }
 
 template <typename T>
-hipError_t launch_sumsq(hipStream_t s, T *p, int nrows, const GsScratch &gs) {
-  const GsPlan g = gs_plan(nrows);
-  SVT_LAUNCH((k_gs_update<T, true>), dim3(g.nrc2), dim3(kBlock), gs_update_lds(0, g.rpb2), s, p, nrows,
-                     g.rpb2, (const T *)nullptr, (int64_t)0, 0, gs.part1, 1, gs.part3);
+hipError_t launch_spmv(hipStream_t s, const SpmvPlan &pl, const int32_t *ptr, const int32_t *idx, const T *val,
+                       const int32_t *segptr, const T *x, const double *xpart, int xnp, T *x_out, double *s_out,
+                       int ncols, const T *prev, T *p, int nrows, const T *Q, int64_t ldq, int nq,
+                       double *dots_out) {
+  if (pl.nseg > 1 && segptr == nullptr) return hipErrorInvalidValue;
+  if (dots_out != nullptr && nq > 0 && Q == nullptr) return hipErrorInvalidValue;
+  const RowPlan rp = row_plan(nrows);
+  if (rp.nblk != pl.nblk || rp.rows_per_blk != pl.rows_per_blk) return hipErrorInvalidValue;
+#define SVT_SPMVR(LN, ST)                                                                          \
+  do {                                                                                            \
+    auto kern = k_spmv_rows<T, LN, ST>;                                                           \
+    hipError_t ea = allow_dynamic_lds(reinterpret_cast<const void *>(kern), pl.lds);              \
+    if (ea != hipSuccess) return ea;                                                              \
+    SVT_LAUNCH(kern, dim3(pl.nblk), dim3(kRowBlock), pl.lds, s, ptr, idx, val, segptr, pl.nseg,    \
+               pl.segcols, x, xpart, xnp, x_out, s_out, ncols, prev, p, nrows, pl.rows_per_blk, Q, \
+               ldq, nq, dots_out);                                                                \
+  } while (0)
+#define SVT_SPMVS(ST)                      \
+  switch (pl.lanes) {                      \
+    case 4: SVT_SPMVR(4, ST); break;       \
+    case 8: SVT_SPMVR(8, ST); break;       \
+    case 16: SVT_SPMVR(16, ST); break;     \
+    case 32: SVT_SPMVR(32, ST); break;     \
+    default: SVT_SPMVR(64, ST); break;     \
+  }
+  if (pl.nseg > 0) {
+    SVT_SPMVS(true);
+  } else {
+    SVT_SPMVS(false);
+  }
+#undef SVT_SPMVS
+#undef SVT_SPMVR
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_finalize(hipStream_t s, const T *p, int nrows, const GsScratch &gs, T *out,
-                           double *coef_out) {
-  const GsPlan g = gs_plan(nrows);
-  SVT_LAUNCH((k_gs_scale<T>), dim3(grid_for(nrows, 1024)), dim3(kBlock), 0, s, p, nrows, gs.part3, g.nrc2,
-                     out, coef_out);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_gs_dots(hipStream_t s, const T *p, int nrows, const T *Q, int64_t ldq, int nq,
-                          const GsScratch &gs) {
-  const GsPlan g = gs_plan(nrows);
-  if (nq < 1 || g.nrc1 > kGsChunks1 || nq + 1 > gs.max_cols) return hipErrorInvalidValue;
-  const int ntiles = (nq + 1 + kTile - 1) / kTile;
-  SVT_LAUNCH((k_gs_dots<T>), dim3(g.nrc1, ntiles), dim3(kBlock), 0, s, p, nrows, g.rpb1, Q, ldq,
-                     nq, gs.part1);
-  return hipGetLastError();
+size_t gs_update_lds(int nq, int rows_per_blk) {
+  return sizeof(double) * ((size_t)nq + 1 + (size_t)rows_per_blk + kRowBlock) + kDotsLds;
 }
 
 template <typename T>
 hipError_t launch_gs_update(hipStream_t s, T *p, int nrows, const T *Q, int64_t ldq, int nq,
-                            const GsScratch &gs, bool second) {
-  const GsPlan g = gs_plan(nrows);
-  if (nq < 1 || g.nrc1 > kGsChunks1 || g.nrc2 > kGsChunks2 || nq + 1 > gs.max_cols) return hipErrorInvalidValue;
-  const size_t lds = gs_update_lds(nq, g.rpb2);
-  if (lds > 64 * 1024) return hipErrorInvalidValue;
-  if (!second)
-    SVT_LAUNCH((k_gs_update<T, false>), dim3(g.nrc2), dim3(kBlock), lds, s, p, nrows, g.rpb2, Q,
-                       ldq, nq, gs.part1, g.nrc1, gs.part2);
-  else
-    SVT_LAUNCH((k_gs_update<T, true>), dim3(g.nrc2), dim3(kBlock), lds, s, p, nrows, g.rpb2, Q,
-                       ldq, nq, gs.part2, g.nrc2, gs.part3);
+                            const double *part_in, double *part_out, bool second) {
+  const RowPlan rp = row_plan(nrows);
+  if (nq < 1 || Q == nullptr) return hipErrorInvalidValue;
+  const size_t lds = gs_update_lds(nq, rp.rows_per_blk);
+  if (!second) {
+    auto kern = k_gs_update<T, false>;
+    hipError_t e = allow_dynamic_lds(reinterpret_cast<const void *>(kern), lds);
+    if (e != hipSuccess) return e;
+    SVT_LAUNCH(kern, dim3(rp.nblk), dim3(kRowBlock), lds, s, p, nrows, rp.rows_per_blk, Q, ldq, nq, part_in,
+               rp.nblk, part_out);
+  } else {
+    auto kern = k_gs_update<T, true>;
+    hipError_t e = allow_dynamic_lds(reinterpret_cast<const void *>(kern), lds);
+    if (e != hipSuccess) return e;
+    SVT_LAUNCH(kern, dim3(rp.nblk), dim3(kRowBlock), lds, s, p, nrows, rp.rows_per_blk, Q, ldq, nq, part_in,
+               rp.nblk, part_out);
+  }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_orthonormalize(hipStream_t s, T *p, int nrows, const T *Q, int64_t ldq, int nq,
-                                 const GsScratch &gs) {
-  if (nq == 0) return launch_sumsq<T>(s, p, nrows, gs);
-  hipError_t e = launch_gs_dots<T>(s, p, nrows, Q, ldq, nq, gs);
-  if (e != hipSuccess) return e;
-  e = launch_gs_update<T>(s, p, nrows, Q, ldq, nq, gs, false);
-  if (e != hipSuccess) return e;
-  return launch_gs_update<T>(s, p, nrows, Q, ldq, nq, gs, true);
+hipError_t launch_sumsq(hipStream_t s, const T *p, int nrows, double *part_out) {
+  const RowPlan rp = row_plan(nrows);
+  SVT_LAUNCH((k_sumsq<T>), dim3(rp.nblk), dim3(kRowBlock), 0, s, p, nrows, rp.rows_per_blk, part_out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_finalize(hipStream_t s, const T *p, int nrows, const double *part, T *out,
+                           double *coef_out) {
+  const RowPlan rp = row_plan(nrows);
+  SVT_LAUNCH((k_gs_scale<T>), dim3(rp.nblk), dim3(kRowBlock), 0, s, p, nrows, part, rp.nblk, out, coef_out);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -833,17 +923,14 @@ hipError_t launch_gather(hipStream_t s, const T *x, const int32_t *map, T *y, in
 }
 
 #define SVT_INSTANTIATE(T)                                                                          \
-  template hipError_t launch_spmv<T>(hipStream_t, int, const SpmvLdsPlan *, const int32_t *,          \
-                                     const int32_t *, const T *, const int32_t *, const T *,          \
-                                     const double *, int, T *, double *, int, const T *, T *, int);   \
-  template hipError_t launch_orthonormalize<T>(hipStream_t, T *, int, const T *, int64_t, int,     \
-                                               const GsScratch &);                                  \
-  template hipError_t launch_gs_dots<T>(hipStream_t, const T *, int, const T *, int64_t, int,      \
-                                        const GsScratch &);                                         \
-  template hipError_t launch_gs_update<T>(hipStream_t, T *, int, const T *, int64_t, int,          \
-                                          const GsScratch &, bool);                                 \
-  template hipError_t launch_sumsq<T>(hipStream_t, T *, int, const GsScratch &);                    \
-  template hipError_t launch_finalize<T>(hipStream_t, const T *, int, const GsScratch &, T *, double *); \
+  template hipError_t launch_spmv<T>(hipStream_t, const SpmvPlan &, const int32_t *, const int32_t *,      \
+                                     const T *, const int32_t *, const T *, const double *, int, T *,  \
+                                     double *, int, const T *, T *, int, const T *, int64_t, int,      \
+                                     double *);                                                        \
+  template hipError_t launch_gs_update<T>(hipStream_t, T *, int, const T *, int64_t, int, const double *, \
+                                          double *, bool);                                             \
+  template hipError_t launch_sumsq<T>(hipStream_t, const T *, int, double *);                          \
+  template hipError_t launch_finalize<T>(hipStream_t, const T *, int, const double *, T *, double *);   \
   template hipError_t launch_randn<T>(hipStream_t, T *, int, uint64_t, uint64_t);                  \
   template hipError_t launch_ritz<T>(hipStream_t, const T *, int64_t, int, int, const double *,    \
                                      const double *, int, T *, int);                                \

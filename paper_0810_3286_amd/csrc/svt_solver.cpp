@@ -241,13 +241,14 @@ struct Problem final : ProblemBase {
   // dimensions of the bidiagonalised orientation A
   int64_t arows = 0, acols = 0;
   bool a_is_y = true;
-  int lanes_r = 32, lanes_c = 32;  // lanes per row of the CSR / CSC kernels
+  int lanes_r = 32, lanes_c = 32;  // lanes per row of the CSR / CSC sampled updates
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int device = 0;
 
   DevMem rowptr, colidx, colptr, rowidx, csc_of_csr;
-  SpmvLdsPlan plan_r{}, plan_c{};     // LDS-staged sparse products (CSR, CSC)
+  SpmvPlan plan_r{}, plan_c{};        // sparse products (CSR, CSC)
+  int lds_limit = 64 * 1024;          // LDS bytes a workgroup may use
   DevMem seg_r, seg_c;                // their segment starts (when nseg > 1)
   DevMem Mr, Mc, Yr, Yc;          // values, T
   DevMem Ub, Vb;                  // bases, T, column-major
@@ -287,10 +288,6 @@ struct Problem final : ProblemBase {
     acols = std::min(m, n);
     lanes_r = lanes_for((double)nnz / (double)m);
     lanes_c = lanes_for((double)nnz / (double)n);
-    if (const char *lv = std::getenv("SVT_SPMV_LANES")) {  // tuning override: 4, 8, 16, 32 or 64
-      const int l = std::atoi(lv);
-      if (l == 4 || l == 8 || l == 16 || l == 32 || l == 64) lanes_r = lanes_c = l;
-    }
 
     rowptr.alloc(sizeof(int32_t) * (m + 1));
     colidx.alloc(sizeof(int32_t) * nnz);
@@ -309,18 +306,17 @@ struct Problem final : ProblemBase {
     HIP_CHECK(hipMemcpyAsync(rowidx.p, ix.rowidx.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, stream));
     HIP_CHECK(hipMemcpyAsync(csc_of_csr.p, ix.csc_of_csr.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, stream));
     {
-      int cus = 0, lds = 0;
-      HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+      int lds = 0;
       HIP_CHECK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
-      lds = std::min(lds, 160 * 1024);
-      plan_r = spmv_lds_plan((int)m, (int)n, (int)sizeof(T), cus, lds);
-      plan_c = spmv_lds_plan((int)n, (int)m, (int)sizeof(T), cus, lds);
-      if (plan_r.ok && plan_r.nseg > 1) {
+      lds_limit = std::min(lds, 160 * 1024);
+      plan_r = spmv_plan((int)m, (int)n, (int)sizeof(T), lds_limit, prm.spmv_mode);
+      plan_c = spmv_plan((int)n, (int)m, (int)sizeof(T), lds_limit, prm.spmv_mode);
+      if (plan_r.nseg > 1) {
         const auto sr = segment_starts(ix.rowptr, ix.colidx, (int)m, plan_r);
         seg_r.alloc(sizeof(int32_t) * sr.size());
         HIP_CHECK(hipMemcpy(seg_r.p, sr.data(), sizeof(int32_t) * sr.size(), hipMemcpyHostToDevice));
       }
-      if (plan_c.ok && plan_c.nseg > 1) {
+      if (plan_c.nseg > 1) {
         const auto sc = segment_starts(ix.colptr, ix.rowidx, (int)n, plan_c);
         seg_c.alloc(sizeof(int32_t) * sc.size());
         HIP_CHECK(hipMemcpy(seg_c.p, sc.data(), sizeof(int32_t) * sc.size(), hipMemcpyHostToDevice));
@@ -359,14 +355,15 @@ struct Problem final : ProblemBase {
     nV.alloc(sizeof(T) * (size_t)acols * (size_t)(newcap + 2));
     ncoef.alloc(sizeof(double) * 2 * (size_t)(newcap + 4));
     const int cols = newcap + 4;
-    n1.alloc(sizeof(double) * (size_t)cols * kGsChunks1);
-    n2.alloc(sizeof(double) * (size_t)cols * kGsChunks2);
-    n3.alloc(sizeof(double) * (size_t)kGsChunks2);
+    const int blocks = std::max(row_plan((int)arows).nblk, row_plan((int)acols).nblk);
+    n1.alloc(sizeof(double) * (size_t)cols * blocks);
+    n2.alloc(sizeof(double) * (size_t)cols * blocks);
+    n3.alloc(sizeof(double) * (size_t)blocks);
     HIP_CHECK(hipMemsetAsync(ncoef.p, 0, ncoef.bytes, stream));
     if (kcap > 0) {
       // the pending vector's |.|^2 partials (part3) cross the growth: the
       // next half-step normalises that vector with them
-      HIP_CHECK(hipMemcpyAsync(n3.p, gs3.p, sizeof(double) * (size_t)kGsChunks2, hipMemcpyDeviceToDevice, stream));
+      HIP_CHECK(hipMemcpyAsync(n3.p, gs3.p, sizeof(double) * (size_t)blocks, hipMemcpyDeviceToDevice, stream));
       HIP_CHECK(hipMemcpyAsync(nU.p, Ub.p, sizeof(T) * (size_t)arows * (size_t)(kcap + 1), hipMemcpyDeviceToDevice, stream));
       HIP_CHECK(hipMemcpyAsync(nV.p, Vb.p, sizeof(T) * (size_t)acols * (size_t)(kcap + 2), hipMemcpyDeviceToDevice, stream));
       HIP_CHECK(hipMemcpyAsync(ncoef.as<double>(), coef.as<double>(), sizeof(double) * (kcap + 4), hipMemcpyDeviceToDevice, stream));
@@ -385,6 +382,7 @@ struct Problem final : ProblemBase {
     gs.part2 = gs2.as<double>();
     gs.part3 = gs3.as<double>();
     gs.max_cols = cols;
+    gs.max_blocks = blocks;
   }
 
   double *alpha_d() { return coef.as<double>(); }                 // alpha_{i+1} at [i]
@@ -415,52 +413,40 @@ struct Problem final : ProblemBase {
   struct Csx {
     const int32_t *ptr, *idx;
     int nrows, ncols;
-    int lanes;
-    const SpmvLdsPlan *plan;   // LDS-staged product plan (null: gather kernel)
+    SpmvPlan *plan;            // row partition, lanes, LDS segments of x (0: gather)
     const int32_t *segptr;
   };
-  // spmv_mode 0: stage x in LDS when it fits in one segment; 1: gather; 2:
-  // stage x in LDS whenever a plan exists (several segments if needed).
-  bool use_lds(const SpmvLdsPlan &pl) const {
-    if (!pl.ok) return false;
-    if (prm.spmv_mode == 1) return false;
-    if (prm.spmv_mode == 2) return true;
-    return pl.nseg == 1;
-  }
   Csx csr_struct() {
-    return {rowptr.as<int32_t>(), colidx.as<int32_t>(), (int)ix.m, (int)ix.n, lanes_r,
-            use_lds(plan_r) ? &plan_r : nullptr, seg_r.as<int32_t>()};
+    return {rowptr.as<int32_t>(), colidx.as<int32_t>(), (int)ix.m, (int)ix.n, &plan_r, seg_r.as<int32_t>()};
   }
   Csx csc_struct() {
-    return {colptr.as<int32_t>(), rowidx.as<int32_t>(), (int)ix.n, (int)ix.m, lanes_c,
-            use_lds(plan_c) ? &plan_c : nullptr, seg_c.as<int32_t>()};
+    return {colptr.as<int32_t>(), rowidx.as<int32_t>(), (int)ix.n, (int)ix.m, &plan_c, seg_c.as<int32_t>()};
   }
-  int spmv_segments(int which) const override {
-    const SpmvLdsPlan &pl = which == 0 ? plan_r : plan_c;
-    return use_lds(pl) ? pl.nseg : 0;
-  }
+  int spmv_segments(int which) const override { return (which == 0 ? plan_r : plan_c).nseg; }
   Csx a_rows_struct() { return a_is_y ? csr_struct() : csc_struct(); }
   Csx a_cols_struct() { return a_is_y ? csc_struct() : csr_struct(); }
 
   // out = A (x / s) - s prev with s from the |x|^2 partials xpart (null: x
-  // normalised, s = 1); x_out / s_out receive the normalised x and s.
+  // normalised, s = 1); x_out / s_out receive the normalised x and s; with
+  // dots, the first Gram-Schmidt pass's partial dot products of out with the
+  // nq columns of Q follow in the same kernel.
   void spmv(const Csx &c, const T *vals, const T *x, const double *xpart, int xnp, T *x_out, double *s_out,
-            const T *prev, T *out) {
-    if (c.plan) {
-      const hipError_t e = launch_spmv<T>(stream, c.lanes, c.plan, c.ptr, c.idx, vals, c.segptr, x, xpart, xnp,
-                                          x_out, s_out, c.ncols, prev, out, c.nrows);
-      if (e == hipSuccess) return;
-      // the device refused the LDS size: use the gather kernel from now on
+            const T *prev, T *out, const T *Q = nullptr, int64_t ldq = 0, int nq = 0, double *dots = nullptr) {
+    hipError_t e = launch_spmv<T>(stream, *c.plan, c.ptr, c.idx, vals, c.segptr, x, xpart, xnp, x_out, s_out,
+                                  c.ncols, prev, out, c.nrows, Q, ldq, nq, dots);
+    if (e == hipErrorInvalidValue && c.plan->nseg > 0) {
+      // the device refused the LDS size: gather x from memory from now on
       (void)hipGetLastError();
-      plan_r.ok = plan_c.ok = false;
+      *c.plan = spmv_plan(c.nrows, c.ncols, (int)sizeof(T), lds_limit, 1);
+      e = launch_spmv<T>(stream, *c.plan, c.ptr, c.idx, vals, nullptr, x, xpart, xnp, x_out, s_out, c.ncols,
+                         prev, out, c.nrows, Q, ldq, nq, dots);
     }
-    HIP_CHECK(launch_spmv<T>(stream, c.lanes, nullptr, c.ptr, c.idx, vals, nullptr, x, xpart, xnp, x_out, s_out,
-                             c.ncols, prev, out, c.nrows));
+    HIP_CHECK(e);
   }
 
   // Segment starts of every row of a compressed structure for the LDS plan.
   static std::vector<int32_t> segment_starts(const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx,
-                                             int nrows, const SpmvLdsPlan &pl) {
+                                             int nrows, const SpmvPlan &pl) {
     std::vector<int32_t> out((size_t)nrows * (pl.nseg + 1));
     for (int i = 0; i < nrows; ++i) {
       const int32_t *b = idx.data() + ptr[i], *e = idx.data() + ptr[i + 1];
@@ -489,26 +475,23 @@ struct Problem final : ProblemBase {
   void half_step(const Csx &c, const T *vals, const T *x_raw, int xnp, T *x_col, double *x_coef,
                  const T *prev, T *Q, int64_t ldq, int nq, T *p) {
     const double vb = sizeof(T);
+    const double len = (double)c.nrows;
+    // algorithmic bytes: the product's (spmv_bytes), the normalised x written
+    // to its basis column, and Q read once by the fused first-pass dots
     prof.begin();
-    spmv(c, vals, x_raw, gs.part3, xnp, x_col, x_coef, prev, p);
-    // plus the normalised x written to its basis column
-    prof.end(kSpmv, spmv_bytes(c, c.ncols, prev != nullptr) + vb * c.ncols);
+    spmv(c, vals, x_raw, gs.part3, xnp, x_col, x_coef, prev, p, Q, ldq, nq, nq > 0 ? gs.part1 : nullptr);
+    prof.end(kSpmv, spmv_bytes(c, c.ncols, prev != nullptr) + vb * c.ncols + vb * len * nq);
     if (nq == 0) {
-      HIP_CHECK(launch_sumsq<T>(stream, p, c.nrows, gs));
+      HIP_CHECK(launch_sumsq<T>(stream, p, c.nrows, gs.part3));
       return;
     }
-    // algorithmic bytes: Q and p read by the dot products; Q read once and p
-    // read and written by each update (the fused second-pass dot products
+    // each update: Q read once, p read and written (the fused dot products
     // and norms reuse the same rows)
-    const double len = (double)c.nrows;
     prof.begin();
-    HIP_CHECK(launch_gs_dots<T>(stream, p, c.nrows, Q, ldq, nq, gs));
-    prof.end(kGsDots, vb * len * (nq + 1.0));
-    prof.begin();
-    HIP_CHECK(launch_gs_update<T>(stream, p, c.nrows, Q, ldq, nq, gs, false));
+    HIP_CHECK(launch_gs_update<T>(stream, p, c.nrows, Q, ldq, nq, gs.part1, gs.part2, false));
     prof.end(kGsUpdate1, vb * len * (nq + 2.0));
     prof.begin();
-    HIP_CHECK(launch_gs_update<T>(stream, p, c.nrows, Q, ldq, nq, gs, true));
+    HIP_CHECK(launch_gs_update<T>(stream, p, c.nrows, Q, ldq, nq, gs.part2, gs.part3, true));
     prof.end(kGsUpdate2, vb * len * (nq + 2.0));
   }
 
@@ -519,14 +502,14 @@ struct Problem final : ProblemBase {
     std::vector<double> alpha, beta;  // host copies, alpha[i] = alpha_{i+1}, beta[i] = beta_{i+1}
   };
 
-  int xnp_of(int nrows) const { return gs_plan(nrows).nrc2; }
+  int xnp_of(int nrows) const { return row_plan(nrows).nblk; }
 
   // Start: v_1 random unit, u_1 = A v_1 / alpha_1, then v_2, beta_2.
   void gkl_start(const T *vr, const T *vc, Gkl &g) {
     ensure_basis(std::min<int64_t>(acols, 8));
     const Csx R = a_rows_struct(), C = a_cols_struct();
     HIP_CHECK(launch_randn<T>(stream, pbuf_v.as<T>(), (int)acols, prm.seed, rng_ctr++));
-    HIP_CHECK(launch_sumsq<T>(stream, pbuf_v.as<T>(), (int)acols, gs));
+    HIP_CHECK(launch_sumsq<T>(stream, pbuf_v.as<T>(), (int)acols, gs.part3));
     // u_1 = A v_1 / alpha_1 (v_1 = the normalised start vector)
     half_step(R, vr, pbuf_v.as<T>(), xnp_of((int)acols), vcol(0), beta_d(), nullptr, Ub.as<T>(), arows, 0,
               pbuf_u.as<T>());
@@ -558,7 +541,7 @@ struct Problem final : ProblemBase {
     const int k = g.k;
     if (!g.finalized) {
       // normalise v_{k+1} and store beta_{k+1} (the next step redoes this)
-      HIP_CHECK(launch_finalize<T>(stream, pbuf_v.as<T>(), (int)acols, gs, vcol(k), beta_d() + k));
+      HIP_CHECK(launch_finalize<T>(stream, pbuf_v.as<T>(), (int)acols, gs.part3, vcol(k), beta_d() + k));
       g.finalized = true;
     }
     g.alpha.resize(k);
