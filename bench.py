@@ -339,7 +339,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-steps", type=int, default=1)
     ap.add_argument("--spmv-mode", type=int, default=0,
-                    help="0: x in LDS when it fits in one segment, 1: gathered, 2: LDS segments")
+                    help="0 or 2: x staged in LDS (column segments when needed), 1: gathered")
     ap.add_argument("--serving-requests", type=int, default=16)
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--no-serving", action="store_true")

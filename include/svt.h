@@ -83,10 +83,10 @@ typedef struct {
                             waits                                            */
   uint64_t seed;         /* start vectors of the bidiagonalisation            */
   int32_t profile;       /* 1: time kernel classes with HIP events            */
-  int32_t spmv_mode;     /* sparse products: 0 (default) stage x in LDS when
-                            it fits in one segment, else gather it from
-                            memory; 1 always gather; 2 always stage in LDS
-                            (column segments when x does not fit)            */
+  int32_t spmv_mode;     /* sparse products: 0 (default) and 2 stage x in
+                            LDS, in column segments when it does not fit
+                            whole (up to 8 of >= 1024 entries; otherwise it
+                            is gathered from memory); 1 always gather        */
   void *stream;          /* hipStream_t to run on; NULL = library-owned stream */
 } svt_params;
 

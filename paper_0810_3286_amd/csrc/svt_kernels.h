@@ -56,8 +56,8 @@ int lanes_for(double mean_per_row);
 
 // Sparse product plan: the row partition of row_plan(nrows), lanes per row,
 // and nseg column segments of segcols entries of x staged in LDS (nseg = 0:
-// x gathered from memory).  mode 0 stages x when it fits in one segment,
-// 1 always gathers, 2 also allows up to 8 segments of >= 1024 entries.
+// x gathered from memory).  mode 0 and 2 stage x in one segment, or in up
+// to 8 segments of >= 1024 entries; 1 always gathers.
 struct SpmvPlan {
   int nblk, rows_per_blk, lanes, nseg, segcols;
   size_t lds;  // dynamic LDS bytes of a launch
