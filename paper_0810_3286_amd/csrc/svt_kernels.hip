@@ -189,46 +189,44 @@ __device__ __forceinline__ void row_dots(VF v, int r0, int r1, const T *__restri
 // kRowLanes rows: the thread's eight Q values of its row (q, loaded before)
 // and its row's value v are already in registers.  The 64 column sums over
 // the 128 row slots go through LDS instead of shuffle trees (the double
-// shuffles cost more than the rest of the kernel): each half of the columns
-// writes its products to buf, 32 threads per column add four of them, and
-// one thread per column adds those 32 in order.  buf: kDotsLds bytes.
-constexpr int kDotsLds = sizeof(double) * (4 * kRowBlock + 32 * 32);
+// shuffles cost more than the rest of the kernel): the products go to buf,
+// 16 threads per column add eight of them each, and one thread per column
+// adds those 16 in order.  buf: kDotsLds bytes.
+constexpr int kDotsLds = sizeof(double) * (8 * kRowBlock + kColsPerPass * 16);
 
 template <typename T>
 __device__ __forceinline__ void row_dots_lds(const T (&q)[8], double v, bool valid, int nq,
                                              double *__restrict__ part, double *buf) {
   const int C = nq + 1;
   const int g = threadIdx.x / kRowLanes;
-  double *prod = buf;                  // 4 x kRowBlock products
-  double *mid = buf + 4 * kRowBlock;   // 32 columns x 32 partial sums
+  double *prod = buf;                  // 8 x kRowBlock products
+  double *mid = buf + 8 * kRowBlock;   // 64 columns x 16 partial sums
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int j = 0; j < 8; ++j) {
+    const int c = g + 8 * j;
+    const double f = (c < nq) ? (double)q[j] : ((c == nq) ? v : 0.0);
+    prod[j * kRowBlock + threadIdx.x] = valid ? f * v : 0.0;
+  }
+  __syncthreads();
+  {
+    // column (gg, j) = threadIdx.x / 16: its 128 row-slot products are
+    // prod[j][gg * 128 + 0 .. 127]; strand s adds rows s, s + 16, ...
+    const int col = threadIdx.x / 16, sidx = threadIdx.x % 16;
+    const int gg = col % 8, j = col / 8;
+    const double *src = prod + j * kRowBlock + gg * kRowLanes + sidx;
+    double t = 0.0;
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      const int j = 4 * h + jj;
-      const int c = g + 8 * j;
-      const double f = (c < nq) ? (double)q[j] : ((c == nq) ? v : 0.0);
-      prod[jj * kRowBlock + threadIdx.x] = valid ? f * v : 0.0;
-    }
-    __syncthreads();
-    {
-      // column (gg, jj) = threadIdx.x / 32: its 128 row-slot products are
-      // prod[jj][gg * 128 + 0 .. 127]
-      const int col = threadIdx.x / 32, sidx = threadIdx.x % 32;
-      const int gg = col % 8, jj = col / 8;
-      const double *src = prod + jj * kRowBlock + gg * kRowLanes;
-      mid[col * 32 + sidx] = ((src[sidx] + src[sidx + 32]) + src[sidx + 64]) + src[sidx + 96];
-    }
-    __syncthreads();
-    if (threadIdx.x < 32) {
-      const int col = threadIdx.x, gg = col % 8, jj = col / 8;
-      const int c = gg + 8 * (4 * h + jj);
-      double t = 0.0;
+    for (int k = 0; k < 8; ++k) t += src[16 * k];
+    mid[col * 16 + sidx] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < kColsPerPass) {
+    const int col = threadIdx.x, gg = col % 8, j = col / 8;
+    const int c = gg + 8 * j;
+    double t = 0.0;
 #pragma unroll
-      for (int k = 0; k < 32; ++k) t += mid[col * 32 + k];
-      if (c < C) part[(size_t)c * gridDim.x + blockIdx.x] = t;
-    }
-    __syncthreads();
+    for (int k = 0; k < 16; ++k) t += mid[col * 16 + k];
+    if (c < C) part[(size_t)c * gridDim.x + blockIdx.x] = t;
   }
 }
 
