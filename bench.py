@@ -35,7 +35,6 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_0810_3286_amd", "csrc", f)
 # rocprofv3 kernel names of each timed kind (substring matches)
 ROCPROF_NAMES = {
     "k_spmv": ("k_spmv",),
-    "k_gs_dots": ("k_gs_dots",),
     "k_gs_update_pass1": ("k_gs_update<float, false>", "k_gs_update<double, false>"),
     "k_ritz": ("k_ritz",),
     "k_sample_update": ("k_sample_update",),

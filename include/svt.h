@@ -203,8 +203,9 @@ svt_status svt_spmv_plan(const svt_problem *h, int32_t which, int32_t *segments)
 
 /* Kernel timing of the last solve when params.profile = 1.  Each kind is
    one kernel, and each timed bracket holds exactly one launch of it:
-     0 k_spmv / k_spmv_lds   sparse product of a bidiagonalisation half-step
-     1 k_gs_dots             first Gram-Schmidt pass, dot products
+     0 k_spmv_rows           sparse product of a bidiagonalisation half-step,
+                             with the first Gram-Schmidt pass's dot products
+     1 (none)                kept for numbering: no longer a kernel of its own
      2 k_gs_update<false>    first update + second pass's dot products
      3 k_ritz                Ritz vectors (one launch per side)
      4 k_sample_update       sampled product, residual and update (one

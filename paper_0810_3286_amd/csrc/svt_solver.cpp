@@ -91,10 +91,10 @@ struct DevMem {
 // kernel-class timing with HIP events (params.profile = 1)
 
 // One kind per kernel (each bracket times exactly one launch):
-//   0 k_spmv / k_spmv_lds, 1 k_gs_dots, 2 k_gs_update (first pass, with the
-//   second pass's dot products), 3 k_ritz, 4 k_sample_update, 5 k_gs_update
-//   (second pass, with the |p|^2 partials).
-enum KernelKind { kSpmv = 0, kGsDots = 1, kGsUpdate1 = 2, kRitz = 3, kSample = 4, kGsUpdate2 = 5, kKinds = 6 };
+//   0 k_spmv_rows (with the first pass's dot products), 1 unused, 2
+//   k_gs_update (first pass, with the second pass's dot products), 3 k_ritz,
+//   4 k_sample_update, 5 k_gs_update (second pass, with the |p|^2 partials).
+enum KernelKind { kSpmv = 0, kUnused1 = 1, kGsUpdate1 = 2, kRitz = 3, kSample = 4, kGsUpdate2 = 5, kKinds = 6 };
 
 struct Profiler {
   bool on = false;
