@@ -3,7 +3,9 @@
 // Invariant kept throughout: B_input = P * B_current * Q^T.  A rotation G
 // applied to rows (a, b) of B_current is undone by P <- P G^T; a rotation H
 // applied to columns (a, b) is undone by Q <- Q H.  When B_current is
-// diagonal, its (sign-corrected) diagonal holds the singular values.
+// diagonal, its (sign-corrected) diagonal holds the singular values.  Only Q
+// and the last row of P are accumulated; P's columns are formed at the end
+// as B_input q_i / sigma_i (half the rotation work).
 //
 // The QR sweep is the Golub-Kahan step: a shift mu from the trailing 2 x 2 of
 // B^T B (the eigenvalue nearer its last diagonal entry), a first right
@@ -26,29 +28,33 @@ struct Rot {
   double c, s, r;
 };
 
-// c, s with -s*a + c*b = 0 and c*a + s*b = r >= 0 (r = hypot(a, b)).
+// sqrt(a^2 + b^2): the plain formula where the squares can neither overflow
+// nor underflow (it is within an ulp of the exact value), hypot elsewhere --
+// hypot's scaling makes it several times slower, and the rotations of the
+// implicit QR are most of the host work of a convergence check.
+inline double norm2(double a, double b) {
+  const double m = std::max(std::fabs(a), std::fabs(b));
+  if (m > 1e-150 && m < 1e150) return std::sqrt(a * a + b * b);
+  return std::hypot(a, b);
+}
+
+// c, s with -s*a + c*b = 0 and c*a + s*b = r >= 0 (r = sqrt(a^2 + b^2)).
 inline Rot make_rot(double a, double b) {
   if (b == 0.0) return {a >= 0.0 ? 1.0 : -1.0, 0.0, std::fabs(a)};
-  const double r = std::hypot(a, b);
+  const double r = norm2(a, b);
   return {a / r, b / r, r};
 }
 
 struct Acc {
   int k;
   bool full;
-  std::vector<double> *P, *Q;  // column-major k x k
+  std::vector<double> *Q;      // column-major k x k
   std::vector<double> *plast;  // last row of P
 
+  // Only the last row of P is accumulated (the residual bounds need it); the
+  // left vectors themselves are formed from Q at the end, P = B Q diag(1/sigma).
   // P <- P G^T for G acting on rows (a, b): new_a = c a + s b, new_b = -s a + c b.
   void left(int a, int b, double c, double s) {
-    if (full) {
-      double *pa = P->data() + (size_t)a * k, *pb = P->data() + (size_t)b * k;
-      for (int i = 0; i < k; ++i) {
-        const double x = pa[i], y = pb[i];
-        pa[i] = c * x + s * y;
-        pb[i] = -s * x + c * y;
-      }
-    }
     double &x = (*plast)[a], &y = (*plast)[b];
     const double xa = x, yb = y;
     x = c * xa + s * yb;
@@ -79,12 +85,11 @@ bool bidiag_svd(const std::vector<double> &d_in, const std::vector<double> &e_in
   std::vector<double> d(d_in), e(k > 1 ? k - 1 : 0, 0.0);
   for (int i = 0; i + 1 < k; ++i) e[i] = e_in[i];
   if (vectors) {
-    out.P.assign((size_t)k * k, 0.0);
     out.Q.assign((size_t)k * k, 0.0);
-    for (int i = 0; i < k; ++i) out.P[(size_t)i * k + i] = out.Q[(size_t)i * k + i] = 1.0;
+    for (int i = 0; i < k; ++i) out.Q[(size_t)i * k + i] = 1.0;
   }
   out.p_last[k - 1] = 1.0;
-  Acc acc{k, vectors, &out.P, &out.Q, &out.p_last};
+  Acc acc{k, vectors, &out.Q, &out.p_last};
 
   for (int i = 0; i < k; ++i)
     if (!std::isfinite(d[i])) return false;
@@ -154,7 +159,7 @@ bool bidiag_svd(const std::vector<double> &d_in, const std::vector<double> &e_in
     const double fm = (hi - 1 > lo) ? e[hi - 2] : 0.0;
     const double t11 = dm * dm + fm * fm, t12 = dm * em, t22 = dn * dn + em * em;
     const double half = 0.5 * (t11 - t22);
-    const double root = std::hypot(half, t12);
+    const double root = norm2(half, t12);
     const double mu = t22 - t12 * t12 / (half + (half >= 0.0 ? root : -root) + (root == 0.0 ? 1.0 : 0.0));
     double y = d[lo] * d[lo] - mu;
     double z = d[lo] * e[lo];
@@ -206,13 +211,28 @@ bool bidiag_svd(const std::vector<double> &d_in, const std::vector<double> &e_in
   }
   out.p_last.swap(pl);
   if (vectors) {
-    std::vector<double> P2((size_t)k * k), Q2((size_t)k * k);
-    for (int i = 0; i < k; ++i) {
-      std::copy_n(out.P.data() + (size_t)ord[i] * k, k, P2.data() + (size_t)i * k);
-      std::copy_n(out.Q.data() + (size_t)ord[i] * k, k, Q2.data() + (size_t)i * k);
-    }
-    out.P.swap(P2);
+    std::vector<double> Q2((size_t)k * k);
+    for (int i = 0; i < k; ++i) std::copy_n(out.Q.data() + (size_t)ord[i] * k, k, Q2.data() + (size_t)i * k);
     out.Q.swap(Q2);
+    // left vectors from the right ones: B q_i = sigma_i p_i with the input B
+    // (upper bidiagonal: (B q)_j = d_j q_j + e_j q_{j+1}); accurate to about
+    // eps sigma_1 / sigma_i, ample for the values above tau that are used.
+    // A zero singular value leaves a zero column.
+    out.P.assign((size_t)k * k, 0.0);
+    for (int i = 0; i < k; ++i) {
+      const double s = out.sigma[i];
+      if (!(s > 0.0)) continue;
+      const double *q = out.Q.data() + (size_t)i * k;
+      double *pc = out.P.data() + (size_t)i * k;
+      double nrm2 = 0.0;
+      for (int j = 0; j < k; ++j) {
+        const double v = d_in[j] * q[j] + (j + 1 < k ? e_in[j] * q[j + 1] : 0.0);
+        pc[j] = v;
+        nrm2 += v * v;
+      }
+      const double inv = 1.0 / std::sqrt(nrm2);
+      for (int j = 0; j < k; ++j) pc[j] *= inv;
+    }
   }
   return true;
 }

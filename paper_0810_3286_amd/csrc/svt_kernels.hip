@@ -39,14 +39,20 @@ void set_launch_events(hipEvent_t start, hipEvent_t stop) {
   t_ev_stop = stop;
 }
 
-// Every launch goes through hipExtLaunchKernelGGL and takes (and clears) the
-// pending timing events, if any.
-#define SVT_LAUNCH(kern, grid, block, lds, stream, ...)                                     \
-  do {                                                                                      \
-    hipEvent_t ev_a_ = t_ev_start, ev_b_ = t_ev_stop;                                       \
-    t_ev_start = t_ev_stop = nullptr;                                                       \
-    hipExtLaunchKernelGGL(kern, grid, block, (std::uint32_t)(lds), stream, ev_a_, ev_b_, 0u, \
-                          __VA_ARGS__);                                                     \
+// A launch with pending timing events goes through hipExtLaunchKernelGGL,
+// which stamps them (and clears them); otherwise through the plain launch,
+// whose host cost is several times lower (the host issues hundreds of
+// launches per SVT iteration and must stay ahead of the device).
+#define SVT_LAUNCH(kern, grid, block, lds, stream, ...)                                       \
+  do {                                                                                        \
+    if (t_ev_start != nullptr) {                                                              \
+      hipEvent_t ev_a_ = t_ev_start, ev_b_ = t_ev_stop;                                       \
+      t_ev_start = t_ev_stop = nullptr;                                                       \
+      hipExtLaunchKernelGGL(kern, grid, block, (std::uint32_t)(lds), stream, ev_a_, ev_b_, 0u, \
+                            __VA_ARGS__);                                                     \
+    } else {                                                                                  \
+      hipLaunchKernelGGL(kern, grid, block, lds, stream, __VA_ARGS__);                        \
+    }                                                                                         \
   } while (0)
 
 namespace {

@@ -87,6 +87,32 @@ struct DevMem {
   T *as() const { return static_cast<T *>(p); }
 };
 
+// Pinned host memory for the small transfers of every SVT iteration (the
+// bidiagonal coefficients, the Ritz combination, the residual partials):
+// copies from pageable memory cost tens of microseconds each.
+struct PinnedMem {
+  void *p = nullptr;
+  size_t bytes = 0;
+  PinnedMem() = default;
+  PinnedMem(const PinnedMem &) = delete;
+  PinnedMem &operator=(const PinnedMem &) = delete;
+  ~PinnedMem() {
+    if (p) (void)hipHostFree(p);
+  }
+  // Room for b bytes (contents not kept).  Callers synchronise the stream
+  // before the buffer is written again.
+  void ensure(size_t b) {
+    if (b <= bytes) return;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    HIP_CHECK(hipHostMalloc(&p, b, hipHostMallocDefault));
+    bytes = b;
+  }
+  template <typename U>
+  U *as() const { return static_cast<U *>(p); }
+};
+
 // ---------------------------------------------------------------------------
 // kernel-class timing with HIP events (params.profile = 1)
 
@@ -258,8 +284,13 @@ struct Problem final : ProblemBase {
   DevMem gs1, gs2, gs3;           // Gram-Schmidt partial sums
   GsScratch gs{};
   DevMem sample_part;             // residual partials, kSampleMaxBlocks + 8 doubles
-  std::vector<double> sample_host;
-  DevMem Pd, Qd, wd;              // Ritz combination (double)
+  PinnedMem sample_host;          // their host copy
+  DevMem ritzd;                   // Ritz combination (double): P (k x r), Q (k x r), w (r)
+  PinnedMem ritz_host;            // its host staging
+  PinnedMem coef_host;            // alpha and beta as fetched
+  hipEvent_t fetch_ev = nullptr;  // behind the copy into coef_host
+  int fetch_k = 0, fetch_kcap = 0;
+  static constexpr int kAheadSteps = 2;  // steps queued while the host checks
   DevMem Fu, Fv;                  // factors of X, T, row-major with stride fstride
   int fstride = 0, fcap = 0;
   int rank = 0;
@@ -327,7 +358,7 @@ struct Problem final : ProblemBase {
     HIP_CHECK(hipMemsetAsync(Yc.p, 0, sizeof(T) * nnz, stream));
 
     sample_part.alloc(sizeof(double) * (kSampleMaxBlocks + 8));
-    sample_host.resize(kSampleMaxBlocks + 8);
+    sample_host.ensure(sizeof(double) * (kSampleMaxBlocks + 8));
     ensure_basis(std::min<int64_t>(acols, 64));
     HIP_CHECK(hipStreamSynchronize(stream));
   }
@@ -399,13 +430,10 @@ struct Problem final : ProblemBase {
       fcap = cap;
       Fu.alloc(sizeof(T) * (size_t)ix.m * fstride);
       Fv.alloc(sizeof(T) * (size_t)ix.n * fstride);
-      wd.alloc(sizeof(double) * cap);
     }
-    const size_t need = sizeof(double) * (size_t)std::max(k, 1) * (size_t)std::max(r, 1);
-    if (Pd.bytes < need) {
-      Pd.alloc(need * 2);
-      Qd.alloc(need * 2);
-    }
+    const size_t need = sizeof(double) * (2 * (size_t)std::max(k, 1) * (size_t)std::max(r, 1) + (size_t)r);
+    if (ritzd.bytes < need) ritzd.alloc(need * 2);
+    ritz_host.ensure(need * 2);
   }
 
   // --------------------------------------------------------- sparse products
@@ -537,18 +565,34 @@ struct Problem final : ProblemBase {
     steps_total += 1;
   }
 
-  void gkl_fetch(Gkl &g) {
+  // Start the fetch of B_k: normalise v_{k+1} and store beta_{k+1} (the
+  // next step redoes this, bit for bit), then copy alpha and beta (one
+  // allocation, one copy) to pinned memory and record fetch_ev behind it.
+  void gkl_fetch_begin(Gkl &g) {
     const int k = g.k;
     if (!g.finalized) {
-      // normalise v_{k+1} and store beta_{k+1} (the next step redoes this)
       HIP_CHECK(launch_finalize<T>(stream, pbuf_v.as<T>(), (int)acols, gs.part3, vcol(k), beta_d() + k));
       g.finalized = true;
     }
-    g.alpha.resize(k);
-    g.beta.resize(k + 1);
-    HIP_CHECK(hipMemcpyAsync(g.alpha.data(), alpha_d(), sizeof(double) * k, hipMemcpyDeviceToHost, stream));
-    HIP_CHECK(hipMemcpyAsync(g.beta.data(), beta_d(), sizeof(double) * (k + 1), hipMemcpyDeviceToHost, stream));
-    HIP_CHECK(hipStreamSynchronize(stream));
+    const size_t span = (size_t)(kcap + 4) + (size_t)(k + 1);
+    coef_host.ensure(sizeof(double) * span);
+    HIP_CHECK(hipMemcpyAsync(coef_host.p, alpha_d(), sizeof(double) * span, hipMemcpyDeviceToHost, stream));
+    if (!fetch_ev) HIP_CHECK(hipEventCreateWithFlags(&fetch_ev, hipEventDisableTiming));
+    HIP_CHECK(hipEventRecord(fetch_ev, stream));
+    fetch_k = k;
+    fetch_kcap = kcap;
+  }
+
+  // Wait for the copy and fill snap with B_k of the fetch (later steps may
+  // already be queued or running).
+  void gkl_fetch_end(Gkl &snap) {
+    HIP_CHECK(hipEventSynchronize(fetch_ev));
+    const int k = fetch_k;
+    const double *h = coef_host.as<double>();
+    snap.k = k;
+    snap.finalized = true;
+    snap.alpha.assign(h, h + k);
+    snap.beta.assign(h + (fetch_kcap + 4), h + (fetch_kcap + 4) + (k + 1));
   }
 
   // SVD of B_k and residual bounds res_i = beta_{k+1} |P_{k,i}|.
@@ -591,12 +635,19 @@ struct Problem final : ProblemBase {
     int next_check = std::max(std::min(cap, mode == 1 ? count + 2 : 3), std::min(cap, k_hint - 2));
     next_check = std::max(next_check, 1);
     std::vector<double> res;
+    Gkl snap;
     for (;;) {
       while (g.k < next_check && g.k < cap) gkl_step(vr, vc, g);
-      gkl_fetch(g);
+      // the check of B_k runs on the host while the device already takes
+      // the next steps: if the check decides they are discarded (they write
+      // only basis columns and coefficients beyond k), otherwise they are
+      // the continuation; the decisions are those of checking without them
+      gkl_fetch_begin(g);
+      for (int a = 0; a < kAheadSteps && g.k < cap; ++a) gkl_step(vr, vc, g);
+      gkl_fetch_end(snap);
       BidiagSVD chk;
-      gkl_ritz(g, false, chk, res);
-      const int k = g.k;
+      gkl_ritz(snap, false, chk, res);
+      const int k = snap.k;
       const double top = chk.sigma.empty() ? 0.0 : chk.sigma[0];
       const double atol = tol * std::max(top, 1e-300);
       bool done = false;
@@ -636,14 +687,18 @@ struct Problem final : ProblemBase {
             std::fprintf(stderr, " | s%d %.10e res %.2e", i + 1, chk.sigma[i], res[i]);
           std::fprintf(stderr, " | tau %.10e\n", tau);
         }
-        gkl_ritz(g, true, sv, res);
+        gkl_ritz(snap, true, sv, res);
+        // the factors are formed from the first k columns of the bases
+        g.k = k;
+        g.alpha = snap.alpha;
+        g.beta = snap.beta;
         return k;
       }
-      if (g.k >= cap) {
+      if (k >= cap) {
         throw Error(SVT_ELANCZOS, "bidiagonalisation reached its step cap (" + std::to_string(cap) +
                                       ") before the Ritz triplets converged");
       }
-      next_check = std::min(cap, g.k + std::max(2, std::min(8, g.k / 16)));
+      next_check = std::min(cap, std::max(g.k, k + std::max(2, std::min(8, k / 16))));
     }
   }
 
@@ -652,27 +707,30 @@ struct Problem final : ProblemBase {
     const int k = g.k;
     ensure_factors(std::max(r, 1), k);
     if (r == 0) { rank = 0; return; }
-    // P (u side) and Q (v side) restricted to the first r columns, k x r row-major
-    std::vector<double> Ph((size_t)k * r), Qh((size_t)k * r);
+    // P (u side) and Q (v side) restricted to the first r columns, k x r
+    // row-major, then w: packed into one pinned block and one copy (the
+    // previous iteration's copy has completed: its residual was synchronised)
+    const size_t kr = (size_t)k * r;
+    double *Ph = ritz_host.as<double>(), *Qh = Ph + kr, *wh = Qh + kr;
     for (int c = 0; c < k; ++c)
       for (int l = 0; l < r; ++l) {
         Ph[(size_t)c * r + l] = sv.P[(size_t)l * k + c];
         Qh[(size_t)c * r + l] = sv.Q[(size_t)l * k + c];
       }
-    HIP_CHECK(hipMemcpyAsync(Pd.p, Ph.data(), sizeof(double) * Ph.size(), hipMemcpyHostToDevice, stream));
-    HIP_CHECK(hipMemcpyAsync(Qd.p, Qh.data(), sizeof(double) * Qh.size(), hipMemcpyHostToDevice, stream));
-    HIP_CHECK(hipMemcpyAsync(wd.p, ws, sizeof(double) * r, hipMemcpyHostToDevice, stream));
+    for (int l = 0; l < r; ++l) wh[l] = ws[l];
+    HIP_CHECK(hipMemcpyAsync(ritzd.p, Ph, sizeof(double) * (2 * kr + r), hipMemcpyHostToDevice, stream));
+    const double *Pd = ritzd.as<double>(), *Qd = Pd + kr, *wd = Qd + kr;
     // Y's left factor (rows m) takes the weights
     T *u_out = a_is_y ? Fu.as<T>() : Fv.as<T>();   // A-rows side
     T *v_out = a_is_y ? Fv.as<T>() : Fu.as<T>();   // A-cols side
-    const double *wu = a_is_y ? wd.as<double>() : nullptr;
-    const double *wv = a_is_y ? nullptr : wd.as<double>();
+    const double *wu = a_is_y ? wd : nullptr;
+    const double *wv = a_is_y ? nullptr : wd;
     // algorithmic bytes: the basis read once, the factor written
     prof.begin();
-    HIP_CHECK(launch_ritz<T>(stream, Ub.as<T>(), arows, (int)arows, k, Pd.as<double>(), wu, r, u_out, fstride));
+    HIP_CHECK(launch_ritz<T>(stream, Ub.as<T>(), arows, (int)arows, k, Pd, wu, r, u_out, fstride));
     prof.end(kRitz, (double)sizeof(T) * (double)arows * (k + fstride));
     prof.begin();
-    HIP_CHECK(launch_ritz<T>(stream, Vb.as<T>(), acols, (int)acols, k, Qd.as<double>(), wv, r, v_out, fstride));
+    HIP_CHECK(launch_ritz<T>(stream, Vb.as<T>(), acols, (int)acols, k, Qd, wv, r, v_out, fstride));
     prof.end(kRitz, (double)sizeof(T) * (double)acols * (k + fstride));
     rank = r;
   }
@@ -696,11 +754,11 @@ struct Problem final : ProblemBase {
     prof.end(kSample, pass_bytes + 4.0 * (ix.n + 1));
     if (!want_res) return 0.0;
     const int nb = sample_blocks((int)ix.m, lanes_r);
-    HIP_CHECK(hipMemcpyAsync(sample_host.data(), sample_part.p, sizeof(double) * nb, hipMemcpyDeviceToHost, stream));
+    HIP_CHECK(hipMemcpyAsync(sample_host.p, sample_part.p, sizeof(double) * nb, hipMemcpyDeviceToHost, stream));
     HIP_CHECK(hipStreamSynchronize(stream));
     double sum = 0.0, comp = 0.0;
     for (int b = 0; b < nb; ++b) {
-      const double y = sample_host[(size_t)b] - comp;
+      const double y = sample_host.as<double>()[b] - comp;
       const double t = sum + y;
       comp = (t - sum) - y;
       sum = t;
@@ -898,6 +956,7 @@ struct Problem final : ProblemBase {
 
   ~Problem() override {
     if (stream) (void)hipStreamSynchronize(stream);
+    if (fetch_ev) (void)hipEventDestroy(fetch_ev);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 };
