@@ -3,9 +3,10 @@
 // Invariant kept throughout: B_input = P * B_current * Q^T.  A rotation G
 // applied to rows (a, b) of B_current is undone by P <- P G^T; a rotation H
 // applied to columns (a, b) is undone by Q <- Q H.  When B_current is
-// diagonal, its (sign-corrected) diagonal holds the singular values.  Only Q
-// and the last row of P are accumulated; P's columns are formed at the end
-// as B_input q_i / sigma_i (half the rotation work).
+// diagonal, its (sign-corrected) diagonal holds the singular values.  Only
+// the last row of P is accumulated (for the residual bounds) and the right
+// rotations are logged; the vectors that are needed are formed afterwards
+// (bidiag_vectors).
 //
 // The QR sweep is the Golub-Kahan step: a shift mu from the trailing 2 x 2 of
 // B^T B (the eigenvalue nearer its last diagonal entry), a first right
@@ -46,13 +47,11 @@ inline Rot make_rot(double a, double b) {
 }
 
 struct Acc {
-  int k;
-  bool full;
-  std::vector<double> *Q;      // column-major k x k
-  std::vector<double> *plast;  // last row of P
+  std::vector<BidiagRot> *rots;  // right rotations, in order
+  std::vector<double> *plast;    // last row of P
 
   // Only the last row of P is accumulated (the residual bounds need it); the
-  // left vectors themselves are formed from Q at the end, P = B Q diag(1/sigma).
+  // vectors are formed afterwards from the log of right rotations.
   // P <- P G^T for G acting on rows (a, b): new_a = c a + s b, new_b = -s a + c b.
   void left(int a, int b, double c, double s) {
     double &x = (*plast)[a], &y = (*plast)[b];
@@ -61,35 +60,26 @@ struct Acc {
     y = -s * xa + c * yb;
   }
   // Q <- Q H for H acting on columns (a, b): new_a = c a + s b, new_b = -s a + c b.
-  void right(int a, int b, double c, double s) {
-    if (!full) return;
-    double *qa = Q->data() + (size_t)a * k, *qb = Q->data() + (size_t)b * k;
-    for (int i = 0; i < k; ++i) {
-      const double x = qa[i], y = qb[i];
-      qa[i] = c * x + s * y;
-      qb[i] = -s * x + c * y;
-    }
-  }
+  void right(int a, int b, double c, double s) { rots->push_back({a, b, c, s}); }
 };
 
 }  // namespace
 
-bool bidiag_svd(const std::vector<double> &d_in, const std::vector<double> &e_in, bool vectors,
-                BidiagSVD &out) {
+bool bidiag_svd(const std::vector<double> &d_in, const std::vector<double> &e_in, BidiagSVD &out) {
   const int k = (int)d_in.size();
   out.sigma.assign(k, 0.0);
   out.p_last.assign(k, 0.0);
   out.P.clear();
   out.Q.clear();
+  out.nvec = 0;
+  out.rots.clear();
+  out.src.assign(k, 0);
+  out.sgn.assign(k, 1);
   if (k == 0) return true;
   std::vector<double> d(d_in), e(k > 1 ? k - 1 : 0, 0.0);
   for (int i = 0; i + 1 < k; ++i) e[i] = e_in[i];
-  if (vectors) {
-    out.Q.assign((size_t)k * k, 0.0);
-    for (int i = 0; i < k; ++i) out.Q[(size_t)i * k + i] = 1.0;
-  }
   out.p_last[k - 1] = 1.0;
-  Acc acc{k, vectors, &out.Q, &out.p_last};
+  Acc acc{&out.rots, &out.p_last};
 
   for (int i = 0; i < k; ++i)
     if (!std::isfinite(d[i])) return false;
@@ -194,13 +184,12 @@ bool bidiag_svd(const std::vector<double> &d_in, const std::vector<double> &e_in
   }
 
   // signs and order
-  for (int i = 0; i < k; ++i) {
+  std::vector<signed char> sg(k, 1);
+  for (int i = 0; i < k; ++i)
     if (d[i] < 0.0) {
       d[i] = -d[i];
-      if (vectors)
-        for (int t = 0; t < k; ++t) out.Q[(size_t)i * k + t] = -out.Q[(size_t)i * k + t];
+      sg[i] = -1;
     }
-  }
   std::vector<int> ord(k);
   std::iota(ord.begin(), ord.end(), 0);
   std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return d[a] > d[b]; });
@@ -208,32 +197,64 @@ bool bidiag_svd(const std::vector<double> &d_in, const std::vector<double> &e_in
   for (int i = 0; i < k; ++i) {
     out.sigma[i] = d[ord[i]];
     pl[i] = out.p_last[ord[i]];
+    out.src[i] = ord[i];
+    out.sgn[i] = sg[ord[i]];
   }
   out.p_last.swap(pl);
-  if (vectors) {
-    std::vector<double> Q2((size_t)k * k);
-    for (int i = 0; i < k; ++i) std::copy_n(out.Q.data() + (size_t)ord[i] * k, k, Q2.data() + (size_t)i * k);
-    out.Q.swap(Q2);
-    // left vectors from the right ones: B q_i = sigma_i p_i with the input B
-    // (upper bidiagonal: (B q)_j = d_j q_j + e_j q_{j+1}); accurate to about
-    // eps sigma_1 / sigma_i, ample for the values above tau that are used.
-    // A zero singular value leaves a zero column.
-    out.P.assign((size_t)k * k, 0.0);
-    for (int i = 0; i < k; ++i) {
-      const double s = out.sigma[i];
-      if (!(s > 0.0)) continue;
-      const double *q = out.Q.data() + (size_t)i * k;
-      double *pc = out.P.data() + (size_t)i * k;
-      double nrm2 = 0.0;
-      for (int j = 0; j < k; ++j) {
-        const double v = d_in[j] * q[j] + (j + 1 < k ? e_in[j] * q[j + 1] : 0.0);
-        pc[j] = v;
-        nrm2 += v * v;
-      }
-      const double inv = 1.0 / std::sqrt(nrm2);
-      for (int j = 0; j < k; ++j) pc[j] *= inv;
+  return true;
+}
+
+void bidiag_vectors(const std::vector<double> &d_in, const std::vector<double> &e_in, int nvec,
+                    BidiagSVD &out) {
+  const int k = (int)d_in.size();
+  nvec = std::max(0, std::min(nvec, k));
+  out.nvec = nvec;
+  out.Q.assign((size_t)k * nvec, 0.0);
+  out.P.assign((size_t)k * nvec, 0.0);
+  if (nvec == 0) return;
+  // Q = H_1 H_2 ... H_n (Q <- Q H per rotation, from the identity), so
+  // column j of Q is H_1 (H_2 (... (H_n e_j))): the rotations applied in
+  // reverse order to unit vectors, all nvec of them together.  H acts on a
+  // vector as (v_a, v_b) <- (c v_a - s v_b, s v_a + c v_b).
+  std::vector<double> V((size_t)nvec * k, 0.0);  // row j holds entry j of every vector
+  for (int i = 0; i < nvec; ++i) V[(size_t)out.src[i] * nvec + i] = 1.0;
+  for (size_t t = out.rots.size(); t-- > 0;) {
+    const BidiagRot &h = out.rots[t];
+    double *va = V.data() + (size_t)h.a * nvec, *vb = V.data() + (size_t)h.b * nvec;
+    for (int i = 0; i < nvec; ++i) {
+      const double x = va[i], y = vb[i];
+      va[i] = h.c * x - h.s * y;
+      vb[i] = h.s * x + h.c * y;
     }
   }
+  for (int i = 0; i < nvec; ++i) {
+    const double sg = out.sgn[i];
+    double *q = out.Q.data() + (size_t)i * k;
+    for (int j = 0; j < k; ++j) q[j] = sg * V[(size_t)j * nvec + i];
+  }
+  // left vectors from the right ones: B q_i = sigma_i p_i with the input B
+  // (upper bidiagonal: (B q)_j = d_j q_j + e_j q_{j+1}); accurate to about
+  // eps sigma_1 / sigma_i, ample for the values above tau that are used.
+  // A zero singular value leaves a zero column.
+  for (int i = 0; i < nvec; ++i) {
+    const double s = out.sigma[i];
+    if (!(s > 0.0)) continue;
+    const double *q = out.Q.data() + (size_t)i * k;
+    double *pc = out.P.data() + (size_t)i * k;
+    double nrm2 = 0.0;
+    for (int j = 0; j < k; ++j) {
+      const double v = d_in[j] * q[j] + (j + 1 < k ? e_in[j] * q[j + 1] : 0.0);
+      pc[j] = v;
+      nrm2 += v * v;
+    }
+    const double inv = 1.0 / std::sqrt(nrm2);
+    for (int j = 0; j < k; ++j) pc[j] *= inv;
+  }
+}
+
+bool bidiag_svd(const std::vector<double> &d, const std::vector<double> &e, bool vectors, BidiagSVD &out) {
+  if (!bidiag_svd(d, e, out)) return false;
+  if (vectors) bidiag_vectors(d, e, (int)d.size(), out);
   return true;
 }
 

@@ -595,11 +595,20 @@ struct Problem final : ProblemBase {
     snap.beta.assign(h + (fetch_kcap + 4), h + (fetch_kcap + 4) + (k + 1));
   }
 
-  // SVD of B_k and residual bounds res_i = beta_{k+1} |P_{k,i}|.
-  void gkl_ritz(const Gkl &g, bool vectors, BidiagSVD &out, std::vector<double> &res) {
+  // B_k as diagonal d and superdiagonal e.
+  static void bidiag_of(const Gkl &g, std::vector<double> &d, std::vector<double> &e) {
     const int k = g.k;
-    std::vector<double> d(g.alpha.begin(), g.alpha.begin() + k), e(k > 1 ? k - 1 : 0);
+    d.assign(g.alpha.begin(), g.alpha.begin() + k);
+    e.assign(k > 1 ? k - 1 : 0, 0.0);
     for (int i = 0; i + 1 < k; ++i) e[i] = g.beta[i + 1];
+  }
+
+  // Singular values of B_k (with the rotation log for gkl_vectors) and the
+  // residual bounds res_i = beta_{k+1} |P_{k,i}|.
+  void gkl_ritz(const Gkl &g, BidiagSVD &out, std::vector<double> &res) {
+    const int k = g.k;
+    std::vector<double> d, e;
+    bidiag_of(g, d, e);
     if (log_level > 1) {
       std::fprintf(stderr, "[svt] coefficients k %d:", k);
       for (int i = 0; i < k; ++i) std::fprintf(stderr, " a%d %.3e b%d %.3e", i + 1, g.alpha[i], i + 2, g.beta[i + 1]);
@@ -609,7 +618,7 @@ struct Problem final : ProblemBase {
       if ((i < k && !std::isfinite(g.alpha[i])) || !std::isfinite(g.beta[i]))
         throw Error(SVT_EDIVERGED, "non-finite bidiagonalisation coefficient at step " + std::to_string(i + 1) +
                                        " of " + std::to_string(k));
-    if (!bidiag_svd(d, e, vectors, out))
+    if (!bidiag_svd(d, e, out))
       throw Error(SVT_ELANCZOS, "bidiagonal SVD did not converge (k = " + std::to_string(k) + ")");
     const double bk1 = (k >= acols) ? 0.0 : std::fabs(g.beta[k]);
     res.resize(k);
@@ -646,7 +655,7 @@ struct Problem final : ProblemBase {
       for (int a = 0; a < kAheadSteps && g.k < cap; ++a) gkl_step(vr, vc, g);
       gkl_fetch_end(snap);
       BidiagSVD chk;
-      gkl_ritz(snap, false, chk, res);
+      gkl_ritz(snap, chk, res);
       const int k = snap.k;
       const double top = chk.sigma.empty() ? 0.0 : chk.sigma[0];
       const double atol = tol * std::max(top, 1e-300);
@@ -687,7 +696,11 @@ struct Problem final : ProblemBase {
             std::fprintf(stderr, " | s%d %.10e res %.2e", i + 1, chk.sigma[i], res[i]);
           std::fprintf(stderr, " | tau %.10e\n", tau);
         }
-        gkl_ritz(snap, true, sv, res);
+        // the singular vectors that are used, from this check's rotations
+        std::vector<double> d, e;
+        bidiag_of(snap, d, e);
+        bidiag_vectors(d, e, mode == 1 ? std::min(count, k) : r, chk);
+        sv = std::move(chk);
         // the factors are formed from the first k columns of the bases
         g.k = k;
         g.alpha = snap.alpha;
