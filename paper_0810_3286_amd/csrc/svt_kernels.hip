@@ -620,35 +620,70 @@ __global__ __launch_bounds__(kBlock) void k_sample_update(
 #pragma unroll
       for (int l = 0; l < RB; ++l) f[l] = (l < r) ? fixed[l] : (T)0;
     }
-    for (int t = beg + lane; t < end; t += L) {
-      const T *g = other + (size_t)idx[t] * rs;
-      T x = (T)0;
+    // kBatch entries per lane at a time: their indices, M and Y values, then
+    // their factor rows, are loaded before any is used; the entries are then
+    // finished in index order (the same sums as one at a time)
+    constexpr int kBatch = (RB > 0 && RB <= 16) ? 4 : ((RB > 0 && RB <= 32) ? 2 : 1);
+    for (int t0 = beg + lane; t0 < end; t0 += kBatch * L) {
+      int jj[kBatch];
+      T mv[kBatch], yv[kBatch];
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        const int t = t0 + q * L;
+        const bool in = t < end;
+        jj[q] = in ? idx[t] : 0;
+        mv[q] = in ? M[t] : (T)0;
+        yv[q] = in ? Y[t] : (T)0;
+      }
+      T x[kBatch];
       if constexpr (RB > 0) {
         // pairs of factor entries per load (rows are 2-element aligned: the
         // row stride is even and the padding is zero); the fma chain still
         // runs in l order with the u-factor entry first, in either orientation
+        typename Vec2<T>::type gv[kBatch][RB / 2];
 #pragma unroll
-        for (int l = 0; l < RB; l += 2) {
-          if (l < r) {
-            const auto gv = *reinterpret_cast<const typename Vec2<T>::type *>(g + l);
-            if (row_side_is_u) {
-              x = fma(f[l], gv.x, x);
-              if (l + 1 < r) x = fma(f[l + 1], gv.y, x);
-            } else {
-              x = fma(gv.x, f[l], x);
-              if (l + 1 < r) x = fma(gv.y, f[l + 1], x);
+        for (int q = 0; q < kBatch; ++q) {
+          const T *g = other + (size_t)jj[q] * rs;
+#pragma unroll
+          for (int l = 0; l < RB; l += 2)
+            if (l < r) gv[q][l / 2] = *reinterpret_cast<const typename Vec2<T>::type *>(g + l);
+        }
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+          T xx = (T)0;
+#pragma unroll
+          for (int l = 0; l < RB; l += 2) {
+            if (l < r) {
+              if (row_side_is_u) {
+                xx = fma(f[l], gv[q][l / 2].x, xx);
+                if (l + 1 < r) xx = fma(f[l + 1], gv[q][l / 2].y, xx);
+              } else {
+                xx = fma(gv[q][l / 2].x, f[l], xx);
+                if (l + 1 < r) xx = fma(gv[q][l / 2].y, f[l + 1], xx);
+              }
             }
           }
+          x[q] = xx;
         }
       } else {
-        x = row_side_is_u ? sampled_dot<T>(fixed, g, r) : sampled_dot<T>(g, fixed, r);
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+          const T *g = other + (size_t)jj[q] * rs;
+          x[q] = row_side_is_u ? sampled_dot<T>(fixed, g, r) : sampled_dot<T>(g, fixed, r);
+        }
       }
-      const T e = M[t] - x;
-      Y[t] = fma(delta, e, Y[t]);
-      const T yk = fma(e, e, -comp);
-      const T tk = sum + yk;
-      comp = (tk - sum) - yk;
-      sum = tk;
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        const int t = t0 + q * L;
+        if (t < end) {
+          const T e = mv[q] - x[q];
+          Y[t] = fma(delta, e, yv[q]);
+          const T yk = fma(e, e, -comp);
+          const T tk = sum + yk;
+          comp = (tk - sum) - yk;
+          sum = tk;
+        }
+      }
     }
   }
   if (part_out == nullptr) return;  // uniform: no residual wanted
