@@ -6,7 +6,7 @@ compare against the stored files.  Run from the repository root:
     python tests/golden/make_oracle_goldens.py 1   # 400 x 400, rank 10: tier A (dense Jacobi)
     python tests/golden/make_oracle_goldens.py 2   # 5000 x 5000, rank 10: tier B (Gram matrix)
     python tests/golden/make_oracle_goldens.py 2 60   # the same, X at iteration 60 (eps = 0)
-    python tests/golden/make_oracle_goldens.py 3   # 10000 x 10000, rank 50: tier B
+    python tests/golden/make_oracle_goldens.py 3 40   # 10000 x 10000, rank 50: tier B, X at iteration 40
 
 With a second argument k the run stops after k iterations with eps = 0, and
 the file holds X^k: a fixed-iteration comparison point for trajectories

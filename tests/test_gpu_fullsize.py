@@ -4,6 +4,8 @@
   runs: at a fixed iteration (60) FP64 with the same ranks and X within
   1e-8, mixed within 5e-4; the complete runs by their shared history, their
   distance to the oracle's result and to the truth;
+* 10000 x 10000, rank 50, |Omega| = 4 d_r against the stored oracle's X at
+  iteration 40 (FP64 within 1e-8, mixed within 5e-4);
 * 10000 x 10000 (rank 50) and 30000 x 30000 (rank 10) in the configuration
   the bench times, by properties that hold at any size: the reported residual
   equals the one recomputed in FP64 from the returned factors, the final rank
@@ -94,6 +96,22 @@ def test_5000_complete_run_against_stored_oracle(precision):
     assert rel_diff_factored(g["U"], g["V"], o["U"], o["V"]) <= 5e-4
     assert rel_diff_factored(g["U"], g["V"], p.ML, p.MR) < 2e-4
     assert abs(g["info"]["iters"] - o["iters"]) <= 30
+
+
+@pytest.mark.parametrize("precision", [B.SVT_FP64, B.SVT_MIXED])
+def test_10000_rank50_matches_stored_oracle_at_iteration_40(precision):
+    # 10000 x 10000, rank 50, |Omega| = 4 d_r: the oracle's X at iteration 40
+    # (eps = 0), stored; FP64 to 1e-8 with the same ranks, mixed to 5e-4
+    gpu_case(f"10000^2 rank 50 precision {precision}, 40 iterations vs stored tier-B oracle")
+    p = workload.config(3)
+    o = _gold("3_k40")
+    g = _solve_fixed(p, precision, 40)
+    assert g["status"] == B.SVT_NOT_CONVERGED and g["info"]["iters"] == 40 == o["iters"]
+    assert g["info"]["k0"] == o["k0"]
+    assert list(g["ranks"]) == o["ranks"]
+    tol = 1e-8 if precision == B.SVT_FP64 else 5e-4
+    np.testing.assert_allclose(g["residuals"], o["residuals"], rtol=tol)
+    assert rel_diff_factored(g["U"], g["V"], o["U"], o["V"]) <= tol
 
 
 @pytest.mark.parametrize("cfg,precision", [(3, B.SVT_MIXED), (4, B.SVT_MIXED), (4, B.SVT_FP64)])
