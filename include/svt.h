@@ -72,9 +72,13 @@ typedef struct {
                             value; 0 = automatic: 1e-12 FP64, 1e-6 MIXED       */
   int32_t lanczos_maxsteps; /* cap on bidiagonalisation steps per SVT step
                                (0 = min(m, n))                                 */
-  int32_t reorth_passes; /* 0 or 2; both run classical Gram-Schmidt twice
-                            (CGS2) on every new basis vector (0 is reserved
-                            for a conditional second pass, not built)        */
+  int32_t reorth_passes; /* classical Gram-Schmidt against the whole basis:
+                            0 (default) one pass per vector, recording the
+                            fraction of the vector's |.|^2 it removes; if a
+                            pass removed more than 1/2 (the DGKS criterion)
+                            the bidiagonalisation restarts with two passes,
+                            kept for the rest of the solve; 1 always one
+                            pass; 2 always two (CGS2)                        */
   double decide_margin;  /* the rank decision accepts an unconverged Ritz value
                             below tau only if value + residual <= tau (1 -
                             margin) and a Ritz value above tau has already

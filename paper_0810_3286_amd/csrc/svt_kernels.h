@@ -78,13 +78,16 @@ hipError_t launch_spmv(hipStream_t s, const SpmvPlan &pl, const int32_t *ptr, co
                        double *dots_out);
 
 // One classical Gram-Schmidt update of p (length nrows, overwritten)
-// against the nq >= 1 orthonormal columns of Q, with coefficients summed from
-// the nq + 1 columns of part_in.  second = false: part_out receives the next
-// pass's partial dot products (nq + 1 columns); second = true: the |p|^2
-// partials (one column).  Two calls after launch_spmv's dots make CGS2.
+// against the nq >= 1 orthonormal columns of Q, with coefficients h summed
+// from the nq + 1 columns of part_in (column nq: |p|^2).  second = false:
+// part_out receives the next pass's partial dot products (nq + 1 columns);
+// second = true: the |p|^2 partials of the result (one column).  One call
+// with second = true after launch_spmv's dots is one pass; a call with
+// second = false and one with second = true make CGS2.  removed (may be
+// null): receives |h|^2 / |p|^2.
 template <typename T>
 hipError_t launch_gs_update(hipStream_t s, T *p, int nrows, const T *Q, int64_t ldq, int nq,
-                            const double *part_in, double *part_out, bool second);
+                            const double *part_in, double *part_out, bool second, double *removed);
 
 // |p|^2 partials (one column).
 template <typename T>

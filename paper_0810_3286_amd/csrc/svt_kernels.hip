@@ -415,11 +415,22 @@ __device__ void reduce_columns(const double *__restrict__ part, int np, int C, d
 // group sums of a row are added in group order.  SECOND = false: the partial
 // dot products of the new p with Q and itself follow (the second pass's
 // coefficients); SECOND = true: only the |p|^2 partials.
+// Fraction of |p|^2 that the pass removes, |h|^2 / |p|^2 (h = Q^T p in hs,
+// |p|^2 in hs[nq]), written by workgroup 0 to *removed (when not null):
+// the orthogonality check of a one-pass reorthogonalisation.
+__device__ __forceinline__ void record_removed(const double *hs, int nq, double *removed) {
+  if (removed == nullptr || blockIdx.x != 0 || threadIdx.x != 0) return;
+  double hh = 0.0;
+  for (int c = 0; c < nq; ++c) hh = fma(hs[c], hs[c], hh);
+  *removed = hs[nq] > 0.0 ? hh / hs[nq] : 0.0;
+}
+
 template <typename T, bool SECOND>
 __global__ __launch_bounds__(kRowBlock) void k_gs_update(T *__restrict__ p, int nrows, int rows_per_blk,
                                                          const T *__restrict__ Q, int64_t ldq, int nq,
                                                          const double *__restrict__ part_in, int np_in,
-                                                         double *__restrict__ part_out) {
+                                                         double *__restrict__ part_out,
+                                                         double *__restrict__ removed) {
   extern __shared__ double smem[];
   double *hs = smem;                       // nq + 1 coefficients
   double *pc = hs + nq + 1;                // rows_per_blk values of the new p
@@ -440,6 +451,7 @@ __global__ __launch_bounds__(kRowBlock) void k_gs_update(T *__restrict__ p, int 
     load_q8<T>(q, Q, ldq, nq, row, valid);
     const double p0 = (valid && g == 0) ? (double)p[row] : 0.0;
     reduce_columns(part_in, np_in, nq + 1, hs);
+    record_removed(hs, nq, removed);
     double a = 0.0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -467,6 +479,7 @@ __global__ __launch_bounds__(kRowBlock) void k_gs_update(T *__restrict__ p, int 
     return;
   }
   reduce_columns(part_in, np_in, nq + 1, hs);
+  record_removed(hs, nq, removed);
   const int last = nq - 1;
   for (int rb = r0; rb < r1; rb += kRowLanes) {
     const int row = rb + i;
@@ -856,7 +869,7 @@ size_t gs_update_lds(int nq, int rows_per_blk) {
 
 template <typename T>
 hipError_t launch_gs_update(hipStream_t s, T *p, int nrows, const T *Q, int64_t ldq, int nq,
-                            const double *part_in, double *part_out, bool second) {
+                            const double *part_in, double *part_out, bool second, double *removed) {
   const RowPlan rp = row_plan(nrows);
   if (nq < 1 || Q == nullptr) return hipErrorInvalidValue;
   const size_t lds = gs_update_lds(nq, rp.rows_per_blk);
@@ -865,13 +878,13 @@ hipError_t launch_gs_update(hipStream_t s, T *p, int nrows, const T *Q, int64_t 
     hipError_t e = allow_dynamic_lds(reinterpret_cast<const void *>(kern), lds);
     if (e != hipSuccess) return e;
     SVT_LAUNCH(kern, dim3(rp.nblk), dim3(kRowBlock), lds, s, p, nrows, rp.rows_per_blk, Q, ldq, nq, part_in,
-               rp.nblk, part_out);
+               rp.nblk, part_out, removed);
   } else {
     auto kern = k_gs_update<T, true>;
     hipError_t e = allow_dynamic_lds(reinterpret_cast<const void *>(kern), lds);
     if (e != hipSuccess) return e;
     SVT_LAUNCH(kern, dim3(rp.nblk), dim3(kRowBlock), lds, s, p, nrows, rp.rows_per_blk, Q, ldq, nq, part_in,
-               rp.nblk, part_out);
+               rp.nblk, part_out, removed);
   }
   return hipGetLastError();
 }
@@ -968,7 +981,7 @@ hipError_t launch_gather(hipStream_t s, const T *x, const int32_t *map, T *y, in
                                      double *, int, const T *, T *, int, const T *, int64_t, int,      \
                                      double *);                                                        \
   template hipError_t launch_gs_update<T>(hipStream_t, T *, int, const T *, int64_t, int, const double *, \
-                                          double *, bool);                                             \
+                                          double *, bool, double *);                                   \
   template hipError_t launch_sumsq<T>(hipStream_t, const T *, int, double *);                          \
   template hipError_t launch_finalize<T>(hipStream_t, const T *, int, const double *, T *, double *);   \
   template hipError_t launch_randn<T>(hipStream_t, T *, int, uint64_t, uint64_t);                  \

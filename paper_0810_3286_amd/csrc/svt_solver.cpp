@@ -280,7 +280,7 @@ struct Problem final : ProblemBase {
   DevMem Ub, Vb;                  // bases, T, column-major
   int kcap = 0;                   // columns available in Ub (Vb has kcap + 1)
   DevMem pbuf_u, pbuf_v;          // unnormalised new vectors of each side, T
-  DevMem coef;                    // alpha[0..], beta[0..], double, 2 (kcap + 4)
+  DevMem coef;                    // alpha[0..], beta[0..], removed[0..]: double, 4 (kcap + 4)
   DevMem gs1, gs2, gs3;           // Gram-Schmidt partial sums
   GsScratch gs{};
   DevMem sample_part;             // residual partials, kSampleMaxBlocks + 8 doubles
@@ -299,11 +299,17 @@ struct Problem final : ProblemBase {
   int k_hint = 0;
   int log_level = 0;
   int64_t steps_total = 0;
+  double reorth_trigger = 0.5;
+  int passes_now = 2;          // Gram-Schmidt passes per vector right now
+  int64_t reorth_restarts = 0; // bidiagonalisations restarted with two passes
 
   // ----------------------------------------------------------------- setup
   void setup(const svt_params &p) {
     prm = p;
     if (const char *lv = std::getenv("SVT_LOG")) log_level = std::atoi(lv);
+    // the one-pass check's threshold (test hook; default 1/2, the DGKS
+    // criterion with eta = 1/sqrt(2))
+    if (const char *tv = std::getenv("SVT_REORTH_TRIGGER")) reorth_trigger = std::atof(tv);
     HIP_CHECK(hipGetDevice(&device));
     if (p.stream) {
       stream = static_cast<hipStream_t>(p.stream);
@@ -384,7 +390,7 @@ struct Problem final : ProblemBase {
     DevMem nU, nV, ncoef, n1, n2, n3;
     nU.alloc(sizeof(T) * (size_t)arows * (size_t)(newcap + 1));
     nV.alloc(sizeof(T) * (size_t)acols * (size_t)(newcap + 2));
-    ncoef.alloc(sizeof(double) * 2 * (size_t)(newcap + 4));
+    ncoef.alloc(sizeof(double) * 4 * (size_t)(newcap + 4));
     const int cols = newcap + 4;
     const int blocks = std::max(row_plan((int)arows).nblk, row_plan((int)acols).nblk);
     n1.alloc(sizeof(double) * (size_t)cols * blocks);
@@ -400,6 +406,8 @@ struct Problem final : ProblemBase {
       HIP_CHECK(hipMemcpyAsync(ncoef.as<double>(), coef.as<double>(), sizeof(double) * (kcap + 4), hipMemcpyDeviceToDevice, stream));
       HIP_CHECK(hipMemcpyAsync(ncoef.as<double>() + (newcap + 4), coef.as<double>() + (kcap + 4),
                                sizeof(double) * (kcap + 4), hipMemcpyDeviceToDevice, stream));
+      HIP_CHECK(hipMemcpyAsync(ncoef.as<double>() + 2 * (newcap + 4), coef.as<double>() + 2 * (kcap + 4),
+                               sizeof(double) * 2 * (kcap + 4), hipMemcpyDeviceToDevice, stream));
     }
     HIP_CHECK(hipStreamSynchronize(stream));
     std::swap(Ub.p, nU.p); std::swap(Ub.bytes, nU.bytes);
@@ -418,6 +426,9 @@ struct Problem final : ProblemBase {
 
   double *alpha_d() { return coef.as<double>(); }                 // alpha_{i+1} at [i]
   double *beta_d() { return coef.as<double>() + (kcap + 4); }     // beta_{i+1} at [i]
+  // fraction of |p|^2 removed by the one-pass reorthogonalisation of
+  // half-step j (j = 0, 1 in gkl_start, 2k and 2k + 1 in step k)
+  double *removed_d() { return coef.as<double>() + 2 * (kcap + 4); }
   T *ucol(int i) { return Ub.as<T>() + (size_t)i * (size_t)arows; }
   T *vcol(int i) { return Vb.as<T>() + (size_t)i * (size_t)acols; }
 
@@ -501,7 +512,7 @@ struct Problem final : ProblemBase {
   // new vector, orthogonalised against the nq columns of Q and left
   // unnormalised in p with its |.|^2 partials in gs.part3.
   void half_step(const Csx &c, const T *vals, const T *x_raw, int xnp, T *x_col, double *x_coef,
-                 const T *prev, T *Q, int64_t ldq, int nq, T *p) {
+                 const T *prev, T *Q, int64_t ldq, int nq, T *p, int j) {
     const double vb = sizeof(T);
     const double len = (double)c.nrows;
     // algorithmic bytes: the product's (spmv_bytes), the normalised x written
@@ -515,11 +526,19 @@ struct Problem final : ProblemBase {
     }
     // each update: Q read once, p read and written (the fused dot products
     // and norms reuse the same rows)
+    if (passes_now == 1) {
+      // one pass; its removed fraction goes to slot j for the check
+      double *rem = prm.reorth_passes == 0 ? removed_d() + j : nullptr;
+      prof.begin();
+      HIP_CHECK(launch_gs_update<T>(stream, p, c.nrows, Q, ldq, nq, gs.part1, gs.part3, true, rem));
+      prof.end(kGsUpdate2, vb * len * (nq + 2.0));
+      return;
+    }
     prof.begin();
-    HIP_CHECK(launch_gs_update<T>(stream, p, c.nrows, Q, ldq, nq, gs.part1, gs.part2, false));
+    HIP_CHECK(launch_gs_update<T>(stream, p, c.nrows, Q, ldq, nq, gs.part1, gs.part2, false, nullptr));
     prof.end(kGsUpdate1, vb * len * (nq + 2.0));
     prof.begin();
-    HIP_CHECK(launch_gs_update<T>(stream, p, c.nrows, Q, ldq, nq, gs.part2, gs.part3, true));
+    HIP_CHECK(launch_gs_update<T>(stream, p, c.nrows, Q, ldq, nq, gs.part2, gs.part3, true, nullptr));
     prof.end(kGsUpdate2, vb * len * (nq + 2.0));
   }
 
@@ -528,6 +547,7 @@ struct Problem final : ProblemBase {
     int k = 0;                // completed steps: u_1..u_k, v_1..v_k, raw v_{k+1}
     bool finalized = false;   // v_{k+1} and beta_{k+1} stored
     std::vector<double> alpha, beta;  // host copies, alpha[i] = alpha_{i+1}, beta[i] = beta_{i+1}
+    std::vector<double> removed;      // removed fraction of each one-pass half-step
   };
 
   int xnp_of(int nrows) const { return row_plan(nrows).nblk; }
@@ -540,10 +560,10 @@ struct Problem final : ProblemBase {
     HIP_CHECK(launch_sumsq<T>(stream, pbuf_v.as<T>(), (int)acols, gs.part3));
     // u_1 = A v_1 / alpha_1 (v_1 = the normalised start vector)
     half_step(R, vr, pbuf_v.as<T>(), xnp_of((int)acols), vcol(0), beta_d(), nullptr, Ub.as<T>(), arows, 0,
-              pbuf_u.as<T>());
+              pbuf_u.as<T>(), 0);
     // v_2 = A^T u_1 - alpha_1 v_1, orthogonal to v_1
     half_step(C, vc, pbuf_u.as<T>(), xnp_of((int)arows), ucol(0), alpha_d(), vcol(0), Vb.as<T>(), acols, 1,
-              pbuf_v.as<T>());
+              pbuf_v.as<T>(), 1);
     g.k = 1;
     g.finalized = false;
     steps_total += 1;
@@ -556,10 +576,10 @@ struct Problem final : ProblemBase {
     const Csx R = a_rows_struct(), C = a_cols_struct();
     // u_{k+1} = A v_{k+1} - beta_{k+1} u_k, orthogonal to u_1..u_k
     half_step(R, vr, pbuf_v.as<T>(), xnp_of((int)acols), vcol(k), beta_d() + k, ucol(k - 1), Ub.as<T>(), arows,
-              k, pbuf_u.as<T>());
+              k, pbuf_u.as<T>(), 2 * k);
     // v_{k+2} = A^T u_{k+1} - alpha_{k+1} v_{k+1}, orthogonal to v_1..v_{k+1}
     half_step(C, vc, pbuf_u.as<T>(), xnp_of((int)arows), ucol(k), alpha_d() + k, vcol(k), Vb.as<T>(), acols,
-              k + 1, pbuf_v.as<T>());
+              k + 1, pbuf_v.as<T>(), 2 * k + 1);
     g.k = k + 1;
     g.finalized = false;
     steps_total += 1;
@@ -574,7 +594,8 @@ struct Problem final : ProblemBase {
       HIP_CHECK(launch_finalize<T>(stream, pbuf_v.as<T>(), (int)acols, gs.part3, vcol(k), beta_d() + k));
       g.finalized = true;
     }
-    const size_t span = (size_t)(kcap + 4) + (size_t)(k + 1);
+    // alpha, beta and the removed fractions of half-steps 0 .. 2k - 1
+    const size_t span = 2 * (size_t)(kcap + 4) + 2 * (size_t)k;
     coef_host.ensure(sizeof(double) * span);
     HIP_CHECK(hipMemcpyAsync(coef_host.p, alpha_d(), sizeof(double) * span, hipMemcpyDeviceToHost, stream));
     if (!fetch_ev) HIP_CHECK(hipEventCreateWithFlags(&fetch_ev, hipEventDisableTiming));
@@ -593,6 +614,7 @@ struct Problem final : ProblemBase {
     snap.finalized = true;
     snap.alpha.assign(h, h + k);
     snap.beta.assign(h + (fetch_kcap + 4), h + (fetch_kcap + 4) + (k + 1));
+    snap.removed.assign(h + 2 * (fetch_kcap + 4), h + 2 * (fetch_kcap + 4) + 2 * k);
   }
 
   // B_k as diagonal d and superdiagonal e.
@@ -641,8 +663,9 @@ struct Problem final : ProblemBase {
     const double tol = prm.lanczos_tol;
     const int cap = step_cap();
     gkl_start(vr, vc, g);
-    int next_check = std::max(std::min(cap, mode == 1 ? count + 2 : 3), std::min(cap, k_hint - 2));
-    next_check = std::max(next_check, 1);
+    int first_check = std::max(std::min(cap, mode == 1 ? count + 2 : 3), std::min(cap, k_hint - 2));
+    first_check = std::max(first_check, 1);
+    int next_check = first_check;
     std::vector<double> res;
     Gkl snap;
     for (;;) {
@@ -654,6 +677,31 @@ struct Problem final : ProblemBase {
       gkl_fetch_begin(g);
       for (int a = 0; a < kAheadSteps && g.k < cap; ++a) gkl_step(vr, vc, g);
       gkl_fetch_end(snap);
+      if (prm.reorth_passes == 0 && passes_now == 1) {
+        // one pass per vector is enough while no pass removes a large part
+        // of its vector (the vector then already was nearly orthogonal, as
+        // the recurrence makes it in exact arithmetic); a pass that removed
+        // more than reorth_trigger of |p|^2 (DGKS: 1/2) left the basis less
+        // orthogonal than two passes would: start this bidiagonalisation
+        // again with two passes, and keep them for the rest of the solve
+        double worst = 0.0;
+        bool bad = false;
+        for (int j = 1; j < 2 * snap.k; ++j) {
+          const double f = snap.removed[(size_t)j];
+          if (!(f <= reorth_trigger)) bad = true;  // also a non-finite value
+          if (f > worst) worst = f;
+        }
+        if (bad) {
+          passes_now = 2;
+          ++reorth_restarts;
+          if (log_level > 0)
+            std::fprintf(stderr, "[svt] one-pass reorthogonalisation removed %.3e of a vector by step %d: "
+                                 "restarting with two passes\n", worst, snap.k);
+          gkl_start(vr, vc, g);
+          next_check = first_check;
+          continue;
+        }
+      }
       BidiagSVD chk;
       gkl_ritz(snap, chk, res);
       const int k = snap.k;
@@ -803,7 +851,13 @@ struct Problem final : ProblemBase {
   }
 
   // -------------------------------------------------------------- solve
+  void reset_passes() {
+    passes_now = prm.reorth_passes == 2 ? 2 : 1;
+    reorth_restarts = 0;
+  }
+
   svt_status solve(svt_info *info) override {
+    reset_passes();
     history.clear();
     prof.reset();
     steps_total = 0;
@@ -936,6 +990,7 @@ struct Problem final : ProblemBase {
 
   int partial_svd(int count, double *sigma, double *U, double *V) override {
     if (count > acols) throw Error(SVT_EINVAL, "count exceeds min(m, n)");
+    reset_passes();
     Gkl g;
     BidiagSVD sv;
     int r = 0;
@@ -965,7 +1020,10 @@ struct Problem final : ProblemBase {
     return sample_pass(r, delta, true);
   }
 
-  void kick(double *sigma1, int32_t *k0) override { do_kick(sigma1, k0); }
+  void kick(double *sigma1, int32_t *k0) override {
+    reset_passes();
+    do_kick(sigma1, k0);
+  }
 
   ~Problem() override {
     if (stream) (void)hipStreamSynchronize(stream);
@@ -992,7 +1050,7 @@ static void validate_params(const svt_params &p) {
   if (p.stop_rule == SVT_STOP_NOISY && p.noise_sigma <= 0) throw Error(SVT_EINVAL, "the noisy stop rule needs noise_sigma > 0");
   if (!finite(p.lanczos_tol) || p.lanczos_tol < 0 || p.lanczos_tol >= 1) throw Error(SVT_EINVAL, "lanczos_tol must be in [0, 1)");
   if (p.lanczos_maxsteps < 0) throw Error(SVT_EINVAL, "lanczos_maxsteps must be >= 0");
-  if (p.reorth_passes != 0 && p.reorth_passes != 2) throw Error(SVT_EINVAL, "reorth_passes must be 0 or 2");
+  if (p.reorth_passes < 0 || p.reorth_passes > 2) throw Error(SVT_EINVAL, "reorth_passes must be 0, 1 or 2");
   if (!finite(p.decide_margin) || p.decide_margin < 0) throw Error(SVT_EINVAL, "decide_margin must be finite and >= 0");
   if (p.spmv_mode < 0 || p.spmv_mode > 2) throw Error(SVT_EINVAL, "spmv_mode must be 0, 1 or 2");
 }

@@ -89,7 +89,7 @@ def test_rejects_bad_parameters():
     vals = np.array([1.0, 2.0])
     for field, bad in [("tau", 0.0), ("tau", float("inf")), ("delta", -1.0), ("eps", -1e-3),
                        ("maxiter", 0), ("incr", 0), ("kick", 2), ("precision", 5),
-                       ("stop_rule", 3), ("lanczos_tol", 1.5), ("reorth_passes", 1),
+                       ("stop_rule", 3), ("lanczos_tol", 1.5), ("reorth_passes", 3),
                        ("decide_margin", -0.1), ("spmv_mode", 3)]:
         p = B.svt_params_default(2, 2, 2)
         setattr(p, field, bad)
