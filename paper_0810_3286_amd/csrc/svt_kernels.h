@@ -64,18 +64,50 @@ struct SpmvPlan {
 };
 SpmvPlan spmv_plan(int nrows, int ncols, int elem_bytes, int lds_bytes, int mode);
 
-// p = A (x / s) - s prev with s^2 the sum of the xnp partials in xpart
-// (xpart null: s = 1, x already normalised; prev may be null).  With x_out
-// non-null the normalised x is written to x_out (ncols entries) and s to
-// *s_out: the previous half-step's vector joins its basis.  segptr: nrows x
-// (nseg + 1) segment starts (null unless nseg > 1).  With dots_out non-null
-// the kernel also writes the first Gram-Schmidt pass's partial dot products
-// of p with the nq columns of Q and |p|^2 (column nq): nq + 1 columns.
+// The input of a sparse product: the other side's new vector x (ncols
+// entries) as the previous half-step left it, with its one-pass
+// reorthogonalisation still pending.  pend holds nqx + 1 columns of np
+// partials (row_plan of x's length): x's dot products with the nqx columns
+// of its basis Q_x, then |x|^2.  The product uses x' = (x - Q_x h) / s, h
+// the column sums, s = sqrt(|x|^2 - |h|^2); nqx = 0: x' = x / |x|; pend
+// null: x' = x.  alpha and beta (device, alpha[c] = alpha_{c+1}, beta[c] =
+// beta_{c+1}) give the image of Q_x h through the bidiagonal relations; side
+// 0: the product is A v (x on the v side), 1: A^T u.
+constexpr int kSpmvAuxCols = 1024;  // largest nqx + side fused into the product
+constexpr long kSpmvAuxBytes = (long)sizeof(double) * (2 * kSpmvAuxCols + 2);
+template <typename T>
+struct SpmvInput {
+  const T *x = nullptr;
+  const double *pend = nullptr;
+  int np = 0;
+  const T *Qx = nullptr;          // x's basis, column-major, leading dimension ldqx
+  int64_t ldqx = 0;
+  int nqx = 0;
+  T *x_out = nullptr;             // receives x' (may be null)
+  double *s_out = nullptr;        // receives s (may be null)
+  double *removed_out = nullptr;  // receives |h|^2 / |x|^2 (may be null)
+  const double *alpha = nullptr, *beta = nullptr;
+  int side = 0;
+};
+
+// p = A x' - s prev over nrows rows (prev may be null), x' as above; with
+// nqx > 0 it is taken as (A x - Q g) / s - s prev, where Q must hold the nq
+// = nqx + side basis columns of p's side.  segptr: nrows x (nseg + 1)
+// segment starts (null unless nseg > 1).  With dots_out non-null the kernel
+// also writes the partial dot products of p with the nq columns of Q and
+// |p|^2 (column nq): nq + 1 columns, p's own pending update.  Returns
+// hipErrorInvalidValue for inconsistent arguments (nqx > 0 with a missing
+// pointer, nq != nqx + side, or nq > kSpmvAuxCols).
 template <typename T>
 hipError_t launch_spmv(hipStream_t s, const SpmvPlan &pl, const int32_t *ptr, const int32_t *idx, const T *val,
-                       const int32_t *segptr, const T *x, const double *xpart, int xnp, T *x_out, double *s_out,
-                       int ncols, const T *prev, T *p, int nrows, const T *Q, int64_t ldq, int nq,
-                       double *dots_out);
+                       const int32_t *segptr, const SpmvInput<T> &in, int ncols, const T *prev, T *p, int nrows,
+                       const T *Q, int64_t ldq, int nq, double *dots_out);
+
+// s (and |h|^2 / |x|^2) of a pending vector, exactly as the sparse product
+// that consumes it computes them: *s_out, *removed_out (may be null).
+// nqx <= kSpmvAuxCols.
+hipError_t launch_pending_norm(hipStream_t s, const double *pend, int np, int nqx, double *s_out,
+                               double *removed_out);
 
 // One classical Gram-Schmidt update of p (length nrows, overwritten)
 // against the nq >= 1 orthonormal columns of Q, with coefficients h summed

@@ -12,7 +12,11 @@
 //     per workgroup, and every workgroup of the next kernel sums those
 //     partials itself, in the same fixed order, so all of them hold the same
 //     coefficients and the results do not depend on scheduling;
-//   * reorthogonalisation is classical Gram-Schmidt applied twice (CGS2);
+//   * full reorthogonalisation is one classical Gram-Schmidt pass, and its
+//     update is deferred into the next sparse product (the product of the
+//     basis with the coefficients follows from the bidiagonal relations), so
+//     a half-step of the bidiagonalisation is one kernel; after a failed
+//     orthogonality check the solver switches to two explicit passes (CGS2);
 //     the bidiagonalisation coefficients stay on the device within a step.
 #include "svt_kernels.h"
 
@@ -89,36 +93,6 @@ template <typename T> __device__ __forceinline__ double norm_floor();
 template <> __device__ __forceinline__ double norm_floor<double>() { return 1e-280; }
 template <> __device__ __forceinline__ double norm_floor<float>() { return 1e-30; }
 
-// Lazy normalisation of the input vector of a sparse product: x = x_raw / s
-// with s^2 the sum of the np partials in xpart (every workgroup sums them in
-// the same order).  Returns s (1 when xpart is null: x_raw is normalised).
-__device__ __forceinline__ double input_norm(const double *__restrict__ xpart, int np, double *sh) {
-  if (xpart == nullptr) return 1.0;
-  double v = 0.0;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) v += xpart[i];
-  v = seg_sum<kWave>(v);
-  const int w = threadIdx.x / kWave, wl = threadIdx.x % kWave, nw = blockDim.x / kWave;
-  if (wl == 0) sh[w] = v;
-  __syncthreads();
-  double t = 0.0;
-  for (int i = 0; i < nw; ++i) t += sh[i];
-  __syncthreads();
-  return sqrt(t);
-}
-
-// Workgroup b writes x_raw[i] / s for its slice of [0, ncols) into x_out and
-// workgroup 0 stores s: the normalised vector joins its basis.
-template <typename T>
-__device__ __forceinline__ void write_normalised(const T *__restrict__ x_raw, int ncols, double s,
-                                                 T *__restrict__ x_out, double *__restrict__ s_out) {
-  if (x_out == nullptr) return;
-  const double inv = (s > norm_floor<T>()) ? 1.0 / s : 0.0;
-  const int chunk = (ncols + gridDim.x - 1) / gridDim.x;
-  const int i0 = blockIdx.x * chunk, i1 = min(ncols, i0 + chunk);
-  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) x_out[i] = (T)((double)x_raw[i] * inv);
-  if (blockIdx.x == 0 && threadIdx.x == 0 && s_out) *s_out = s;
-}
-
 // ---------------------------------------------------------------------------
 // Row-range kernels: kRowBlock threads own the rows [r0, r0 + rows_per_blk)
 // of a vector (row_plan); the sparse product and both Gram-Schmidt updates
@@ -140,6 +114,107 @@ __device__ __forceinline__ double row_block_sum(double v, double *sh /* kRowWave
     for (int i = 0; i < kRowWaves; ++i) t += sh[i];
   __syncthreads();
   return t;
+}
+
+// hs[c] = sum_i part[c * np + i] for c < C, into LDS.  Wave w takes the
+// columns w, w + 16, ... four at a time; its lanes read consecutive partials
+// of a column (coalesced: a column's np partials are contiguous), add their
+// own ones in index order and the 64 lane sums reduce by a shuffle tree.  The
+// order does not depend on the workgroup, so every workgroup holds the same
+// values.
+__device__ void reduce_columns(const double *__restrict__ part, int np, int C, double *hs) {
+  const int w = threadIdx.x / kWave, wl = threadIdx.x % kWave;
+  for (int cb = w; cb < C; cb += 4 * kRowWaves) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i0 = 0; i0 < np; i0 += 4 * kWave) {
+      double v[4][4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int c = cb + k * kRowWaves;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int ii = i0 + j * kWave + wl;
+          v[k][j] = (c < C && ii < np) ? part[(size_t)c * np + ii] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[k] += v[k][j];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double t = seg_sum<kWave>(acc[k]);
+      const int c = cb + k * kRowWaves;
+      if (wl == 0 && c < C) hs[c] = t;
+    }
+  }
+  __syncthreads();
+}
+
+// A pending one-pass reorthogonalisation (the bidiagonalisation of Section
+// 5.1.1 with full reorthogonalisation): the new vector x of one side is kept
+// unorthogonalised, with the partials of its dot products with the nqx basis
+// columns Q_x of its side (columns 0 .. nqx - 1 of pend) and of |x|^2
+// (column nqx).  pending_norm sums them into hs (h = hs[0 .. nqx), |x|^2 =
+// hs[nqx]) and returns s = |x - Q_x h| = sqrt(|x|^2 - |h|^2) (Q_x
+// orthonormal); *hh receives |h|^2.  Every workgroup computes the same values
+// in the same order.  kRowBlock threads; ends synchronised.
+__device__ double pending_norm(const double *__restrict__ pend, int np, int nqx, double *hs, double *hh) {
+  reduce_columns(pend, np, nqx + 1, hs);
+  if (threadIdx.x < kWave) {
+    double t = 0.0;
+    for (int c = threadIdx.x; c < nqx; c += kWave) t = fma(hs[c], hs[c], t);
+    t = seg_sum<kWave>(t);
+    if (threadIdx.x == 0) *hh = t;
+  }
+  __syncthreads();
+  return sqrt(fmax(hs[nqx] - *hh, 0.0));
+}
+
+// Workgroup b writes x_out[i] = (x[i] - sum_c Qx[i, c] h[c]) * inv for its
+// slice of [0, ncols) (ceil(ncols / gridDim.x) entries): the pending vector,
+// orthogonalised and normalised, joins its basis.  Thread (row slot i, column
+// group g) adds the columns g + 8 j of each 64-column pass in order; the
+// eight group sums of an entry are added in group order (upd: kRowBlock
+// doubles of LDS).  The result does not depend on the slicing.
+template <typename T>
+__device__ void write_corrected(const T *__restrict__ x, int ncols, const T *__restrict__ Qx, int64_t ldqx,
+                                int nqx, const double *h, double inv, T *__restrict__ x_out, double *upd) {
+  const int chunk = (ncols + gridDim.x - 1) / gridDim.x;
+  const int i0 = blockIdx.x * chunk, i1 = min(ncols, i0 + chunk);
+  if (nqx == 0) {
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) x_out[i] = (T)((double)x[i] * inv);
+    return;
+  }
+  const int il = threadIdx.x % kRowLanes, g = threadIdx.x / kRowLanes;
+  const int last = nqx - 1;
+  for (int rb = i0; rb < i1; rb += kRowLanes) {
+    const int row = rb + il;
+    const bool valid = row < i1;
+    double a = 0.0;
+    if (valid) {
+      for (int cb = 0; cb < nqx; cb += kColsPerPass) {
+        T q[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) q[j] = Qx[(size_t)min(cb + g + 8 * j, last) * ldqx + row];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int c = cb + g + 8 * j;
+          if (c < nqx) a = fma((double)q[j], h[c], a);
+        }
+      }
+    }
+    upd[g * kRowLanes + il] = a;
+    __syncthreads();
+    if (g == 0 && valid) {
+      double tot = 0.0;
+#pragma unroll
+      for (int gg = 0; gg < kColGroups; ++gg) tot += upd[gg * kRowLanes + il];
+      x_out[row] = (T)(((double)x[row] - tot) * inv);
+    }
+    __syncthreads();
+  }
 }
 
 // Partial dot products of the workgroup's rows: part[c * gridDim.x + b] =
@@ -247,47 +322,91 @@ __device__ __forceinline__ void load_q8(T (&q)[8], const T *__restrict__ Q, int6
   for (int j = 0; j < 8; ++j) q[j] = (valid && nq > 0) ? Q[(size_t)min(g + 8 * j, last) * ldq + row] : (T)0;
 }
 
-// p = A (x_raw / s) - s prev over one compressed orientation, s from xpart
-// (input_norm); with x_out, the normalised x is also written out (the
-// previous half-step's vector joins its basis).  STAGE: x is copied into LDS
-// in nseg column segments of segcols entries (coalesced, every thread's loads
-// issued before its stores) and the per-entry gathers hit LDS; otherwise they
-// gather x from memory.  segptr[row * (nseg + 1) + s] is the first entry of
-// segment s of the row (null when nseg == 1: ptr is used).  L lanes take a
-// row and each lane keeps kSpmvUnroll entries in flight, accumulating them in
-// index order (the result does not depend on the unrolling).  With part_out,
-// the first Gram-Schmidt pass's partial dot products of p with the nq
-// columns of Q (and |p|^2) follow in the same kernel (row_dots).
+// The sparse product of one bidiagonalisation half-step, p = A x - s prev
+// over one compressed orientation, with x = (x_raw - Q_x h) / s the pending
+// vector of the other side (pending_norm; in.pend null: x_raw is normalised,
+// s = 1; nqx = 0: x = x_raw / s).  Workgroups also write x to in.x_out
+// (write_corrected) and workgroup 0 writes s and |h|^2 / |x_raw|^2.
+//
+// The product is taken of x_raw: A Q_x h = Q g with g from the bidiagonal
+// relations (A v_c = beta_c u_{c-1} + alpha_c u_c and A^T u_c = alpha_c v_c +
+// beta_{c+1} v_{c+1}, valid to rounding for the stored, reorthogonalised
+// vectors), so p = (A x_raw - Q g) / s - s prev needs only the rows of Q the
+// workgroup owns, not all of Q_x.  side 0 (p on the u side, x on the v side,
+// nq = nqx): g[c] = alpha[c] h[c] + beta[c + 1] h[c + 1]; side 1 (nq = nqx +
+// 1): g[c] = alpha[c] h[c] + beta[c] h[c - 1] (terms with indices outside h
+// vanish).  alpha[c], beta[c]: alpha_{c+1}, beta_{c+1}.
+//
+// STAGE: x_raw is copied into LDS in nseg column segments of segcols entries
+// (coalesced, every thread's loads issued before its stores) and the
+// per-entry gathers hit LDS; otherwise they gather x_raw from memory.
+// segptr[row * (nseg + 1) + s] is the first entry of segment s of the row
+// (null when nseg == 1: ptr is used).  L lanes take a row and each lane keeps
+// kSpmvUnroll entries in flight, accumulating them in index order (the
+// result does not depend on the unrolling).  With part_out, the partial dot
+// products of p with the nq columns of Q and |p|^2 follow in the same kernel
+// (row_dots): p's own pending one-pass update.
+//
+// Dynamic LDS: the row sums (16-byte aligned); a region of max(x's segment,
+// kDotsLds) bytes rounded up to 16, holding x's segment during the product
+// and partial sums and the dot products' scratch before and after it; then
+// kSpmvAuxBytes for h and g.
 constexpr int kSpmvUnroll = 16;
 constexpr int kStageUnroll = 16;
 
 template <typename T, int L, bool STAGE>
 __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
     const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx, const T *__restrict__ val,
-    const int32_t *__restrict__ segptr, int nseg, int segcols, const T *__restrict__ x,
-    const double *__restrict__ xpart, int xnp, T *__restrict__ x_out, double *__restrict__ s_out, int ncols,
+    const int32_t *__restrict__ segptr, int nseg, int segcols, const SpmvInput<T> in, int ncols,
     const T *__restrict__ prev, T *__restrict__ p, int nrows, int rows_per_blk, const T *__restrict__ Q,
     int64_t ldq, int nq, double *__restrict__ part_out) {
   extern __shared__ double smem_d[];
-  __shared__ double sh[kRowWaves];
   __shared__ double sred[kRowWaves][8];
+  __shared__ double hh_s;
   T *racc = reinterpret_cast<T *>(smem_d);  // rows_per_blk row sums, then the rows of p
-  // after racc (16-byte aligned): segcols entries of x (STAGE), reused by the
-  // fused dot products once the product is done
-  char *region = reinterpret_cast<char *>(smem_d) + ((sizeof(T) * rows_per_blk + 15) / 16) * 16;
-  T *xs = reinterpret_cast<T *>(region);
+  const size_t racc_bytes = ((sizeof(T) * rows_per_blk + 15) / 16) * 16;
+  char *region = reinterpret_cast<char *>(smem_d) + racc_bytes;
+  const size_t xseg_bytes = sizeof(T) * (size_t)segcols;
+  const size_t region_bytes = ((xseg_bytes > (size_t)kDotsLds ? xseg_bytes : (size_t)kDotsLds) + 15) / 16 * 16;
+  T *xs = reinterpret_cast<T *>(region);            // x's segment (STAGE)
+  double *upd = reinterpret_cast<double *>(region);  // kRowBlock partial sums (before and after the product)
+  double *hs = reinterpret_cast<double *>(region + region_bytes);  // h, |x_raw|^2: kSpmvAuxCols + 1
+  double *gl = hs + kSpmvAuxCols + 1;                                 // g: kSpmvAuxCols
+  const bool corr = in.nqx > 0;
   // epilogue fast path: this thread's Q values are loaded now and arrive
   // while the product runs
-  const bool fast = part_out != nullptr && nq < kColsPerPass && rows_per_blk <= kRowLanes;
-  const int frow = blockIdx.x * rows_per_blk + threadIdx.x % kRowLanes;
-  const bool fvalid = fast && threadIdx.x % kRowLanes < rows_per_blk && frow < nrows;
+  const bool fast = (part_out != nullptr || corr) && nq < kColsPerPass && rows_per_blk <= kRowLanes;
+  const int il = threadIdx.x % kRowLanes, g = threadIdx.x / kRowLanes;
+  const int frow = blockIdx.x * rows_per_blk + il;
+  const bool fvalid = fast && il < rows_per_blk && frow < nrows;
   T q8[8];
   load_q8<T>(q8, Q, ldq, nq, frow, fvalid);
   const int lane = threadIdx.x % L, grp = threadIdx.x / L;
   constexpr int kGroups = kRowBlock / L;
-  const double sn = input_norm(xpart, xnp, sh);
-  write_normalised<T>(x, ncols, sn, x_out, s_out);
-  const T inv = (T)((sn > norm_floor<T>()) ? 1.0 / sn : 0.0);
+  double sn = 1.0;
+  if (in.pend != nullptr) {
+    sn = pending_norm(in.pend, in.np, in.nqx, hs, &hh_s);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && in.removed_out != nullptr) {
+      const double nn = hs[in.nqx];
+      *in.removed_out = nn > 0.0 ? hh_s / nn : 0.0;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && in.s_out != nullptr) *in.s_out = sn;
+  const double inv = (sn > norm_floor<T>()) ? 1.0 / sn : 0.0;
+  if (corr) {
+    for (int c = threadIdx.x; c < nq; c += kRowBlock) {
+      double t = 0.0;
+      if (c < in.nqx) t = in.alpha[c] * hs[c];
+      if (in.side == 0) {
+        if (c + 1 < in.nqx) t = fma(in.beta[c + 1], hs[c + 1], t);
+      } else {
+        if (c >= 1 && c - 1 < in.nqx) t = fma(in.beta[c], hs[c - 1], t);
+      }
+      gl[c] = t;
+    }
+  }
+  if (in.x_out != nullptr) write_corrected<T>(in.x, ncols, in.Qx, in.ldqx, in.nqx, hs, inv, in.x_out, upd);
+  const T *x = in.x;
   const int r0 = blockIdx.x * rows_per_blk;
   const int r1 = min(nrows, r0 + rows_per_blk);
   const int nsg = STAGE ? nseg : 1;
@@ -296,7 +415,7 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
     const T *xv = x;
     if constexpr (STAGE) {
       const int cn = min(segcols, ncols - c0);
-      __syncthreads();  // the previous segment's gathers are done
+      __syncthreads();  // the previous segment's gathers (or the LDS's earlier use) are done
       for (int base = threadIdx.x; base < cn; base += kRowBlock * kStageUnroll) {
         T v[kStageUnroll];
 #pragma unroll
@@ -341,30 +460,69 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
         T vv[kSpmvUnroll];
 #pragma unroll
         for (int j = 0; j < kSpmvUnroll; ++j) {
-          const bool in = t + j * L < end;
-          ii[j] = in ? idx[t + j * L] : c0;
-          vv[j] = in ? val[t + j * L] : (T)0;
+          const bool inr = t + j * L < end;
+          ii[j] = inr ? idx[t + j * L] : c0;
+          vv[j] = inr ? val[t + j * L] : (T)0;
         }
 #pragma unroll
         for (int j = 0; j < kSpmvUnroll; ++j)
           if (t + j * L < end) acc = fma(vv[j], xv[ii[j] - c0], acc);
       }
       acc = seg_sum<L>(acc);
-      if (lane == 0) {
-        const T tot = (sgm == 0) ? acc : racc[row - r0] + acc;
-        if (sgm + 1 < nsg) {
-          racc[row - r0] = tot;
-        } else {
-          const T y = tot * inv;
-          const T pv = prev ? fma(-(T)sn, prev[row], y) : y;
-          p[row] = pv;
-          racc[row - r0] = pv;
-        }
-      }
+      if (lane == 0) racc[row - r0] = (sgm == 0) ? acc : racc[row - r0] + acc;
     }
   }
+  __syncthreads();  // racc complete; the region is free again
+  if (corr) {
+    // p = (A x_raw - Q g) / s - s prev, Q g summed like write_corrected
+    const int last = nq > 0 ? nq - 1 : 0;
+    for (int rb = r0; rb < r1; rb += kRowLanes) {
+      const int row = rb + il;
+      const bool valid = row < r1;
+      double a = 0.0;
+      if (fast) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int c = g + 8 * j;
+          if (fvalid && c < nq) a = fma((double)q8[j], gl[c], a);
+        }
+      } else if (valid) {
+        for (int cb = 0; cb < nq; cb += kColsPerPass) {
+          T q[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) q[j] = Q[(size_t)min(cb + g + 8 * j, last) * ldq + row];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int c = cb + g + 8 * j;
+            if (c < nq) a = fma((double)q[j], gl[c], a);
+          }
+        }
+      }
+      upd[g * kRowLanes + il] = a;
+      __syncthreads();
+      if (g == 0 && valid) {
+        double tot = 0.0;
+#pragma unroll
+        for (int gg = 0; gg < kColGroups; ++gg) tot += upd[gg * kRowLanes + il];
+        double y = ((double)racc[row - r0] - tot) * inv;
+        if (prev != nullptr) y = fma(-sn, (double)prev[row], y);
+        const T pv = (T)y;
+        p[row] = pv;
+        racc[row - r0] = pv;
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int row = r0 + threadIdx.x; row < r1; row += kRowBlock) {
+      double y = (double)racc[row - r0] * inv;
+      if (prev != nullptr) y = fma(-sn, (double)prev[row], y);
+      const T pv = (T)y;
+      p[row] = pv;
+      racc[row - r0] = pv;
+    }
+    __syncthreads();
+  }
   if (part_out == nullptr) return;  // uniform
-  __syncthreads();
   if (fast) {
     row_dots_lds<T>(q8, fvalid ? (double)racc[frow - r0] : 0.0, fvalid, nq, part_out,
                     reinterpret_cast<double *>(region));
@@ -373,40 +531,19 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
   }
 }
 
-// hs[c] = sum_i part[c * np + i] for c < C, into LDS.  Wave w takes the
-// columns w, w + 16, ... four at a time; its lanes read consecutive partials
-// of a column (coalesced: a column's np partials are contiguous), add their
-// own ones in index order and the 64 lane sums reduce by a shuffle tree.  The
-// order does not depend on the workgroup, so every workgroup holds the same
-// values.
-__device__ void reduce_columns(const double *__restrict__ part, int np, int C, double *hs) {
-  const int w = threadIdx.x / kWave, wl = threadIdx.x % kWave;
-  for (int cb = w; cb < C; cb += 4 * kRowWaves) {
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int i0 = 0; i0 < np; i0 += 4 * kWave) {
-      double v[4][4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int c = cb + k * kRowWaves;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int ii = i0 + j * kWave + wl;
-          v[k][j] = (c < C && ii < np) ? part[(size_t)c * np + ii] : 0.0;
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[k] += v[k][j];
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const double t = seg_sum<kWave>(acc[k]);
-      const int c = cb + k * kRowWaves;
-      if (wl == 0 && c < C) hs[c] = t;
-    }
+// s and |h|^2 / |x_raw|^2 of a pending vector (pending_norm, the same
+// arithmetic as the sparse product that consumes it) into *s_out and
+// *removed_out (may be null).  One workgroup; dynamic LDS: nqx + 1 doubles.
+__global__ __launch_bounds__(kRowBlock) void k_pending_norm(const double *__restrict__ pend, int np, int nqx,
+                                                            double *__restrict__ s_out,
+                                                            double *__restrict__ removed_out) {
+  extern __shared__ double hs_d[];
+  __shared__ double hh;
+  const double s = pending_norm(pend, np, nqx, hs_d, &hh);
+  if (threadIdx.x == 0) {
+    *s_out = s;
+    if (removed_out != nullptr) *removed_out = hs_d[nqx] > 0.0 ? hh / hs_d[nqx] : 0.0;
   }
-  __syncthreads();
 }
 
 // p <- p - Q h over the workgroup's rows, with h = the column sums of
@@ -535,15 +672,17 @@ __global__ __launch_bounds__(kRowBlock) void k_sumsq(const T *__restrict__ p, in
   if (threadIdx.x == 0) part_out[blockIdx.x] = tot;
 }
 
-// out = p / |p| with |p|^2 = the sum of part[0..np) (input_norm: the same
-// order as the sparse product that would normalise it); workgroup 0 stores
-// |p| in *coef_out.  out = 0 when |p| underflows.
+// out = p / |p| with |p|^2 = the sum of part[0..np) (pending_norm with no
+// basis columns: the same arithmetic as the sparse product that would
+// normalise it); workgroup 0 stores |p| in *coef_out.  out = 0 when |p|
+// underflows.
 template <typename T>
 __global__ __launch_bounds__(kRowBlock) void k_gs_scale(const T *__restrict__ p, int n,
                                                         const double *__restrict__ part, int np,
                                                         T *__restrict__ out, double *__restrict__ coef_out) {
-  __shared__ double sh[kRowWaves];
-  const double nrm = input_norm(part, np, sh);
+  __shared__ double hs[1];
+  __shared__ double hh;
+  const double nrm = pending_norm(part, np, 0, hs, &hh);
   const double inv = (nrm > norm_floor<T>()) ? 1.0 / nrm : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) *coef_out = nrm;
   for (int i = blockIdx.x * kRowBlock + threadIdx.x; i < n; i += gridDim.x * kRowBlock)
@@ -808,7 +947,7 @@ SpmvPlan spmv_plan(int nrows, int ncols, int elem_bytes, int lds_bytes, int mode
   pl.segcols = 0;
   if (mode != 1) {
     // 2 KiB of headroom for the kernel's static LDS
-    const long budget = ((long)lds_bytes - 2048 - racc) / elem_bytes;
+    const long budget = ((long)lds_bytes - 2048 - racc - kSpmvAuxBytes) / elem_bytes;
     long seg = std::min<long>(ncols, budget);
     if (seg < ncols) seg = (seg / 64) * 64;
     if (seg >= 1) {
@@ -822,18 +961,30 @@ SpmvPlan spmv_plan(int nrows, int ncols, int elem_bytes, int lds_bytes, int mode
       }
     }
   }
-  // the region after racc holds x's segment, then the fused dot products
-  pl.lds = (size_t)racc + std::max((size_t)elem_bytes * (size_t)pl.segcols, (size_t)kDotsLds);
+  // the region after racc holds x's segment, then the fused dot products;
+  // h and g follow it
+  const size_t region = (std::max((size_t)elem_bytes * (size_t)pl.segcols, (size_t)kDotsLds) + 15) / 16 * 16;
+  pl.lds = (size_t)racc + region + kSpmvAuxBytes;
   return pl;
 }
 
 template <typename T>
 hipError_t launch_spmv(hipStream_t s, const SpmvPlan &pl, const int32_t *ptr, const int32_t *idx, const T *val,
-                       const int32_t *segptr, const T *x, const double *xpart, int xnp, T *x_out, double *s_out,
-                       int ncols, const T *prev, T *p, int nrows, const T *Q, int64_t ldq, int nq,
-                       double *dots_out) {
+                       const int32_t *segptr, const SpmvInput<T> &in, int ncols, const T *prev, T *p, int nrows,
+                       const T *Q, int64_t ldq, int nq, double *dots_out) {
   if (pl.nseg > 1 && segptr == nullptr) return hipErrorInvalidValue;
-  if (dots_out != nullptr && nq > 0 && Q == nullptr) return hipErrorInvalidValue;
+  if (in.x == nullptr || p == nullptr) return hipErrorInvalidValue;
+  if ((dots_out != nullptr || in.nqx > 0) && nq > 0 && Q == nullptr) return hipErrorInvalidValue;
+  if (in.nqx < 0 || nq < 0) return hipErrorInvalidValue;
+  if (in.nqx > 0) {
+    // the deferred update: its coefficients and their image must fit the
+    // LDS reserved for them, and Q must be the basis the relations name
+    if (in.pend == nullptr || in.Qx == nullptr || in.alpha == nullptr || in.beta == nullptr) return hipErrorInvalidValue;
+    if (in.side != 0 && in.side != 1) return hipErrorInvalidValue;
+    if (nq != in.nqx + in.side || nq > kSpmvAuxCols) return hipErrorInvalidValue;
+    if (in.x_out != nullptr && in.ldqx < ncols) return hipErrorInvalidValue;
+  }
+  if (in.pend != nullptr && in.np < 1) return hipErrorInvalidValue;
   const RowPlan rp = row_plan(nrows);
   if (rp.nblk != pl.nblk || rp.rows_per_blk != pl.rows_per_blk) return hipErrorInvalidValue;
 #define SVT_SPMVR(LN, ST)                                                                          \
@@ -842,8 +993,7 @@ hipError_t launch_spmv(hipStream_t s, const SpmvPlan &pl, const int32_t *ptr, co
     hipError_t ea = allow_dynamic_lds(reinterpret_cast<const void *>(kern), pl.lds);              \
     if (ea != hipSuccess) return ea;                                                              \
     SVT_LAUNCH(kern, dim3(pl.nblk), dim3(kRowBlock), pl.lds, s, ptr, idx, val, segptr, pl.nseg,    \
-               pl.segcols, x, xpart, xnp, x_out, s_out, ncols, prev, p, nrows, pl.rows_per_blk, Q, \
-               ldq, nq, dots_out);                                                                \
+               pl.segcols, in, ncols, prev, p, nrows, pl.rows_per_blk, Q, ldq, nq, dots_out);      \
   } while (0)
 #define SVT_SPMVS(ST)                      \
   switch (pl.lanes) {                      \
@@ -901,6 +1051,14 @@ hipError_t launch_finalize(hipStream_t s, const T *p, int nrows, const double *p
                            double *coef_out) {
   const RowPlan rp = row_plan(nrows);
   SVT_LAUNCH((k_gs_scale<T>), dim3(rp.nblk), dim3(kRowBlock), 0, s, p, nrows, part, rp.nblk, out, coef_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pending_norm(hipStream_t s, const double *pend, int np, int nqx, double *s_out,
+                               double *removed_out) {
+  if (pend == nullptr || s_out == nullptr || np < 1 || nqx < 0 || nqx > kSpmvAuxCols) return hipErrorInvalidValue;
+  SVT_LAUNCH(k_pending_norm, dim3(1), dim3(kRowBlock), sizeof(double) * ((size_t)nqx + 1), s, pend, np, nqx,
+             s_out, removed_out);
   return hipGetLastError();
 }
 
@@ -977,9 +1135,8 @@ hipError_t launch_gather(hipStream_t s, const T *x, const int32_t *map, T *y, in
 
 #define SVT_INSTANTIATE(T)                                                                          \
   template hipError_t launch_spmv<T>(hipStream_t, const SpmvPlan &, const int32_t *, const int32_t *,      \
-                                     const T *, const int32_t *, const T *, const double *, int, T *,  \
-                                     double *, int, const T *, T *, int, const T *, int64_t, int,      \
-                                     double *);                                                        \
+                                     const T *, const int32_t *, const SpmvInput<T> &, int, const T *, \
+                                     T *, int, const T *, int64_t, int, double *);                     \
   template hipError_t launch_gs_update<T>(hipStream_t, T *, int, const T *, int64_t, int, const double *, \
                                           double *, bool, double *);                                   \
   template hipError_t launch_sumsq<T>(hipStream_t, const T *, int, double *);                          \

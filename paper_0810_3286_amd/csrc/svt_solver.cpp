@@ -117,9 +117,11 @@ struct PinnedMem {
 // kernel-class timing with HIP events (params.profile = 1)
 
 // One kind per kernel (each bracket times exactly one launch):
-//   0 k_spmv_rows (with the first pass's dot products), 1 unused, 2
-//   k_gs_update (first pass, with the second pass's dot products), 3 k_ritz,
-//   4 k_sample_update, 5 k_gs_update (second pass, with the |p|^2 partials).
+//   0 k_spmv_rows (with the deferred one-pass update of its input and the
+//   dot products of its output), 1 unused, 2 k_gs_update (first of two
+//   passes, with the second pass's dot products), 3 k_ritz, 4
+//   k_sample_update, 5 k_gs_update (one pass with the |p|^2 partials: the
+//   second of two, or a deferred update too wide to fuse).
 enum KernelKind { kSpmv = 0, kUnused1 = 1, kGsUpdate1 = 2, kRitz = 3, kSample = 4, kGsUpdate2 = 5, kKinds = 6 };
 
 struct Profiler {
@@ -398,8 +400,11 @@ struct Problem final : ProblemBase {
     n3.alloc(sizeof(double) * (size_t)blocks);
     HIP_CHECK(hipMemsetAsync(ncoef.p, 0, ncoef.bytes, stream));
     if (kcap > 0) {
-      // the pending vector's |.|^2 partials (part3) cross the growth: the
-      // next half-step normalises that vector with them
+      // the pending vector's partials (its dot products and |.|^2, in any
+      // of the three buffers) cross the growth: the next half-step
+      // orthogonalises and normalises that vector with them
+      HIP_CHECK(hipMemcpyAsync(n1.p, gs1.p, gs1.bytes, hipMemcpyDeviceToDevice, stream));
+      HIP_CHECK(hipMemcpyAsync(n2.p, gs2.p, gs2.bytes, hipMemcpyDeviceToDevice, stream));
       HIP_CHECK(hipMemcpyAsync(n3.p, gs3.p, sizeof(double) * (size_t)blocks, hipMemcpyDeviceToDevice, stream));
       HIP_CHECK(hipMemcpyAsync(nU.p, Ub.p, sizeof(T) * (size_t)arows * (size_t)(kcap + 1), hipMemcpyDeviceToDevice, stream));
       HIP_CHECK(hipMemcpyAsync(nV.p, Vb.p, sizeof(T) * (size_t)acols * (size_t)(kcap + 2), hipMemcpyDeviceToDevice, stream));
@@ -465,20 +470,19 @@ struct Problem final : ProblemBase {
   Csx a_rows_struct() { return a_is_y ? csr_struct() : csc_struct(); }
   Csx a_cols_struct() { return a_is_y ? csc_struct() : csr_struct(); }
 
-  // out = A (x / s) - s prev with s from the |x|^2 partials xpart (null: x
-  // normalised, s = 1); x_out / s_out receive the normalised x and s; with
-  // dots, the first Gram-Schmidt pass's partial dot products of out with the
-  // nq columns of Q follow in the same kernel.
-  void spmv(const Csx &c, const T *vals, const T *x, const double *xpart, int xnp, T *x_out, double *s_out,
-            const T *prev, T *out, const T *Q = nullptr, int64_t ldq = 0, int nq = 0, double *dots = nullptr) {
-    hipError_t e = launch_spmv<T>(stream, *c.plan, c.ptr, c.idx, vals, c.segptr, x, xpart, xnp, x_out, s_out,
-                                  c.ncols, prev, out, c.nrows, Q, ldq, nq, dots);
+  // out = A x' - s prev, x' the input `in` (launch_spmv); with dots, the
+  // partial dot products of out with the nq columns of Q and |out|^2 follow
+  // in the same kernel.
+  void spmv(const Csx &c, const T *vals, const SpmvInput<T> &in, const T *prev, T *out, const T *Q = nullptr,
+            int64_t ldq = 0, int nq = 0, double *dots = nullptr) {
+    hipError_t e = launch_spmv<T>(stream, *c.plan, c.ptr, c.idx, vals, c.segptr, in, c.ncols, prev, out,
+                                  c.nrows, Q, ldq, nq, dots);
     if (e == hipErrorInvalidValue && c.plan->nseg > 0) {
       // the device refused the LDS size: gather x from memory from now on
       (void)hipGetLastError();
       *c.plan = spmv_plan(c.nrows, c.ncols, (int)sizeof(T), lds_limit, 1);
-      e = launch_spmv<T>(stream, *c.plan, c.ptr, c.idx, vals, nullptr, x, xpart, xnp, x_out, s_out, c.ncols,
-                         prev, out, c.nrows, Q, ldq, nq, dots);
+      e = launch_spmv<T>(stream, *c.plan, c.ptr, c.idx, vals, nullptr, in, c.ncols, prev, out, c.nrows, Q, ldq,
+                         nq, dots);
     }
     HIP_CHECK(e);
   }
@@ -506,92 +510,152 @@ struct Problem final : ProblemBase {
            (has_prev ? vb * c.nrows : 0.0);
   }
 
-  // One half-step of the bidiagonalisation.  In: the other side's new vector
-  // x_raw (unnormalised) whose |.|^2 partials sit in gs.part3 (xnp of them);
-  // the normalised x goes to x_col and its norm to *x_coef.  Out: this side's
-  // new vector, orthogonalised against the nq columns of Q and left
-  // unnormalised in p with its |.|^2 partials in gs.part3.
-  void half_step(const Csx &c, const T *vals, const T *x_raw, int xnp, T *x_col, double *x_coef,
-                 const T *prev, T *Q, int64_t ldq, int nq, T *p, int j) {
+  // A new vector of the bidiagonalisation whose orthogonalisation is still
+  // pending: its partials are in part buffer `buf` (1, 2, 3: gs.part1 ..
+  // part3), nq dot products with its side's basis, then |.|^2.  nq = 0: only
+  // the norm is pending (the vector is already orthogonal).
+  struct PendingVec {
+    int buf = 3;
+    int nq = 0;
+  };
+  double *part_buf(int b) { return b == 1 ? gs.part1 : (b == 2 ? gs.part2 : gs.part3); }
+
+  // Whether the one-pass update of a pending vector with nqx basis columns is
+  // fused into the next sparse product (p's side then has nqx + side
+  // columns); wider updates run as their own kernel first.
+  static bool fused_update(int nqx, int side) { return nqx > 0 && nqx + side <= kSpmvAuxCols; }
+
+  // One half-step of the bidiagonalisation: p = A x' - s prev (side 0) or
+  // A^T x' - s prev (side 1), where x' = (x_raw - Q_x h) / s is the other
+  // side's pending vector xp orthogonalised against its nqx basis columns
+  // Q_x and normalised; x' goes to x_col, s to *x_coef and |h|^2 / |x_raw|^2
+  // to *x_removed.  p is left in place with its own update pending against
+  // the nq columns of Q (returned).  Two passes (passes_now == 2): every
+  // vector is orthogonalised in its own half-step (the pending part is only
+  // its norm, in gs.part3).
+  PendingVec half_step(const Csx &c, const T *vals, T *x_raw, PendingVec xp, const T *Qx, int64_t ldqx, T *x_col,
+                       double *x_coef, double *x_removed, const T *prev, T *Q, int64_t ldq, int nq, T *p,
+                       int side) {
     const double vb = sizeof(T);
     const double len = (double)c.nrows;
-    // algorithmic bytes: the product's (spmv_bytes), the normalised x written
-    // to its basis column, and Q read once by the fused first-pass dots
+    const int xnp = xnp_of(c.ncols);
+    SpmvInput<T> in;
+    in.x = x_raw;
+    in.np = xnp;
+    in.x_out = x_col;
+    in.s_out = x_coef;
+    if (passes_now == 1) {
+      if (xp.nq > 0 && !fused_update(xp.nq, side)) {
+        // too wide to fuse: x's update runs first, in place
+        prof.begin();
+        HIP_CHECK(launch_gs_update<T>(stream, x_raw, c.ncols, Qx, ldqx, xp.nq, part_buf(xp.buf), gs.part3, true,
+                                      x_removed));
+        prof.end(kGsUpdate2, vb * c.ncols * (xp.nq + 2.0));
+        xp = PendingVec{3, 0};
+      }
+      in.pend = part_buf(xp.buf);
+      in.Qx = Qx;
+      in.ldqx = ldqx;
+      in.nqx = xp.nq;
+      in.removed_out = xp.nq > 0 ? x_removed : nullptr;
+      in.alpha = alpha_d();
+      in.beta = beta_d();
+      in.side = side;
+      const int out_buf = side == 0 ? 1 : 2;
+      // algorithmic bytes: the product's (spmv_bytes), x' written to its
+      // basis column, Q_x read once for it, and Q read once for the image
+      // of the update and the dot products
+      prof.begin();
+      spmv(c, vals, in, prev, p, Q, ldq, nq, part_buf(out_buf));
+      prof.end(kSpmv, spmv_bytes(c, c.ncols, prev != nullptr) + vb * c.ncols * (1.0 + xp.nq) + vb * len * nq);
+      return PendingVec{out_buf, nq};
+    }
+    in.pend = part_buf(xp.buf);  // x already orthogonal: only its norm
     prof.begin();
-    spmv(c, vals, x_raw, gs.part3, xnp, x_col, x_coef, prev, p, Q, ldq, nq, nq > 0 ? gs.part1 : nullptr);
+    spmv(c, vals, in, prev, p, Q, ldq, nq, nq > 0 ? gs.part1 : nullptr);
     prof.end(kSpmv, spmv_bytes(c, c.ncols, prev != nullptr) + vb * c.ncols + vb * len * nq);
     if (nq == 0) {
       HIP_CHECK(launch_sumsq<T>(stream, p, c.nrows, gs.part3));
-      return;
+      return PendingVec{3, 0};
     }
     // each update: Q read once, p read and written (the fused dot products
     // and norms reuse the same rows)
-    if (passes_now == 1) {
-      // one pass; its removed fraction goes to slot j for the check
-      double *rem = prm.reorth_passes == 0 ? removed_d() + j : nullptr;
-      prof.begin();
-      HIP_CHECK(launch_gs_update<T>(stream, p, c.nrows, Q, ldq, nq, gs.part1, gs.part3, true, rem));
-      prof.end(kGsUpdate2, vb * len * (nq + 2.0));
-      return;
-    }
     prof.begin();
     HIP_CHECK(launch_gs_update<T>(stream, p, c.nrows, Q, ldq, nq, gs.part1, gs.part2, false, nullptr));
     prof.end(kGsUpdate1, vb * len * (nq + 2.0));
     prof.begin();
     HIP_CHECK(launch_gs_update<T>(stream, p, c.nrows, Q, ldq, nq, gs.part2, gs.part3, true, nullptr));
     prof.end(kGsUpdate2, vb * len * (nq + 2.0));
+    return PendingVec{3, 0};
   }
 
   // ------------------------------------------------- bidiagonalisation (a3)
   struct Gkl {
     int k = 0;                // completed steps: u_1..u_k, v_1..v_k, raw v_{k+1}
-    bool finalized = false;   // v_{k+1} and beta_{k+1} stored
+    bool finalized = false;   // beta_{k+1} stored
     std::vector<double> alpha, beta;  // host copies, alpha[i] = alpha_{i+1}, beta[i] = beta_{i+1}
-    std::vector<double> removed;      // removed fraction of each one-pass half-step
+    std::vector<double> removed;      // removed fraction of each one-pass half-step's vector
+    PendingVec pu, pv;        // the raw vectors in pbuf_u and pbuf_v
   };
 
   int xnp_of(int nrows) const { return row_plan(nrows).nblk; }
 
-  // Start: v_1 random unit, u_1 = A v_1 / alpha_1, then v_2, beta_2.
+  // Start: v_1 random unit, u_1 = A v_1 / alpha_1, then v_2, beta_2.  The
+  // removed fraction of the vector made by half-step j goes to slot j (it is
+  // computed where that vector is orthogonalised: in half-step j + 1).
   void gkl_start(const T *vr, const T *vc, Gkl &g) {
     ensure_basis(std::min<int64_t>(acols, 8));
     const Csx R = a_rows_struct(), C = a_cols_struct();
     HIP_CHECK(launch_randn<T>(stream, pbuf_v.as<T>(), (int)acols, prm.seed, rng_ctr++));
     HIP_CHECK(launch_sumsq<T>(stream, pbuf_v.as<T>(), (int)acols, gs.part3));
+    g.pv = PendingVec{3, 0};
     // u_1 = A v_1 / alpha_1 (v_1 = the normalised start vector)
-    half_step(R, vr, pbuf_v.as<T>(), xnp_of((int)acols), vcol(0), beta_d(), nullptr, Ub.as<T>(), arows, 0,
-              pbuf_u.as<T>(), 0);
+    g.pu = half_step(R, vr, pbuf_v.as<T>(), g.pv, Vb.as<T>(), acols, vcol(0), beta_d(), nullptr, nullptr,
+                     Ub.as<T>(), arows, 0, pbuf_u.as<T>(), 0);
     // v_2 = A^T u_1 - alpha_1 v_1, orthogonal to v_1
-    half_step(C, vc, pbuf_u.as<T>(), xnp_of((int)arows), ucol(0), alpha_d(), vcol(0), Vb.as<T>(), acols, 1,
-              pbuf_v.as<T>(), 1);
+    g.pv = half_step(C, vc, pbuf_u.as<T>(), g.pu, Ub.as<T>(), arows, ucol(0), alpha_d(), removed_d(), vcol(0),
+                     Vb.as<T>(), acols, 1, pbuf_v.as<T>(), 1);
     g.k = 1;
     g.finalized = false;
     steps_total += 1;
   }
 
-  // One more step: u_{k+1}, alpha_{k+1}, v_{k+2} (unnormalised).
+  // One more step: u_{k+1}, alpha_{k+1}, v_{k+2} (pending).
   void gkl_step(const T *vr, const T *vc, Gkl &g) {
     const int k = g.k;
     ensure_basis(k + 1);
     const Csx R = a_rows_struct(), C = a_cols_struct();
     // u_{k+1} = A v_{k+1} - beta_{k+1} u_k, orthogonal to u_1..u_k
-    half_step(R, vr, pbuf_v.as<T>(), xnp_of((int)acols), vcol(k), beta_d() + k, ucol(k - 1), Ub.as<T>(), arows,
-              k, pbuf_u.as<T>(), 2 * k);
+    g.pu = half_step(R, vr, pbuf_v.as<T>(), g.pv, Vb.as<T>(), acols, vcol(k), beta_d() + k, removed_d() + 2 * k - 1,
+                     ucol(k - 1), Ub.as<T>(), arows, k, pbuf_u.as<T>(), 0);
     // v_{k+2} = A^T u_{k+1} - alpha_{k+1} v_{k+1}, orthogonal to v_1..v_{k+1}
-    half_step(C, vc, pbuf_u.as<T>(), xnp_of((int)arows), ucol(k), alpha_d() + k, vcol(k), Vb.as<T>(), acols,
-              k + 1, pbuf_v.as<T>(), 2 * k + 1);
+    g.pv = half_step(C, vc, pbuf_u.as<T>(), g.pu, Ub.as<T>(), arows, ucol(k), alpha_d() + k, removed_d() + 2 * k,
+                     vcol(k), Vb.as<T>(), acols, k + 1, pbuf_v.as<T>(), 1);
     g.k = k + 1;
     g.finalized = false;
     steps_total += 1;
   }
 
-  // Start the fetch of B_k: normalise v_{k+1} and store beta_{k+1} (the
-  // next step redoes this, bit for bit), then copy alpha and beta (one
-  // allocation, one copy) to pinned memory and record fetch_ev behind it.
+  // Start the fetch of B_k: store beta_{k+1} = |v_{k+1}| (and the removed
+  // fraction of v_{k+1}'s update; the next step redoes both, bit for bit),
+  // then copy alpha, beta and the removed fractions (one allocation, one
+  // copy) to pinned memory and record fetch_ev behind it.
   void gkl_fetch_begin(Gkl &g) {
     const int k = g.k;
     if (!g.finalized) {
-      HIP_CHECK(launch_finalize<T>(stream, pbuf_v.as<T>(), (int)acols, gs.part3, vcol(k), beta_d() + k));
+      const int xnp = xnp_of((int)acols);
+      if (passes_now == 1 && fused_update(g.pv.nq, 0)) {
+        HIP_CHECK(launch_pending_norm(stream, part_buf(g.pv.buf), xnp, g.pv.nq, beta_d() + k,
+                                      removed_d() + 2 * k - 1));
+      } else {
+        if (g.pv.nq > 0) {
+          // an update too wide to fuse runs here, as the next step would
+          HIP_CHECK(launch_gs_update<T>(stream, pbuf_v.as<T>(), (int)acols, Vb.as<T>(), acols, g.pv.nq,
+                                        part_buf(g.pv.buf), gs.part3, true, removed_d() + 2 * k - 1));
+          g.pv = PendingVec{3, 0};
+        }
+        HIP_CHECK(launch_finalize<T>(stream, pbuf_v.as<T>(), (int)acols, gs.part3, vcol(k), beta_d() + k));
+      }
       g.finalized = true;
     }
     // alpha, beta and the removed fractions of half-steps 0 .. 2k - 1
@@ -981,7 +1045,9 @@ struct Problem final : ProblemBase {
     dout.alloc(sizeof(T) * nout);
     HIP_CHECK(hipMemcpyAsync(dx.p, hx.data(), sizeof(T) * nin, hipMemcpyHostToDevice, stream));
     const Csx c = trans ? csc_struct() : csr_struct();
-    spmv(c, trans ? Yc.as<T>() : Yr.as<T>(), dx.as<T>(), nullptr, 0, nullptr, nullptr, nullptr, dout.as<T>());
+    SpmvInput<T> in;
+    in.x = dx.as<T>();
+    spmv(c, trans ? Yc.as<T>() : Yr.as<T>(), in, nullptr, dout.as<T>());
     std::vector<T> ho((size_t)nout);
     HIP_CHECK(hipMemcpyAsync(ho.data(), dout.p, sizeof(T) * nout, hipMemcpyDeviceToHost, stream));
     HIP_CHECK(hipStreamSynchronize(stream));
