@@ -74,7 +74,9 @@ SpmvPlan spmv_plan(int nrows, int ncols, int elem_bytes, int lds_bytes, int mode
 // beta_{c+1}) give the image of Q_x h through the bidiagonal relations; side
 // 0: the product is A v (x on the v side), 1: A^T u.
 constexpr int kSpmvAuxCols = 1024;  // largest nqx + side fused into the product
-constexpr long kSpmvAuxBytes = (long)sizeof(double) * (2 * kSpmvAuxCols + 2);
+// LDS scratch of the column reductions (64 columns x 17 padded strands)
+constexpr int kReduceScratch = 1088;
+constexpr long kSpmvAuxBytes = (long)sizeof(double) * (2 * kSpmvAuxCols + 2 + kReduceScratch);
 template <typename T>
 struct SpmvInput {
   const T *x = nullptr;

@@ -116,40 +116,45 @@ __device__ __forceinline__ double row_block_sum(double v, double *sh /* kRowWave
   return t;
 }
 
-// hs[c] = sum_i part[c * np + i] for c < C, into LDS.  Wave w takes the
-// columns w, w + 16, ... four at a time; its lanes read consecutive partials
-// of a column (coalesced: a column's np partials are contiguous), add their
-// own ones in index order and the 64 lane sums reduce by a shuffle tree.  The
-// order does not depend on the workgroup, so every workgroup holds the same
-// values.
-__device__ void reduce_columns(const double *__restrict__ part, int np, int C, double *hs) {
-  const int w = threadIdx.x / kWave, wl = threadIdx.x % kWave;
-  for (int cb = w; cb < C; cb += 4 * kRowWaves) {
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int i0 = 0; i0 < np; i0 += 4 * kWave) {
-      double v[4][4];
+// hs[c] = sum_i part[c * np + i] for c < C (C, np >= 1), into LDS; red:
+// kReduceScratch doubles of LDS.  A pass takes 64 columns with 16 strands
+// each: strand k of column c adds the partials k, k + 16, ... in order (only
+// the threads of existing columns load; within a thread the loads are
+// unconditional, from clamped addresses, and issued together: a
+// conditional load becomes a branch after which the compiler waits for the
+// value), and thread c of the pass adds the 16 strand sums in order.  No
+// shuffle trees: every level of a double shuffle is a round trip through
+// the LDS crossbar.  Every workgroup gets the same values.  kRowBlock
+// threads; ends synchronised.
+constexpr int kRedStrands = 16;
+constexpr int kRedCols = kRowBlock / kRedStrands;  // 64 columns per pass
+constexpr int kRedLoads = 16;                      // loads in flight per strand
+static_assert(kReduceScratch >= kRedCols * (kRedStrands + 1), "reduction scratch");
+__device__ void reduce_columns(const double *__restrict__ part, int np, int C, double *hs, double *red) {
+  const int cl = threadIdx.x / kRedStrands, k = threadIdx.x % kRedStrands;
+  for (int cb = 0; cb < C; cb += kRedCols) {
+    double t = 0.0;
+    if (cb + cl < C) {
+      const size_t col = (size_t)(cb + cl) * np;
+      for (int i0 = 0; i0 < np; i0 += kRedStrands * kRedLoads) {
+        double v[kRedLoads];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int c = cb + k * kRowWaves;
+        for (int j = 0; j < kRedLoads; ++j) v[j] = part[col + min(i0 + k + kRedStrands * j, np - 1)];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int ii = i0 + j * kWave + wl;
-          v[k][j] = (c < C && ii < np) ? part[(size_t)c * np + ii] : 0.0;
-        }
+        for (int j = 0; j < kRedLoads; ++j)
+          if (i0 + k + kRedStrands * j < np) t += v[j];
       }
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[k] += v[k][j];
     }
+    red[cl * (kRedStrands + 1) + k] = t;  // padded rows: few bank conflicts either way
+    __syncthreads();
+    if (threadIdx.x < kRedCols && cb + threadIdx.x < C) {
+      double u = 0.0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const double t = seg_sum<kWave>(acc[k]);
-      const int c = cb + k * kRowWaves;
-      if (wl == 0 && c < C) hs[c] = t;
+      for (int kk = 0; kk < kRedStrands; ++kk) u += red[threadIdx.x * (kRedStrands + 1) + kk];
+      hs[cb + threadIdx.x] = u;
     }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // A pending one-pass reorthogonalisation (the bidiagonalisation of Section
@@ -160,16 +165,36 @@ __device__ void reduce_columns(const double *__restrict__ part, int np, int C, d
 // hs[nqx]) and returns s = |x - Q_x h| = sqrt(|x|^2 - |h|^2) (Q_x
 // orthonormal); *hh receives |h|^2.  Every workgroup computes the same values
 // in the same order.  kRowBlock threads; ends synchronised.
-__device__ double pending_norm(const double *__restrict__ pend, int np, int nqx, double *hs, double *hh) {
-  reduce_columns(pend, np, nqx + 1, hs);
+// |h|^2: lane l of wave 0 adds hs[c]^2 for c = l, l + 64, ... in order, and
+// thread 0 adds the 64 lane sums in order (a fixed-trip loop whose LDS reads
+// are issued together; a serial loop over nqx would wait for each read).
+// red: kReduceScratch doubles of LDS.
+__device__ double pending_finish(const double *hs, int nqx, double *hh, double *red) {
+  if (nqx == 0) {
+    // no basis columns (uniform): |h|^2 = 0, read back only by thread 0
+    if (threadIdx.x == 0) *hh = 0.0;
+    return sqrt(fmax(hs[0] - 0.0, 0.0));
+  }
   if (threadIdx.x < kWave) {
     double t = 0.0;
     for (int c = threadIdx.x; c < nqx; c += kWave) t = fma(hs[c], hs[c], t);
-    t = seg_sum<kWave>(t);
-    if (threadIdx.x == 0) *hh = t;
+    red[threadIdx.x] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int l = 0; l < kWave; ++l) t += red[l];
+    *hh = t;
   }
   __syncthreads();
   return sqrt(fmax(hs[nqx] - *hh, 0.0));
+}
+
+__device__ double pending_norm(const double *__restrict__ pend, int np, int nqx, double *hs, double *hh,
+                               double *red) {
+  reduce_columns(pend, np, nqx + 1, hs, red);
+  return pending_finish(hs, nqx, hh, red);
 }
 
 // Workgroup b writes x_out[i] = (x[i] - sum_c Qx[i, c] h[c]) * inv for its
@@ -215,6 +240,37 @@ __device__ void write_corrected(const T *__restrict__ x, int ncols, const T *__r
     }
     __syncthreads();
   }
+}
+
+// write_corrected when the slice has at most kRowLanes entries and nqx <
+// kColsPerPass: the thread's eight Q_x values of its entry (qx, loaded by
+// load_q8 at the slice's entry i0 + row slot) and the entry's x (xv, in the
+// column group 0 threads) were loaded earlier.  Same arithmetic and order.
+template <typename T>
+__device__ void write_corrected_pre(const T (&qx)[8], double xv, int ncols, int nqx, const double *h, double inv,
+                                    T *__restrict__ x_out, double *upd) {
+  const int chunk = (ncols + gridDim.x - 1) / gridDim.x;
+  const int i0 = blockIdx.x * chunk, i1 = min(ncols, i0 + chunk);
+  const int il = threadIdx.x % kRowLanes, g = threadIdx.x / kRowLanes;
+  const int row = i0 + il;
+  const bool valid = row < i1;
+  double a = 0.0;
+  if (valid) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c = g + 8 * j;
+      if (c < nqx) a = fma((double)qx[j], h[c], a);
+    }
+  }
+  upd[g * kRowLanes + il] = a;
+  __syncthreads();
+  if (g == 0 && valid) {
+    double tot = 0.0;
+#pragma unroll
+    for (int gg = 0; gg < kColGroups; ++gg) tot += upd[gg * kRowLanes + il];
+    x_out[row] = (T)((xv - tot) * inv);
+  }
+  __syncthreads();
 }
 
 // Partial dot products of the workgroup's rows: part[c * gridDim.x + b] =
@@ -312,14 +368,22 @@ __device__ __forceinline__ void row_dots_lds(const T (&q)[8], double v, bool val
 }
 
 // The thread's eight Q values of row `row` in the column-group layout
-// (columns g + 8 j, clamped to a valid column; masked by the caller).
+// (columns g + 8 j, clamped to a valid column).  Invalid threads load row 0
+// instead (Q has at least one row when nq > 0): the values are in flight
+// without a branch, and every use masks them.  nq = 0 or Q null: zeros.
 template <typename T>
 __device__ __forceinline__ void load_q8(T (&q)[8], const T *__restrict__ Q, int64_t ldq, int nq, int row,
                                         bool valid) {
   const int g = threadIdx.x / kRowLanes;
-  const int last = nq > 0 ? nq - 1 : 0;
+  if (nq > 0 && Q != nullptr) {
+    const int last = nq - 1;
+    const int r = valid ? row : 0;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) q[j] = (valid && nq > 0) ? Q[(size_t)min(g + 8 * j, last) * ldq + row] : (T)0;
+    for (int j = 0; j < 8; ++j) q[j] = Q[(size_t)min(g + 8 * j, last) * ldq + r];
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) q[j] = (T)0;
+  }
 }
 
 // The sparse product of one bidiagonalisation half-step, p = A x - s prev
@@ -347,12 +411,62 @@ __device__ __forceinline__ void load_q8(T (&q)[8], const T *__restrict__ Q, int6
 // products of p with the nq columns of Q and |p|^2 follow in the same kernel
 // (row_dots): p's own pending one-pass update.
 //
+// Order of work: the loads that depend on nothing are issued first (this
+// thread's rows of Q and prev, this workgroup's slice of x and Q_x, x's first
+// segment), then the pending partials are summed; measured, this beats
+// staging x after the update of x is written.
+//
 // Dynamic LDS: the row sums (16-byte aligned); a region of max(x's segment,
 // kDotsLds) bytes rounded up to 16, holding x's segment during the product
-// and partial sums and the dot products' scratch before and after it; then
-// kSpmvAuxBytes for h and g.
+// and the dot products' scratch after it; then kSpmvAuxBytes for h, g and
+// kReduceScratch partial sums.
 constexpr int kSpmvUnroll = 16;
-constexpr int kStageUnroll = 16;
+constexpr int kStageVec = 4;  // 16-byte loads in flight per thread while staging x
+
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using type = float4; };
+template <> struct Vec16<double> { using type = double2; };
+
+// xs[0 .. cn) = src[0 .. cn); each thread's loads are issued before its
+// stores.  FP32: 16-byte loads and stores (four in flight per thread) when
+// src is 16-byte aligned (xs is); FP64: sixteen 8-byte loads in flight per
+// thread (measured faster than 16-byte loads for a two-segment x).
+template <typename T>
+__device__ __forceinline__ void stage_segment(const T *__restrict__ src, int cn, T *xs) {
+  if constexpr (sizeof(T) == 8) {
+    for (int base = threadIdx.x; base < cn; base += kRowBlock * 16) {
+      T v[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v[j] = src[min(base + j * kRowBlock, cn - 1)];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int ii = base + j * kRowBlock;
+        if (ii < cn) xs[ii] = v[j];
+      }
+    }
+  } else {
+    using V = typename Vec16<T>::type;
+    constexpr int kv = 16 / sizeof(T);
+    int done = 0;
+    if ((reinterpret_cast<uintptr_t>(src) & 15) == 0 && cn >= kv) {
+      const int nv = cn / kv;
+      const V *s4 = reinterpret_cast<const V *>(src);
+      V *d4 = reinterpret_cast<V *>(xs);
+      for (int base = threadIdx.x; base < nv; base += kRowBlock * kStageVec) {
+        V v[kStageVec];
+#pragma unroll
+        for (int j = 0; j < kStageVec; ++j) v[j] = s4[min(base + j * kRowBlock, nv - 1)];
+#pragma unroll
+        for (int j = 0; j < kStageVec; ++j) {
+          const int ii = base + j * kRowBlock;
+          if (ii < nv) d4[ii] = v[j];
+        }
+      }
+      done = nv * kv;
+    }
+    for (int ii = done + threadIdx.x; ii < cn; ii += kRowBlock) xs[ii] = src[ii];
+  }
+}
 
 template <typename T, int L, bool STAGE>
 __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
@@ -368,24 +482,34 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
   char *region = reinterpret_cast<char *>(smem_d) + racc_bytes;
   const size_t xseg_bytes = sizeof(T) * (size_t)segcols;
   const size_t region_bytes = ((xseg_bytes > (size_t)kDotsLds ? xseg_bytes : (size_t)kDotsLds) + 15) / 16 * 16;
-  T *xs = reinterpret_cast<T *>(region);            // x's segment (STAGE)
-  double *upd = reinterpret_cast<double *>(region);  // kRowBlock partial sums (before and after the product)
+  T *xs = reinterpret_cast<T *>(region);                          // x's segment (STAGE)
   double *hs = reinterpret_cast<double *>(region + region_bytes);  // h, |x_raw|^2: kSpmvAuxCols + 1
-  double *gl = hs + kSpmvAuxCols + 1;                                 // g: kSpmvAuxCols
+  double *gl = hs + kSpmvAuxCols + 1;                               // g: kSpmvAuxCols
+  double *upd = gl + kSpmvAuxCols + 1;                              // kReduceScratch partial sums
   const bool corr = in.nqx > 0;
-  // epilogue fast path: this thread's Q values are loaded now and arrive
-  // while the product runs
-  const bool fast = (part_out != nullptr || corr) && nq < kColsPerPass && rows_per_blk <= kRowLanes;
   const int il = threadIdx.x % kRowLanes, g = threadIdx.x / kRowLanes;
+  // this thread's Q values for the epilogue (rows of at most kRowLanes per
+  // workgroup and nq < kColsPerPass)
+  const bool fast = (part_out != nullptr || corr) && nq < kColsPerPass && rows_per_blk <= kRowLanes;
   const int frow = blockIdx.x * rows_per_blk + il;
   const bool fvalid = fast && il < rows_per_blk && frow < nrows;
   T q8[8];
   load_q8<T>(q8, Q, ldq, nq, frow, fvalid);
-  const int lane = threadIdx.x % L, grp = threadIdx.x / L;
-  constexpr int kGroups = kRowBlock / L;
+  const T prev8 = (fast && prev != nullptr) ? prev[fvalid ? frow : 0] : (T)0;
+  // this workgroup's slice of x and its rows of Q_x (write_corrected)
+  const int xchunk = (ncols + gridDim.x - 1) / gridDim.x;
+  const int xrow = blockIdx.x * xchunk + il;
+  const bool xfast = corr && in.x_out != nullptr && xchunk <= kRowLanes && in.nqx < kColsPerPass;
+  const bool xvalid = xfast && il < xchunk && xrow < ncols;
+  T qx8[8];
+  load_q8<T>(qx8, in.Qx, in.ldqx, in.nqx, xrow, xvalid && corr);
+  const T xv0 = in.x[xvalid ? xrow : 0];
+  const T *x = in.x;
+  if constexpr (STAGE) stage_segment<T>(x, min(segcols, ncols), xs);
+  // s, h and g
   double sn = 1.0;
   if (in.pend != nullptr) {
-    sn = pending_norm(in.pend, in.np, in.nqx, hs, &hh_s);
+    sn = pending_norm(in.pend, in.np, in.nqx, hs, &hh_s, upd);
     if (blockIdx.x == 0 && threadIdx.x == 0 && in.removed_out != nullptr) {
       const double nn = hs[in.nqx];
       *in.removed_out = nn > 0.0 ? hh_s / nn : 0.0;
@@ -405,8 +529,13 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
       gl[c] = t;
     }
   }
-  if (in.x_out != nullptr) write_corrected<T>(in.x, ncols, in.Qx, in.ldqx, in.nqx, hs, inv, in.x_out, upd);
-  const T *x = in.x;
+  if (xfast) {
+    write_corrected_pre<T>(qx8, (double)xv0, ncols, in.nqx, hs, inv, in.x_out, upd);
+  } else if (in.x_out != nullptr) {
+    write_corrected<T>(x, ncols, in.Qx, in.ldqx, in.nqx, hs, inv, in.x_out, upd);
+  }
+  const int lane = threadIdx.x % L, grp = threadIdx.x / L;
+  constexpr int kGroups = kRowBlock / L;
   const int r0 = blockIdx.x * rows_per_blk;
   const int r1 = min(nrows, r0 + rows_per_blk);
   const int nsg = STAGE ? nseg : 1;
@@ -414,20 +543,9 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
     const int c0 = STAGE ? sgm * segcols : 0;
     const T *xv = x;
     if constexpr (STAGE) {
-      const int cn = min(segcols, ncols - c0);
-      __syncthreads();  // the previous segment's gathers (or the LDS's earlier use) are done
-      for (int base = threadIdx.x; base < cn; base += kRowBlock * kStageUnroll) {
-        T v[kStageUnroll];
-#pragma unroll
-        for (int j = 0; j < kStageUnroll; ++j) {
-          const int ii = base + j * kRowBlock;
-          v[j] = (ii < cn) ? x[c0 + ii] : (T)0;
-        }
-#pragma unroll
-        for (int j = 0; j < kStageUnroll; ++j) {
-          const int ii = base + j * kRowBlock;
-          if (ii < cn) xs[ii] = v[j];
-        }
+      if (sgm > 0) {
+        __syncthreads();  // the previous segment's gathers are done
+        stage_segment<T>(x + c0, min(segcols, ncols - c0), xs);
       }
       __syncthreads();
       xv = xs;
@@ -505,7 +623,7 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
 #pragma unroll
         for (int gg = 0; gg < kColGroups; ++gg) tot += upd[gg * kRowLanes + il];
         double y = ((double)racc[row - r0] - tot) * inv;
-        if (prev != nullptr) y = fma(-sn, (double)prev[row], y);
+        if (prev != nullptr) y = fma(-sn, (double)(fast ? prev8 : prev[row]), y);
         const T pv = (T)y;
         p[row] = pv;
         racc[row - r0] = pv;
@@ -514,8 +632,10 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
     }
   } else {
     for (int row = r0 + threadIdx.x; row < r1; row += kRowBlock) {
+      // with `fast`, a workgroup has at most kRowLanes rows and thread i
+      // (< kRowLanes) loaded prev of row r0 + i at the start
       double y = (double)racc[row - r0] * inv;
-      if (prev != nullptr) y = fma(-sn, (double)prev[row], y);
+      if (prev != nullptr) y = fma(-sn, (double)(fast ? prev8 : prev[row]), y);
       const T pv = (T)y;
       p[row] = pv;
       racc[row - r0] = pv;
@@ -539,7 +659,8 @@ __global__ __launch_bounds__(kRowBlock) void k_pending_norm(const double *__rest
                                                             double *__restrict__ removed_out) {
   extern __shared__ double hs_d[];
   __shared__ double hh;
-  const double s = pending_norm(pend, np, nqx, hs_d, &hh);
+  __shared__ double red[kReduceScratch];
+  const double s = pending_norm(pend, np, nqx, hs_d, &hh, red);
   if (threadIdx.x == 0) {
     *s_out = s;
     if (removed_out != nullptr) *removed_out = hs_d[nqx] > 0.0 ? hh / hs_d[nqx] : 0.0;
@@ -571,8 +692,8 @@ __global__ __launch_bounds__(kRowBlock) void k_gs_update(T *__restrict__ p, int 
   extern __shared__ double smem[];
   double *hs = smem;                       // nq + 1 coefficients
   double *pc = hs + nq + 1;                // rows_per_blk values of the new p
-  double *upd = pc + rows_per_blk;         // kRowBlock partial updates
-  double *dbuf = upd + kRowBlock;          // kDotsLds bytes for the fused dot products
+  double *upd = pc + rows_per_blk;         // kReduceScratch: partial updates, reduction scratch
+  double *dbuf = upd + kReduceScratch;     // kDotsLds bytes for the fused dot products
   __shared__ double sh[kRowWaves];
   __shared__ double sred[kRowWaves][8];
   const int r0 = blockIdx.x * rows_per_blk;
@@ -586,8 +707,8 @@ __global__ __launch_bounds__(kRowBlock) void k_gs_update(T *__restrict__ p, int 
     const bool valid = row < r1;
     T q[8];
     load_q8<T>(q, Q, ldq, nq, row, valid);
-    const double p0 = (valid && g == 0) ? (double)p[row] : 0.0;
-    reduce_columns(part_in, np_in, nq + 1, hs);
+    const T p0 = p[valid ? row : r0];
+    reduce_columns(part_in, np_in, nq + 1, hs, upd);
     record_removed(hs, nq, removed);
     double a = 0.0;
 #pragma unroll
@@ -601,7 +722,7 @@ __global__ __launch_bounds__(kRowBlock) void k_gs_update(T *__restrict__ p, int 
       double tot = 0.0;
 #pragma unroll
       for (int gg = 0; gg < kColGroups; ++gg) tot += upd[gg * kRowLanes + i];
-      const T pv = (T)(p0 - tot);
+      const T pv = (T)((double)p0 - tot);
       p[row] = pv;
       pc[i] = (double)pv;
     }
@@ -615,7 +736,7 @@ __global__ __launch_bounds__(kRowBlock) void k_gs_update(T *__restrict__ p, int 
     }
     return;
   }
-  reduce_columns(part_in, np_in, nq + 1, hs);
+  reduce_columns(part_in, np_in, nq + 1, hs, upd);
   record_removed(hs, nq, removed);
   const int last = nq - 1;
   for (int rb = r0; rb < r1; rb += kRowLanes) {
@@ -682,7 +803,8 @@ __global__ __launch_bounds__(kRowBlock) void k_gs_scale(const T *__restrict__ p,
                                                         T *__restrict__ out, double *__restrict__ coef_out) {
   __shared__ double hs[1];
   __shared__ double hh;
-  const double nrm = pending_norm(part, np, 0, hs, &hh);
+  __shared__ double red[kReduceScratch];
+  const double nrm = pending_norm(part, np, 0, hs, &hh, red);
   const double inv = (nrm > norm_floor<T>()) ? 1.0 / nrm : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) *coef_out = nrm;
   for (int i = blockIdx.x * kRowBlock + threadIdx.x; i < n; i += gridDim.x * kRowBlock)
@@ -1014,7 +1136,7 @@ hipError_t launch_spmv(hipStream_t s, const SpmvPlan &pl, const int32_t *ptr, co
 }
 
 size_t gs_update_lds(int nq, int rows_per_blk) {
-  return sizeof(double) * ((size_t)nq + 1 + (size_t)rows_per_blk + kRowBlock) + kDotsLds;
+  return sizeof(double) * ((size_t)nq + 1 + (size_t)rows_per_blk + kReduceScratch) + kDotsLds;
 }
 
 template <typename T>
