@@ -74,8 +74,9 @@ SpmvPlan spmv_plan(int nrows, int ncols, int elem_bytes, int lds_bytes, int mode
 // beta_{c+1}) give the image of Q_x h through the bidiagonal relations; side
 // 0: the product is A v (x on the v side), 1: A^T u.
 constexpr int kSpmvAuxCols = 1024;  // largest nqx + side fused into the product
-// LDS scratch of the column reductions (64 columns x 17 padded strands)
-constexpr int kReduceScratch = 1088;
+// LDS scratch of the column reductions (64 columns x 17 padded strands, then
+// 64 sums of squares)
+constexpr int kReduceScratch = 1152;
 constexpr long kSpmvAuxBytes = (long)sizeof(double) * (2 * kSpmvAuxCols + 2 + kReduceScratch);
 template <typename T>
 struct SpmvInput {
@@ -144,13 +145,16 @@ hipError_t launch_ritz(hipStream_t s, const T *Q, int64_t ldq, int nrows, int k,
 
 // For each stored entry t of row i (col j = idx[t]):
 //   x = sum_l U[u_row, l] V[v_row, l]  (fma chain in l order, u entry first),
-//   e = M[t] - x, Y[t] = Y[t] + delta e.
-// With part_out non-null, workgroup b writes its sum of e^2 to part_out[b]
-// (sample_blocks() workgroups).
+//   e = M[t] - x, Y[t] = Y[t] + delta e, and (Y2 non-null) Y2[map2[t]] = the
+//   same value: the other orientation's copy of Y.
+// rs: row stride of both factors, a multiple of 16 / sizeof(T) (>= r), rows
+// zero padded.  With part_out non-null, workgroup b writes its sum of e^2 to
+// part_out[b] (sample_blocks() workgroups).
 template <typename T>
 hipError_t launch_sample_update(hipStream_t s, int lanes, const int32_t *ptr, const int32_t *idx,
-                                const T *M, T *Y, int nrows, const T *Fu, const T *Fv,
-                                int r, int rs, bool row_side_is_u, double delta, double *part_out);
+                                const T *M, T *Y, T *Y2, const int32_t *map2, int nrows, const T *Fu,
+                                const T *Fv, int r, int rs, bool row_side_is_u, double delta,
+                                double *part_out);
 int sample_blocks(int nrows, int lanes);
 
 // y[t] = a * x[t] (the kick: Y = k0 delta M).

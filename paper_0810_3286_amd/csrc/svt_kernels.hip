@@ -161,40 +161,58 @@ __device__ void reduce_columns(const double *__restrict__ part, int np, int C, d
 // 5.1.1 with full reorthogonalisation): the new vector x of one side is kept
 // unorthogonalised, with the partials of its dot products with the nqx basis
 // columns Q_x of its side (columns 0 .. nqx - 1 of pend) and of |x|^2
-// (column nqx).  pending_norm sums them into hs (h = hs[0 .. nqx), |x|^2 =
-// hs[nqx]) and returns s = |x - Q_x h| = sqrt(|x|^2 - |h|^2) (Q_x
-// orthonormal); *hh receives |h|^2.  Every workgroup computes the same values
-// in the same order.  kRowBlock threads; ends synchronised.
-// |h|^2: lane l of wave 0 adds hs[c]^2 for c = l, l + 64, ... in order, and
-// thread 0 adds the 64 lane sums in order (a fixed-trip loop whose LDS reads
-// are issued together; a serial loop over nqx would wait for each read).
-// red: kReduceScratch doubles of LDS.
-__device__ double pending_finish(const double *hs, int nqx, double *hh, double *red) {
-  if (nqx == 0) {
-    // no basis columns (uniform): |h|^2 = 0, read back only by thread 0
-    if (threadIdx.x == 0) *hh = 0.0;
-    return sqrt(fmax(hs[0] - 0.0, 0.0));
-  }
-  if (threadIdx.x < kWave) {
+// (column nqx).  reduce_pending sums them into hs (h = hs[0 .. nqx), |x|^2 =
+// hs[nqx]) like reduce_columns, and thread 0 then forms |h|^2 and s = |x -
+// Q_x h| = sqrt(|x|^2 - |h|^2) (Q_x orthonormal) into scal[0] and scal[1].
+// |h|^2: thread t < 64 of each pass adds the squares of its columns in pass
+// order, and thread 0 adds the 64 sums in order.  Every workgroup computes
+// the same values.  kRowBlock threads; hs is visible to all threads on
+// return, scal only to thread 0 until the caller's next barrier.  red:
+// kReduceScratch doubles of LDS.
+static_assert(kReduceScratch >= kRedCols * (kRedStrands + 2), "reduction scratch");
+__device__ void reduce_pending(const double *__restrict__ pend, int np, int nqx, double *hs, double *red,
+                               double *scal) {
+  const int C = nqx + 1;
+  const int cl = threadIdx.x / kRedStrands, k = threadIdx.x % kRedStrands;
+  double *sqs = red + kRedCols * (kRedStrands + 1);
+  double sq = 0.0;
+  for (int cb = 0; cb < C; cb += kRedCols) {
     double t = 0.0;
-    for (int c = threadIdx.x; c < nqx; c += kWave) t = fma(hs[c], hs[c], t);
-    red[threadIdx.x] = t;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
+    if (cb + cl < C) {
+      const size_t col = (size_t)(cb + cl) * np;
+      for (int i0 = 0; i0 < np; i0 += kRedStrands * kRedLoads) {
+        double v[kRedLoads];
 #pragma unroll
-    for (int l = 0; l < kWave; ++l) t += red[l];
-    *hh = t;
+        for (int j = 0; j < kRedLoads; ++j) v[j] = pend[col + min(i0 + k + kRedStrands * j, np - 1)];
+#pragma unroll
+        for (int j = 0; j < kRedLoads; ++j)
+          if (i0 + k + kRedStrands * j < np) t += v[j];
+      }
+    }
+    red[cl * (kRedStrands + 1) + k] = t;
+    __syncthreads();
+    if (threadIdx.x < kRedCols) {
+      const int c = cb + threadIdx.x;
+      if (c < C) {
+        double u = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < kRedStrands; ++kk) u += red[threadIdx.x * (kRedStrands + 1) + kk];
+        hs[c] = u;
+        if (c < nqx) sq = fma(u, u, sq);
+      }
+      if (cb + kRedCols >= C) sqs[threadIdx.x] = sq;  // last pass
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  return sqrt(fmax(hs[nqx] - *hh, 0.0));
-}
-
-__device__ double pending_norm(const double *__restrict__ pend, int np, int nqx, double *hs, double *hh,
-                               double *red) {
-  reduce_columns(pend, np, nqx + 1, hs, red);
-  return pending_finish(hs, nqx, hh, red);
+  if (threadIdx.x == 0) {
+    double hh = 0.0;
+    if (nqx > 0) {
+#pragma unroll
+      for (int l = 0; l < kRedCols; ++l) hh += sqs[l];
+    }
+    scal[0] = hh;
+    scal[1] = sqrt(fmax(hs[nqx] - hh, 0.0));
+  }
 }
 
 // Workgroup b writes x_out[i] = (x[i] - sum_c Qx[i, c] h[c]) * inv for its
@@ -476,7 +494,6 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
     int64_t ldq, int nq, double *__restrict__ part_out) {
   extern __shared__ double smem_d[];
   __shared__ double sred[kRowWaves][8];
-  __shared__ double hh_s;
   T *racc = reinterpret_cast<T *>(smem_d);  // rows_per_blk row sums, then the rows of p
   const size_t racc_bytes = ((sizeof(T) * rows_per_blk + 15) / 16) * 16;
   char *region = reinterpret_cast<char *>(smem_d) + racc_bytes;
@@ -486,37 +503,48 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
   double *hs = reinterpret_cast<double *>(region + region_bytes);  // h, |x_raw|^2: kSpmvAuxCols + 1
   double *gl = hs + kSpmvAuxCols + 1;                               // g: kSpmvAuxCols
   double *upd = gl + kSpmvAuxCols + 1;                              // kReduceScratch partial sums
+  __shared__ double scal[2];  // |h|^2, s (reduce_pending)
   const bool corr = in.nqx > 0;
   const int il = threadIdx.x % kRowLanes, g = threadIdx.x / kRowLanes;
-  // this thread's Q values for the epilogue (rows of at most kRowLanes per
-  // workgroup and nq < kColsPerPass)
+  // this thread's Q values and prev for the epilogue (rows of at most
+  // kRowLanes per workgroup and nq < kColsPerPass)
   const bool fast = (part_out != nullptr || corr) && nq < kColsPerPass && rows_per_blk <= kRowLanes;
   const int frow = blockIdx.x * rows_per_blk + il;
   const bool fvalid = fast && il < rows_per_blk && frow < nrows;
   T q8[8];
   load_q8<T>(q8, Q, ldq, nq, frow, fvalid);
   const T prev8 = (fast && prev != nullptr) ? prev[fvalid ? frow : 0] : (T)0;
-  // this workgroup's slice of x and its rows of Q_x (write_corrected)
+  // this workgroup's slice of x and its rows of Q_x (x' = (x - Q_x h) / s),
+  // one entry per row slot: loaded now in FP32, after the product in FP64
+  // (whose product loop has no registers to spare)
   const int xchunk = (ncols + gridDim.x - 1) / gridDim.x;
   const int xrow = blockIdx.x * xchunk + il;
-  const bool xfast = corr && in.x_out != nullptr && xchunk <= kRowLanes && in.nqx < kColsPerPass;
+  const bool xfast = in.x_out != nullptr && xchunk <= kRowLanes && in.nqx < kColsPerPass;
   const bool xvalid = xfast && il < xchunk && xrow < ncols;
+  constexpr bool kEarlyX = sizeof(T) == 4;
   T qx8[8];
-  load_q8<T>(qx8, in.Qx, in.ldqx, in.nqx, xrow, xvalid && corr);
-  const T xv0 = in.x[xvalid ? xrow : 0];
+  T xv0 = (T)0;
+  if (kEarlyX) {
+    load_q8<T>(qx8, in.Qx, in.ldqx, in.nqx, xrow, xvalid);
+    xv0 = in.x[xvalid ? xrow : 0];
+  }
   const T *x = in.x;
   if constexpr (STAGE) stage_segment<T>(x, min(segcols, ncols), xs);
-  // s, h and g
-  double sn = 1.0;
+  // h, |x|^2 (all threads), then s (thread 0; the others read it after the
+  // next barrier) and g
   if (in.pend != nullptr) {
-    sn = pending_norm(in.pend, in.np, in.nqx, hs, &hh_s, upd);
-    if (blockIdx.x == 0 && threadIdx.x == 0 && in.removed_out != nullptr) {
-      const double nn = hs[in.nqx];
-      *in.removed_out = nn > 0.0 ? hh_s / nn : 0.0;
+    reduce_pending(in.pend, in.np, in.nqx, hs, upd, scal);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (in.removed_out != nullptr) {
+        const double nn = hs[in.nqx];
+        *in.removed_out = nn > 0.0 ? scal[0] / nn : 0.0;
+      }
+      if (in.s_out != nullptr) *in.s_out = scal[1];
     }
+  } else {
+    if (threadIdx.x == 0) scal[1] = 1.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && in.s_out != nullptr) *in.s_out = 1.0;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0 && in.s_out != nullptr) *in.s_out = sn;
-  const double inv = (sn > norm_floor<T>()) ? 1.0 / sn : 0.0;
   if (corr) {
     for (int c = threadIdx.x; c < nq; c += kRowBlock) {
       double t = 0.0;
@@ -528,11 +556,6 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
       }
       gl[c] = t;
     }
-  }
-  if (xfast) {
-    write_corrected_pre<T>(qx8, (double)xv0, ncols, in.nqx, hs, inv, in.x_out, upd);
-  } else if (in.x_out != nullptr) {
-    write_corrected<T>(x, ncols, in.Qx, in.ldqx, in.nqx, hs, inv, in.x_out, upd);
   }
   const int lane = threadIdx.x % L, grp = threadIdx.x / L;
   constexpr int kGroups = kRowBlock / L;
@@ -590,39 +613,96 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
       if (lane == 0) racc[row - r0] = (sgm == 0) ? acc : racc[row - r0] + acc;
     }
   }
-  __syncthreads();  // racc complete; the region is free again
-  if (corr) {
-    // p = (A x_raw - Q g) / s - s prev, Q g summed like write_corrected
-    const int last = nq > 0 ? nq - 1 : 0;
-    for (int rb = r0; rb < r1; rb += kRowLanes) {
-      const int row = rb + il;
-      const bool valid = row < r1;
-      double a = 0.0;
-      if (fast) {
+  if (!kEarlyX) {
+    load_q8<T>(qx8, in.Qx, in.ldqx, in.nqx, xrow, xvalid);
+    xv0 = in.x[xvalid ? xrow : 0];
+  }
+  __syncthreads();  // racc complete, s published; the region is free again
+  const double sn = scal[1];
+  const double inv = (sn > norm_floor<T>()) ? 1.0 / sn : 0.0;
+  double *updp = reinterpret_cast<double *>(region);  // the epilogue's partial sums
+  if (xfast && fast) {
+    // x' and p in one round: thread (row slot, column group) adds its
+    // columns of Q_x h and Q g, and the group sums are added in group order
+    double ax = 0.0, ap = 0.0;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int c = g + 8 * j;
-          if (fvalid && c < nq) a = fma((double)q8[j], gl[c], a);
-        }
-      } else if (valid) {
-        for (int cb = 0; cb < nq; cb += kColsPerPass) {
-          T q[8];
+    for (int j = 0; j < 8; ++j) {
+      const int c = g + 8 * j;
+      if (xvalid && c < in.nqx) ax = fma((double)qx8[j], hs[c], ax);
+      if (corr && fvalid && c < nq) ap = fma((double)q8[j], gl[c], ap);
+    }
+    upd[g * kRowLanes + il] = ax;
+    updp[g * kRowLanes + il] = ap;
+    __syncthreads();
+    if (g == 0) {
+      if (xvalid) {
+        double tx = 0.0;
 #pragma unroll
-          for (int j = 0; j < 8; ++j) q[j] = Q[(size_t)min(cb + g + 8 * j, last) * ldq + row];
+        for (int gg = 0; gg < kColGroups; ++gg) tx += upd[gg * kRowLanes + il];
+        in.x_out[xrow] = (T)(((double)xv0 - tx) * inv);
+      }
+      if (fvalid) {
+        double tp = 0.0;
+#pragma unroll
+        for (int gg = 0; gg < kColGroups; ++gg) tp += updp[gg * kRowLanes + il];
+        double y = ((double)racc[il] - tp) * inv;
+        if (prev != nullptr) y = fma(-sn, (double)prev8, y);
+        const T pv = (T)y;
+        p[frow] = pv;
+        racc[il] = pv;
+      }
+    }
+    __syncthreads();
+  } else {
+    if (xfast) {
+      write_corrected_pre<T>(qx8, (double)xv0, ncols, in.nqx, hs, inv, in.x_out, upd);
+    } else if (in.x_out != nullptr) {
+      write_corrected<T>(x, ncols, in.Qx, in.ldqx, in.nqx, hs, inv, in.x_out, upd);
+    }
+    if (corr) {
+      // p = (A x_raw - Q g) / s - s prev, Q g summed like write_corrected
+      const int last = nq > 0 ? nq - 1 : 0;
+      for (int rb = r0; rb < r1; rb += kRowLanes) {
+        const int row = rb + il;
+        const bool valid = row < r1;
+        double a = 0.0;
+        if (fast) {
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
-            const int c = cb + g + 8 * j;
-            if (c < nq) a = fma((double)q[j], gl[c], a);
+            const int c = g + 8 * j;
+            if (fvalid && c < nq) a = fma((double)q8[j], gl[c], a);
+          }
+        } else if (valid) {
+          for (int cb = 0; cb < nq; cb += kColsPerPass) {
+            T q[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) q[j] = Q[(size_t)min(cb + g + 8 * j, last) * ldq + row];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const int c = cb + g + 8 * j;
+              if (c < nq) a = fma((double)q[j], gl[c], a);
+            }
           }
         }
-      }
-      upd[g * kRowLanes + il] = a;
-      __syncthreads();
-      if (g == 0 && valid) {
-        double tot = 0.0;
+        updp[g * kRowLanes + il] = a;
+        __syncthreads();
+        if (g == 0 && valid) {
+          double tot = 0.0;
 #pragma unroll
-        for (int gg = 0; gg < kColGroups; ++gg) tot += upd[gg * kRowLanes + il];
-        double y = ((double)racc[row - r0] - tot) * inv;
+          for (int gg = 0; gg < kColGroups; ++gg) tot += updp[gg * kRowLanes + il];
+          double y = ((double)racc[row - r0] - tot) * inv;
+          if (prev != nullptr) y = fma(-sn, (double)(fast ? prev8 : prev[row]), y);
+          const T pv = (T)y;
+          p[row] = pv;
+          racc[row - r0] = pv;
+        }
+        __syncthreads();
+      }
+    } else {
+      for (int row = r0 + threadIdx.x; row < r1; row += kRowBlock) {
+        // with `fast`, a workgroup has at most kRowLanes rows and thread i
+        // (< kRowLanes) loaded prev of row r0 + i at the start
+        double y = (double)racc[row - r0] * inv;
         if (prev != nullptr) y = fma(-sn, (double)(fast ? prev8 : prev[row]), y);
         const T pv = (T)y;
         p[row] = pv;
@@ -630,17 +710,6 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
       }
       __syncthreads();
     }
-  } else {
-    for (int row = r0 + threadIdx.x; row < r1; row += kRowBlock) {
-      // with `fast`, a workgroup has at most kRowLanes rows and thread i
-      // (< kRowLanes) loaded prev of row r0 + i at the start
-      double y = (double)racc[row - r0] * inv;
-      if (prev != nullptr) y = fma(-sn, (double)(fast ? prev8 : prev[row]), y);
-      const T pv = (T)y;
-      p[row] = pv;
-      racc[row - r0] = pv;
-    }
-    __syncthreads();
   }
   if (part_out == nullptr) return;  // uniform
   if (fast) {
@@ -658,12 +727,12 @@ __global__ __launch_bounds__(kRowBlock) void k_pending_norm(const double *__rest
                                                             double *__restrict__ s_out,
                                                             double *__restrict__ removed_out) {
   extern __shared__ double hs_d[];
-  __shared__ double hh;
+  __shared__ double scal[2];
   __shared__ double red[kReduceScratch];
-  const double s = pending_norm(pend, np, nqx, hs_d, &hh, red);
+  reduce_pending(pend, np, nqx, hs_d, red, scal);
   if (threadIdx.x == 0) {
-    *s_out = s;
-    if (removed_out != nullptr) *removed_out = hs_d[nqx] > 0.0 ? hh / hs_d[nqx] : 0.0;
+    *s_out = scal[1];
+    if (removed_out != nullptr) *removed_out = hs_d[nqx] > 0.0 ? scal[0] / hs_d[nqx] : 0.0;
   }
 }
 
@@ -802,9 +871,11 @@ __global__ __launch_bounds__(kRowBlock) void k_gs_scale(const T *__restrict__ p,
                                                         const double *__restrict__ part, int np,
                                                         T *__restrict__ out, double *__restrict__ coef_out) {
   __shared__ double hs[1];
-  __shared__ double hh;
+  __shared__ double scal[2];
   __shared__ double red[kReduceScratch];
-  const double nrm = pending_norm(part, np, 0, hs, &hh, red);
+  reduce_pending(part, np, 0, hs, red, scal);
+  __syncthreads();
+  const double nrm = scal[1];
   const double inv = (nrm > norm_floor<T>()) ? 1.0 / nrm : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) *coef_out = nrm;
   for (int i = blockIdx.x * kRowBlock + threadIdx.x; i < n; i += gridDim.x * kRowBlock)
@@ -832,24 +903,44 @@ __global__ __launch_bounds__(kBlock) void k_randn(T *__restrict__ out, int n, ui
   }
 }
 
-// Ritz vectors: a thread owns one row and a tile of up to 4 outputs.
+// Ritz vectors: out[i, l] = w[l] sum_c Q[i, c] P[c, l] (an fma chain in c
+// order) for l < r, zero for r <= l < rs.  A thread owns row i and the
+// kRitzTile columns of blockIdx.y (small tiles: the kernel is bound by load
+// latency, so more threads beat fewer re-reads of the basis); it loads
+// kRitzBatch<T> entries of its row at a time (coalesced across the rows,
+// unconditional from clamped addresses), and P and w are uniform across the
+// workgroup (scalar loads).
+constexpr int kRitzTile = 4;
+template <typename T> constexpr int kRitzBatch = 256 / sizeof(T);  // 64 (FP32) or 32 (FP64) loads in flight
+constexpr int kRitzBlock = 128;
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_ritz(const T *__restrict__ Q, int64_t ldq, int nrows, int k,
-                                                 const double *__restrict__ P, const double *__restrict__ w,
-                                                 int r, T *__restrict__ out, int rs) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  const int l0 = blockIdx.y * 4;
+__global__ __launch_bounds__(kRitzBlock) void k_ritz(const T *__restrict__ Q, int64_t ldq, int nrows, int k,
+                                                     const double *__restrict__ P, const double *__restrict__ w,
+                                                     int r, T *__restrict__ out, int rs) {
+  const int i = blockIdx.x * kRitzBlock + threadIdx.x;
+  const int l0 = blockIdx.y * kRitzTile;
   if (i >= nrows) return;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int c = 0; c < k; ++c) {
-    const double q = (double)Q[(size_t)c * ldq + i];
-    const double *pr = P + (size_t)c * r;
+  const int nl = min(kRitzTile, r - l0);
+  double acc[kRitzTile];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-      if (l0 + t < r) acc[t] = fma(q, pr[l0 + t], acc[t]);
+  for (int t = 0; t < kRitzTile; ++t) acc[t] = 0.0;
+  constexpr int B = kRitzBatch<T>;
+  for (int c0 = 0; c0 < k; c0 += B) {
+    T q[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) q[j] = Q[(size_t)min(c0 + j, k - 1) * ldq + i];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      if (c0 + j < k) {
+        const double *pr = P + (size_t)(c0 + j) * r + l0;
+#pragma unroll
+        for (int t = 0; t < kRitzTile; ++t)
+          if (t < nl) acc[t] = fma((double)q[j], pr[t], acc[t]);
+      }
+    }
   }
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < kRitzTile; ++t) {
     const int l = l0 + t;
     if (l < r) out[(size_t)i * rs + l] = (T)(w ? acc[t] * w[l] : acc[t]);
     else if (l < rs) out[(size_t)i * rs + l] = (T)0;
@@ -858,12 +949,12 @@ __global__ __launch_bounds__(kBlock) void k_ritz(const T *__restrict__ Q, int64_
 
 // Sampled product, residual and iterate update in one pass over a compressed
 // orientation of Omega.  The dot product is the same fma chain in either
-// orientation (u-factor entry first), so the row- and column-compressed
-// copies of Y receive bit-identical updates.  Each workgroup writes its
-// (compensated) sum of e^2; the host adds the partials in order.
-template <typename T> struct Vec2;
-template <> struct Vec2<double> { using type = double2; };
-template <> struct Vec2<float> { using type = float2; };
+// orientation (u-factor entry first).  With Y2, the new value of entry t is
+// also written to Y2[map2[t]]: the other orientation's copy of Y receives the
+// same values without a second pass (one scattered 4- or 8-byte store per
+// entry instead of the factor-row gathers of a second sampled product).
+// Each workgroup writes its (compensated) sum of e^2; the host adds the
+// partials in order.
 
 template <typename T>
 __device__ __forceinline__ T sampled_dot(const T *__restrict__ urow, const T *__restrict__ vrow, int r) {
@@ -873,12 +964,15 @@ __device__ __forceinline__ T sampled_dot(const T *__restrict__ urow, const T *__
 }
 
 // RB > 0: the fixed (row-side) factor row is held in RB registers (r <= RB);
-// RB == 0: any r, both factors read from memory.
+// RB == 0: any r, both factors read from memory.  rs: a multiple of
+// 16 / sizeof(T), rows zero padded (the gathered rows are read 16 bytes at a
+// time).
 template <typename T, int L, int RB>
 __global__ __launch_bounds__(kBlock) void k_sample_update(
     const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx, const T *__restrict__ M,
-    T *__restrict__ Y, int nrows, int rows_per_blk, const T *__restrict__ Fu, const T *__restrict__ Fv,
-    int r, int rs, int row_side_is_u, T delta, double *__restrict__ part_out) {
+    T *__restrict__ Y, T *__restrict__ Y2, const int32_t *__restrict__ map2, int nrows, int rows_per_blk,
+    const T *__restrict__ Fu, const T *__restrict__ Fv, int r, int rs, int row_side_is_u, T delta,
+    double *__restrict__ part_out) {
   __shared__ double sbuf[kWaves];
   const int r0 = blockIdx.x * rows_per_blk;
   const int r1 = min(nrows, r0 + rows_per_blk);
@@ -899,7 +993,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_update(
     // finished in index order (the same sums as one at a time)
     constexpr int kBatch = (RB > 0 && RB <= 16) ? 4 : ((RB > 0 && RB <= 32) ? 2 : 1);
     for (int t0 = beg + lane; t0 < end; t0 += kBatch * L) {
-      int jj[kBatch];
+      int jj[kBatch], mp[kBatch];
       T mv[kBatch], yv[kBatch];
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
@@ -908,33 +1002,32 @@ __global__ __launch_bounds__(kBlock) void k_sample_update(
         jj[q] = in ? idx[t] : 0;
         mv[q] = in ? M[t] : (T)0;
         yv[q] = in ? Y[t] : (T)0;
+        mp[q] = (in && Y2 != nullptr) ? map2[t] : 0;
       }
       T x[kBatch];
       if constexpr (RB > 0) {
-        // pairs of factor entries per load (rows are 2-element aligned: the
-        // row stride is even and the padding is zero); the fma chain still
-        // runs in l order with the u-factor entry first, in either orientation
-        typename Vec2<T>::type gv[kBatch][RB / 2];
+        // 16 bytes of the gathered factor row per load (rows are 16-byte
+        // aligned and zero padded); the fma chain still runs in l order with
+        // the u-factor entry first, in either orientation
+        using V = typename Vec16<T>::type;
+        constexpr int kv = 16 / sizeof(T);
+        V gv[kBatch][RB / kv];
 #pragma unroll
         for (int q = 0; q < kBatch; ++q) {
           const T *g = other + (size_t)jj[q] * rs;
 #pragma unroll
-          for (int l = 0; l < RB; l += 2)
-            if (l < r) gv[q][l / 2] = *reinterpret_cast<const typename Vec2<T>::type *>(g + l);
+          for (int l = 0; l < RB; l += kv)
+            if (l < r) gv[q][l / kv] = *reinterpret_cast<const V *>(g + l);
         }
 #pragma unroll
         for (int q = 0; q < kBatch; ++q) {
           T xx = (T)0;
 #pragma unroll
-          for (int l = 0; l < RB; l += 2) {
-            if (l < r) {
-              if (row_side_is_u) {
-                xx = fma(f[l], gv[q][l / 2].x, xx);
-                if (l + 1 < r) xx = fma(f[l + 1], gv[q][l / 2].y, xx);
-              } else {
-                xx = fma(gv[q][l / 2].x, f[l], xx);
-                if (l + 1 < r) xx = fma(gv[q][l / 2].y, f[l + 1], xx);
-              }
+          for (int l = 0; l < RB; l += kv) {
+            const T *gc = reinterpret_cast<const T *>(&gv[q][l / kv]);
+#pragma unroll
+            for (int c = 0; c < kv; ++c) {
+              if (l + c < r) xx = row_side_is_u ? fma(f[l + c], gc[c], xx) : fma(gc[c], f[l + c], xx);
             }
           }
           x[q] = xx;
@@ -951,7 +1044,9 @@ __global__ __launch_bounds__(kBlock) void k_sample_update(
         const int t = t0 + q * L;
         if (t < end) {
           const T e = mv[q] - x[q];
-          Y[t] = fma(delta, e, yv[q]);
+          const T yn = fma(delta, e, yv[q]);
+          Y[t] = yn;
+          if (Y2 != nullptr) Y2[mp[q]] = yn;
           const T yk = fma(e, e, -comp);
           const T tk = sum + yk;
           comp = (tk - sum) - yk;
@@ -1194,8 +1289,8 @@ template <typename T>
 hipError_t launch_ritz(hipStream_t s, const T *Q, int64_t ldq, int nrows, int k, const double *P,
                        const double *w, int r, T *out, int rs) {
   if (rs < 1) return hipSuccess;
-  dim3 grid((nrows + kBlock - 1) / kBlock, (rs + 3) / 4);
-  SVT_LAUNCH((k_ritz<T>), grid, dim3(kBlock), 0, s, Q, ldq, nrows, k, P, w, r, out, rs);
+  dim3 grid((nrows + kRitzBlock - 1) / kRitzBlock, (rs + kRitzTile - 1) / kRitzTile);
+  SVT_LAUNCH((k_ritz<T>), grid, dim3(kRitzBlock), 0, s, Q, ldq, nrows, k, P, w, r, out, rs);
   return hipGetLastError();
 }
 
@@ -1206,13 +1301,15 @@ int sample_blocks(int nrows, int lanes) {
 
 template <typename T>
 hipError_t launch_sample_update(hipStream_t s, int lanes, const int32_t *ptr, const int32_t *idx,
-                                const T *M, T *Y, int nrows, const T *Fu, const T *Fv, int r, int rs,
-                                bool row_side_is_u, double delta, double *part_out) {
+                                const T *M, T *Y, T *Y2, const int32_t *map2, int nrows, const T *Fu,
+                                const T *Fv, int r, int rs, bool row_side_is_u, double delta,
+                                double *part_out) {
+  if (rs % (16 / (int)sizeof(T)) != 0 || rs < r || (Y2 != nullptr && map2 == nullptr)) return hipErrorInvalidValue;
   const RowChunks ch =
       row_chunks(nrows, std::max((kBlock / lanes) * 4, (nrows + kSampleMaxBlocks - 1) / kSampleMaxBlocks));
 #define SVT_SU2(LN, RB)                                                                          \
-  SVT_LAUNCH((k_sample_update<T, LN, RB>), dim3(ch.nblk), dim3(kBlock), 0, s, ptr, idx, M, Y, \
-                     nrows, ch.rows_per_blk, Fu, Fv, r, rs, row_side_is_u ? 1 : 0, (T)delta, part_out)
+  SVT_LAUNCH((k_sample_update<T, LN, RB>), dim3(ch.nblk), dim3(kBlock), 0, s, ptr, idx, M, Y, Y2, \
+             map2, nrows, ch.rows_per_blk, Fu, Fv, r, rs, row_side_is_u ? 1 : 0, (T)delta, part_out)
 #define SVT_SU(LN)                         \
   do {                                     \
     if (r <= 8) SVT_SU2(LN, 8);            \
@@ -1267,8 +1364,8 @@ hipError_t launch_gather(hipStream_t s, const T *x, const int32_t *map, T *y, in
   template hipError_t launch_ritz<T>(hipStream_t, const T *, int64_t, int, int, const double *,    \
                                      const double *, int, T *, int);                                \
   template hipError_t launch_sample_update<T>(hipStream_t, int, const int32_t *, const int32_t *,  \
-                                              const T *, T *, int, const T *, const T *, int, int,  \
-                                              bool, double, double *);                              \
+                                              const T *, T *, T *, const int32_t *, int, const T *, \
+                                              const T *, int, int, bool, double, double *);         \
   template hipError_t launch_axpby<T>(hipStream_t, const T *, T *, int64_t, double);               \
   template hipError_t launch_gather<T>(hipStream_t, const T *, const int32_t *, T *, int64_t);
 

@@ -442,7 +442,9 @@ struct Problem final : ProblemBase {
   void ensure_factors(int r, int k) {
     if (r > fcap) {
       const int cap = std::max(r, fcap * 2);
-      fstride = std::max(2, (cap + 1) & ~1);
+      // rows of 16 bytes' multiples (the sampled update reads them 16 bytes at a time)
+      constexpr int al = 16 / (int)sizeof(T);
+      fstride = std::max(al, (cap + al - 1) / al * al);
       fcap = cap;
       Fu.alloc(sizeof(T) * (size_t)ix.m * fstride);
       Fv.alloc(sizeof(T) * (size_t)ix.n * fstride);
@@ -860,23 +862,21 @@ struct Problem final : ProblemBase {
     rank = r;
   }
 
-  // Sampled product + residual + update on both copies; returns residual^2
-  // (workgroup partials added on the host in order, compensated).
+  // Sampled product + residual + update of both copies of Y in one pass over
+  // the row-compressed order (the column copy through csc_of_csr); returns
+  // residual^2 (workgroup partials added on the host in order, compensated).
   double sample_pass(int r, double delta, bool want_res) {
     const double vb = sizeof(T);
-    // algorithmic bytes per pass: index, M and Y read, Y written, the row
-    // pointers, both factors once
-    const double pass_bytes = (double)ix.nnz * (4.0 + 3.0 * vb) + vb * (double)(ix.m + ix.n) * r;
+    // algorithmic bytes: index, M and Y read, Y written, the position in the
+    // column copy read and that copy written, the row pointers, both factors
+    // once
+    const double pass_bytes = (double)ix.nnz * (8.0 + 4.0 * vb) + vb * (double)(ix.m + ix.n) * r;
     prof.begin();
     HIP_CHECK(launch_sample_update<T>(stream, lanes_r, rowptr.as<int32_t>(), colidx.as<int32_t>(), Mr.as<T>(),
-                                      Yr.as<T>(), (int)ix.m, Fu.as<T>(), Fv.as<T>(), r, fstride, true, delta,
+                                      Yr.as<T>(), Yc.as<T>(), csc_of_csr.as<int32_t>(), (int)ix.m, Fu.as<T>(),
+                                      Fv.as<T>(), r, fstride, true, delta,
                                       want_res ? sample_part.as<double>() : nullptr));
     prof.end(kSample, pass_bytes + 4.0 * (ix.m + 1));
-    prof.begin();
-    HIP_CHECK(launch_sample_update<T>(stream, lanes_c, colptr.as<int32_t>(), rowidx.as<int32_t>(), Mc.as<T>(),
-                                      Yc.as<T>(), (int)ix.n, Fu.as<T>(), Fv.as<T>(), r, fstride, false, delta,
-                                      nullptr));
-    prof.end(kSample, pass_bytes + 4.0 * (ix.n + 1));
     if (!want_res) return 0.0;
     const int nb = sample_blocks((int)ix.m, lanes_r);
     HIP_CHECK(hipMemcpyAsync(sample_host.p, sample_part.p, sizeof(double) * nb, hipMemcpyDeviceToHost, stream));
