@@ -506,6 +506,21 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
   __shared__ double scal[2];  // |h|^2, s (reduce_pending)
   const bool corr = in.nqx > 0;
   const int il = threadIdx.x % kRowLanes, g = threadIdx.x / kRowLanes;
+  const int lane = threadIdx.x % L, grp = threadIdx.x / L;
+  constexpr int kGroups = kRowBlock / L;
+  const int r0 = blockIdx.x * rows_per_blk;
+  const int r1 = min(nrows, r0 + rows_per_blk);
+  // x staged in one segment and at most one row per lane group: the row's
+  // bounds are loaded first, its first half batch of entries right after the
+  // other independent loads, so both round trips overlap the staging of x
+  // and the pending update (a full batch held that long would spill)
+  const bool early = STAGE && L >= 8 && nseg == 1 && rows_per_blk <= kGroups;
+  const int erow = r0 + grp;
+  int ebeg = 0, eend = 0;
+  if (early && erow < r1) {
+    ebeg = ptr[erow];
+    eend = ptr[erow + 1];
+  }
   // this thread's Q values and prev for the epilogue (rows of at most
   // kRowLanes per workgroup and nq < kColsPerPass)
   const bool fast = (part_out != nullptr || corr) && nq < kColsPerPass && rows_per_blk <= kRowLanes;
@@ -527,6 +542,18 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
   if (kEarlyX) {
     load_q8<T>(qx8, in.Qx, in.ldqx, in.nqx, xrow, xvalid);
     xv0 = in.x[xvalid ? xrow : 0];
+  }
+  constexpr int kEarly = kSpmvUnroll / 2;
+  int eii[kEarly];
+  T evv[kEarly];
+  if (early) {
+#pragma unroll
+    for (int j = 0; j < kEarly; ++j) {
+      const int t = ebeg + lane + j * L;
+      const bool inr = t < eend;
+      eii[j] = inr ? idx[t] : 0;
+      evv[j] = inr ? val[t] : (T)0;
+    }
   }
   const T *x = in.x;
   if constexpr (STAGE) stage_segment<T>(x, min(segcols, ncols), xs);
@@ -557,10 +584,6 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
       gl[c] = t;
     }
   }
-  const int lane = threadIdx.x % L, grp = threadIdx.x / L;
-  constexpr int kGroups = kRowBlock / L;
-  const int r0 = blockIdx.x * rows_per_blk;
-  const int r1 = min(nrows, r0 + rows_per_blk);
   const int nsg = STAGE ? nseg : 1;
   for (int sgm = 0; sgm < nsg; ++sgm) {
     const int c0 = STAGE ? sgm * segcols : 0;
@@ -584,6 +607,13 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
       }
       T acc = (T)0;
       int t = beg + lane;
+      if (early) {
+        // the first batch arrived with the early loads (same order)
+#pragma unroll
+        for (int j = 0; j < kEarly; ++j)
+          if (t + j * L < end) acc = fma(evv[j], xv[eii[j]], acc);
+        t += kEarly * L;
+      }
       for (; t + (kSpmvUnroll - 1) * L < end; t += kSpmvUnroll * L) {
         int ii[kSpmvUnroll];
         T vv[kSpmvUnroll];
