@@ -95,16 +95,18 @@ struct SpmvInput {
 
 // p = A x' - s prev over nrows rows (prev may be null), x' as above; with
 // nqx > 0 it is taken as (A x - Q g) / s - s prev, where Q must hold the nq
-// = nqx + side basis columns of p's side.  segptr: nrows x (nseg + 1)
-// segment starts (null unless nseg > 1).  With dots_out non-null the kernel
+// = nqx + side basis columns of p's side.  Column indices: idx16 (16-bit,
+// ncols <= 65536: a quarter less streamed per entry) when not null, else
+// idx.  segptr: nrows x (nseg + 1) segment starts (null unless nseg > 1).  With dots_out non-null the kernel
 // also writes the partial dot products of p with the nq columns of Q and
 // |p|^2 (column nq): nq + 1 columns, p's own pending update.  Returns
 // hipErrorInvalidValue for inconsistent arguments (nqx > 0 with a missing
 // pointer, nq != nqx + side, or nq > kSpmvAuxCols).
 template <typename T>
-hipError_t launch_spmv(hipStream_t s, const SpmvPlan &pl, const int32_t *ptr, const int32_t *idx, const T *val,
-                       const int32_t *segptr, const SpmvInput<T> &in, int ncols, const T *prev, T *p, int nrows,
-                       const T *Q, int64_t ldq, int nq, double *dots_out);
+hipError_t launch_spmv(hipStream_t s, const SpmvPlan &pl, const int32_t *ptr, const int32_t *idx,
+                       const uint16_t *idx16, const T *val, const int32_t *segptr, const SpmvInput<T> &in,
+                       int ncols, const T *prev, T *p, int nrows, const T *Q, int64_t ldq, int nq,
+                       double *dots_out);
 
 // s (and |h|^2 / |x|^2) of a pending vector, exactly as the sparse product
 // that consumes it computes them: *s_out, *removed_out (may be null).

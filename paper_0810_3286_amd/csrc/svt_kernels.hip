@@ -486,9 +486,9 @@ __device__ __forceinline__ void stage_segment(const T *__restrict__ src, int cn,
   }
 }
 
-template <typename T, int L, bool STAGE>
+template <typename T, typename I, int L, bool STAGE>
 __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
-    const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx, const T *__restrict__ val,
+    const int32_t *__restrict__ ptr, const I *__restrict__ idx, const T *__restrict__ val,
     const int32_t *__restrict__ segptr, int nseg, int segcols, const SpmvInput<T> in, int ncols,
     const T *__restrict__ prev, T *__restrict__ p, int nrows, int rows_per_blk, const T *__restrict__ Q,
     int64_t ldq, int nq, double *__restrict__ part_out) {
@@ -551,7 +551,7 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
     for (int j = 0; j < kEarly; ++j) {
       const int t = ebeg + lane + j * L;
       const bool inr = t < eend;
-      eii[j] = inr ? idx[t] : 0;
+      eii[j] = inr ? (int)idx[t] : 0;
       evv[j] = inr ? val[t] : (T)0;
     }
   }
@@ -619,7 +619,7 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
         T vv[kSpmvUnroll];
 #pragma unroll
         for (int j = 0; j < kSpmvUnroll; ++j) {
-          ii[j] = idx[t + j * L];
+          ii[j] = (int)idx[t + j * L];
           vv[j] = val[t + j * L];
         }
 #pragma unroll
@@ -632,7 +632,7 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
 #pragma unroll
         for (int j = 0; j < kSpmvUnroll; ++j) {
           const bool inr = t + j * L < end;
-          ii[j] = inr ? idx[t + j * L] : c0;
+          ii[j] = inr ? (int)idx[t + j * L] : c0;
           vv[j] = inr ? val[t + j * L] : (T)0;
         }
 #pragma unroll
@@ -1215,28 +1215,13 @@ SpmvPlan spmv_plan(int nrows, int ncols, int elem_bytes, int lds_bytes, int mode
   return pl;
 }
 
-template <typename T>
-hipError_t launch_spmv(hipStream_t s, const SpmvPlan &pl, const int32_t *ptr, const int32_t *idx, const T *val,
-                       const int32_t *segptr, const SpmvInput<T> &in, int ncols, const T *prev, T *p, int nrows,
-                       const T *Q, int64_t ldq, int nq, double *dots_out) {
-  if (pl.nseg > 1 && segptr == nullptr) return hipErrorInvalidValue;
-  if (in.x == nullptr || p == nullptr) return hipErrorInvalidValue;
-  if ((dots_out != nullptr || in.nqx > 0) && nq > 0 && Q == nullptr) return hipErrorInvalidValue;
-  if (in.nqx < 0 || nq < 0) return hipErrorInvalidValue;
-  if (in.nqx > 0) {
-    // the deferred update: its coefficients and their image must fit the
-    // LDS reserved for them, and Q must be the basis the relations name
-    if (in.pend == nullptr || in.Qx == nullptr || in.alpha == nullptr || in.beta == nullptr) return hipErrorInvalidValue;
-    if (in.side != 0 && in.side != 1) return hipErrorInvalidValue;
-    if (nq != in.nqx + in.side || nq > kSpmvAuxCols) return hipErrorInvalidValue;
-    if (in.x_out != nullptr && in.ldqx < ncols) return hipErrorInvalidValue;
-  }
-  if (in.pend != nullptr && in.np < 1) return hipErrorInvalidValue;
-  const RowPlan rp = row_plan(nrows);
-  if (rp.nblk != pl.nblk || rp.rows_per_blk != pl.rows_per_blk) return hipErrorInvalidValue;
+template <typename T, typename I>
+hipError_t launch_spmv_i(hipStream_t s, const SpmvPlan &pl, const int32_t *ptr, const I *idx, const T *val,
+                         const int32_t *segptr, const SpmvInput<T> &in, int ncols, const T *prev, T *p,
+                         int nrows, const T *Q, int64_t ldq, int nq, double *dots_out) {
 #define SVT_SPMVR(LN, ST)                                                                          \
   do {                                                                                            \
-    auto kern = k_spmv_rows<T, LN, ST>;                                                           \
+    auto kern = k_spmv_rows<T, I, LN, ST>;                                                        \
     hipError_t ea = allow_dynamic_lds(reinterpret_cast<const void *>(kern), pl.lds);              \
     if (ea != hipSuccess) return ea;                                                              \
     SVT_LAUNCH(kern, dim3(pl.nblk), dim3(kRowBlock), pl.lds, s, ptr, idx, val, segptr, pl.nseg,    \
@@ -1258,6 +1243,35 @@ hipError_t launch_spmv(hipStream_t s, const SpmvPlan &pl, const int32_t *ptr, co
 #undef SVT_SPMVS
 #undef SVT_SPMVR
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_spmv(hipStream_t s, const SpmvPlan &pl, const int32_t *ptr, const int32_t *idx,
+                       const uint16_t *idx16, const T *val, const int32_t *segptr, const SpmvInput<T> &in,
+                       int ncols, const T *prev, T *p, int nrows, const T *Q, int64_t ldq, int nq,
+                       double *dots_out) {
+  if (pl.nseg > 1 && segptr == nullptr) return hipErrorInvalidValue;
+  if (in.x == nullptr || p == nullptr) return hipErrorInvalidValue;
+  if (idx16 != nullptr && ncols > 65536) return hipErrorInvalidValue;
+  if ((dots_out != nullptr || in.nqx > 0) && nq > 0 && Q == nullptr) return hipErrorInvalidValue;
+  if (in.nqx < 0 || nq < 0) return hipErrorInvalidValue;
+  if (in.nqx > 0) {
+    // the deferred update: its coefficients and their image must fit the
+    // LDS reserved for them, and Q must be the basis the relations name
+    if (in.pend == nullptr || in.Qx == nullptr || in.alpha == nullptr || in.beta == nullptr) return hipErrorInvalidValue;
+    if (in.side != 0 && in.side != 1) return hipErrorInvalidValue;
+    if (nq != in.nqx + in.side || nq > kSpmvAuxCols) return hipErrorInvalidValue;
+    if (in.x_out != nullptr && in.ldqx < ncols) return hipErrorInvalidValue;
+  }
+  if (in.pend != nullptr && in.np < 1) return hipErrorInvalidValue;
+  const RowPlan rp = row_plan(nrows);
+  if (rp.nblk != pl.nblk || rp.rows_per_blk != pl.rows_per_blk) return hipErrorInvalidValue;
+  if (idx16 != nullptr)
+    return launch_spmv_i<T, uint16_t>(s, pl, ptr, idx16, val, segptr, in, ncols, prev, p, nrows, Q, ldq, nq,
+                                      dots_out);
+  if (idx == nullptr) return hipErrorInvalidValue;
+  return launch_spmv_i<T, int32_t>(s, pl, ptr, idx, val, segptr, in, ncols, prev, p, nrows, Q, ldq, nq,
+                                   dots_out);
 }
 
 size_t gs_update_lds(int nq, int rows_per_blk) {
@@ -1384,8 +1398,8 @@ hipError_t launch_gather(hipStream_t s, const T *x, const int32_t *map, T *y, in
 
 #define SVT_INSTANTIATE(T)                                                                          \
   template hipError_t launch_spmv<T>(hipStream_t, const SpmvPlan &, const int32_t *, const int32_t *,      \
-                                     const T *, const int32_t *, const SpmvInput<T> &, int, const T *, \
-                                     T *, int, const T *, int64_t, int, double *);                     \
+                                     const uint16_t *, const T *, const int32_t *, const SpmvInput<T> &, \
+                                     int, const T *, T *, int, const T *, int64_t, int, double *);     \
   template hipError_t launch_gs_update<T>(hipStream_t, T *, int, const T *, int64_t, int, const double *, \
                                           double *, bool, double *);                                   \
   template hipError_t launch_sumsq<T>(hipStream_t, const T *, int, double *);                          \

@@ -278,6 +278,7 @@ struct Problem final : ProblemBase {
   SpmvPlan plan_r{}, plan_c{};        // sparse products (CSR, CSC)
   int lds_limit = 64 * 1024;          // LDS bytes a workgroup may use
   DevMem seg_r, seg_c;                // their segment starts (when nseg > 1)
+  DevMem colidx16, rowidx16;          // 16-bit copies of colidx / rowidx (n, m <= 65536)
   DevMem Mr, Mc, Yr, Yc;          // values, T
   DevMem Ub, Vb;                  // bases, T, column-major
   int kcap = 0;                   // columns available in Ub (Vb has kcap + 1)
@@ -344,6 +345,19 @@ struct Problem final : ProblemBase {
     HIP_CHECK(hipMemcpyAsync(colptr.p, ix.colptr.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, stream));
     HIP_CHECK(hipMemcpyAsync(rowidx.p, ix.rowidx.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, stream));
     HIP_CHECK(hipMemcpyAsync(csc_of_csr.p, ix.csc_of_csr.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, stream));
+    // 16-bit column indices where they fit: the sparse product streams 6
+    // instead of 8 bytes per FP32 entry
+    std::vector<uint16_t> c16, r16;
+    if (n <= 65536) {
+      c16.assign(ix.colidx.begin(), ix.colidx.end());
+      colidx16.alloc(sizeof(uint16_t) * std::max<int64_t>(nnz, 1));
+      HIP_CHECK(hipMemcpyAsync(colidx16.p, c16.data(), sizeof(uint16_t) * nnz, hipMemcpyHostToDevice, stream));
+    }
+    if (m <= 65536) {
+      r16.assign(ix.rowidx.begin(), ix.rowidx.end());
+      rowidx16.alloc(sizeof(uint16_t) * std::max<int64_t>(nnz, 1));
+      HIP_CHECK(hipMemcpyAsync(rowidx16.p, r16.data(), sizeof(uint16_t) * nnz, hipMemcpyHostToDevice, stream));
+    }
     {
       int lds = 0;
       HIP_CHECK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
@@ -458,15 +472,18 @@ struct Problem final : ProblemBase {
   // orientation helpers: A's row-compressed and column-compressed structures
   struct Csx {
     const int32_t *ptr, *idx;
+    const uint16_t *idx16;     // 16-bit copy of idx (null when ncols > 65536)
     int nrows, ncols;
     SpmvPlan *plan;            // row partition, lanes, LDS segments of x (0: gather)
     const int32_t *segptr;
   };
   Csx csr_struct() {
-    return {rowptr.as<int32_t>(), colidx.as<int32_t>(), (int)ix.m, (int)ix.n, &plan_r, seg_r.as<int32_t>()};
+    return {rowptr.as<int32_t>(), colidx.as<int32_t>(), colidx16.as<uint16_t>(), (int)ix.m, (int)ix.n, &plan_r,
+            seg_r.as<int32_t>()};
   }
   Csx csc_struct() {
-    return {colptr.as<int32_t>(), rowidx.as<int32_t>(), (int)ix.n, (int)ix.m, &plan_c, seg_c.as<int32_t>()};
+    return {colptr.as<int32_t>(), rowidx.as<int32_t>(), rowidx16.as<uint16_t>(), (int)ix.n, (int)ix.m, &plan_c,
+            seg_c.as<int32_t>()};
   }
   int spmv_segments(int which) const override { return (which == 0 ? plan_r : plan_c).nseg; }
   Csx a_rows_struct() { return a_is_y ? csr_struct() : csc_struct(); }
@@ -477,14 +494,14 @@ struct Problem final : ProblemBase {
   // in the same kernel.
   void spmv(const Csx &c, const T *vals, const SpmvInput<T> &in, const T *prev, T *out, const T *Q = nullptr,
             int64_t ldq = 0, int nq = 0, double *dots = nullptr) {
-    hipError_t e = launch_spmv<T>(stream, *c.plan, c.ptr, c.idx, vals, c.segptr, in, c.ncols, prev, out,
-                                  c.nrows, Q, ldq, nq, dots);
+    hipError_t e = launch_spmv<T>(stream, *c.plan, c.ptr, c.idx, c.idx16, vals, c.segptr, in, c.ncols, prev,
+                                  out, c.nrows, Q, ldq, nq, dots);
     if (e == hipErrorInvalidValue && c.plan->nseg > 0) {
       // the device refused the LDS size: gather x from memory from now on
       (void)hipGetLastError();
       *c.plan = spmv_plan(c.nrows, c.ncols, (int)sizeof(T), lds_limit, 1);
-      e = launch_spmv<T>(stream, *c.plan, c.ptr, c.idx, vals, nullptr, in, c.ncols, prev, out, c.nrows, Q, ldq,
-                         nq, dots);
+      e = launch_spmv<T>(stream, *c.plan, c.ptr, c.idx, c.idx16, vals, nullptr, in, c.ncols, prev, out, c.nrows,
+                         Q, ldq, nq, dots);
     }
     HIP_CHECK(e);
   }
@@ -504,11 +521,13 @@ struct Problem final : ProblemBase {
     return out;
   }
 
-  // Algorithmic bytes: index and value of every stored entry, the gathered
-  // vector once, the previous vector and the result.
+  // Algorithmic bytes: index (2 or 4 bytes, as stored) and value of every
+  // stored entry, the gathered vector once, the previous vector and the
+  // result.
   double spmv_bytes(const Csx &c, int ncols_x, bool has_prev) const {
     const double vb = sizeof(T);
-    return (double)ix.nnz * (vb + 4.0) + 4.0 * (c.nrows + 1) + vb * ncols_x + vb * c.nrows +
+    const double ib = c.idx16 ? 2.0 : 4.0;
+    return (double)ix.nnz * (vb + ib) + 4.0 * (c.nrows + 1) + vb * ncols_x + vb * c.nrows +
            (has_prev ? vb * c.nrows : 0.0);
   }
 
