@@ -486,6 +486,30 @@ __device__ __forceinline__ void stage_segment(const T *__restrict__ src, int cn,
   }
 }
 
+// stage_segment through the LDS DMA path (global_load_lds_dwordx4): wave w
+// copies the 1 KB chunks w, w + 16, ... of src straight into LDS, without
+// registers and with every chunk in flight at once; lanes past the end of
+// the segment are masked off (a wave's LDS writes are 16 bytes per active
+// lane from its uniform chunk base).  src 16-byte aligned; the tail of cn
+// that is not a whole 16-byte unit is copied by plain loads.  Returns after
+// the copies have landed (this thread's; the caller's barrier covers all).
+template <typename T>
+__device__ __forceinline__ void stage_segment_dma(const T *__restrict__ src, int cn, T *xs) {
+  constexpr int kv = 16 / sizeof(T);
+  const int nv = cn / kv;
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  const int nchunks = (nv + kWave - 1) / kWave;
+  for (int ch = w; ch < nchunks; ch += kRowWaves) {
+    const int e = ch * kWave + l;
+    if (e < nv)
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src + (size_t)e * kv),
+                                       (__attribute__((address_space(3))) void *)(xs + (size_t)ch * kWave * kv),
+                                       16, 0, 0);
+  }
+  for (int ii = nv * kv + threadIdx.x; ii < cn; ii += kRowBlock) xs[ii] = src[ii];
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
 template <typename T, typename I, int L, bool STAGE>
 __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
     const int32_t *__restrict__ ptr, const I *__restrict__ idx, const T *__restrict__ val,
@@ -556,7 +580,7 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
     }
   }
   const T *x = in.x;
-  if constexpr (STAGE) stage_segment<T>(x, min(segcols, ncols), xs);
+  if constexpr (STAGE) stage_segment_dma<T>(x, min(segcols, ncols), xs);
   // h, |x|^2 (all threads), then s (thread 0; the others read it after the
   // next barrier) and g
   if (in.pend != nullptr) {
@@ -591,7 +615,7 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
     if constexpr (STAGE) {
       if (sgm > 0) {
         __syncthreads();  // the previous segment's gathers are done
-        stage_segment<T>(x + c0, min(segcols, ncols - c0), xs);
+        stage_segment_dma<T>(x + c0, min(segcols, ncols - c0), xs);
       }
       __syncthreads();
       xv = xs;
