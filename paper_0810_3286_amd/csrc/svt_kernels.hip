@@ -387,21 +387,21 @@ __device__ __forceinline__ void row_dots_lds(const T (&q)[8], double v, bool val
 
 // The thread's eight Q values of row `row` in the column-group layout
 // (columns g + 8 j, clamped to a valid column).  Invalid threads load row 0
-// instead (Q has at least one row when nq > 0): the values are in flight
-// without a branch, and every use masks them.  nq = 0 or Q null: zeros.
+// instead, and with nq = 0 or Q null every load reads fallback[0] (a valid
+// element): the loads have no branch, so the compiler has no merged value to
+// convert, and waits for them only where they are used; every use masks
+// them (c < nq, valid rows).
 template <typename T>
 __device__ __forceinline__ void load_q8(T (&q)[8], const T *__restrict__ Q, int64_t ldq, int nq, int row,
-                                        bool valid) {
+                                        bool valid, const T *__restrict__ fallback) {
   const int g = threadIdx.x / kRowLanes;
-  if (nq > 0 && Q != nullptr) {
-    const int last = nq - 1;
-    const int r = valid ? row : 0;
+  const bool have = nq > 0 && Q != nullptr;
+  const T *base = have ? Q : fallback;
+  const int64_t ld = have ? ldq : 0;
+  const int last = have ? nq - 1 : 0;
+  const int r = (have && valid) ? row : 0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) q[j] = Q[(size_t)min(g + 8 * j, last) * ldq + r];
-  } else {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) q[j] = (T)0;
-  }
+  for (int j = 0; j < 8; ++j) q[j] = base[(size_t)min(g + 8 * j, last) * ld + r];
 }
 
 // The sparse product of one bidiagonalisation half-step, p = A x - s prev
@@ -491,12 +491,16 @@ __device__ __forceinline__ void stage_segment(const T *__restrict__ src, int cn,
 // registers and with every chunk in flight at once; lanes past the end of
 // the segment are masked off (a wave's LDS writes are 16 bytes per active
 // lane from its uniform chunk base).  src 16-byte aligned; the tail of cn
-// that is not a whole 16-byte unit is copied by plain loads.  Returns after
-// the copies have landed (this thread's; the caller's barrier covers all).
+// that is not a whole 16-byte unit is copied first, by plain loads.  Returns
+// with the copies in flight: the caller waits (stage_wait) before the
+// barrier after which the segment is read, so that loads issued in between
+// travel together with them.
 template <typename T>
 __device__ __forceinline__ void stage_segment_dma(const T *__restrict__ src, int cn, T *xs) {
   constexpr int kv = 16 / sizeof(T);
   const int nv = cn / kv;
+  if (nv * kv < cn)
+    for (int ii = nv * kv + threadIdx.x; ii < cn; ii += kRowBlock) xs[ii] = src[ii];
   const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
   const int nchunks = (nv + kWave - 1) / kWave;
   for (int ch = w; ch < nchunks; ch += kRowWaves) {
@@ -506,9 +510,11 @@ __device__ __forceinline__ void stage_segment_dma(const T *__restrict__ src, int
                                        (__attribute__((address_space(3))) void *)(xs + (size_t)ch * kWave * kv),
                                        16, 0, 0);
   }
-  for (int ii = nv * kv + threadIdx.x; ii < cn; ii += kRowBlock) xs[ii] = src[ii];
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
+
+// This thread's LDS DMA copies have landed (they count as vector memory
+// operations); a barrier after it covers the workgroup's.
+__device__ __forceinline__ void stage_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 template <typename T, typename I, int L, bool STAGE>
 __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
@@ -551,8 +557,8 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
   const int frow = blockIdx.x * rows_per_blk + il;
   const bool fvalid = fast && il < rows_per_blk && frow < nrows;
   T q8[8];
-  load_q8<T>(q8, Q, ldq, nq, frow, fvalid);
-  const T prev8 = (fast && prev != nullptr) ? prev[fvalid ? frow : 0] : (T)0;
+  load_q8<T>(q8, Q, ldq, nq, frow, fvalid, in.x);
+  const T prev8 = (prev != nullptr ? prev : in.x)[(fvalid && prev != nullptr) ? frow : 0];
   // this workgroup's slice of x and its rows of Q_x (x' = (x - Q_x h) / s),
   // one entry per row slot: loaded now in FP32, after the product in FP64
   // (whose product loop has no registers to spare)
@@ -564,7 +570,7 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
   T qx8[8];
   T xv0 = (T)0;
   if (kEarlyX) {
-    load_q8<T>(qx8, in.Qx, in.ldqx, in.nqx, xrow, xvalid);
+    load_q8<T>(qx8, in.Qx, in.ldqx, in.nqx, xrow, xvalid, in.x);
     xv0 = in.x[xvalid ? xrow : 0];
   }
   constexpr int kEarly = kSpmvUnroll / 2;
@@ -617,6 +623,7 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
         __syncthreads();  // the previous segment's gathers are done
         stage_segment_dma<T>(x + c0, min(segcols, ncols - c0), xs);
       }
+      stage_wait();
       __syncthreads();
       xv = xs;
     }
@@ -668,7 +675,7 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
     }
   }
   if (!kEarlyX) {
-    load_q8<T>(qx8, in.Qx, in.ldqx, in.nqx, xrow, xvalid);
+    load_q8<T>(qx8, in.Qx, in.ldqx, in.nqx, xrow, xvalid, in.x);
     xv0 = in.x[xvalid ? xrow : 0];
   }
   __syncthreads();  // racc complete, s published; the region is free again
@@ -829,7 +836,7 @@ __global__ __launch_bounds__(kRowBlock) void k_gs_update(T *__restrict__ p, int 
     const int row = r0 + i;
     const bool valid = row < r1;
     T q[8];
-    load_q8<T>(q, Q, ldq, nq, row, valid);
+    load_q8<T>(q, Q, ldq, nq, row, valid, p);
     const T p0 = p[valid ? row : r0];
     reduce_columns(part_in, np_in, nq + 1, hs, upd);
     record_removed(hs, nq, removed);
