@@ -573,6 +573,19 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
     load_q8<T>(qx8, in.Qx, in.ldqx, in.nqx, xrow, xvalid, in.x);
     xv0 = in.x[xvalid ? xrow : 0];
   }
+  // the bidiagonal coefficients of g (thread c = threadIdx.x < nq <=
+  // kSpmvAuxCols = kRowBlock needs alpha[c] and beta[c + 1] (side 0) or
+  // beta[c] (side 1)), from clamped indices: loaded here in FP32, just
+  // before g in FP64 (no registers to spare there)
+  const int gc = threadIdx.x;
+  double ga = 0.0, gb = 0.0;
+  auto load_g = [&]() {
+    if (corr) {
+      ga = in.alpha[min(gc, in.nqx - 1)];
+      gb = in.side == 0 ? in.beta[min(gc + 1, in.nqx - 1)] : in.beta[min(gc, in.nqx)];
+    }
+  };
+  if constexpr (sizeof(T) == 4) load_g();
   constexpr int kEarly = kSpmvUnroll / 2;
   int eii[kEarly];
   T evv[kEarly];
@@ -602,17 +615,16 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
     if (threadIdx.x == 0) scal[1] = 1.0;
     if (blockIdx.x == 0 && threadIdx.x == 0 && in.s_out != nullptr) *in.s_out = 1.0;
   }
-  if (corr) {
-    for (int c = threadIdx.x; c < nq; c += kRowBlock) {
-      double t = 0.0;
-      if (c < in.nqx) t = in.alpha[c] * hs[c];
-      if (in.side == 0) {
-        if (c + 1 < in.nqx) t = fma(in.beta[c + 1], hs[c + 1], t);
-      } else {
-        if (c >= 1 && c - 1 < in.nqx) t = fma(in.beta[c], hs[c - 1], t);
-      }
-      gl[c] = t;
+  if constexpr (sizeof(T) == 8) load_g();
+  if (corr && gc < nq) {
+    double t = 0.0;
+    if (gc < in.nqx) t = ga * hs[gc];
+    if (in.side == 0) {
+      if (gc + 1 < in.nqx) t = fma(gb, hs[gc + 1], t);
+    } else {
+      if (gc >= 1 && gc - 1 < in.nqx) t = fma(gb, hs[gc - 1], t);
     }
+    gl[gc] = t;
   }
   const int nsg = STAGE ? nseg : 1;
   for (int sgm = 0; sgm < nsg; ++sgm) {
