@@ -37,6 +37,7 @@ ROCPROF_NAMES = {
     "k_spmv": ("k_spmv",),
     "k_gs_update_pass1": ("k_gs_update<float, false>", "k_gs_update<double, false>"),
     "k_ritz": ("k_ritz",),
+    "k_gather": ("k_gather",),
     "k_sample_update": ("k_sample_update",),
     "k_gs_update_pass2": ("k_gs_update<float, true>", "k_gs_update<double, true>"),
 }

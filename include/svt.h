@@ -207,14 +207,18 @@ svt_status svt_spmv_plan(const svt_problem *h, int32_t which, int32_t *segments)
 
 /* Kernel timing of the last solve when params.profile = 1.  Each kind is
    one kernel, and each timed bracket holds exactly one launch of it:
-     0 k_spmv_rows           sparse product of a bidiagonalisation half-step,
-                             with the first Gram-Schmidt pass's dot products
-     1 (none)                kept for numbering: no longer a kernel of its own
-     2 k_gs_update<false>    first update + second pass's dot products
+     0 k_spmv_rows           a bidiagonalisation half-step: the deferred
+                             update of its input, the sparse product and
+                             the dot products of its output
+     1 k_gather4             the column copy of Y refreshed from the row
+                             copy (one launch per iteration)
+     2 k_gs_update<false>    two-pass mode: first update + second pass's
+                             dot products
      3 k_ritz                Ritz vectors (one launch per side)
-     4 k_sample_update       sampled product, residual and update (one
-                             launch per compressed orientation)
-     5 k_gs_update<true>     second update + |p|^2 partials
+     4 k_sample_update       sampled product, residual and update of the
+                             row copy of Y (one launch per iteration)
+     5 k_gs_update<true>     one update + |p|^2 partials (two-pass mode, or
+                             an update too wide to defer)
    Outputs: the number of launches, their summed duration in milliseconds
    (HIP events on the solve's stream) and their summed algorithmic bytes:
    the index, value and vector traffic each launch must move at least once.

@@ -147,16 +147,14 @@ hipError_t launch_ritz(hipStream_t s, const T *Q, int64_t ldq, int nrows, int k,
 
 // For each stored entry t of row i (col j = idx[t]):
 //   x = sum_l U[u_row, l] V[v_row, l]  (fma chain in l order, u entry first),
-//   e = M[t] - x, Y[t] = Y[t] + delta e, and (Y2 non-null) Y2[map2[t]] = the
-//   same value: the other orientation's copy of Y.
+//   e = M[t] - x, Y[t] = Y[t] + delta e.
 // rs: row stride of both factors, a multiple of 16 / sizeof(T) (>= r), rows
 // zero padded.  With part_out non-null, workgroup b writes its sum of e^2 to
 // part_out[b] (sample_blocks() workgroups).
 template <typename T>
 hipError_t launch_sample_update(hipStream_t s, int lanes, const int32_t *ptr, const int32_t *idx,
-                                const T *M, T *Y, T *Y2, const int32_t *map2, int nrows, const T *Fu,
-                                const T *Fv, int r, int rs, bool row_side_is_u, double delta,
-                                double *part_out);
+                                const T *M, T *Y, int nrows, const T *Fu, const T *Fv, int r, int rs,
+                                bool row_side_is_u, double delta, double *part_out);
 int sample_blocks(int nrows, int lanes);
 
 // y[t] = a * x[t] (the kick: Y = k0 delta M).

@@ -1022,12 +1022,11 @@ __global__ __launch_bounds__(kRitzBlock) void k_ritz(const T *__restrict__ Q, in
 
 // Sampled product, residual and iterate update in one pass over a compressed
 // orientation of Omega.  The dot product is the same fma chain in either
-// orientation (u-factor entry first).  With Y2, the new value of entry t is
-// also written to Y2[map2[t]]: the other orientation's copy of Y receives the
-// same values without a second pass (one scattered 4- or 8-byte store per
-// entry instead of the factor-row gathers of a second sampled product).
-// Each workgroup writes its (compensated) sum of e^2; the host adds the
-// partials in order.
+// orientation (u-factor entry first).  The other orientation's copy of Y is
+// refreshed from this one by a permutation gather (k_gather4), which costs
+// less than a second sampled product or a scatter of 4-byte stores.  Each
+// workgroup writes its (compensated) sum of e^2; the host adds the partials
+// in order.
 
 template <typename T>
 __device__ __forceinline__ T sampled_dot(const T *__restrict__ urow, const T *__restrict__ vrow, int r) {
@@ -1043,7 +1042,7 @@ __device__ __forceinline__ T sampled_dot(const T *__restrict__ urow, const T *__
 template <typename T, int L, int RB>
 __global__ __launch_bounds__(kBlock) void k_sample_update(
     const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx, const T *__restrict__ M,
-    T *__restrict__ Y, T *__restrict__ Y2, const int32_t *__restrict__ map2, int nrows, int rows_per_blk,
+    T *__restrict__ Y, int nrows, int rows_per_blk,
     const T *__restrict__ Fu, const T *__restrict__ Fv, int r, int rs, int row_side_is_u, T delta,
     double *__restrict__ part_out) {
   __shared__ double sbuf[kWaves];
@@ -1066,7 +1065,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_update(
     // finished in index order (the same sums as one at a time)
     constexpr int kBatch = (RB > 0 && RB <= 16) ? 4 : ((RB > 0 && RB <= 32) ? 2 : 1);
     for (int t0 = beg + lane; t0 < end; t0 += kBatch * L) {
-      int jj[kBatch], mp[kBatch];
+      int jj[kBatch];
       T mv[kBatch], yv[kBatch];
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
@@ -1075,7 +1074,6 @@ __global__ __launch_bounds__(kBlock) void k_sample_update(
         jj[q] = in ? idx[t] : 0;
         mv[q] = in ? M[t] : (T)0;
         yv[q] = in ? Y[t] : (T)0;
-        mp[q] = (in && Y2 != nullptr) ? map2[t] : 0;
       }
       T x[kBatch];
       if constexpr (RB > 0) {
@@ -1117,9 +1115,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_update(
         const int t = t0 + q * L;
         if (t < end) {
           const T e = mv[q] - x[q];
-          const T yn = fma(delta, e, yv[q]);
-          Y[t] = yn;
-          if (Y2 != nullptr) Y2[mp[q]] = yn;
+          Y[t] = fma(delta, e, yv[q]);
           const T yk = fma(e, e, -comp);
           const T tk = sum + yk;
           comp = (tk - sum) - yk;
@@ -1154,6 +1150,27 @@ __global__ __launch_bounds__(kBlock) void k_gather(const T *__restrict__ x, cons
                                                    T *__restrict__ y, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
     y[i] = x[map[i]];
+}
+
+// y[i] = x[map[i]], four consecutive i per thread: one 16-byte load of the
+// map, the four gathers in flight together, 16-byte stores (map and y
+// 16-byte aligned).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather4(const T *__restrict__ x, const int32_t *__restrict__ map,
+                                                    T *__restrict__ y, int64_t n) {
+  const int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * 4;
+  if (i0 + 3 < n) {
+    const int4 m = *reinterpret_cast<const int4 *>(map + i0);
+    const T a = x[m.x], b = x[m.y], c = x[m.z], d = x[m.w];
+    if constexpr (sizeof(T) == 4) {
+      *reinterpret_cast<float4 *>(y + i0) = make_float4(a, b, c, d);
+    } else {
+      *reinterpret_cast<double2 *>(y + i0) = make_double2(a, b);
+      *reinterpret_cast<double2 *>(y + i0 + 2) = make_double2(c, d);
+    }
+  } else {
+    for (int64_t i = i0; i < n; ++i) y[i] = x[map[i]];
+  }
 }
 
 
@@ -1388,15 +1405,14 @@ int sample_blocks(int nrows, int lanes) {
 
 template <typename T>
 hipError_t launch_sample_update(hipStream_t s, int lanes, const int32_t *ptr, const int32_t *idx,
-                                const T *M, T *Y, T *Y2, const int32_t *map2, int nrows, const T *Fu,
-                                const T *Fv, int r, int rs, bool row_side_is_u, double delta,
-                                double *part_out) {
-  if (rs % (16 / (int)sizeof(T)) != 0 || rs < r || (Y2 != nullptr && map2 == nullptr)) return hipErrorInvalidValue;
+                                const T *M, T *Y, int nrows, const T *Fu, const T *Fv, int r, int rs,
+                                bool row_side_is_u, double delta, double *part_out) {
+  if (rs % (16 / (int)sizeof(T)) != 0 || rs < r) return hipErrorInvalidValue;
   const RowChunks ch =
       row_chunks(nrows, std::max((kBlock / lanes) * 4, (nrows + kSampleMaxBlocks - 1) / kSampleMaxBlocks));
 #define SVT_SU2(LN, RB)                                                                          \
-  SVT_LAUNCH((k_sample_update<T, LN, RB>), dim3(ch.nblk), dim3(kBlock), 0, s, ptr, idx, M, Y, Y2, \
-             map2, nrows, ch.rows_per_blk, Fu, Fv, r, rs, row_side_is_u ? 1 : 0, (T)delta, part_out)
+  SVT_LAUNCH((k_sample_update<T, LN, RB>), dim3(ch.nblk), dim3(kBlock), 0, s, ptr, idx, M, Y, nrows, \
+             ch.rows_per_blk, Fu, Fv, r, rs, row_side_is_u ? 1 : 0, (T)delta, part_out)
 #define SVT_SU(LN)                         \
   do {                                     \
     if (r <= 8) SVT_SU2(LN, 8);            \
@@ -1435,7 +1451,13 @@ hipError_t launch_f2d(hipStream_t s, const float *x, double *y, int64_t n) {
 
 template <typename T>
 hipError_t launch_gather(hipStream_t s, const T *x, const int32_t *map, T *y, int64_t n) {
-  SVT_LAUNCH((k_gather<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, x, map, y, n);
+  if (n <= 0) return hipSuccess;
+  if ((reinterpret_cast<uintptr_t>(map) & 15) == 0 && (reinterpret_cast<uintptr_t>(y) & 15) == 0) {
+    const int64_t threads = (n + 3) / 4;
+    SVT_LAUNCH((k_gather4<T>), dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, x, map, y, n);
+  } else {
+    SVT_LAUNCH((k_gather<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, x, map, y, n);
+  }
   return hipGetLastError();
 }
 
@@ -1451,8 +1473,8 @@ hipError_t launch_gather(hipStream_t s, const T *x, const int32_t *map, T *y, in
   template hipError_t launch_ritz<T>(hipStream_t, const T *, int64_t, int, int, const double *,    \
                                      const double *, int, T *, int);                                \
   template hipError_t launch_sample_update<T>(hipStream_t, int, const int32_t *, const int32_t *,  \
-                                              const T *, T *, T *, const int32_t *, int, const T *, \
-                                              const T *, int, int, bool, double, double *);         \
+                                              const T *, T *, int, const T *, const T *, int, int,  \
+                                              bool, double, double *);                              \
   template hipError_t launch_axpby<T>(hipStream_t, const T *, T *, int64_t, double);               \
   template hipError_t launch_gather<T>(hipStream_t, const T *, const int32_t *, T *, int64_t);
 

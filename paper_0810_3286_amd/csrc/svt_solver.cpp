@@ -118,11 +118,12 @@ struct PinnedMem {
 
 // One kind per kernel (each bracket times exactly one launch):
 //   0 k_spmv_rows (with the deferred one-pass update of its input and the
-//   dot products of its output), 1 unused, 2 k_gs_update (first of two
+//   dot products of its output), 1 k_gather4 (column copy of Y), 2
+//   k_gs_update (first of two
 //   passes, with the second pass's dot products), 3 k_ritz, 4
 //   k_sample_update, 5 k_gs_update (one pass with the |p|^2 partials: the
 //   second of two, or a deferred update too wide to fuse).
-enum KernelKind { kSpmv = 0, kUnused1 = 1, kGsUpdate1 = 2, kRitz = 3, kSample = 4, kGsUpdate2 = 5, kKinds = 6 };
+enum KernelKind { kSpmv = 0, kGather = 1, kGsUpdate1 = 2, kRitz = 3, kSample = 4, kGsUpdate2 = 5, kKinds = 6 };
 
 struct Profiler {
   bool on = false;
@@ -274,7 +275,7 @@ struct Problem final : ProblemBase {
   bool own_stream = false;
   int device = 0;
 
-  DevMem rowptr, colidx, colptr, rowidx, csc_of_csr;
+  DevMem rowptr, colidx, colptr, rowidx, csr_of_csc;
   SpmvPlan plan_r{}, plan_c{};        // sparse products (CSR, CSC)
   int lds_limit = 64 * 1024;          // LDS bytes a workgroup may use
   DevMem seg_r, seg_c;                // their segment starts (when nseg > 1)
@@ -333,7 +334,6 @@ struct Problem final : ProblemBase {
     colidx.alloc(sizeof(int32_t) * nnz);
     colptr.alloc(sizeof(int32_t) * (n + 1));
     rowidx.alloc(sizeof(int32_t) * nnz);
-    csc_of_csr.alloc(sizeof(int32_t) * nnz);
     Mr.alloc(sizeof(T) * nnz);
     Mc.alloc(sizeof(T) * nnz);
     Yr.alloc(sizeof(T) * nnz);
@@ -344,7 +344,12 @@ struct Problem final : ProblemBase {
     HIP_CHECK(hipMemcpyAsync(colidx.p, ix.colidx.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, stream));
     HIP_CHECK(hipMemcpyAsync(colptr.p, ix.colptr.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, stream));
     HIP_CHECK(hipMemcpyAsync(rowidx.p, ix.rowidx.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, stream));
-    HIP_CHECK(hipMemcpyAsync(csc_of_csr.p, ix.csc_of_csr.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, stream));
+    // the inverse permutation: the column copy of Y gathers its values from
+    // the row copy after each sampled pass
+    std::vector<int32_t> inv((size_t)nnz);
+    for (int64_t t = 0; t < nnz; ++t) inv[(size_t)ix.csc_of_csr[(size_t)t]] = (int32_t)t;
+    csr_of_csc.alloc(sizeof(int32_t) * std::max<int64_t>(nnz, 1));
+    HIP_CHECK(hipMemcpyAsync(csr_of_csc.p, inv.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, stream));
     // 16-bit column indices where they fit: the sparse product streams 6
     // instead of 8 bytes per FP32 entry
     std::vector<uint16_t> c16, r16;
@@ -881,21 +886,24 @@ struct Problem final : ProblemBase {
     rank = r;
   }
 
-  // Sampled product + residual + update of both copies of Y in one pass over
-  // the row-compressed order (the column copy through csc_of_csr); returns
-  // residual^2 (workgroup partials added on the host in order, compensated).
+  // Sampled product + residual + update of Y in one pass over the
+  // row-compressed order, then the column copy gathered from it through
+  // csr_of_csc; returns residual^2 (workgroup partials added on the host in
+  // order, compensated).
   double sample_pass(int r, double delta, bool want_res) {
     const double vb = sizeof(T);
-    // algorithmic bytes: index, M and Y read, Y written, the position in the
-    // column copy read and that copy written, the row pointers, both factors
-    // once
-    const double pass_bytes = (double)ix.nnz * (8.0 + 4.0 * vb) + vb * (double)(ix.m + ix.n) * r;
+    // algorithmic bytes of the sampled pass: index, M and Y read, Y written,
+    // the row pointers, both factors once
+    const double pass_bytes = (double)ix.nnz * (4.0 + 3.0 * vb) + vb * (double)(ix.m + ix.n) * r;
     prof.begin();
     HIP_CHECK(launch_sample_update<T>(stream, lanes_r, rowptr.as<int32_t>(), colidx.as<int32_t>(), Mr.as<T>(),
-                                      Yr.as<T>(), Yc.as<T>(), csc_of_csr.as<int32_t>(), (int)ix.m, Fu.as<T>(),
-                                      Fv.as<T>(), r, fstride, true, delta,
+                                      Yr.as<T>(), (int)ix.m, Fu.as<T>(), Fv.as<T>(), r, fstride, true, delta,
                                       want_res ? sample_part.as<double>() : nullptr));
     prof.end(kSample, pass_bytes + 4.0 * (ix.m + 1));
+    // the column copy: the map read, one value gathered and one written per entry
+    prof.begin();
+    HIP_CHECK(launch_gather<T>(stream, Yr.as<T>(), csr_of_csc.as<int32_t>(), Yc.as<T>(), ix.nnz));
+    prof.end(kGather, (double)ix.nnz * (4.0 + 2.0 * vb));
     if (!want_res) return 0.0;
     const int nb = sample_blocks((int)ix.m, lanes_r);
     HIP_CHECK(hipMemcpyAsync(sample_host.p, sample_part.p, sizeof(double) * nb, hipMemcpyDeviceToHost, stream));

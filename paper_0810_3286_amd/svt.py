@@ -31,7 +31,7 @@ SVT_CSR = 1
 SVT_STOP_RELRES = 0
 SVT_STOP_NOISY = 1
 
-KERNEL_KINDS = {0: "k_spmv", 2: "k_gs_update_pass1", 3: "k_ritz", 4: "k_sample_update",
+KERNEL_KINDS = {0: "k_spmv", 1: "k_gather", 2: "k_gs_update_pass1", 3: "k_ritz", 4: "k_sample_update",
                 5: "k_gs_update_pass2"}
 
 
