@@ -981,37 +981,51 @@ __global__ __launch_bounds__(kBlock) void k_randn(T *__restrict__ out, int n, ui
 // kRitzTile columns of blockIdx.y (small tiles: the kernel is bound by load
 // latency, so more threads beat fewer re-reads of the basis); it loads
 // kRitzBatch<T> entries of its row at a time (coalesced across the rows,
-// unconditional from clamped addresses), and P and w are uniform across the
-// workgroup (scalar loads).
+// unconditional from clamped addresses).  The tile's rows of P are staged in
+// LDS kRitzChunk at a time: read as uniform values they became one scalar
+// load and one wait per entry.
 constexpr int kRitzTile = 4;
 template <typename T> constexpr int kRitzBatch = 256 / sizeof(T);  // 64 (FP32) or 32 (FP64) loads in flight
 constexpr int kRitzBlock = 128;
+constexpr int kRitzChunk = 512;
 template <typename T>
 __global__ __launch_bounds__(kRitzBlock) void k_ritz(const T *__restrict__ Q, int64_t ldq, int nrows, int k,
                                                      const double *__restrict__ P, const double *__restrict__ w,
                                                      int r, T *__restrict__ out, int rs) {
+  __shared__ double ps[kRitzChunk * kRitzTile];
   const int i = blockIdx.x * kRitzBlock + threadIdx.x;
+  const bool valid = i < nrows;
+  const int ir = valid ? i : 0;
   const int l0 = blockIdx.y * kRitzTile;
-  if (i >= nrows) return;
   const int nl = min(kRitzTile, r - l0);
   double acc[kRitzTile];
 #pragma unroll
   for (int t = 0; t < kRitzTile; ++t) acc[t] = 0.0;
   constexpr int B = kRitzBatch<T>;
-  for (int c0 = 0; c0 < k; c0 += B) {
-    T q[B];
+  for (int cc = 0; cc < k; cc += kRitzChunk) {
+    const int kc = min(kRitzChunk, k - cc);
+    __syncthreads();  // the previous chunk's reads are done
+    for (int e = threadIdx.x; e < kc * kRitzTile; e += kRitzBlock) {
+      const int c = e / kRitzTile, t = e % kRitzTile;
+      ps[e] = (t < nl) ? P[(size_t)(cc + c) * r + l0 + t] : 0.0;
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < kc; c0 += B) {
+      T q[B];
 #pragma unroll
-    for (int j = 0; j < B; ++j) q[j] = Q[(size_t)min(c0 + j, k - 1) * ldq + i];
+      for (int j = 0; j < B; ++j) q[j] = Q[(size_t)(cc + min(c0 + j, kc - 1)) * ldq + ir];
 #pragma unroll
-    for (int j = 0; j < B; ++j) {
-      if (c0 + j < k) {
-        const double *pr = P + (size_t)(c0 + j) * r + l0;
+      for (int j = 0; j < B; ++j) {
+        if (c0 + j < kc) {
+          const double *pr = ps + (c0 + j) * kRitzTile;
 #pragma unroll
-        for (int t = 0; t < kRitzTile; ++t)
-          if (t < nl) acc[t] = fma((double)q[j], pr[t], acc[t]);
+          for (int t = 0; t < kRitzTile; ++t)
+            if (t < nl) acc[t] = fma((double)q[j], pr[t], acc[t]);
+        }
       }
     }
   }
+  if (!valid) return;
 #pragma unroll
   for (int t = 0; t < kRitzTile; ++t) {
     const int l = l0 + t;
