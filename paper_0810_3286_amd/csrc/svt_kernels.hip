@@ -984,7 +984,7 @@ __global__ __launch_bounds__(kBlock) void k_randn(T *__restrict__ out, int n, ui
 // unconditional from clamped addresses).  The tile's rows of P are staged in
 // LDS kRitzChunk at a time: read as uniform values they became one scalar
 // load and one wait per entry.
-constexpr int kRitzTile = 4;
+constexpr int kRitzTile = 2;
 template <typename T> constexpr int kRitzBatch = 256 / sizeof(T);  // 64 (FP32) or 32 (FP64) loads in flight
 constexpr int kRitzBlock = 128;
 constexpr int kRitzChunk = 512;
