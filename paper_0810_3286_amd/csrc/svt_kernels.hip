@@ -351,14 +351,15 @@ constexpr int kDotsLds = sizeof(double) * (8 * kRowBlock + kColsPerPass * 16);
 
 template <typename T>
 __device__ __forceinline__ void row_dots_lds(const T (&q)[8], double v, bool valid, int nq,
-                                             double *__restrict__ part, double *buf) {
+                                             double *__restrict__ part, double *buf, int cb = 0) {
+  // cb: the pass's first column (q holds columns cb + g + 8 j)
   const int C = nq + 1;
   const int g = threadIdx.x / kRowLanes;
   double *prod = buf;                  // 8 x kRowBlock products
   double *mid = buf + 8 * kRowBlock;   // 64 columns x 16 partial sums
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const int c = g + 8 * j;
+    const int c = cb + g + 8 * j;
     const double f = (c < nq) ? (double)q[j] : ((c == nq) ? v : 0.0);
     prod[j * kRowBlock + threadIdx.x] = valid ? f * v : 0.0;
   }
@@ -377,7 +378,7 @@ __device__ __forceinline__ void row_dots_lds(const T (&q)[8], double v, bool val
   __syncthreads();
   if (threadIdx.x < kColsPerPass) {
     const int col = threadIdx.x, gg = col % 8, j = col / 8;
-    const int c = gg + 8 * j;
+    const int c = cb + gg + 8 * j;
     double t = 0.0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) t += mid[col * 16 + k];
@@ -393,7 +394,8 @@ __device__ __forceinline__ void row_dots_lds(const T (&q)[8], double v, bool val
 // them (c < nq, valid rows).
 template <typename T>
 __device__ __forceinline__ void load_q8(T (&q)[8], const T *__restrict__ Q, int64_t ldq, int nq, int row,
-                                        bool valid, const T *__restrict__ fallback) {
+                                        bool valid, const T *__restrict__ fallback, int cb = 0) {
+  // cb: first column of the pass (columns cb + g + 8 j)
   const int g = threadIdx.x / kRowLanes;
   const bool have = nq > 0 && Q != nullptr;
   const T *base = have ? Q : fallback;
@@ -401,7 +403,7 @@ __device__ __forceinline__ void load_q8(T (&q)[8], const T *__restrict__ Q, int6
   const int last = have ? nq - 1 : 0;
   const int r = (have && valid) ? row : 0;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) q[j] = base[(size_t)min(g + 8 * j, last) * ld + r];
+  for (int j = 0; j < 8; ++j) q[j] = base[(size_t)min(cb + g + 8 * j, last) * ld + r];
 }
 
 // The sparse product of one bidiagonalisation half-step, p = A x - s prev
@@ -515,6 +517,26 @@ __device__ __forceinline__ void stage_segment_dma(const T *__restrict__ src, int
 // This thread's LDS DMA copies have landed (they count as vector memory
 // operations); a barrier after it covers the workgroup's.
 __device__ __forceinline__ void stage_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// The dot products for nq >= kColsPerPass with at most one row per row
+// slot: 64 columns per pass through LDS (row_dots_lds with a column base;
+// the general row_dots reduces through shuffle trees).  Not inlined, so
+// that its registers do not add to the sparse product's.
+template <typename T>
+__device__ __attribute__((noinline)) void row_dots_passes(const T *racc, int r0, int r1, const T *__restrict__ Q,
+                                                          int64_t ldq, int nq, const T *__restrict__ fallback,
+                                                          double *__restrict__ part, double *buf) {
+  const int il = threadIdx.x % kRowLanes;
+  const int row = r0 + il;
+  const bool valid = row < r1;
+  const double v = valid ? (double)racc[il] : 0.0;
+  for (int cb = 0; cb < nq + 1; cb += kColsPerPass) {
+    T qa[8];
+    load_q8<T>(qa, Q, ldq, nq, row, valid, fallback, cb);
+    if (cb > 0) __syncthreads();  // the previous pass's scratch is read
+    row_dots_lds<T>(qa, v, valid, nq, part, buf, cb);
+  }
+}
 
 template <typename T, typename I, int L, bool STAGE>
 __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
@@ -788,6 +810,8 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
   if (fast) {
     row_dots_lds<T>(q8, fvalid ? (double)racc[frow - r0] : 0.0, fvalid, nq, part_out,
                     reinterpret_cast<double *>(region));
+  } else if (rows_per_blk <= kRowLanes) {
+    row_dots_passes<T>(racc, r0, r1, Q, ldq, nq, in.x, part_out, reinterpret_cast<double *>(region));
   } else {
     row_dots<T>([&](int row) { return (double)racc[row - r0]; }, r0, r1, Q, ldq, nq, part_out, sred);
   }
