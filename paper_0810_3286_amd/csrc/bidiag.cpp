@@ -13,11 +13,18 @@
 // rotation chosen from (d0^2 - mu, d0 e0), and a bulge chased to the bottom by
 // alternating left and right rotations.  A zero diagonal entry splits the
 // problem after rotating its superdiagonal neighbour away.
+//
+// Both parts are host work that the device waits for, so each is compiled
+// twice, for the baseline x86-64 target and with AVX2 and FMA, and the
+// second is taken where the processor has them.  The QR sweep is a chain of
+// dependent square roots and divisions (FMA shortens it); the vectors are
+// independent of each other and are taken a block of columns at a time.
 #include "bidiag.h"
 
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <thread>
 
 namespace svt {
 
@@ -33,14 +40,14 @@ struct Rot {
 // nor underflow (it is within an ulp of the exact value), hypot elsewhere --
 // hypot's scaling makes it several times slower, and the rotations of the
 // implicit QR are most of the host work of a convergence check.
-inline double norm2(double a, double b) {
+__attribute__((always_inline)) inline double norm2(double a, double b) {
   const double m = std::max(std::fabs(a), std::fabs(b));
   if (m > 1e-150 && m < 1e150) return std::sqrt(a * a + b * b);
   return std::hypot(a, b);
 }
 
 // c, s with -s*a + c*b = 0 and c*a + s*b = r >= 0 (r = sqrt(a^2 + b^2)).
-inline Rot make_rot(double a, double b) {
+__attribute__((always_inline)) inline Rot make_rot(double a, double b) {
   if (b == 0.0) return {a >= 0.0 ? 1.0 : -1.0, 0.0, std::fabs(a)};
   const double r = norm2(a, b);
   return {a / r, b / r, r};
@@ -53,19 +60,23 @@ struct Acc {
   // Only the last row of P is accumulated (the residual bounds need it); the
   // vectors are formed afterwards from the log of right rotations.
   // P <- P G^T for G acting on rows (a, b): new_a = c a + s b, new_b = -s a + c b.
-  void left(int a, int b, double c, double s) {
+  __attribute__((always_inline)) void left(int a, int b, double c, double s) {
     double &x = (*plast)[a], &y = (*plast)[b];
     const double xa = x, yb = y;
     x = c * xa + s * yb;
     y = -s * xa + c * yb;
   }
   // Q <- Q H for H acting on columns (a, b): new_a = c a + s b, new_b = -s a + c b.
-  void right(int a, int b, double c, double s) { rots->push_back({a, b, c, s}); }
+  __attribute__((always_inline)) void right(int a, int b, double c, double s) { rots->push_back({a, b, c, s}); }
 };
 
-}  // namespace
+bool have_avx2_fma() {
+  static const bool yes = __builtin_cpu_supports("avx2") && __builtin_cpu_supports("fma");
+  return yes;
+}
 
-bool bidiag_svd(const std::vector<double> &d_in, const std::vector<double> &e_in, BidiagSVD &out) {
+__attribute__((always_inline)) inline bool svd_core(const std::vector<double> &d_in,
+                                                    const std::vector<double> &e_in, BidiagSVD &out) {
   const int k = (int)d_in.size();
   out.sigma.assign(k, 0.0);
   out.p_last.assign(k, 0.0);
@@ -204,6 +215,66 @@ bool bidiag_svd(const std::vector<double> &d_in, const std::vector<double> &e_in
   return true;
 }
 
+__attribute__((target("avx2,fma"))) bool svd_avx2(const std::vector<double> &d, const std::vector<double> &e,
+                                                   BidiagSVD &out) {
+  return svd_core(d, e, out);
+}
+
+bool svd_base(const std::vector<double> &d, const std::vector<double> &e, BidiagSVD &out) {
+  return svd_core(d, e, out);
+}
+
+constexpr int kVecChunk = 8;    // vectors per block: a k x 8 block stays in L1
+constexpr int kVecThreads = 8;  // threads for a large log
+constexpr double kVecThreadWork = 4e6;  // rotations x vectors above which threads pay
+
+// The logged rotations applied in reverse order to a k x W row-major block:
+// H on rows (a, b) maps (v_a, v_b) to (c v_a - s v_b, s v_a + c v_b).
+template <int W>
+__attribute__((always_inline)) inline void apply_log_reverse_core(double *V, const BidiagRot *rots, size_t nrot) {
+  // A sweep's rotations act on (c, c+1) for increasing c, so in reverse
+  // order each one shares its row a with the next one's row b: that row is
+  // carried in registers instead of making a round trip through memory.
+  double cr[W];
+  int crow = -1;
+  for (int i = 0; i < W; ++i) cr[i] = 0.0;
+  for (size_t t = nrot; t-- > 0;) {
+    const BidiagRot h = rots[t];
+    double *va = V + (size_t)h.a * W, *vb = V + (size_t)h.b * W;
+    double x[W], y[W];
+    if (h.b == crow) {
+      for (int i = 0; i < W; ++i) y[i] = cr[i];
+    } else {
+      for (int i = 0; i < W; ++i) y[i] = vb[i];
+    }
+    for (int i = 0; i < W; ++i) x[i] = va[i];
+    for (int i = 0; i < W; ++i) {
+      // x's products first: the carried y then enters one multiply-add
+      const double cx = h.c * x[i], sx = h.s * x[i];
+      const double na = cx - h.s * y[i];
+      const double nb = sx + h.c * y[i];
+      va[i] = na;
+      vb[i] = nb;
+      cr[i] = na;
+    }
+    crow = h.a;
+  }
+}
+
+__attribute__((target("avx2,fma"))) void apply_log_reverse_avx2(double *V, const BidiagRot *rots, size_t nrot) {
+  apply_log_reverse_core<kVecChunk>(V, rots, nrot);
+}
+
+void apply_log_reverse_base(double *V, const BidiagRot *rots, size_t nrot) {
+  apply_log_reverse_core<kVecChunk>(V, rots, nrot);
+}
+
+}  // namespace
+
+bool bidiag_svd(const std::vector<double> &d, const std::vector<double> &e, BidiagSVD &out) {
+  return have_avx2_fma() ? svd_avx2(d, e, out) : svd_base(d, e, out);
+}
+
 void bidiag_vectors(const std::vector<double> &d_in, const std::vector<double> &e_in, int nvec,
                     BidiagSVD &out) {
   const int k = (int)d_in.size();
@@ -214,23 +285,41 @@ void bidiag_vectors(const std::vector<double> &d_in, const std::vector<double> &
   if (nvec == 0) return;
   // Q = H_1 H_2 ... H_n (Q <- Q H per rotation, from the identity), so
   // column j of Q is H_1 (H_2 (... (H_n e_j))): the rotations applied in
-  // reverse order to unit vectors, all nvec of them together.  H acts on a
-  // vector as (v_a, v_b) <- (c v_a - s v_b, s v_a + c v_b).
-  std::vector<double> V((size_t)nvec * k, 0.0);  // row j holds entry j of every vector
-  for (int i = 0; i < nvec; ++i) V[(size_t)out.src[i] * nvec + i] = 1.0;
-  for (size_t t = out.rots.size(); t-- > 0;) {
-    const BidiagRot &h = out.rots[t];
-    double *va = V.data() + (size_t)h.a * nvec, *vb = V.data() + (size_t)h.b * nvec;
-    for (int i = 0; i < nvec; ++i) {
-      const double x = va[i], y = vb[i];
-      va[i] = h.c * x - h.s * y;
-      vb[i] = h.s * x + h.c * y;
+  // reverse order to unit vectors.  The vectors are independent, so they are
+  // taken kVecChunk at a time: a block of k x kVecChunk stays in the L1
+  // cache while the whole log streams past it, and a large log spreads the
+  // blocks over threads.
+  const int nchunk = (nvec + kVecChunk - 1) / kVecChunk;
+  std::vector<double> V((size_t)nchunk * k * kVecChunk, 0.0);  // [block][row][kVecChunk]
+  for (int i = 0; i < nvec; ++i)
+    V[((size_t)(i / kVecChunk) * k + out.src[i]) * kVecChunk + i % kVecChunk] = 1.0;
+  const BidiagRot *rots = out.rots.data();
+  const size_t nrot = out.rots.size();
+  const bool avx2 = have_avx2_fma();
+  auto run = [&](int c0, int c1) {
+    for (int c = c0; c < c1; ++c) {
+      double *blk = V.data() + (size_t)c * k * kVecChunk;
+      if (avx2)
+        apply_log_reverse_avx2(blk, rots, nrot);
+      else
+        apply_log_reverse_base(blk, rots, nrot);
     }
+  };
+  const int nthr = ((double)nrot * nvec > kVecThreadWork) ? std::min(nchunk, kVecThreads) : 1;
+  if (nthr <= 1) {
+    run(0, nchunk);
+  } else {
+    const int per = (nchunk + nthr - 1) / nthr;
+    std::vector<std::thread> th;
+    for (int c0 = per; c0 < nchunk; c0 += per) th.emplace_back(run, c0, std::min(nchunk, c0 + per));
+    run(0, std::min(nchunk, per));
+    for (auto &t : th) t.join();
   }
   for (int i = 0; i < nvec; ++i) {
     const double sg = out.sgn[i];
     double *q = out.Q.data() + (size_t)i * k;
-    for (int j = 0; j < k; ++j) q[j] = sg * V[(size_t)j * nvec + i];
+    const double *v = V.data() + (size_t)(i / kVecChunk) * k * kVecChunk + i % kVecChunk;
+    for (int j = 0; j < k; ++j) q[j] = sg * v[(size_t)j * kVecChunk];
   }
   // left vectors from the right ones: B q_i = sigma_i p_i with the input B
   // (upper bidiagonal: (B q)_j = d_j q_j + e_j q_{j+1}); accurate to about
