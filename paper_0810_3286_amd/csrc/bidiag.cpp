@@ -12,7 +12,12 @@
 // B^T B (the eigenvalue nearer its last diagonal entry), a first right
 // rotation chosen from (d0^2 - mu, d0 e0), and a bulge chased to the bottom by
 // alternating left and right rotations.  A zero diagonal entry splits the
-// problem after rotating its superdiagonal neighbour away.
+// problem after rotating its superdiagonal neighbour away.  On longer blocks
+// two sweeps run at once, one with each eigenvalue of that 2 x 2 as its
+// shift, the second bulge a few columns behind the first: a sweep is one
+// long chain of dependent square roots and divisions, and two independent
+// chains take about the time of one (about 15% more rotations in all, at
+// half the time each).
 //
 // Both parts are host work that the device waits for, so each is compiled
 // twice, for the baseline x86-64 target and with AVX2 and FMA, and the
@@ -31,6 +36,8 @@ namespace svt {
 namespace {
 
 constexpr double kEps = 2.220446049250313e-16;
+constexpr int kPairMin = 16;  // blocks of at least this many columns take paired sweeps
+constexpr int kPairLag = 3;   // columns between the two bulges
 
 struct Rot {
   double c, s, r;
@@ -162,11 +169,10 @@ __attribute__((always_inline)) inline bool svd_core(const std::vector<double> &d
     const double half = 0.5 * (t11 - t22);
     const double root = norm2(half, t12);
     const double mu = t22 - t12 * t12 / (half + (half >= 0.0 ? root : -root) + (root == 0.0 ? 1.0 : 0.0));
-    double y = d[lo] * d[lo] - mu;
-    double z = d[lo] * e[lo];
-    for (int c = lo; c < hi; ++c) {
+    // One chase step at column c of a sweep whose bulge state is (y, z).
+    auto chase = [&](int c, double &y, double &z) __attribute__((always_inline)) {
       // right rotation on columns (c, c+1) zeroing z against y
-      Rot h = make_rot(y, z);
+      const Rot h = make_rot(y, z);
       if (c > lo) e[c - 1] = h.r;
       {
         const double dc = d[c], ec = e[c], dn1 = d[c + 1];
@@ -177,7 +183,7 @@ __attribute__((always_inline)) inline bool svd_core(const std::vector<double> &d
       }
       acc.right(c, c + 1, h.c, h.s);
       // left rotation on rows (c, c+1) zeroing the bulge against d[c]
-      Rot g = make_rot(d[c], z);
+      const Rot g = make_rot(d[c], z);
       d[c] = g.r;
       {
         const double ec = e[c], dn1 = d[c + 1];
@@ -191,6 +197,29 @@ __attribute__((always_inline)) inline bool svd_core(const std::vector<double> &d
       }
       acc.left(c, c + 1, g.c, g.s);
       y = e[c];
+    };
+    if (hi - lo < kPairMin) {
+      double y = d[lo] * d[lo] - mu;
+      double z = d[lo] * e[lo];
+      for (int c = lo; c < hi; ++c) chase(c, y, z);
+      continue;
+    }
+    // Two sweeps, with the shift above and with the other eigenvalue of the
+    // trailing 2 x 2 of B^T B, the second kPairLag columns behind the first:
+    // they touch disjoint entries, so this is the two sweeps one after the
+    // other (every rotation that shares a row or column with a later one of
+    // the other sweep comes first), but the two dependency chains overlap.
+    const double mu2 = std::max(t11 + t22 - mu, 0.0);
+    double ya = d[lo] * d[lo] - mu, za = d[lo] * e[lo];
+    double yb = 0.0, zb = 0.0;
+    for (int c = lo; c < hi + kPairLag; ++c) {
+      if (c < hi) chase(c, ya, za);
+      const int cb = c - kPairLag;
+      if (cb == lo) {
+        yb = d[lo] * d[lo] - mu2;
+        zb = d[lo] * e[lo];
+      }
+      if (cb >= lo) chase(cb, yb, zb);
     }
   }
 

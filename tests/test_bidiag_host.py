@@ -107,3 +107,50 @@ def test_bidiag_zero_diagonal_and_split(driver):
     d[39] = 0.0          # last diagonal zero: chased up its column
     e[25] = 0.0          # splits into two blocks
     check(driver, d, e, 12)
+
+
+def gkl_coefficients(A, k, seed):
+    """alpha, beta of k steps of the Golub-Kahan bidiagonalisation of A
+    (Section 5.1.1's partial SVD) with full reorthogonalisation, in numpy:
+    the B_k of an actual low-rank-plus-noise matrix."""
+    rng = np.random.default_rng(seed)
+    m, n = A.shape
+    v = rng.standard_normal(n)
+    v /= np.linalg.norm(v)
+    U, V = np.zeros((m, k)), np.zeros((n, k))
+    alpha, beta = np.zeros(k), np.zeros(k)
+    u_prev, b = np.zeros(m), 0.0
+    for j in range(k):
+        V[:, j] = v
+        u = A @ v - b * u_prev
+        u -= U[:, :j] @ (U[:, :j].T @ u)
+        alpha[j] = np.linalg.norm(u)
+        u /= alpha[j]
+        U[:, j] = u
+        w = A.T @ u - alpha[j] * v
+        w -= V[:, :j + 1] @ (V[:, :j + 1].T @ w)
+        b = np.linalg.norm(w)
+        beta[j] = b
+        v, u_prev = w / b, u
+    # B_k upper bidiagonal: diagonal alpha, superdiagonal beta_2 .. beta_k
+    return alpha, beta[:-1]
+
+
+@pytest.mark.parametrize("k,rank,seed", [(60, 10, 5), (200, 50, 6)])
+def test_bidiag_lanczos_matrix(driver, k, rank, seed):
+    rng = np.random.default_rng(seed)
+    m, n = 400, 300
+    A = rng.standard_normal((m, rank)) @ rng.standard_normal((rank, n)) * 10.0 + 0.1 * rng.standard_normal((m, n))
+    d, e = gkl_coefficients(A, k, seed)
+    check(driver, d, e, min(rank + 1, k))
+
+
+def test_bidiag_graded_and_clustered(driver):
+    rng = np.random.default_rng(7)
+    k = 120
+    d = 1e6 * 0.8 ** np.arange(k)        # graded over many orders of magnitude
+    e = d[:-1] * rng.uniform(0.01, 0.5, k - 1)
+    check(driver, d, e, 20)
+    d = np.full(k, 3.0) + 1e-10 * rng.standard_normal(k)   # one tight cluster
+    e = 1e-3 * rng.uniform(0.5, 1.0, k - 1)
+    check(driver, d, e, 8)
