@@ -538,6 +538,130 @@ __device__ __attribute__((noinline)) void row_dots_passes(const T *racc, int r0,
   }
 }
 
+// The wide-basis passes for row blocks of at most kNarrowLanes rows: the
+// same work as the 128-row-slot layout (load_q8, row_dots_lds,
+// write_corrected and the correction loop) with 64 row slots and 16 column
+// groups, so a pass covers kNarrowCols = 128 columns and a block of 40 rows
+// (10000 rows over 250 workgroups) leaves 24 of 64 slots idle instead of 88
+// of 128; half as many passes, each one memory round trip and a few
+// barriers.  Thread t: row slot t % 64, columns cb + t / 64 + 16 j.
+constexpr int kNarrowLanes = 64;
+constexpr int kNarrowGroups = kRowBlock / kNarrowLanes;   // 16
+constexpr int kNarrowCols = 8 * kNarrowGroups;            // 128 columns per pass
+constexpr int kNarrowStrands = kRowBlock / kNarrowCols;   // 8 strands per column
+
+template <typename T>
+__device__ __forceinline__ void load_q8_narrow(T (&q)[8], const T *__restrict__ Q, int64_t ldq, int nq, int row,
+                                               bool valid, const T *__restrict__ fallback, int cb) {
+  const int g = threadIdx.x / kNarrowLanes;
+  const bool have = nq > 0 && Q != nullptr;
+  const T *base = have ? Q : fallback;
+  const int64_t ld = have ? ldq : 0;
+  const int last = have ? nq - 1 : 0;
+  const int r = (have && valid) ? row : 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) q[j] = base[(size_t)min(cb + g + kNarrowGroups * j, last) * ld + r];
+}
+
+// One pass of the dot products in the narrow layout: columns cb + gg + 16 j
+// of Q (and column nq: |p|^2), each summed over the 64 row slots by 8
+// strands of 8 slots, then the 8 strand sums in order.  buf: kDotsLds bytes.
+template <typename T>
+__device__ __forceinline__ void row_dots_lds_narrow(const T (&q)[8], double v, bool valid, int nq,
+                                                    double *__restrict__ part, double *buf, int cb) {
+  static_assert(8 * kRowBlock + kNarrowCols * kNarrowStrands <= kDotsLds / (int)sizeof(double), "dots scratch");
+  const int C = nq + 1;
+  const int g = threadIdx.x / kNarrowLanes;
+  double *prod = buf;                  // 8 x kRowBlock products
+  double *mid = buf + 8 * kRowBlock;   // 128 columns x 8 partial sums
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int c = cb + g + kNarrowGroups * j;
+    const double f = (c < nq) ? (double)q[j] : ((c == nq) ? v : 0.0);
+    prod[j * kRowBlock + threadIdx.x] = valid ? f * v : 0.0;
+  }
+  __syncthreads();
+  {
+    const int col = threadIdx.x / kNarrowStrands, sidx = threadIdx.x % kNarrowStrands;
+    const int gg = col % kNarrowGroups, j = col / kNarrowGroups;
+    const double *src = prod + j * kRowBlock + gg * kNarrowLanes + sidx;
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < kNarrowLanes / kNarrowStrands; ++k) t += src[kNarrowStrands * k];
+    mid[col * kNarrowStrands + sidx] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < kNarrowCols) {
+    const int col = threadIdx.x, gg = col % kNarrowGroups, j = col / kNarrowGroups;
+    const int c = cb + gg + kNarrowGroups * j;
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < kNarrowStrands; ++k) t += mid[col * kNarrowStrands + k];
+    if (c < C) part[(size_t)c * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+template <typename T>
+__device__ __attribute__((noinline)) void row_dots_passes_narrow(const T *racc, int r0, int r1,
+                                                                 const T *__restrict__ Q, int64_t ldq, int nq,
+                                                                 const T *__restrict__ fallback,
+                                                                 double *__restrict__ part, double *buf) {
+  const int il = threadIdx.x % kNarrowLanes;
+  const int row = r0 + il;
+  const bool valid = row < r1;
+  const double v = valid ? (double)racc[il] : 0.0;
+  for (int cb = 0; cb < nq + 1; cb += kNarrowCols) {
+    T qa[8];
+    load_q8_narrow<T>(qa, Q, ldq, nq, row, valid, fallback, cb);
+    if (cb > 0) __syncthreads();  // the previous pass's scratch is read
+    row_dots_lds_narrow<T>(qa, v, valid, nq, part, buf, cb);
+  }
+}
+
+// Sum over the narrow layout's column passes of Q[row, c] * w[c] (c < nq)
+// for this thread's row slot and column group, in pass order.
+template <typename T>
+__device__ __forceinline__ double narrow_combine(const T *__restrict__ Q, int64_t ldq, int nq, int row,
+                                                 const double *w) {
+  const int g = threadIdx.x / kNarrowLanes;
+  const int last = nq - 1;
+  double a = 0.0;
+  for (int cb = 0; cb < nq; cb += kNarrowCols) {
+    T q[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) q[j] = Q[(size_t)min(cb + g + kNarrowGroups * j, last) * ldq + row];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c = cb + g + kNarrowGroups * j;
+      if (c < nq) a = fma((double)q[j], w[c], a);
+    }
+  }
+  return a;
+}
+
+// write_corrected for a slice of at most kNarrowLanes entries (nqx >= 1):
+// x_out[i] = (x[i] - sum_c Qx[i, c] h[c]) * inv, the 16 group sums of an
+// entry added in group order (upd: kRowBlock doubles of LDS).
+template <typename T>
+__device__ void write_corrected_narrow(const T *__restrict__ x, int ncols, const T *__restrict__ Qx, int64_t ldqx,
+                                       int nqx, const double *h, double inv, T *__restrict__ x_out, double *upd) {
+  const int chunk = (ncols + gridDim.x - 1) / gridDim.x;
+  const int i0 = blockIdx.x * chunk, i1 = min(ncols, i0 + chunk);
+  const int il = threadIdx.x % kNarrowLanes, g = threadIdx.x / kNarrowLanes;
+  const int row = i0 + il;
+  const bool valid = row < i1;
+  const double a = valid ? narrow_combine<T>(Qx, ldqx, nqx, row, h) : 0.0;
+  upd[g * kNarrowLanes + il] = a;
+  __syncthreads();
+  if (g == 0 && valid) {
+    double tot = 0.0;
+#pragma unroll
+    for (int gg = 0; gg < kNarrowGroups; ++gg) tot += upd[gg * kNarrowLanes + il];
+    x_out[row] = (T)(((double)x[row] - tot) * inv);
+  }
+  __syncthreads();
+}
+
 template <typename T, typename I, int L, bool STAGE>
 __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
     const int32_t *__restrict__ ptr, const I *__restrict__ idx, const T *__restrict__ val,
@@ -752,9 +876,31 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
     if (xfast) {
       write_corrected_pre<T>(qx8, (double)xv0, ncols, in.nqx, hs, inv, in.x_out, upd);
     } else if (in.x_out != nullptr) {
-      write_corrected<T>(x, ncols, in.Qx, in.ldqx, in.nqx, hs, inv, in.x_out, upd);
+      if (in.nqx > 0 && xchunk <= kNarrowLanes)
+        write_corrected_narrow<T>(x, ncols, in.Qx, in.ldqx, in.nqx, hs, inv, in.x_out, upd);
+      else
+        write_corrected<T>(x, ncols, in.Qx, in.ldqx, in.nqx, hs, inv, in.x_out, upd);
     }
-    if (corr) {
+    if (corr && !fast && nq > 0 && rows_per_blk <= kNarrowLanes) {
+      // p = (A x_raw - Q g) / s - s prev in the narrow layout
+      const int nl = threadIdx.x % kNarrowLanes, ng = threadIdx.x / kNarrowLanes;
+      const int row = r0 + nl;
+      const bool valid = row < r1;
+      const double a = valid ? narrow_combine<T>(Q, ldq, nq, row, gl) : 0.0;
+      updp[ng * kNarrowLanes + nl] = a;
+      __syncthreads();
+      if (ng == 0 && valid) {
+        double tot = 0.0;
+#pragma unroll
+        for (int gg = 0; gg < kNarrowGroups; ++gg) tot += updp[gg * kNarrowLanes + nl];
+        double y = ((double)racc[row - r0] - tot) * inv;
+        if (prev != nullptr) y = fma(-sn, (double)prev[row], y);
+        const T pv = (T)y;
+        p[row] = pv;
+        racc[row - r0] = pv;
+      }
+      __syncthreads();
+    } else if (corr) {
       // p = (A x_raw - Q g) / s - s prev, Q g summed like write_corrected
       const int last = nq > 0 ? nq - 1 : 0;
       for (int rb = r0; rb < r1; rb += kRowLanes) {
@@ -810,6 +956,8 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
   if (fast) {
     row_dots_lds<T>(q8, fvalid ? (double)racc[frow - r0] : 0.0, fvalid, nq, part_out,
                     reinterpret_cast<double *>(region));
+  } else if (rows_per_blk <= kNarrowLanes) {
+    row_dots_passes_narrow<T>(racc, r0, r1, Q, ldq, nq, in.x, part_out, reinterpret_cast<double *>(region));
   } else if (rows_per_blk <= kRowLanes) {
     row_dots_passes<T>(racc, r0, r1, Q, ldq, nq, in.x, part_out, reinterpret_cast<double *>(region));
   } else {
