@@ -40,6 +40,7 @@ ROCPROF_NAMES = {
     "k_gather": ("k_gather",),
     "k_sample_update": ("k_sample_update",),
     "k_gs_update_pass2": ("k_gs_update<float, true>", "k_gs_update<double, true>"),
+    "k_pending_reduce": ("k_pending_reduce",),
 }
 
 

@@ -219,10 +219,12 @@ svt_status svt_spmv_plan(const svt_problem *h, int32_t which, int32_t *segments)
                              row copy of Y (one launch per iteration)
      5 k_gs_update<true>     one update + |p|^2 partials (two-pass mode, or
                              an update too wide to defer)
+     6 k_pending_reduce      the column sums of a pending vector's partials
+                             ahead of a half-step (wide bases only)
    Outputs: the number of launches, their summed duration in milliseconds
    (HIP events on the solve's stream) and their summed algorithmic bytes:
    the index, value and vector traffic each launch must move at least once.
-   Any output pointer may be NULL; EINVAL for a kind outside 0..5. */
+   Any output pointer may be NULL; EINVAL for a kind outside 0..6. */
 svt_status svt_kernel_stats(const svt_problem *h, int32_t kind, int64_t *launches,
                             double *total_ms, double *total_bytes);
 

@@ -39,9 +39,10 @@ RowPlan row_plan(int nrows);
 
 // Partial-sum buffers of the bidiagonalisation (device memory owned by the
 // solver): part1 and part2 hold max_cols columns of max_blocks partials,
-// part3 max_blocks partials.
+// part3 max_blocks partials, red max_cols column sums.
 struct GsScratch {
   double *part1, *part2, *part3;
+  double *red;
   int max_cols, max_blocks;
 };
 
@@ -113,6 +114,11 @@ hipError_t launch_spmv(hipStream_t s, const SpmvPlan &pl, const int32_t *ptr, co
 // nqx <= kSpmvAuxCols.
 hipError_t launch_pending_norm(hipStream_t s, const double *pend, int np, int nqx, double *s_out,
                                double *removed_out);
+
+// The nqx + 1 column sums of a pending vector's partials (np each) into
+// out, bit for bit as a sparse product or launch_pending_norm would form
+// them; either then takes out as one partial (np = 1).  nqx <= kSpmvAuxCols.
+hipError_t launch_pending_reduce(hipStream_t s, const double *pend, int np, int nqx, double *out);
 
 // One classical Gram-Schmidt update of p (length nrows, overwritten)
 // against the nq >= 1 orthonormal columns of Q, with coefficients h summed

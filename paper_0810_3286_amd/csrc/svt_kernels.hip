@@ -176,6 +176,28 @@ __device__ void reduce_pending(const double *__restrict__ pend, int np, int nqx,
   const int cl = threadIdx.x / kRedStrands, k = threadIdx.x % kRedStrands;
   double *sqs = red + kRedCols * (kRedStrands + 1);
   double sq = 0.0;
+  if (np == 1) {
+    // the column sums were formed by k_pending_reduce: one load each, and
+    // |h|^2 in the same order as below (thread t < 64 adds the squares of
+    // columns t, t + 64, ... in pass order)
+    for (int c = threadIdx.x; c < C; c += blockDim.x) hs[c] = pend[c];
+    __syncthreads();
+    if (threadIdx.x < kRedCols) {
+      for (int c = threadIdx.x; c < nqx; c += kRedCols) sq = fma(hs[c], hs[c], sq);
+      sqs[threadIdx.x] = sq;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double hh = 0.0;
+      if (nqx > 0) {
+#pragma unroll
+        for (int l = 0; l < kRedCols; ++l) hh += sqs[l];
+      }
+      scal[0] = hh;
+      scal[1] = sqrt(fmax(hs[nqx] - hh, 0.0));
+    }
+    return;
+  }
   for (int cb = 0; cb < C; cb += kRedCols) {
     double t = 0.0;
     if (cb + cl < C) {
@@ -965,6 +987,43 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
   }
 }
 
+// The column sums of a pending vector's partials (nqx + 1 columns of np),
+// formed exactly as reduce_pending forms them (the same strands, added in
+// the same order), into out[0 .. nqx].  A consumer given out as a single
+// partial (np = 1) takes the same values with one load each, where every
+// workgroup of a sparse product would otherwise read all (nqx + 1) np
+// partials in 64-column passes.  kPreCols columns per workgroup.
+constexpr int kPreCols = 16;
+__global__ __launch_bounds__(kPreCols * kRedStrands) void k_pending_reduce(const double *__restrict__ pend, int np,
+                                                                           int C, double *__restrict__ out) {
+  __shared__ double red[kPreCols * (kRedStrands + 1)];
+  const int cl = threadIdx.x / kRedStrands, k = threadIdx.x % kRedStrands;
+  const int c = blockIdx.x * kPreCols + cl;
+  double t = 0.0;
+  if (c < C) {
+    const size_t col = (size_t)c * np;
+    for (int i0 = 0; i0 < np; i0 += kRedStrands * kRedLoads) {
+      double v[kRedLoads];
+#pragma unroll
+      for (int j = 0; j < kRedLoads; ++j) v[j] = pend[col + min(i0 + k + kRedStrands * j, np - 1)];
+#pragma unroll
+      for (int j = 0; j < kRedLoads; ++j)
+        if (i0 + k + kRedStrands * j < np) t += v[j];
+    }
+  }
+  red[cl * (kRedStrands + 1) + k] = t;
+  __syncthreads();
+  if (threadIdx.x < kPreCols) {
+    const int cc = blockIdx.x * kPreCols + threadIdx.x;
+    if (cc < C) {
+      double u = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < kRedStrands; ++kk) u += red[threadIdx.x * (kRedStrands + 1) + kk];
+      out[cc] = u;
+    }
+  }
+}
+
 // s and |h|^2 / |x_raw|^2 of a pending vector (pending_norm, the same
 // arithmetic as the sparse product that consumes it) into *s_out and
 // *removed_out (may be null).  One workgroup; dynamic LDS: nqx + 1 doubles.
@@ -1566,6 +1625,14 @@ hipError_t launch_pending_norm(hipStream_t s, const double *pend, int np, int nq
   if (pend == nullptr || s_out == nullptr || np < 1 || nqx < 0 || nqx > kSpmvAuxCols) return hipErrorInvalidValue;
   SVT_LAUNCH(k_pending_norm, dim3(1), dim3(kRowBlock), sizeof(double) * ((size_t)nqx + 1), s, pend, np, nqx,
              s_out, removed_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pending_reduce(hipStream_t s, const double *pend, int np, int nqx, double *out) {
+  if (pend == nullptr || out == nullptr || np < 1 || nqx < 0 || nqx > kSpmvAuxCols) return hipErrorInvalidValue;
+  const int C = nqx + 1;
+  SVT_LAUNCH(k_pending_reduce, dim3((C + kPreCols - 1) / kPreCols), dim3(kPreCols * kRedStrands), 0, s, pend, np, C,
+             out);
   return hipGetLastError();
 }
 

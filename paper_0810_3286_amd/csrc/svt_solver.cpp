@@ -123,7 +123,9 @@ struct PinnedMem {
 //   passes, with the second pass's dot products), 3 k_ritz, 4
 //   k_sample_update, 5 k_gs_update (one pass with the |p|^2 partials: the
 //   second of two, or a deferred update too wide to fuse).
-enum KernelKind { kSpmv = 0, kGather = 1, kGsUpdate1 = 2, kRitz = 3, kSample = 4, kGsUpdate2 = 5, kKinds = 6 };
+enum KernelKind {
+  kSpmv = 0, kGather = 1, kGsUpdate1 = 2, kRitz = 3, kSample = 4, kGsUpdate2 = 5, kPendReduce = 6, kKinds = 7
+};
 
 struct Profiler {
   bool on = false;
@@ -286,6 +288,7 @@ struct Problem final : ProblemBase {
   DevMem pbuf_u, pbuf_v;          // unnormalised new vectors of each side, T
   DevMem coef;                    // alpha[0..], beta[0..], removed[0..]: double, 4 (kcap + 4)
   DevMem gs1, gs2, gs3;           // Gram-Schmidt partial sums
+  DevMem gsr;                     // a pending vector's column sums (k_pending_reduce)
   GsScratch gs{};
   DevMem sample_part;             // residual partials, kSampleMaxBlocks + 8 doubles
   PinnedMem sample_host;          // their host copy
@@ -304,6 +307,11 @@ struct Problem final : ProblemBase {
   int log_level = 0;
   int64_t steps_total = 0;
   double reorth_trigger = 0.5;
+  // basis width from which a pending vector's partials are summed by their
+  // own kernel before the sparse product: the width where the product
+  // leaves its single-pass epilogue (below it each workgroup of the product
+  // sums them in one pass, cheaper than the extra launch)
+  int prereduce_min = 64;
   int passes_now = 2;          // Gram-Schmidt passes per vector right now
   int64_t reorth_restarts = 0; // bidiagonalisations restarted with two passes
 
@@ -314,6 +322,9 @@ struct Problem final : ProblemBase {
     // the one-pass check's threshold (test hook; default 1/2, the DGKS
     // criterion with eta = 1/sqrt(2))
     if (const char *tv = std::getenv("SVT_REORTH_TRIGGER")) reorth_trigger = std::atof(tv);
+    // the basis width that switches on the separate partial sums (tuning
+    // and test hook; both sides of it give the same bits)
+    if (const char *pv = std::getenv("SVT_PREREDUCE_MIN")) prereduce_min = std::max(1, std::atoi(pv));
     HIP_CHECK(hipGetDevice(&device));
     if (p.stream) {
       stream = static_cast<hipStream_t>(p.stream);
@@ -417,6 +428,7 @@ struct Problem final : ProblemBase {
     n1.alloc(sizeof(double) * (size_t)cols * blocks);
     n2.alloc(sizeof(double) * (size_t)cols * blocks);
     n3.alloc(sizeof(double) * (size_t)blocks);
+    gsr.alloc(sizeof(double) * (size_t)cols);
     HIP_CHECK(hipMemsetAsync(ncoef.p, 0, ncoef.bytes, stream));
     if (kcap > 0) {
       // the pending vector's partials (its dot products and |.|^2, in any
@@ -444,6 +456,7 @@ struct Problem final : ProblemBase {
     gs.part1 = gs1.as<double>();
     gs.part2 = gs2.as<double>();
     gs.part3 = gs3.as<double>();
+    gs.red = gsr.as<double>();
     gs.max_cols = cols;
     gs.max_blocks = blocks;
   }
@@ -580,6 +593,15 @@ struct Problem final : ProblemBase {
         xp = PendingVec{3, 0};
       }
       in.pend = part_buf(xp.buf);
+      if (xp.nq >= prereduce_min) {
+        // a wide basis: the partials are summed once, here, instead of by
+        // every workgroup of the product (the same sums, bit for bit)
+        prof.begin();
+        HIP_CHECK(launch_pending_reduce(stream, in.pend, xnp, xp.nq, gs.red));
+        prof.end(kPendReduce, 8.0 * (xp.nq + 1.0) * (xnp + 1.0));
+        in.pend = gs.red;
+        in.np = 1;
+      }
       in.Qx = Qx;
       in.ldqx = ldqx;
       in.nqx = xp.nq;

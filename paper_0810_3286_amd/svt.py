@@ -32,7 +32,7 @@ SVT_STOP_RELRES = 0
 SVT_STOP_NOISY = 1
 
 KERNEL_KINDS = {0: "k_spmv", 1: "k_gather", 2: "k_gs_update_pass1", 3: "k_ritz", 4: "k_sample_update",
-                5: "k_gs_update_pass2"}
+                5: "k_gs_update_pass2", 6: "k_pending_reduce"}
 
 
 class svt_params(ctypes.Structure):
