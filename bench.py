@@ -209,6 +209,48 @@ def traffic_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_m
     print("\n".join(lines))
 
 
+def table2_runs(precisions=("fp64", "mixed"), seed: int = 7) -> dict:
+    """Table 2's shapes (Section 5.2.2): n = 1000, (r, |Omega| / d_r) = (10, 6),
+    (50, 4), (100, 3), noise ratios 1e-2, 1e-1, 1, each solved once with the
+    eq. (5.10) stop (the paper averages five runs).  Per case: iterations,
+    seconds (from svt_create's return to the factors, warm), relative error
+    against the truth, and the paper's iterations and error for reference."""
+    import numpy as np
+    import workload
+    from paper_0810_3286_amd import svt as B
+    paper = {(10, 1e-2): (51, 0.78e-2), (50, 1e-2): (48, 0.95e-2), (100, 1e-2): (50, 1.13e-2),
+             (10, 1e-1): (19, 0.72e-1), (50, 1e-1): (17, 0.89e-1), (100, 1e-1): (17, 1.01e-1),
+             (10, 1.0): (3, 0.52), (50, 1.0): (3, 0.63), (100, 1.0): (3, 0.69)}
+    out = []
+    for prec in precisions:
+        for ratio in workload.TABLE2_NOISE_RATIOS:
+            for r, c in workload.TABLE2_RANK_OVERSAMPLING:
+                p = workload.noisy_lowrank(1000, r, c, ratio, seed)
+                prm = B.svt_params_default(p.m, p.n, len(p.vals))
+                prm.tau, prm.delta, prm.eps, prm.maxiter, prm.incr = p.tau, p.delta, p.eps, p.maxiter, p.incr
+                prm.stop_rule = B.SVT_STOP_NOISY
+                prm.noise_sigma = p.noise_sigma
+                prm.precision = B.SVT_FP64 if prec == "fp64" else B.SVT_MIXED
+                h = B.svt_create(p.m, p.n, p.rows, p.cols, p.vals, prm)
+                try:
+                    B.svt_solve(h)   # warm-up: the library's first-call costs
+                    t0 = time.perf_counter()
+                    st, info = B.svt_solve(h)
+                    U, w, V = B.svt_factors(h, p.m, p.n)
+                    dt = time.perf_counter() - t0
+                finally:
+                    B.svt_destroy(h)
+                M = p.ML @ p.MR.T
+                rel = float(np.linalg.norm(U @ V.T - M) / np.linalg.norm(M))
+                pi, pe = paper[(r, ratio)]
+                out.append({"precision": prec, "noise_ratio": ratio, "rank": r, "nnz_over_dr": c,
+                            "iters": int(info.iters), "seconds": dt, "rel_error": rel,
+                            "paper_iters": pi, "paper_rel_error": pe, "status": int(st)})
+                log(f"[bench] table2 {prec} ratio {ratio:g} rank {r}: {info.iters} iterations, "
+                    f"{dt:.3f} s, relative error {rel:.3e} (paper: {pi}, {pe:.2e})")
+    return {"table2": out}
+
+
 def copy_calibration(mib: int, reps: int = 3):
     """Device-to-device copies of a known size through the HIP runtime's copy
     kernel: under rocprofv3 --pmc its FETCH_SIZE / WRITE_SIZE per dispatch,
@@ -354,6 +396,8 @@ def main():
                     help="write the HBM traffic file from rocprofv3 --pmc runs of this bench "
                          "(FETCH_SIZE, WRITE_SIZE) and of --copy-calibration (same two counters); "
                          "needs --traffic-mib and --traffic-bench-json")
+    ap.add_argument("--table2", action="store_true",
+                    help="run Table 2's noisy-data shapes (n = 1000) and print their results instead")
     ap.add_argument("--traffic-mib", type=int, default=256)
     ap.add_argument("--traffic-bench-json", help="the JSON line of the counted bench run")
     args = ap.parse_args()
@@ -366,6 +410,10 @@ def main():
         alg = {k: v.get("bytes_per_launch") for k, v in bj["kernels"].items()}
         traffic_summary(*args.traffic_summary, args.traffic_mib, bj["config"]["workload"],
                         bj["config"]["precision"], alg)
+        return
+
+    if args.table2:
+        print(json.dumps(table2_runs()), flush=True)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:

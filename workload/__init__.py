@@ -143,6 +143,38 @@ CONFIGS = {
 }
 
 
+# Table 2 (Section 5.2.2): n = 1000 with (r, |Omega| / d_r) = (10, 6),
+# (50, 4), (100, 3), at noise ratios 1e-2, 1e-1 and 1.
+TABLE2_RANK_OVERSAMPLING = ((10, 6.0), (50, 4.0), (100, 3.0))
+TABLE2_NOISE_RATIOS = (1e-2, 1e-1, 1.0)
+
+
+def noisy_lowrank(n: int, r: int, c: float, noise_ratio: float, seed: int = 0, *,
+                  eps: float = 1e-4, maxiter: int = 500) -> Problem:
+    """Gaussian rank-r n x n truth on a uniform random Omega of c d_r entries,
+    observed as B = M + Z with Z white Gaussian noise of standard deviation
+    sigma = noise_ratio |P_Omega M|_F / sqrt(|Omega|), so that the noise ratio
+    |P_Omega Z|_F / |P_Omega M|_F is noise_ratio in expectation (Section
+    5.2.2's model).  ``vals`` holds B; ``clean`` (an extra attribute) holds
+    P_Omega M, and ``noise_sigma`` the sigma to give the stop rule."""
+    nnz = int(round(c * degrees_of_freedom(n, n, r)))
+    rng = np.random.default_rng(seed)
+    ML = rng.standard_normal((n, r))
+    MR = rng.standard_normal((n, r))
+    lin = sample_omega(rng, n, n, nnz)
+    rows = (lin // n).astype(np.int32)
+    cols = (lin % n).astype(np.int32)
+    clean = _observed_values(ML, MR, rows, cols)
+    sigma = noise_ratio * float(np.linalg.norm(clean)) / math.sqrt(float(nnz))
+    vals = clean + sigma * rng.standard_normal(nnz)
+    p = Problem(m=n, n=n, r=r, rows=rows, cols=cols, vals=vals, ML=ML, MR=MR,
+                tau=5.0 * float(n), delta=1.2 * float(n) * float(n) / float(nnz), eps=float(eps),
+                maxiter=int(maxiter), incr=5, name=f"svt-noisy-{n}sq-r{r}-nr{noise_ratio:g}",
+                noise_sigma=float(sigma))
+    p.clean = clean
+    return p
+
+
 def config(idx: int, seed: int = 0) -> Problem:
     """Square workload ``idx`` (1..4): tau = 5n, delta = 1.2 n^2/|Omega|."""
     c = CONFIGS[idx]
