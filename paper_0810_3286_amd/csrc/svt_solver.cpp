@@ -298,6 +298,7 @@ struct Problem final : ProblemBase {
   hipEvent_t fetch_ev = nullptr;  // behind the copy into coef_host
   int fetch_k = 0, fetch_kcap = 0;
   static constexpr int kAheadSteps = 2;  // steps queued while the host checks
+  static constexpr int kProbeMaxK = 128;  // bases from which the first check does not probe below
   DevMem Fu, Fv;                  // factors of X, T, row-major with stride fstride
   int fstride = 0, fcap = 0;
   int rank = 0;
@@ -775,7 +776,12 @@ struct Problem final : ProblemBase {
     const double tol = prm.lanczos_tol;
     const int cap = step_cap();
     gkl_start(vr, vc, g);
-    int first_check = std::max(std::min(cap, mode == 1 ? count + 2 : 3), std::min(cap, k_hint - 2));
+    // the first check: where the previous iteration stopped, less 2 on
+    // small bases (a check there costs about two steps, so probing below is
+    // cheap); on wide bases a check costs tens of steps (its host SVD grows
+    // as k^2), so it is placed at the previous count itself
+    const int probe = k_hint >= kProbeMaxK ? 0 : 2;
+    int first_check = std::max(std::min(cap, mode == 1 ? count + 2 : 3), std::min(cap, k_hint - probe));
     first_check = std::max(first_check, 1);
     int next_check = first_check;
     std::vector<double> res;
