@@ -420,7 +420,7 @@ struct Problem final : ProblemBase {
     if (cap <= kcap) return;
     int newcap = std::max(cap, std::min<int>((int)acols, std::max(kcap * 2, 16)));
     newcap = (int)std::min<int64_t>(newcap, acols);
-    DevMem nU, nV, ncoef, n1, n2, n3;
+    DevMem nU, nV, ncoef, n1, n2, n3, nr;
     nU.alloc(sizeof(T) * (size_t)arows * (size_t)(newcap + 1));
     nV.alloc(sizeof(T) * (size_t)acols * (size_t)(newcap + 2));
     ncoef.alloc(sizeof(double) * 4 * (size_t)(newcap + 4));
@@ -429,7 +429,7 @@ struct Problem final : ProblemBase {
     n1.alloc(sizeof(double) * (size_t)cols * blocks);
     n2.alloc(sizeof(double) * (size_t)cols * blocks);
     n3.alloc(sizeof(double) * (size_t)blocks);
-    gsr.alloc(sizeof(double) * (size_t)cols);
+    nr.alloc(sizeof(double) * (size_t)cols);
     HIP_CHECK(hipMemsetAsync(ncoef.p, 0, ncoef.bytes, stream));
     if (kcap > 0) {
       // the pending vector's partials (its dot products and |.|^2, in any
@@ -453,6 +453,7 @@ struct Problem final : ProblemBase {
     std::swap(gs1.p, n1.p); std::swap(gs1.bytes, n1.bytes);
     std::swap(gs2.p, n2.p); std::swap(gs2.bytes, n2.bytes);
     std::swap(gs3.p, n3.p); std::swap(gs3.bytes, n3.bytes);
+    std::swap(gsr.p, nr.p); std::swap(gsr.bytes, nr.bytes);
     kcap = newcap;
     gs.part1 = gs1.as<double>();
     gs.part2 = gs2.as<double>();
