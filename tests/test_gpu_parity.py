@@ -313,6 +313,29 @@ def test_partial_svd_across_basis_growth(precision):
     np.testing.assert_allclose(sig, so, rtol=0, atol=tol * so[0])
 
 
+@pytest.mark.parametrize("m", [16384, 16640])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_partial_svd_row_block_boundary(m, precision):
+    # 256 row blocks of 64 rows (m = 16384) take the 64-row-slot passes of
+    # the sparse product once the basis reaches 64 columns; 65 rows (m =
+    # 16640) take the 128-row-slot passes.  Both against the oracle.
+    gpu_case(f"partial_svd {m} x 200, 70 triplets, precision {precision}")
+    p = workload.gaussian_lowrank(m, 200, 5, 200000, 31)
+    y = workload.dense_random_iterate(p, 32)
+    h = _create(p, precision=precision)
+    try:
+        B.svt_set_iterate(h, y)
+        sig, U, V, steps = B.svt_partial_svd(h, 70, p.m, p.n)
+    finally:
+        B.svt_destroy(h)
+    assert steps > 64
+    Yd = np.zeros((p.m, p.n))
+    Yd[p.rows, p.cols] = y
+    so = oracle.top_triplets_dense(Yd, 70)[1]
+    tol = 1e-11 if precision == 0 else 2e-5
+    np.testing.assert_allclose(sig, so, rtol=0, atol=tol * so[0])
+
+
 def test_mixed_hard_request_stays_finite():
     # a request whose singular values cluster at tau needs long
     # bidiagonalisations every iteration (it does not converge in 60)
