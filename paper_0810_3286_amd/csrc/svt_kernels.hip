@@ -177,9 +177,10 @@ __device__ void reduce_pending(const double *__restrict__ pend, int np, int nqx,
   double *sqs = red + kRedCols * (kRedStrands + 1);
   double sq = 0.0;
   if (np == 1) {
-    // the column sums were formed by k_pending_reduce: one load each, and
-    // |h|^2 in the same order as below (thread t < 64 adds the squares of
-    // columns t, t + 64, ... in pass order)
+    // one partial per column (the sums k_pending_reduce formed, or the
+    // output of a one-workgroup product): one load each gives the values
+    // the passes below would, and |h|^2 is added in their order (thread
+    // t < 64 adds the squares of columns t, t + 64, ... in pass order)
     for (int c = threadIdx.x; c < C; c += blockDim.x) hs[c] = pend[c];
     __syncthreads();
     if (threadIdx.x < kRedCols) {
