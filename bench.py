@@ -6,10 +6,13 @@ left on the device) on the 30000 x 30000, rank-10, |Omega| = 6 d_r workload
 values and index structures resident in HBM) before the timed region.
 
 value = SVT iterations per second over the timed steps (loop iterations of
-Algorithm 1, the kick's skipped steps not counted); sampled entries/s =
-|Omega| x iterations/s.  The roofline object covers the dominant kernel,
-timed with HIP events on the solve's stream during the profiled steps.
-The CPU baseline times the FP64 oracle on the host.
+Algorithm 1, the kick's skipped steps not counted) of the plain FP64 solver
+(the paper's precision); sampled entries/s = |Omega| x iterations/s.  The
+mixed form (FP32 bulk, FP64 reductions) is reported beside it.  The roofline
+object covers the headline's dominant kernel, timed with HIP events on the
+solve's stream during the profiled steps.  The serving form reports
+converged solves/s and latency percentiles over converged solves.  The CPU
+baseline times the FP64 oracle on the host.
 """
 from __future__ import annotations
 
@@ -72,63 +75,53 @@ def measured_traffic(kernel: str, workload: str, precision: str):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
-def cpu_baseline(p, seconds: float):
-    """The oracle's SVT iteration at this size, timed on column slabs.
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    At n >= 5000 the oracle takes the singular triplets of each iterate from
-    the Gram matrix (tier B: a sparse product Y^T Y, then LAPACK's symmetric
-    eigensolver, multithreaded BLAS).  Its cost per iteration is a c^2 term
-    (the Gram product and the dense matrix) plus a c^3 term (the
-    eigensolver) in the number c of columns.  The sample runs the oracle's
-    ``gram_triplets`` as it stands on the first c and 2c columns of
-    P_Omega(M) (c doubled until the 2c run takes about seconds / 2), fits
-    t(c) = a c^2 + b c^3 through the two timings, and evaluates it at n;
-    the sampled-entry residual and update (O(|Omega| r)) are left out.
+
+def cpu_baseline(p, seconds: float):
+    """The CPU oracle as it stands, timed on the host on the same workload.
+
+    At this size the oracle runs tier C: Algorithm 1 with the s_k largest
+    singular triplets of each sparse iterate from SciPy's partial SVD
+    (ARPACK), the sampled residual and the update in NumPy.  The sample is
+    the kick plus the first SVT iterations, ended once the loop has run
+    ``seconds``; the value is those loop iterations over the loop's wall time
+    (the kick is reported apart, as on the GPU).
     """
-    import scipy.sparse as sp
-    import oracle
+    import oracle.krylov as ok
     try:
         from threadpoolctl import threadpool_info
         threads = max([i["num_threads"] for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
     except Exception:  # noqa: BLE001
         threads = int(os.environ.get("OMP_NUM_THREADS", "1"))
-    m, n = p.m, p.n
-    order = np.argsort(p.cols, kind="stable")
-    cols_sorted = p.cols[order]
-
-    def run(c):
-        hi = np.searchsorted(cols_sorted, c)
-        sel = order[:hi]
-        Ys = sp.csr_matrix((p.vals[sel], (p.rows[sel], p.cols[sel])), shape=(m, c))
-        t0 = time.perf_counter()
-        oracle.gram_triplets(Ys, p.tau)
-        return time.perf_counter() - t0
-
-    c = 256
-    while True:
-        t1 = run(c)
-        t2 = run(2 * c)
-        log(f"[bench] cpu baseline: gram_triplets on {c} and {2 * c} columns: {t1:.2f} s, {t2:.2f} s")
-        if t2 >= seconds / 2 or 4 * c > n:
-            break
-        c *= 2
-    # t = a c^2 + b c^3 through (c, t1) and (2c, t2)
-    b = (t2 - 4.0 * t1) / (4.0 * c ** 3)
-    a = (t1 - b * c ** 3) / c ** 2
-    if a < 0 or b < 0:  # timing noise: scale the larger run by the cube alone
-        a, b = 0.0, t2 / (2 * c) ** 3
-    per_iter = a * n ** 2 + b * n ** 3
-    iters_per_s = 1.0 / per_iter
+    t0 = time.perf_counter()
+    out = ok.svt_krylov(p.m, p.n, p.rows, p.cols, p.vals, p.tau, p.delta, p.eps, p.maxiter, p.incr,
+                        max_seconds=seconds)
+    t_all = time.perf_counter() - t0
+    loop_s = float(np.sum(out["seconds"]))
+    iters = len(out["seconds"])
+    ips = iters / loop_s
+    log(f"[bench] cpu baseline: {iters} oracle iterations in {loop_s:.1f} s (+ kick {t_all - loop_s:.1f} s)")
     return {
-        "value": iters_per_s,
+        "value": ips,
         "unit": "SVT iters/s",
-        "sampled_entries_per_s": iters_per_s * p.nnz,
+        "sampled_entries_per_s": ips * p.nnz,
         "cores": threads,
+        "cpu_model": _cpu_model(),
+        "host_cpus": os.cpu_count(),
         "kind": "oracle",
-        "sample": (f"the oracle's tier-B triplets (sparse Gram product + LAPACK eigh) on the first {c} and "
-                   f"{2 * c} columns of P_Omega(M) ({m} rows): {t1:.2f} s and {t2:.2f} s; "
-                   f"t(c) = a c^2 + b c^3 fitted through both and evaluated at c = {n}: "
-                   f"{per_iter:.0f} s per SVT iteration"),
+        "sample": (f"the FP64 oracle (tier C: Algorithm 1 with SciPy's ARPACK partial SVD of each sparse "
+                   f"iterate) on the same {p.m} x {p.n} workload: the kick ({t_all - loop_s:.1f} s) and SVT "
+                   f"iterations 1..{iters}, timed ({loop_s:.1f} s of loop, {loop_s / iters:.2f} s per "
+                   f"iteration); BLAS threads {threads}, the sparse products single-threaded"),
+        "oracle_ranks": out["ranks"],
     }
 
 
@@ -210,7 +203,7 @@ def traffic_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_m
 
 
 def table2_runs(precisions=("fp64", "mixed"), seed: int = 7) -> dict:
-    """Table 2's shapes (Section 5.2.2): n = 1000, (r, |Omega| / d_r) = (10, 6),
+    """Table 2's shapes (Section 5.2.1): n = 1000, (r, |Omega| / d_r) = (10, 6),
     (50, 4), (100, 3), noise ratios 1e-2, 1e-1, 1, each solved once with the
     eq. (5.10) stop (the paper averages five runs).  Per case: iterations,
     seconds (from svt_create's return to the factors, warm), relative error
@@ -271,7 +264,7 @@ def copy_calibration(mib: int, reps: int = 3):
 
 
 def serving_bench(n_req: int, slots: int, budget_gib: float, precision: int, seed: int = 0,
-                  load_frac: float = 0.7, mix: str = "baseline", step_cap: int = 256):
+                  load_frac: float = 0.7, mix: str = "baseline", step_cap: int = 512):
     """Serving form on a stream of mixed completion requests.
 
     mix "baseline": m, n uniform in [500, 8000] (rectangular), r in
@@ -282,9 +275,11 @@ def serving_bench(n_req: int, slots: int, budget_gib: float, precision: int, see
     500, noise off; each request's bidiagonalisation is capped at step_cap
     steps (a request that needs more ends with SVT_ELANCZOS), so a request
     outside the method's regime holds its slot for a bounded time.
-    Closed loop (all requests at t = 0) gives the capacity C in solves/s; an
-    open loop with Poisson arrivals at load_frac * C gives the latency
-    (arrival to completion) percentiles."""
+    Closed loop (all requests at t = 0) gives the capacity C in requests/s;
+    an open loop with Poisson arrivals at load_frac * C gives the latency
+    (arrival to completion).  Solves/s and the latency percentiles count
+    converged solves (SVT_OK) only; the status split and the latencies of the
+    other requests are reported beside them."""
     import threading
     import workload
     from paper_0810_3286_amd import svt as B
@@ -315,15 +310,17 @@ def serving_bench(n_req: int, slots: int, budget_gib: float, precision: int, see
         t0 = time.perf_counter()
         tickets = [B.svt_submit(srv, p.m, p.n, p.rows, p.cols, p.vals, params(p)) for p in closed]
         iters = 0
+        closed_ok = 0
         for i, t in enumerate(tickets):
             st, info = B.svt_wait(srv, t)
             iters += info.iters
             statuses.append(st)
+            closed_ok += int(st == B.SVT_OK)
             B.svt_release(srv, t)
             log(f"[bench] serving closed loop: request {i} done (status {st}, {info.iters} iterations)")
         t_closed = time.perf_counter() - t0
         capacity = n_req / t_closed
-        log(f"[bench] serving closed loop: {n_req} solves in {t_closed:.2f} s")
+        log(f"[bench] serving closed loop: {n_req} requests ({closed_ok} converged) in {t_closed:.2f} s")
         # open loop: Poisson arrivals at load_frac * capacity
         rate = load_frac * capacity
         rng = np.random.default_rng(seed + 1)
@@ -344,29 +341,39 @@ def serving_bench(n_req: int, slots: int, budget_gib: float, precision: int, see
         th = threading.Thread(target=submitter)
         th.start()
         th.join()
-        lat = []
+        lat, lat_failed = [], []
         for i, p in enumerate(openp):
             st, info = B.svt_wait(srv, tix[i])
             _, _, _, _, times = B.svt_result(srv, tix[i], p.m, p.n)
-            lat.append(times[2] - times[0])
+            li = times[2] - times[0]
+            (lat if st == B.SVT_OK else lat_failed).append(li)
             statuses.append(st)
             B.svt_release(srv, tix[i])
-            log(f"[bench] serving open loop: request {i} done (status {st}, latency {lat[-1]:.2f} s)")
+            log(f"[bench] serving open loop: request {i} done (status {st}, latency {li:.2f} s)")
         t_open = time.perf_counter() - t1
         stats = B.svt_server_stats(srv)
     finally:
         B.svt_server_destroy(srv)
     lat = np.array(lat)
+    pct = (lambda a, q: float(np.percentile(a, q)) if len(a) else None)
+    open_ok = len(lat)
     return {
         "requests_per_run": n_req, "slots": slots, "budget_gib": budget_gib,
         "precision": "mixed" if precision == B.SVT_MIXED else "fp64",
-        "closed_loop_solves_per_s": capacity,
+        # converged solves (SVT_OK) only; requests that ended otherwise are
+        # counted apart
+        "closed_loop_solves_per_s": closed_ok / t_closed,
+        "closed_loop_converged": closed_ok,
+        "closed_loop_requests_per_s": capacity,
         "closed_loop_svt_iters_per_s": iters / t_closed,
         "mix": mix, "step_cap": step_cap,
         "status_counts": {B.svt_status_string(k): int(v) for k, v in
                           zip(*np.unique(np.array(statuses), return_counts=True))},
-        "open_loop_rate_per_s": rate, "open_loop_solves_per_s": n_req / t_open,
-        "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+        "open_loop_rate_per_s": rate,
+        "open_loop_solves_per_s": open_ok / t_open,
+        "open_loop_converged": open_ok,
+        "p50_latency_s": pct(lat, 50), "p99_latency_s": pct(lat, 99),
+        "failed_latency_s": sorted(float(x) for x in lat_failed),
         "max_running": stats["max_running"], "peak_admitted_gib": stats["peak_bytes"] / (1 << 30),
     }
 
@@ -377,7 +384,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=4)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
+                    help="the headline form (fp64: the paper's precision); the other form is "
+                         "reported beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-steps", type=int, default=1)
@@ -387,8 +396,10 @@ def main():
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-mix", choices=["baseline", "table1"], default="baseline")
-    ap.add_argument("--serving-step-cap", type=int, default=256)
-    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
+    ap.add_argument("--serving-step-cap", type=int, default=512)
+    ap.add_argument("--no-other", action="store_true",
+                    help="skip the run of the other precision (mixed beside an fp64 headline, or fp64 "
+                         "beside a mixed one)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration)")
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
@@ -522,34 +533,39 @@ def main():
                      "traffic": traffic, "bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": avg_s * 1e6},
     }
-    if not args.no_fp64 and args.precision == "mixed":
-        # the plain FP64 GPU solver on the same workload, for comparison
+    if not args.no_other:
+        # the other precision on the same workload: the mixed form beside the
+        # plain FP64 solver (or the FP64 solver beside a mixed headline)
+        other = "mixed" if args.precision == "fp64" else "fp64"
         prm = B.svt_params_default(p.m, p.n, p.nnz)
         prm.tau, prm.delta, prm.eps, prm.maxiter, prm.incr = p.tau, p.delta, p.eps, p.maxiter, p.incr
-        prm.precision = B.SVT_FP64
+        prm.precision = B.SVT_MIXED if other == "mixed" else B.SVT_FP64
         prm.spmv_mode = args.spmv_mode
-        h64 = B.svt_create(p.m, p.n, p.rows, p.cols, p.vals, prm)
+        ho = B.svt_create(p.m, p.n, p.rows, p.cols, p.vals, prm)
         try:
-            log("[bench] fp64 comparison solves")
-            B.svt_solve(h64)
+            log(f"[bench] {other} solves")
+            for _ in range(max(args.warmup, 1)):
+                B.svt_solve(ho)
             t0 = time.perf_counter()
-            it64 = 0
+            ito = 0
             for _ in range(args.steps):
-                _, inf = B.svt_solve(h64)
-                it64 += inf.iters
-            t64 = time.perf_counter() - t0
-            U64, _, V64 = B.svt_factors(h64, p.m, p.n)
+                _, inf = B.svt_solve(ho)
+                ito += inf.iters
+            to = time.perf_counter() - t0
+            Uo, _, Vo = B.svt_factors(ho, p.m, p.n)
         finally:
-            B.svt_destroy(h64)
-        out["fp64"] = {"svt_iters_per_s": it64 / t64, "sampled_entries_per_s": it64 / t64 * p.nnz,
-                       "iters_per_solve": it64 / args.steps, "ms_per_step": t64 / args.steps * 1e3,
-                       "rel_error_vs_truth": rel_diff_factored(U64, V64, p.ML, p.MR),
-                       "mixed_vs_fp64_rel_diff": rel_diff_factored(U, V, U64, V64)}
+            B.svt_destroy(ho)
+        out[other] = {"svt_iters_per_s": ito / to, "sampled_entries_per_s": ito / to * p.nnz,
+                      "iters_per_solve": ito / args.steps, "ms_per_step": to / args.steps * 1e3,
+                      "dtype": "f64" if other == "fp64" else "f32+f64",
+                      "rel_error_vs_truth": rel_diff_factored(Uo, Vo, p.ML, p.MR),
+                      "rel_diff_vs_headline": rel_diff_factored(Uo, Vo, U, V)}
     if not args.no_serving:
         log("[bench] serving stream")
-        out["serving"] = serving_bench(args.serving_requests, args.serving_slots, 64.0,
-                                       B.SVT_MIXED if args.precision == "mixed" else B.SVT_FP64,
+        # the serving form runs mixed-precision solves (its workload's definition)
+        out["serving"] = serving_bench(args.serving_requests, args.serving_slots, 64.0, B.SVT_MIXED,
                                        mix=args.serving_mix, step_cap=args.serving_step_cap)
+        # converged solves only (the status split is in "serving")
         out["solves_per_s"] = out["serving"]["closed_loop_solves_per_s"]
         out["p99_latency_s"] = out["serving"]["p99_latency_s"]
     if not args.no_cpu_baseline:

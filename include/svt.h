@@ -139,8 +139,9 @@ svt_status svt_create(int64_t m, int64_t n, int64_t nnz, int32_t fmt,
 svt_status svt_solve(svt_problem *h, svt_info *info);
 
 /* Per-iteration record of the last solve, k = 1..len: rank r_k, the number
-   s_k of triplets Algorithm 1 computes, the relative residual, and the
-   bidiagonalisation steps.  Any output pointer may be NULL; at most cap
+   s_k of triplets Algorithm 1 computes (Section 5.1.1's rule for s_k), the
+   relative residual of eq. (5.5), and the bidiagonalisation steps (the
+   quantities Section 5.2.1 reports per run: iterations, rank, error).  Any output pointer may be NULL; at most cap
    entries are written; *len_out receives the full length. */
 svt_status svt_history(const svt_problem *h, int32_t cap, int32_t *ranks,
                        int32_t *s_hist, double *residuals, int32_t *gkl_steps,
@@ -153,13 +154,22 @@ svt_status svt_history(const svt_problem *h, int32_t cap, int32_t *ranks,
 svt_status svt_factors(const svt_problem *h, int32_t *rank_out, double *U,
                        double *w, double *V);
 
-/* X^opt at q arbitrary positions (rows[i], cols[i]) -> out[i]. */
+/* X^opt at q arbitrary positions (rows[i], cols[i]) -> out[i]: the completed
+   entries outside Omega, which is what matrix completion is for (Section
+   1.1; Algorithm 1 returns X^opt as the estimate of M).  EINVAL for an index
+   out of range or a NULL array with q > 0. */
 svt_status svt_predict(const svt_problem *h, int64_t q, const int32_t *rows,
                        const int32_t *cols, double *out);
 
-/* Release the handle and its device memory.  NULL is ignored. */
+/* Release the handle and its device memory (the index structures, values,
+   iterate and factors that Algorithm 1 of Section 5.1.5 keeps between
+   iterations).  NULL is ignored. */
 void svt_destroy(svt_problem *h);
 
+/* Short text of a status code, including the two ends of Algorithm 1's loop
+   (Section 5.1.5): SVT_OK (the stop test of eq. (5.5) or (5.10) passed) and
+   SVT_NOT_CONVERGED (k_max reached).  Never NULL; unknown codes give
+   "unknown status". */
 const char *svt_status_string(int32_t status);
 
 /* Message for the last error on this handle (NULL handle: the last error of
@@ -205,6 +215,13 @@ svt_status svt_kick(svt_problem *h, double *sigma1, int32_t *k0);
    device refused the LDS size).  EINVAL for a bad handle or which. */
 svt_status svt_spmv_plan(const svt_problem *h, int32_t which, int32_t *segments);
 
+/* Device memory of a handle: the bytes it holds now and the most it has
+   held at once since svt_create (including the moments when a growing
+   buffer's old and new copies are both live).  The bidiagonalisation bases
+   of Section 5.1.1 grow with the steps taken, up to lanczos_maxsteps.
+   Either pointer may be NULL; EINVAL for a bad handle. */
+svt_status svt_device_bytes(const svt_problem *h, size_t *current, size_t *peak);
+
 /* Kernel timing of the last solve when params.profile = 1.  Each kind is
    one kernel, and each timed bracket holds exactly one launch of it:
      0 k_spmv_rows           a bidiagonalisation half-step: the deferred
@@ -241,9 +258,14 @@ svt_status svt_kernel_stats(const svt_problem *h, int32_t kind, int64_t *launche
  * ------------------------------------------------------------------ */
 typedef struct svt_server svt_server;
 
-/* Predicted device bytes of a problem (index structures, values, iterate,
-   bidiagonalisation bases for up to 256 steps, factors, scratch).  A
-   request submitted with lanczos_maxsteps > 0 is admitted on its own cap. */
+/* Predicted device bytes of a problem: index structures, values, iterate,
+   bidiagonalisation bases and their partial sums for up to 512 steps (the
+   default step cap of a served request), counted twice because a growing
+   basis briefly holds its old and new copies, factors up to the rank that
+   cap allows, and scratch.  An upper bound of the peak that svt_device_bytes
+   reports for a handle created with lanczos_maxsteps = 512.  A request
+   submitted with lanczos_maxsteps > 0 is admitted, and run, on its own cap;
+   with 0 it runs with 512. */
 svt_status svt_footprint(int64_t m, int64_t n, int64_t nnz, int32_t precision, size_t *bytes);
 
 /* hbm_budget_bytes > 0: device memory the admitted solves may hold at once;

@@ -16,6 +16,9 @@ Contents (each function cites the passage of the paper it writes out):
 * ``gram_triplets``    singular triplets above tau of a sparse Y from its Gram
                        matrix's eigendecomposition (LAPACK, FP64)
 * ``svt_sparse``       Algorithm 1, tier B: sparse Y, Gram-matrix triplets
+* ``krylov.svt_krylov`` Algorithm 1, tier C: sparse Y, the s_k largest
+                       triplets from a library partial SVD (SciPy / ARPACK),
+                       the repeat loop over s_k as printed
 """
 from .svt import (  # noqa: F401
     jacobi_svd,

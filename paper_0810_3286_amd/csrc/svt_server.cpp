@@ -57,6 +57,42 @@ struct Request {
   double t_submit = 0, t_start = 0, t_done = 0;
 };
 
+// Device bytes of one solve whose bidiagonalisation runs at most kmax steps
+// (the handle's step cap: its bases never grow past it, and the rank of X,
+// hence the factor width, cannot exceed it).  Counts every buffer a handle
+// allocates, with a growing buffer's old and new copies both live.
+size_t footprint_bytes(int64_t m, int64_t n, int64_t nnz, int32_t precision, double kmax) {
+  const double vb = precision == SVT_MIXED ? 4.0 : 8.0;
+  const double big = (double)std::max(m, n), small = (double)std::min(m, n);
+  const double kcap = std::min(small, kmax);
+  const double nblk = std::max(256.0, std::ceil(big / 2048.0));   // reduction partials per column
+  const double rank = kcap;                                        // rank bound of X
+  double b = 0.0;
+  b += 4.0 * (3.0 * (double)nnz + (double)(m + n + 2));    // colidx, rowidx, csr_of_csc, rowptr, colptr
+  b += 2.0 * 2.0 * (double)nnz;                            // 16-bit index copies
+  b += 4.0 * 9.0 * (double)(m + n);                        // LDS plan segment starts (up to 8 segments)
+  b += 4.0 * vb * (double)nnz;                             // M and Y, both orders
+  double grow = 0.0;                                       // buffers that grow with the basis
+  grow += vb * (big * (kcap + 1) + small * (kcap + 2));    // Lanczos bases
+  grow += 8.0 * (kcap + 4) * (4.0 + 2.0 * nblk + 1.0) + 8.0 * nblk;  // coefficients and partials
+  b += 2.0 * grow;                                         // old and new copies during growth
+  b += vb * (big + small);                                 // working vectors
+  b += vb * (double)(m + n) * (rank + 16.0 / vb) * 1.0;    // factors (row stride padded to 16 bytes)
+  b += 2.0 * 8.0 * (2.0 * kcap * rank + rank);             // Ritz combination matrices
+  b += 8.0 * (1024 + 8);                                   // residual partials
+  return (size_t)(b * 1.05) + (1u << 20);                  // margin for allocation granularity
+}
+
+// Without a step cap in the parameters, a request runs (and is admitted) with
+// 512 steps: about 3.5 steps per singular value above tau are typical, so
+// ranks up to ~140.
+constexpr double kDefaultStepCap = 512.0;
+
+double request_cap(const svt_params &p) {
+  return p.lanczos_maxsteps > 0 ? (double)p.lanczos_maxsteps : kDefaultStepCap;
+}
+
+
 }  // namespace
 
 struct svt_server {
@@ -116,6 +152,8 @@ struct svt_server {
   void run(Request *r, hipStream_t stream) {
     svt_params p = r->prm;
     p.stream = stream;  // the slot's own stream (library-owned when null)
+    // the step cap the admission footprint assumed
+    p.lanczos_maxsteps = (int32_t)request_cap(p);
     svt_problem *h = nullptr;
     svt_status st = svt_create(r->m, r->n, r->nnz, SVT_COO, r->rows.data(), r->cols.data(), r->vals.data(), &p, &h);
     if (st != SVT_OK) {
@@ -143,29 +181,6 @@ struct svt_server {
   }
 };
 
-namespace {
-
-// Device bytes of one solve whose bidiagonalisation runs at most kmax steps.
-size_t footprint_bytes(int64_t m, int64_t n, int64_t nnz, int32_t precision, double kmax) {
-  const double vb = precision == SVT_MIXED ? 4.0 : 8.0;
-  const double big = (double)std::max(m, n), small = (double)std::min(m, n);
-  const double kcap = std::min(small, kmax);
-  double b = 0.0;
-  b += 4.0 * (3.0 * (double)nnz + (double)(m + n + 2));   // colidx, rowidx, csc_of_csr, rowptr, colptr
-  b += 4.0 * vb * (double)nnz;                            // M and Y, both orders
-  b += vb * (big * (kcap + 1) + small * (kcap + 2));      // Lanczos bases
-  b += vb * (big + small);                                // working vectors
-  b += vb * (double)(m + n) * 130.0;                      // factors (rank up to 128, padded)
-  b += 8.0 * (kcap + 4) * (32 + 256 + 8) + 16.0 * 1024;   // reduction partials
-  b += 8.0 * (double)(m + n + 2) * 3.0;                   // LDS plan segment starts (worst case)
-  return (size_t)(b * 1.05) + (1u << 20);                 // margin for allocation granularity
-}
-
-// Without a step cap in the parameters, admission assumes 256 steps: about
-// 3.5 steps per singular value above tau are typical, so ranks up to ~70.
-constexpr double kDefaultStepCap = 256.0;
-
-}  // namespace
 
 extern "C" {
 
@@ -201,8 +216,7 @@ svt_status svt_submit(svt_server *s, int64_t m, int64_t n, int64_t nnz, const in
   r->m = m; r->n = n; r->nnz = nnz;
   if (params) r->prm = *params;
   else svt_params_default(m, n, nnz, &r->prm);
-  r->footprint = footprint_bytes(m, n, nnz, r->prm.precision,
-                                 r->prm.lanczos_maxsteps > 0 ? (double)r->prm.lanczos_maxsteps : kDefaultStepCap);
+  r->footprint = footprint_bytes(m, n, nnz, r->prm.precision, request_cap(r->prm));
   r->rows.assign(rows, rows + nnz);
   r->cols.assign(cols, cols + nnz);
   r->vals.assign(vals, vals + nnz);

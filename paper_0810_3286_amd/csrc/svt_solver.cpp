@@ -263,6 +263,8 @@ struct ProblemBase {
   // x segments staged in LDS by the row- (0) or column-compressed (1)
   // product; 0 when that product gathers x from memory
   virtual int spmv_segments(int which) const = 0;
+  virtual void mem_stats(size_t *cur, size_t *peak) const = 0;
+  size_t peak_bytes = 0;
   std::vector<Record> history;
   Profiler prof;
 };
@@ -399,6 +401,7 @@ struct Problem final : ProblemBase {
     sample_part.alloc(sizeof(double) * (kSampleMaxBlocks + 8));
     sample_host.ensure(sizeof(double) * (kSampleMaxBlocks + 8));
     ensure_basis(std::min<int64_t>(acols, 64));
+    note_peak(0);
     HIP_CHECK(hipStreamSynchronize(stream));
   }
 
@@ -416,10 +419,13 @@ struct Problem final : ProblemBase {
   }
 
   // Bases with room for `cap` bidiagonalisation steps (grown geometrically).
+  // Growth never passes the step cap (lanczos_maxsteps, else min(m, n)):
+  // the footprint a server admits a request on assumes that bound.
   void ensure_basis(int cap) {
+    cap = std::min(cap, step_cap());
     if (cap <= kcap) return;
     int newcap = std::max(cap, std::min<int>((int)acols, std::max(kcap * 2, 16)));
-    newcap = (int)std::min<int64_t>(newcap, acols);
+    newcap = std::min(newcap, step_cap());
     DevMem nU, nV, ncoef, n1, n2, n3, nr;
     nU.alloc(sizeof(T) * (size_t)arows * (size_t)(newcap + 1));
     nV.alloc(sizeof(T) * (size_t)acols * (size_t)(newcap + 2));
@@ -430,6 +436,8 @@ struct Problem final : ProblemBase {
     n2.alloc(sizeof(double) * (size_t)cols * blocks);
     n3.alloc(sizeof(double) * (size_t)blocks);
     nr.alloc(sizeof(double) * (size_t)cols);
+    // old and new bases are both live until the copies below complete
+    note_peak(nU.bytes + nV.bytes + ncoef.bytes + n1.bytes + n2.bytes + n3.bytes + nr.bytes);
     HIP_CHECK(hipMemsetAsync(ncoef.p, 0, ncoef.bytes, stream));
     if (kcap > 0) {
       // the pending vector's partials (its dot products and |.|^2, in any
@@ -455,6 +463,7 @@ struct Problem final : ProblemBase {
     std::swap(gs3.p, n3.p); std::swap(gs3.bytes, n3.bytes);
     std::swap(gsr.p, nr.p); std::swap(gsr.bytes, nr.bytes);
     kcap = newcap;
+    note_peak(0);
     gs.part1 = gs1.as<double>();
     gs.part2 = gs2.as<double>();
     gs.part3 = gs3.as<double>();
@@ -475,7 +484,8 @@ struct Problem final : ProblemBase {
   // combination matrices.
   void ensure_factors(int r, int k) {
     if (r > fcap) {
-      const int cap = std::max(r, fcap * 2);
+      // doubling, but never past the largest rank the step cap allows
+      const int cap = std::max(r, std::min(fcap * 2, step_cap()));
       // rows of 16 bytes' multiples (the sampled update reads them 16 bytes at a time)
       constexpr int al = 16 / (int)sizeof(T);
       fstride = std::max(al, (cap + al - 1) / al * al);
@@ -486,6 +496,24 @@ struct Problem final : ProblemBase {
     const size_t need = sizeof(double) * (2 * (size_t)std::max(k, 1) * (size_t)std::max(r, 1) + (size_t)r);
     if (ritzd.bytes < need) ritzd.alloc(need * 2);
     ritz_host.ensure(need * 2);
+    note_peak(0);
+  }
+
+  // Device bytes held now (every buffer of the handle) and the most held at
+  // once, including the moments when a growing buffer's old and new copies
+  // are both live.
+  size_t device_bytes() const {
+    const DevMem *all[] = {&rowptr, &colidx, &colptr, &rowidx, &csr_of_csc, &seg_r, &seg_c, &colidx16, &rowidx16,
+                           &Mr, &Mc, &Yr, &Yc, &Ub, &Vb, &pbuf_u, &pbuf_v, &coef, &gs1, &gs2, &gs3, &gsr,
+                           &sample_part, &ritzd, &Fu, &Fv};
+    size_t b = 0;
+    for (const DevMem *d : all) b += d->bytes;
+    return b;
+  }
+  void note_peak(size_t extra) { peak_bytes = std::max(peak_bytes, device_bytes() + extra); }
+  void mem_stats(size_t *cur, size_t *peak) const override {
+    if (cur) *cur = device_bytes();
+    if (peak) *peak = peak_bytes;
   }
 
   // --------------------------------------------------------- sparse products
@@ -920,14 +948,20 @@ struct Problem final : ProblemBase {
   // csr_of_csc; returns residual^2 (workgroup partials added on the host in
   // order, compensated).
   double sample_pass(int r, double delta, bool want_res) {
+    return sample_pass_on(Fu.as<T>(), Fv.as<T>(), fstride, r, delta, want_res ? sample_part.as<double>() : nullptr);
+  }
+
+  // The same pass with the factors (row stride rs) and the partials' buffer
+  // given; part null: no residual.
+  double sample_pass_on(const T *fu, const T *fv, int rs, int r, double delta, double *part) {
+    const bool want_res = part != nullptr;
     const double vb = sizeof(T);
     // algorithmic bytes of the sampled pass: index, M and Y read, Y written,
     // the row pointers, both factors once
     const double pass_bytes = (double)ix.nnz * (4.0 + 3.0 * vb) + vb * (double)(ix.m + ix.n) * r;
     prof.begin();
     HIP_CHECK(launch_sample_update<T>(stream, lanes_r, rowptr.as<int32_t>(), colidx.as<int32_t>(), Mr.as<T>(),
-                                      Yr.as<T>(), (int)ix.m, Fu.as<T>(), Fv.as<T>(), r, fstride, true, delta,
-                                      want_res ? sample_part.as<double>() : nullptr));
+                                      Yr.as<T>(), (int)ix.m, fu, fv, r, rs, true, delta, part));
     prof.end(kSample, pass_bytes + 4.0 * (ix.m + 1));
     // the column copy: the map read, one value gathered and one written per entry
     prof.begin();
@@ -935,7 +969,7 @@ struct Problem final : ProblemBase {
     prof.end(kGather, (double)ix.nnz * (4.0 + 2.0 * vb));
     if (!want_res) return 0.0;
     const int nb = sample_blocks((int)ix.m, lanes_r);
-    HIP_CHECK(hipMemcpyAsync(sample_host.p, sample_part.p, sizeof(double) * nb, hipMemcpyDeviceToHost, stream));
+    HIP_CHECK(hipMemcpyAsync(sample_host.p, part, sizeof(double) * nb, hipMemcpyDeviceToHost, stream));
     HIP_CHECK(hipStreamSynchronize(stream));
     double sum = 0.0, comp = 0.0;
     for (int b = 0; b < nb; ++b) {
@@ -1099,6 +1133,7 @@ struct Problem final : ProblemBase {
     DevMem dx, dout;
     dx.alloc(sizeof(T) * nin);
     dout.alloc(sizeof(T) * nout);
+    note_peak(dx.bytes + dout.bytes);
     HIP_CHECK(hipMemcpyAsync(dx.p, hx.data(), sizeof(T) * nin, hipMemcpyHostToDevice, stream));
     const Csx c = trans ? csc_struct() : csr_struct();
     SpmvInput<T> in;
@@ -1442,6 +1477,12 @@ svt_status svt_kick(svt_problem *h, double *sigma1, int32_t *k0) {
 svt_status svt_spmv_plan(const svt_problem *h, int32_t which, int32_t *segments) {
   if (!h || !h->impl || (which != 0 && which != 1) || !segments) return SVT_EINVAL;
   *segments = h->impl->spmv_segments(which);
+  return SVT_OK;
+}
+
+svt_status svt_device_bytes(const svt_problem *h, size_t *current, size_t *peak) {
+  if (!h || !h->impl) return SVT_EINVAL;
+  h->impl->mem_stats(current, peak);
   return SVT_OK;
 }
 

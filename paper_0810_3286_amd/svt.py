@@ -113,6 +113,7 @@ def _signatures(lib):
         "svt_kick": (ctypes.c_int32, [h, _dp, _ip]),
         "svt_kernel_stats": (ctypes.c_int32, [h, ctypes.c_int32, _lp, _dp, _dp]),
         "svt_spmv_plan": (ctypes.c_int32, [h, ctypes.c_int32, _ip]),
+        "svt_device_bytes": (ctypes.c_int32, [h, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
         "svt_footprint": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                            ctypes.POINTER(ctypes.c_size_t)]),
         "svt_server_create": (ctypes.c_int32, [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
@@ -309,6 +310,14 @@ def svt_spmv_plan(h, which: int) -> int:
     seg = ctypes.c_int32()
     _check(load().svt_spmv_plan(h, which, ctypes.byref(seg)), h)
     return seg.value
+
+
+def svt_device_bytes(h):
+    """(bytes held now, most bytes held at once) of a handle's device memory."""
+    cur = ctypes.c_size_t()
+    peak = ctypes.c_size_t()
+    _check(load().svt_device_bytes(h, ctypes.byref(cur), ctypes.byref(peak)), h)
+    return cur.value, peak.value
 
 
 # ---------------------------------------------------------------- serving

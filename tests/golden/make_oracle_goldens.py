@@ -3,16 +3,22 @@
 Calls only the CPU oracle on the seeded workloads; the HIP path's tests
 compare against the stored files.  Run from the repository root:
 
-    python tests/golden/make_oracle_goldens.py 1   # 400 x 400, rank 10: tier A (dense Jacobi)
-    python tests/golden/make_oracle_goldens.py 2   # 5000 x 5000, rank 10: tier B (Gram matrix)
+    python tests/golden/make_oracle_goldens.py 1      # 400 x 400, rank 10: tier A (dense Jacobi)
+    python tests/golden/make_oracle_goldens.py 2      # 5000 x 5000, rank 10: tier B (Gram matrix)
     python tests/golden/make_oracle_goldens.py 2 60   # the same, X at iteration 60 (eps = 0)
     python tests/golden/make_oracle_goldens.py 3 40   # 10000 x 10000, rank 50: tier B, X at iteration 40
+    python tests/golden/make_oracle_goldens.py 3 C    # the same, complete run: tier C (library partial SVD)
+    python tests/golden/make_oracle_goldens.py 4 C    # 30000 x 30000, rank 10: tier C, complete run,
+                                                      # plus X at iterations 20 and 60
 
 With a second argument k the run stops after k iterations with eps = 0, and
 the file holds X^k: a fixed-iteration comparison point for trajectories
 that amplify rounding differences (near the end of the 5000 x 5000 run the
 rank of X flips between 10, 11 and 12, and two solvers that differ only in
-rounding part ways).
+rounding part ways).  With "C" the complete run of tier C is stored, and for
+the 30000 x 30000 workload also its X^20 and X^60 (the loop is the same up to
+there whatever eps is, so these equal runs stopped at 20 and 60 with
+eps = 0).
 """
 import os
 import sys
@@ -25,33 +31,72 @@ sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
 import workload  # noqa: E402
+from oracle.krylov import svt_krylov  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
+SNAPSHOTS = {4: (20, 60)}
+# tier C's X^k checked against a stored tier-B X^k of the same workload (the
+# comparison is stored; the factors are not stored twice)
+CROSS_CHECK = {3: 40}
 
-def main(cfg: int, kfix: int = 0):
+
+def _save(path, U, w, V, iters, k0, sigma1, ranks, s_hist, residuals, seconds, tier, **extra):
+    np.savez_compressed(path, U=U, w=w, V=V, iters=iters, k0=k0, sigma1=sigma1,
+                        ranks=np.array(ranks), s_hist=np.array(s_hist),
+                        residuals=np.array(residuals), seconds=seconds, tier=tier, **extra)
+    print(f"wrote {path}: tier {tier}, {iters} iterations, k0 {k0}", flush=True)
+
+
+def main(cfg: int, arg: str = "0"):
     p = workload.config(cfg, seed=0)
-    eps, maxiter = (0.0, kfix) if kfix > 0 else (p.eps, p.maxiter)
     t = time.time()
+
+    def progress(k, r, res, *rest):
+        print(f"  iteration {k}: rank {r}, residual {res:.3e}, {time.time() - t:.0f} s", flush=True)
+
+    if arg == "C":
+        snaps = tuple(SNAPSHOTS.get(cfg, ())) + ((CROSS_CHECK[cfg],) if cfg in CROSS_CHECK else ())
+        out = svt_krylov(p.m, p.n, p.rows, p.cols, p.vals, p.tau, p.delta, p.eps, p.maxiter, p.incr,
+                         progress=progress, keep_iterates_at=snaps)
+        dt = time.time() - t
+        extra = {}
+        if cfg in CROSS_CHECK and CROSS_CHECK[cfg] in out["snapshots"]:
+            from tests.helpers import rel_diff_factored
+            kk = CROSS_CHECK[cfg]
+            b = np.load(os.path.join(HERE, f"oracle_config{cfg}_k{kk}.npz"))
+            U, w, V = out["snapshots"][kk]
+            extra = dict(cross_k=kk, cross_tier=str(b["tier"]),
+                         cross_x_rel_diff=rel_diff_factored(U, V, b["U"], b["V"]),
+                         cross_ranks_equal=bool(list(b["ranks"]) == out["ranks"][:kk]),
+                         cross_s_equal=bool(list(b["s_hist"]) == out["s_hist"][:kk]),
+                         cross_res_rel_diff=float(np.max(np.abs(np.array(out["residuals"][:kk]) - b["residuals"])
+                                                         / b["residuals"])))
+            print(f"cross-check at k = {kk} against tier {extra['cross_tier']}: {extra}", flush=True)
+        for kk in SNAPSHOTS.get(cfg, ()):
+            if kk in out["snapshots"]:
+                U, w, V = out["snapshots"][kk]
+                _save(os.path.join(HERE, f"oracle_config{cfg}_k{kk}.npz"), U, w, V, kk, out["k0"],
+                      out["sigma1"], out["ranks"][:kk], out["s_hist"][:kk], out["residuals"][:kk],
+                      float(np.sum(out["seconds"][:kk])), "C")
+        _save(os.path.join(HERE, f"oracle_config{cfg}.npz"), out["U"], out["w"], out["V"], out["iters"],
+              out["k0"], out["sigma1"], out["ranks"], out["s_hist"], out["residuals"], dt, "C", **extra)
+        return
+    kfix = int(arg)
+    eps, maxiter = (0.0, kfix) if kfix > 0 else (p.eps, p.maxiter)
     if cfg == 1:
         out = oracle.svt_dense(p.m, p.n, p.rows, p.cols, p.vals, p.tau, p.delta, eps,
                                maxiter, p.incr)
         tier = "A"
     else:
         out = oracle.svt_sparse(p.m, p.n, p.rows, p.cols, p.vals, p.tau, p.delta, eps,
-                                maxiter, p.incr,
-                                progress=lambda k, r, res: print(f"  iteration {k}: rank {r}, "
-                                                                 f"residual {res:.3e}", flush=True))
+                                maxiter, p.incr, progress=progress)
         tier = "B"
     dt = time.time() - t
     suffix = f"_k{kfix}" if kfix > 0 else ""
-    path = os.path.join(HERE, f"oracle_config{cfg}{suffix}.npz")
-    np.savez_compressed(path, U=out["U"], w=out["w"], V=out["V"], iters=out["iters"],
-                        k0=out["k0"], sigma1=out["sigma1"], ranks=np.array(out["ranks"]),
-                        s_hist=np.array(out["s_hist"]), residuals=np.array(out["residuals"]),
-                        seconds=dt, tier=tier)
-    print(f"wrote {path}: tier {tier}, {out['iters']} iterations, k0 {out['k0']}, {dt:.1f} s")
+    _save(os.path.join(HERE, f"oracle_config{cfg}{suffix}.npz"), out["U"], out["w"], out["V"], out["iters"],
+          out["k0"], out["sigma1"], out["ranks"], out["s_hist"], out["residuals"], dt, tier)
 
 
 if __name__ == "__main__":
-    main(int(sys.argv[1]) if len(sys.argv) > 1 else 1, int(sys.argv[2]) if len(sys.argv) > 2 else 0)
+    main(int(sys.argv[1]) if len(sys.argv) > 1 else 1, sys.argv[2] if len(sys.argv) > 2 else "0")

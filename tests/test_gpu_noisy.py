@@ -1,4 +1,4 @@
-"""Noisy-data completion (Section 5.2.2, eq. (5.10) stop) on the GPU: parity
+"""Noisy-data completion (Section 5.2.1, Table 2; eq. (5.10) stop) on the GPU: parity
 with the oracle on small cases, and Table 2's shapes (n = 1000; rank 10, 50,
 100 at 6, 4, 3 d_r; noise ratios 1e-2, 1e-1, 1) against what the paper
 reports for them: a relative error of about the noise ratio."""

@@ -129,3 +129,27 @@ def test_failing_request_frees_its_slot():
     assert st1 == st1b == B.SVT_ELANCZOS and info1.iters >= 1 and U.shape == (hard.m, 0)
     assert st2 == B.SVT_OK
     assert times1[0] <= times1[1] <= times1[2] <= times2[1] <= times2[2]
+
+
+@pytest.mark.parametrize("precision", [B.SVT_FP64, B.SVT_MIXED])
+def test_footprint_bounds_the_device_bytes(precision):
+    # the admission footprint is an upper bound of what a handle run with the
+    # served step cap (512) ever holds, basis growth included
+    for c in [(700, 500, 5, 42000, 11), (2400, 1800, 50, 4 * 50 * (2400 + 1800 - 50), 2),
+              (3000, 250, 10, 6 * 10 * (3250 - 10), 4)]:
+        gpu_case(f"footprint vs device bytes {c} precision {precision}")
+        p = workload.gaussian_lowrank(*c, maxiter=60)
+        prm = _prm(p, precision)
+        prm.maxiter = 60
+        prm.lanczos_maxsteps = 512
+        h = B.svt_create(p.m, p.n, p.rows, p.cols, p.vals, prm)
+        try:
+            try:
+                B.svt_solve(h)
+            except B.SvtError:
+                pass  # the bound must hold whatever the outcome
+            cur, peak = B.svt_device_bytes(h)
+        finally:
+            B.svt_destroy(h)
+        fp = B.svt_footprint(p.m, p.n, p.nnz, precision)
+        assert 0 < cur <= peak <= fp, (c, cur, peak, fp)

@@ -1,4 +1,4 @@
-"""The oracle's noisy-data stop (eq. (5.10), Section 5.2.2) pinned to what
+"""The oracle's noisy-data stop (eq. (5.10), Section 5.2.1) pinned to what
 the paper and the mathematics fix, not to its own formula:
 
 * the stop iterate is the first one consistent with the data: its residual

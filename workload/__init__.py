@@ -143,7 +143,7 @@ CONFIGS = {
 }
 
 
-# Table 2 (Section 5.2.2): n = 1000 with (r, |Omega| / d_r) = (10, 6),
+# Table 2 (Section 5.2.1): n = 1000 with (r, |Omega| / d_r) = (10, 6),
 # (50, 4), (100, 3), at noise ratios 1e-2, 1e-1 and 1.
 TABLE2_RANK_OVERSAMPLING = ((10, 6.0), (50, 4.0), (100, 3.0))
 TABLE2_NOISE_RATIOS = (1e-2, 1e-1, 1.0)
@@ -155,7 +155,7 @@ def noisy_lowrank(n: int, r: int, c: float, noise_ratio: float, seed: int = 0, *
     observed as B = M + Z with Z white Gaussian noise of standard deviation
     sigma = noise_ratio |P_Omega M|_F / sqrt(|Omega|), so that the noise ratio
     |P_Omega Z|_F / |P_Omega M|_F is noise_ratio in expectation (Section
-    5.2.2's model).  ``vals`` holds B; ``clean`` (an extra attribute) holds
+    5.2.1's model).  ``vals`` holds B; ``clean`` (an extra attribute) holds
     P_Omega M, and ``noise_sigma`` the sigma to give the stop rule."""
     nnz = int(round(c * degrees_of_freedom(n, n, r)))
     rng = np.random.default_rng(seed)
