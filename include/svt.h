@@ -204,6 +204,27 @@ svt_status svt_partial_svd(svt_problem *h, int32_t count, double *sigma,
 svt_status svt_sample_update(svt_problem *h, int32_t r, const double *U,
                              const double *V, double delta, double *res2);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the pass of
+   svt_sample_update with the factors already on the device.  Calls no
+   hipMalloc, hipFree or allocating routine.
+     U, V:   device pointers in the handle's value type (double for
+             SVT_FP64, float for SVT_MIXED), row-major m x r and n x r with
+             row stride `stride` elements, 16-byte aligned; owned by the
+             caller and only read.
+     stride: >= max(r, 1) and a multiple of 16 / sizeof(value) (2 or 4).
+   Returns ||P_Omega(M - U V^T)||_F^2 in *res2 (may be NULL) and applies
+   Y += delta P_Omega(M - U V^T), on the handle's stream, synchronised
+   before return.  The workgroup partials of the residual go to a fixed
+   array of the library in each device's memory (1032 doubles; any problem
+   size fits: the pass uses at most 1024 workgroups), held until the process
+   ends; every call on one device shares it, so calls that overlap on one
+   device race (one call at a time per device).  EINVAL for a bad stride,
+   unaligned or NULL factors with r > 0, a non-finite delta, or when the
+   handle's device is not current. */
+svt_status svt_sample_update_noalloc(svt_problem *h, int32_t r, const void *U, const void *V,
+                                     int64_t stride, double delta, double *res2);
+
 /* The kick alone: sets Y = k0 delta P_Omega(M) with k0 from eq. (5.3) (or
    k0_override), returning sigma1 = ||P_Omega M||_2 and k0. */
 svt_status svt_kick(svt_problem *h, double *sigma1, int32_t *k0);

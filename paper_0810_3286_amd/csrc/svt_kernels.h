@@ -163,6 +163,18 @@ hipError_t launch_sample_update(hipStream_t s, int lanes, const int32_t *ptr, co
                                 bool row_side_is_u, double delta, double *part_out);
 int sample_blocks(int nrows, int lanes);
 
+// Allocation-free sampled pass: a fixed device array of
+// kNoAllocScratchDoubles doubles per device (at least sample_blocks() for
+// any size) receives the workgroup partials.  noalloc_scratch(device, &p)
+// gives its address on `device`, which must be the current device on the
+// first call for that device (the address is looked up with
+// hipGetSymbolAddress and cached).  hipErrorInvalidValue for a device index
+// outside [0, kMaxDevices), hipErrorInvalidDevice when another device is
+// current on that first call.
+constexpr int kNoAllocScratchDoubles = kSampleMaxBlocks + 8;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch(int device, double **out);
+
 // y[t] = a * x[t] (the kick: Y = k0 delta M).
 template <typename T>
 hipError_t launch_axpby(hipStream_t s, const T *x, T *y, int64_t n, double a);

@@ -1652,6 +1652,33 @@ hipError_t launch_ritz(hipStream_t s, const T *Q, int64_t ldq, int nrows, int k,
   return hipGetLastError();
 }
 
+// The residual partials of the allocation-free sampled pass
+// (svt_sample_update_noalloc): one fixed array per device, shared by every
+// such call on that device (calls that overlap on one device race).  Host
+// code never passes `scratch` itself to a kernel: its device address comes
+// from hipGetSymbolAddress, looked up once per device with that device
+// current, and cached.
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+hipError_t noalloc_scratch(int device, double **out) {
+  static std::mutex mu;
+  static double *addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices || out == nullptr) return hipErrorInvalidValue;
+  std::lock_guard<std::mutex> lk(mu);
+  if (addr[device] == nullptr) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // the caller makes the device current
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = static_cast<double *>(p);
+  }
+  *out = addr[device];
+  return hipSuccess;
+}
+
 int sample_blocks(int nrows, int lanes) {
   return row_chunks(nrows, std::max((kBlock / lanes) * 4, (nrows + kSampleMaxBlocks - 1) / kSampleMaxBlocks))
       .nblk;

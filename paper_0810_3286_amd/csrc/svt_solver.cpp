@@ -259,6 +259,7 @@ struct ProblemBase {
   virtual void apply(int trans, const double *x, double *out) = 0;
   virtual int partial_svd(int count, double *sigma, double *U, double *V) = 0;
   virtual double sample_update(int r, const double *U, const double *V, double delta) = 0;
+  virtual double sample_update_noalloc(int r, const void *U, const void *V, int64_t rs, double delta) = 0;
   virtual void kick(double *sigma1, int32_t *k0) = 0;
   // x segments staged in LDS by the row- (0) or column-compressed (1)
   // product; 0 when that product gathers x from memory
@@ -293,6 +294,7 @@ struct Problem final : ProblemBase {
   DevMem gsr;                     // a pending vector's column sums (k_pending_reduce)
   GsScratch gs{};
   DevMem sample_part;             // residual partials, kSampleMaxBlocks + 8 doubles
+  double *noalloc_part = nullptr; // the device's fixed scratch (svt_sample_update_noalloc)
   PinnedMem sample_host;          // their host copy
   DevMem ritzd;                   // Ritz combination (double): P (k x r), Q (k x r), w (r)
   PinnedMem ritz_host;            // its host staging
@@ -400,6 +402,9 @@ struct Problem final : ProblemBase {
 
     sample_part.alloc(sizeof(double) * (kSampleMaxBlocks + 8));
     sample_host.ensure(sizeof(double) * (kSampleMaxBlocks + 8));
+    // the allocation-free pass's scratch address on this device (looked up
+    // once per device, with the device current)
+    HIP_CHECK(noalloc_scratch(device, &noalloc_part));
     ensure_basis(std::min<int64_t>(acols, 64));
     note_peak(0);
     HIP_CHECK(hipStreamSynchronize(stream));
@@ -1177,6 +1182,29 @@ struct Problem final : ProblemBase {
     return sample_pass(r, delta, true);
   }
 
+  // svt_sample_update_noalloc: device factors in the value type T, row
+  // stride rs; the partials go to the device's fixed scratch array.  No
+  // device or host allocation: the partials' host copy is the pinned buffer
+  // made at setup.
+  double sample_update_noalloc(int r, const void *U, const void *V, int64_t rs, double delta) override {
+    constexpr int al = 16 / (int)sizeof(T);
+    if (rs < std::max(r, 1) || rs % al != 0 || rs > INT32_MAX)
+      throw Error(SVT_EINVAL, "stride must be >= max(r, 1) and a multiple of " + std::to_string(al) +
+                                  " elements of the handle's value type");
+    if (r > 0 && ((reinterpret_cast<uintptr_t>(U) & 15) || (reinterpret_cast<uintptr_t>(V) & 15)))
+      throw Error(SVT_EINVAL, "U and V must be 16-byte aligned device pointers");
+    const int nb = sample_blocks((int)ix.m, lanes_r);
+    if (nb > kNoAllocScratchDoubles || (size_t)nb * sizeof(double) > sample_host.bytes)
+      throw Error(SVT_EINVAL, "the residual partials (" + std::to_string(nb) +
+                                  ") exceed the fixed scratch of the allocation-free pass");
+    if (!noalloc_part) throw Error(SVT_ESTATE, "no scratch address for this device");
+    int cur = -1;
+    HIP_CHECK(hipGetDevice(&cur));
+    if (cur != device) throw Error(SVT_EINVAL, "the handle's device is not the current device");
+    rank = 0;  // the handle's X is not this caller's X
+    return sample_pass_on(static_cast<const T *>(U), static_cast<const T *>(V), (int)rs, r, delta, noalloc_part);
+  }
+
   void kick(double *sigma1, int32_t *k0) override {
     reset_passes();
     do_kick(sigma1, k0);
@@ -1457,6 +1485,16 @@ svt_status svt_sample_update(svt_problem *h, int32_t r, const double *U, const d
   if (!h || !h->impl || r < 0 || (r > 0 && (!U || !V)) || !std::isfinite(delta)) return SVT_EINVAL;
   return guarded(h, [&] {
     const double v = h->impl->sample_update(r, U, V, delta);
+    if (res2) *res2 = v;
+    return SVT_OK;
+  });
+}
+
+svt_status svt_sample_update_noalloc(svt_problem *h, int32_t r, const void *U, const void *V, int64_t stride,
+                                     double delta, double *res2) {
+  if (!h || !h->impl || r < 0 || (r > 0 && (!U || !V)) || !std::isfinite(delta)) return SVT_EINVAL;
+  return guarded(h, [&] {
+    const double v = h->impl->sample_update_noalloc(r, U, V, stride, delta);
     if (res2) *res2 = v;
     return SVT_OK;
   });

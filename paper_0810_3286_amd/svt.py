@@ -111,6 +111,8 @@ def _signatures(lib):
         "svt_partial_svd": (ctypes.c_int32, [h, ctypes.c_int32, _dp, _dp, _dp, _ip]),
         "svt_sample_update": (ctypes.c_int32, [h, ctypes.c_int32, _dp, _dp, ctypes.c_double, _dp]),
         "svt_kick": (ctypes.c_int32, [h, _dp, _ip]),
+        "svt_sample_update_noalloc": (ctypes.c_int32, [h, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                                       ctypes.c_int64, ctypes.c_double, _dp]),
         "svt_kernel_stats": (ctypes.c_int32, [h, ctypes.c_int32, _lp, _dp, _dp]),
         "svt_spmv_plan": (ctypes.c_int32, [h, ctypes.c_int32, _ip]),
         "svt_device_bytes": (ctypes.c_int32, [h, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
@@ -286,6 +288,16 @@ def svt_sample_update(h, U, V, delta: float) -> float:
     r = U.shape[1] if U.ndim == 2 else 0
     res2 = ctypes.c_double()
     _check(load().svt_sample_update(h, r, _p(U), _p(V), float(delta), ctypes.byref(res2)), h)
+    return res2.value
+
+
+def svt_sample_update_noalloc(h, r: int, U_dev: int, V_dev: int, stride: int, delta: float) -> float:
+    """svt_sample_update with device-resident factors (integer device
+    addresses, the handle's value type, row stride ``stride``); allocates
+    nothing."""
+    res2 = ctypes.c_double()
+    _check(load().svt_sample_update_noalloc(h, r, ctypes.c_void_p(U_dev), ctypes.c_void_p(V_dev), stride,
+                                            float(delta), ctypes.byref(res2)), h)
     return res2.value
 
 
