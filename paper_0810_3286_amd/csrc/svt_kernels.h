@@ -146,7 +146,9 @@ template <typename T>
 hipError_t launch_randn(hipStream_t s, T *out, int n, uint64_t seed, uint64_t ctr);
 
 // out[i, l] = w[l] * sum_c Q[i, c] P[c, l] for l < r; zero for r <= l < rs.
-// P is k x r row-major (double), w may be null (no scaling).
+// P is k x r row-major (double), w may be null (no scaling).  FP64 sums on
+// the matrix cores in both precisions.  hipErrorInvalidValue for k < 1,
+// r > rs or ldq < nrows.
 template <typename T>
 hipError_t launch_ritz(hipStream_t s, const T *Q, int64_t ldq, int nrows, int k,
                        const double *P, const double *w, int r, T *out, int rs);

@@ -1208,61 +1208,74 @@ __global__ __launch_bounds__(kBlock) void k_randn(T *__restrict__ out, int n, ui
   }
 }
 
-// Ritz vectors: out[i, l] = w[l] sum_c Q[i, c] P[c, l] (an fma chain in c
-// order) for l < r, zero for r <= l < rs.  A thread owns row i and the
-// kRitzTile columns of blockIdx.y (small tiles: the kernel is bound by load
-// latency, so more threads beat fewer re-reads of the basis); it loads
-// kRitzBatch<T> entries of its row at a time (coalesced across the rows,
-// unconditional from clamped addresses).  The tile's rows of P are staged in
-// LDS kRitzChunk at a time: read as uniform values they became one scalar
-// load and one wait per entry.
-constexpr int kRitzTile = 2;
-template <typename T> constexpr int kRitzBatch = 256 / sizeof(T);  // 64 (FP32) or 32 (FP64) loads in flight
-constexpr int kRitzBlock = 128;
-constexpr int kRitzChunk = 512;
-template <typename T>
-__global__ __launch_bounds__(kRitzBlock) void k_ritz(const T *__restrict__ Q, int64_t ldq, int nrows, int k,
-                                                     const double *__restrict__ P, const double *__restrict__ w,
-                                                     int r, T *__restrict__ out, int rs) {
-  __shared__ double ps[kRitzChunk * kRitzTile];
-  const int i = blockIdx.x * kRitzBlock + threadIdx.x;
-  const bool valid = i < nrows;
-  const int ir = valid ? i : 0;
-  const int l0 = blockIdx.y * kRitzTile;
-  const int nl = min(kRitzTile, r - l0);
-  double acc[kRitzTile];
+// Ritz vectors: out[i, l] = w[l] sum_c Q[i, c] P[c, l] for l < r, zero for
+// r <= l < rs: a tall-skinny product (rows x k) times (k x r), on the FP64
+// matrix cores (v_mfma_f64_16x16x4f64; FP32 bases are widened on load, so the
+// sums are FP64 in both precisions).  A workgroup owns 64 rows (one
+// wavefront per 16) and up to 64 output columns (four 16-column tiles; wider
+// factors take more workgroups along y), so every basis entry is read once
+// per 64 output columns.  P is staged in LDS kRitzKc rows at a time; each
+// stage's basis loads are issued before the staging barrier.  Operand
+// layouts of the 16x16x4 FP64 instruction, lane l: A[l % 16][l / 16] (row,
+// c), B[l / 16][l % 16] (c, column), and element v of the result holds
+// D[l / 16 + 4 v][l % 16] (rows interleaved by four; checked on the device).
+constexpr int kRitzRows = 64;
+constexpr int kRitzCols = 64;
+constexpr int kRitzKc = 64;
+constexpr int kRitzThreads = 256;
+using d4_t = __attribute__((ext_vector_type(4))) double;
+
+template <typename T, int NT>
+__global__ __launch_bounds__(kRitzThreads) void k_ritz(const T *__restrict__ Q, int64_t ldq, int nrows, int k,
+                                                       const double *__restrict__ P, const double *__restrict__ w,
+                                                       int r, T *__restrict__ out, int rs) {
+  __shared__ double ps[kRitzKc * kRitzCols];
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int row0 = blockIdx.x * kRitzRows + wave * 16;
+  const int l0 = blockIdx.y * kRitzCols;
+  const int arow = row0 + lane % 16;
+  const bool avalid = arow < nrows;
+  const T *qrow = Q + (avalid ? arow : 0);
+  const int kq = lane / 16;
+  d4_t acc[NT];
 #pragma unroll
-  for (int t = 0; t < kRitzTile; ++t) acc[t] = 0.0;
-  constexpr int B = kRitzBatch<T>;
-  for (int cc = 0; cc < k; cc += kRitzChunk) {
-    const int kc = min(kRitzChunk, k - cc);
-    __syncthreads();  // the previous chunk's reads are done
-    for (int e = threadIdx.x; e < kc * kRitzTile; e += kRitzBlock) {
-      const int c = e / kRitzTile, t = e % kRitzTile;
-      ps[e] = (t < nl) ? P[(size_t)(cc + c) * r + l0 + t] : 0.0;
+  for (int t = 0; t < NT; ++t) acc[t] = d4_t{0.0, 0.0, 0.0, 0.0};
+  for (int c0 = 0; c0 < k; c0 += kRitzKc) {
+    const int kc = min(kRitzKc, k - c0);
+    // this stage's A operands: column c0 + 4 s + kq of the lane's row
+    // (unconditional loads from clamped addresses, masked afterwards)
+    double a[kRitzKc / 4];
+#pragma unroll
+    for (int st = 0; st < kRitzKc / 4; ++st) {
+      const int c = 4 * st + kq;
+      const double v = (double)qrow[(size_t)min(c0 + c, k - 1) * ldq];
+      a[st] = (c < kc && avalid) ? v : 0.0;
+    }
+    __syncthreads();  // the previous stage's reads of ps are done
+    for (int e = threadIdx.x; e < kRitzKc * kRitzCols; e += kRitzThreads) {
+      const int c = e / kRitzCols, col = l0 + e % kRitzCols;
+      ps[e] = (c < kc && col < r) ? P[(size_t)(c0 + c) * r + col] : 0.0;
     }
     __syncthreads();
-    for (int c0 = 0; c0 < kc; c0 += B) {
-      T q[B];
 #pragma unroll
-      for (int j = 0; j < B; ++j) q[j] = Q[(size_t)(cc + min(c0 + j, kc - 1)) * ldq + ir];
+    for (int st = 0; st < kRitzKc / 4; ++st) {
 #pragma unroll
-      for (int j = 0; j < B; ++j) {
-        if (c0 + j < kc) {
-          const double *pr = ps + (c0 + j) * kRitzTile;
-#pragma unroll
-          for (int t = 0; t < kRitzTile; ++t)
-            if (t < nl) acc[t] = fma((double)q[j], pr[t], acc[t]);
-        }
+      for (int t = 0; t < NT; ++t) {
+        const double bv = ps[(4 * st + kq) * kRitzCols + t * 16 + lane % 16];
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], bv, acc[t], 0, 0, 0);
       }
     }
   }
-  if (!valid) return;
 #pragma unroll
-  for (int t = 0; t < kRitzTile; ++t) {
-    const int l = l0 + t;
-    if (l < r) out[(size_t)i * rs + l] = (T)(w ? acc[t] * w[l] : acc[t]);
-    else if (l < rs) out[(size_t)i * rs + l] = (T)0;
+  for (int t = 0; t < NT; ++t) {
+    const int col = l0 + t * 16 + lane % 16;
+    if (col >= rs) continue;
+    const double scale = col < r ? (w ? w[col] : 1.0) : 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = row0 + kq + 4 * v;
+      if (row < nrows) out[(size_t)row * rs + col] = (T)(acc[t][v] * scale);
+    }
   }
 }
 
@@ -1646,9 +1659,17 @@ hipError_t launch_randn(hipStream_t s, T *out, int n, uint64_t seed, uint64_t ct
 template <typename T>
 hipError_t launch_ritz(hipStream_t s, const T *Q, int64_t ldq, int nrows, int k, const double *P,
                        const double *w, int r, T *out, int rs) {
-  if (rs < 1) return hipSuccess;
-  dim3 grid((nrows + kRitzBlock - 1) / kRitzBlock, (rs + kRitzTile - 1) / kRitzTile);
-  SVT_LAUNCH((k_ritz<T>), grid, dim3(kRitzBlock), 0, s, Q, ldq, nrows, k, P, w, r, out, rs);
+  if (rs < 1 || nrows < 1) return hipSuccess;
+  if (k < 1 || r > rs || ldq < nrows) return hipErrorInvalidValue;
+  const dim3 grid((nrows + kRitzRows - 1) / kRitzRows, (rs + kRitzCols - 1) / kRitzCols);
+  // 16-column tiles per workgroup: enough for the first kRitzCols columns
+  const int nt = std::min(kRitzCols, rs + 15) / 16;
+  switch (nt) {
+    case 1: SVT_LAUNCH((k_ritz<T, 1>), grid, dim3(kRitzThreads), 0, s, Q, ldq, nrows, k, P, w, r, out, rs); break;
+    case 2: SVT_LAUNCH((k_ritz<T, 2>), grid, dim3(kRitzThreads), 0, s, Q, ldq, nrows, k, P, w, r, out, rs); break;
+    case 3: SVT_LAUNCH((k_ritz<T, 3>), grid, dim3(kRitzThreads), 0, s, Q, ldq, nrows, k, P, w, r, out, rs); break;
+    default: SVT_LAUNCH((k_ritz<T, 4>), grid, dim3(kRitzThreads), 0, s, Q, ldq, nrows, k, P, w, r, out, rs); break;
+  }
   return hipGetLastError();
 }
 

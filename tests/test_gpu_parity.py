@@ -108,7 +108,7 @@ def test_sparse_products_full_size_30000(precision, mode):
 
 
 @pytest.mark.parametrize("case", SMALL + [(400, 400, 10, 47400, 0)])
-@pytest.mark.parametrize("rank", [0, 1, 7, 12])
+@pytest.mark.parametrize("rank", [0, 1, 7, 12, 20, 40, 70, 100])
 def test_sample_update(case, rank):
     m, n, r, nnz, seed = case
     gpu_case(f"sample_update {case} rank {rank}")
@@ -131,6 +131,41 @@ def test_sample_update(case, rank):
     np.testing.assert_allclose(res2, np.sum(e * e), rtol=1e-12)
     np.testing.assert_allclose(y_csr, y + delta * e, rtol=1e-12, atol=1e-12 * np.abs(y).max())
     assert np.array_equal(y_csr, y_csc)  # both compressed copies identical bit for bit
+
+
+@pytest.mark.parametrize("case", SMALL + [(400, 400, 10, 47400, 0)])
+@pytest.mark.parametrize("rank", [1, 12, 20, 40, 70, 100])
+def test_sample_update_mixed(case, rank):
+    # the mixed form's pass (FP32 factors, values and products; compensated
+    # FP32 sum of e^2 promoted to FP64): every kernel variant (factor rows in
+    # 8, 16, 32 or 64 registers, or read from memory) against the oracle's
+    # plain definition on the FP32-rounded inputs
+    m, n, r, nnz, seed = case
+    gpu_case(f"sample_update mixed {case} rank {rank}")
+    p = workload.gaussian_lowrank(m, n, r, nnz, seed, shuffle=True)
+    y = workload.dense_random_iterate(p, seed + 11)
+    rng = np.random.default_rng(seed + 31)
+    U = rng.standard_normal((m, rank))
+    V = rng.standard_normal((n, rank))
+    delta = 1.7
+    h = _create(p, precision=B.SVT_MIXED)
+    try:
+        B.svt_set_iterate(h, y)
+        res2 = B.svt_sample_update(h, U, V, delta)
+        y_csr = B.svt_get_iterate(h, p.nnz, 0)
+        y_csc = B.svt_get_iterate(h, p.nnz, 1)
+    finally:
+        B.svt_destroy(h)
+    f32 = lambda a: np.asarray(a, np.float32).astype(np.float64)  # noqa: E731
+    Uf, Vf, Mf, yf = f32(U), f32(V), f32(p.vals), f32(y)
+    x = oracle.sampled_entries(Uf, Vf, p.rows, p.cols)
+    e = Mf - x
+    # FP32 rounding of the rank-r dot products: ~r 2^-24 sum |u_l v_l|
+    mag = oracle.sampled_entries(np.abs(Uf), np.abs(Vf), p.rows, p.cols) + np.abs(Mf)
+    err = (rank + 2) * 2.0 ** -23 * mag
+    assert np.all(np.abs((y_csr - yf) / delta - e) <= err / 1.0 + 4 * 2.0 ** -24 * np.abs(yf + delta * e) / delta)
+    assert abs(res2 - np.sum(e * e)) <= 2 * np.sum(np.abs(e) * err) + 1e-6 * np.sum(e * e)
+    assert np.array_equal(y_csr, y_csc)
 
 
 @pytest.mark.parametrize("case", SMALL)
@@ -157,6 +192,36 @@ def test_partial_svd_against_jacobi(case):
             assert abs(abs(U[:, i] @ Uo[:, i]) - 1) <= 1e-9
             assert abs(abs(V[:, i] @ Vo[:, i]) - 1) <= 1e-9
     assert np.linalg.norm(Yd @ V - U * sig) <= 1e-10 * so[0]
+
+
+@pytest.mark.parametrize("precision", [B.SVT_FP64, B.SVT_MIXED])
+@pytest.mark.parametrize("count", [17, 40, 64, 70, 130])
+def test_partial_svd_wide_factors(count, precision):
+    # Ritz vectors of 17 to 130 columns: one to four 16-column tiles per
+    # workgroup and more than one group of 64 output columns (the matrix-core
+    # product of the basis with the small SVD's vectors); 333 rows: a ragged
+    # last group of 64 rows
+    gpu_case(f"partial_svd {count} triplets precision {precision}")
+    m, n = 333, 290
+    p = workload.gaussian_lowrank(m, n, 5, 40000, 9)
+    y = workload.dense_random_iterate(p, 21)
+    prm = B.svt_params_default(p.m, p.n, p.nnz)
+    prm.precision = precision
+    h = B.svt_create(p.m, p.n, p.rows, p.cols, p.vals, prm)
+    try:
+        B.svt_set_iterate(h, y)
+        sig, U, V, steps = B.svt_partial_svd(h, count, m, n)
+    finally:
+        B.svt_destroy(h)
+    Yd = np.zeros((m, n))
+    Yd[p.rows, p.cols] = y
+    Uo, so, Vo = oracle.top_triplets_dense(Yd, count)
+    tol = 1e-11 if precision == B.SVT_FP64 else 2e-6
+    np.testing.assert_allclose(sig, so, rtol=0, atol=tol * so[0])
+    # Y v_i = sigma_i u_i and orthonormal factors, column by column
+    assert np.linalg.norm(Yd @ V - U * sig) <= 10 * tol * so[0] * np.sqrt(count)
+    np.testing.assert_allclose(U.T @ U, np.eye(count), atol=100 * tol)
+    np.testing.assert_allclose(V.T @ V, np.eye(count), atol=100 * tol)
 
 
 @pytest.mark.parametrize("case", SMALL + [(400, 400, 10, 47400, 0)])
