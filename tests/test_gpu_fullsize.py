@@ -58,11 +58,11 @@ def _solve_fixed(p, precision, k):
 
 # Near the end of the 5000^2 run sigma_11 and sigma_12 of the iterate hover
 # around tau, the rank flips between 10, 11 and 12, and a rounding-level
-# difference between two solvers grows by about 1.37 per iteration (1e-15 at
-# iteration 10, 1e-7 at 100, order one after 150): both still converge, to
-# different iterates within ~1e-4 of the truth.  Exact parity is therefore
-# checked at a fixed iteration (60) before the amplification reaches the
-# tolerance, and the complete runs by what they must share.
+# difference grows by orders of magnitude: between oracle runs that differ
+# only by rounding, 1e-14 up to iteration 50, 8e-7 at 100, order one after
+# 150 (tests/test_oracle_spread.py).  Exact parity is therefore checked at a
+# fixed iteration (60), and the complete runs by what the oracle's own
+# spread allows.
 def test_5000_fp64_matches_stored_oracle_at_iteration_60():
     gpu_case("5000^2 rank 10 FP64, 60 iterations vs stored tier-B oracle")
     p = workload.config(2)
@@ -97,16 +97,16 @@ def test_5000_complete_run_against_stored_oracle(precision):
     tol = 1e-8 if precision == B.SVT_FP64 else 5e-4
     np.testing.assert_allclose(g["residuals"][:head], o["residuals"][:head], rtol=tol)
     assert list(g["ranks"][:60]) == o["ranks"][:60]
-    # both end within 1e-4 of the truth, hence within 5e-4 of each other
-    assert rel_diff_factored(g["U"], g["V"], o["U"], o["V"]) <= 5e-4
+    # The oracle's own complete runs, with inputs or start vectors that
+    # differ only by rounding, stop anywhere in a range of iterations and end
+    # a few 1e-5 apart (tests/test_oracle_spread.py); the window and the
+    # tolerance come from that spread, not from GPU runs
+    from tests.test_oracle_spread import gpu_window
+    lo, hi, xtol = gpu_window()
+    assert lo <= g["info"]["iters"] <= hi
+    tol_x = xtol if precision == B.SVT_FP64 else max(xtol, 5e-4)
+    assert rel_diff_factored(g["U"], g["V"], o["U"], o["V"]) <= tol_x
     assert rel_diff_factored(g["U"], g["V"], p.ML, p.MR) < 2e-4
-    # from about iteration 170 on, the residual of either run hovers between
-    # eps and 3 eps while the rank flips, and the first dip below eps can come
-    # anywhere in that phase (the oracle's came at 244, the GPU runs' between
-    # 200 and 260 depending on rounding): the stop must fall in the phase,
-    # after the oracle first came within 2.5 eps
-    first = 1 + int(np.argmax(np.asarray(o["residuals"]) <= 2.5 * p.eps))
-    assert first <= g["info"]["iters"] <= 1.5 * o["iters"]
 
 
 @pytest.mark.parametrize("precision", [B.SVT_FP64, B.SVT_MIXED])
