@@ -48,6 +48,18 @@ typedef enum {
 typedef enum { SVT_FP64 = 0, SVT_MIXED = 1 } svt_precision;
 typedef enum { SVT_COO = 0, SVT_CSR = 1 } svt_index_format;
 typedef enum { SVT_STOP_RELRES = 0, SVT_STOP_NOISY = 1 } svt_stop_rule;
+/* SVT_CONSTRAINT_EQUALITY: X = M on Omega in the limit (Algorithm 1).
+   SVT_CONSTRAINT_INEQUALITY: the matrix Dantzig selector of Section 3.3 for
+   completion, |X_ij - B_ij| <= E on Omega (eq. (3.8) with A = P_Omega),
+   by the iteration of eq. (3.10): two nonnegative multipliers Y+ and Y- on
+   Omega, X^k = D_tau(Y+ - Y-), Y+- = [Y+- + delta P_Omega(+-(B - X^k) - E)]_+.
+   Its stop test is the relative violation ||[|P_Omega(X - B)| - E]_+||_F /
+   ||P_Omega B||_F <= eps (eq. (5.5) when E = 0), or with SVT_STOP_NOISY the
+   data-consistency test of eq. (5.10) on ||P_Omega(X - B)||_F^2; the
+   recorded residual is the relative violation either way.  Its kick is eq. (5.3)
+   with S_E(B) = sign(B) max(|B| - E, 0) in place of M (while X = 0 the
+   multipliers grow as k delta max(+-B - E, 0)). */
+typedef enum { SVT_CONSTRAINT_EQUALITY = 0, SVT_CONSTRAINT_INEQUALITY = 1 } svt_constraint;
 
 /*
  * Solver parameters.  svt_params_default() fills the paper's choices:
@@ -92,6 +104,10 @@ typedef struct {
                             whole (up to 8 of >= 1024 entries; otherwise it
                             is gathered from memory); 1 always gather        */
   void *stream;          /* hipStream_t to run on; NULL = library-owned stream */
+  double ineq_tol;       /* E of SVT_CONSTRAINT_INEQUALITY (one tolerance for
+                            every observed entry), >= 0                        */
+  int32_t constraint;    /* svt_constraint; default SVT_CONSTRAINT_EQUALITY   */
+  int32_t reserved;      /* set to 0                                          */
 } svt_params;
 
 typedef struct {
@@ -187,6 +203,13 @@ const char *svt_last_error(const svt_problem *h);
 svt_status svt_set_iterate(svt_problem *h, const double *y);
 svt_status svt_get_iterate(const svt_problem *h, int32_t which, double *y);
 
+/* SVT_CONSTRAINT_INEQUALITY handles: set / read the multipliers Y+ and Y-
+   of eq. (3.10), in the order of the triplets passed to svt_create (setting
+   them also sets the iterate Y = Y+ - Y-).  EINVAL for a negative or
+   non-finite value, ESTATE for an equality-constrained handle. */
+svt_status svt_set_multipliers(svt_problem *h, const double *yp, const double *ym);
+svt_status svt_get_multipliers(const svt_problem *h, double *yp, double *ym);
+
 /* out = Y x (trans = 0; x has n entries, out m) or Y^T x (trans = 1): the
    sparse products that drive the bidiagonalisation (Section 2.2). */
 svt_status svt_apply(svt_problem *h, int32_t trans, const double *x, double *out);
@@ -200,7 +223,10 @@ svt_status svt_partial_svd(svt_problem *h, int32_t count, double *sigma,
 
 /* One fused pass of Algorithm 1's last two lines on the current Y with a
    caller-given X = U V^T (U m x r, V n x r, row-major): returns
-   ||P_Omega(M - X)||_F^2 in *res2 and applies Y += delta P_Omega(M - X). */
+   ||P_Omega(M - X)||_F^2 in *res2 and applies Y += delta P_Omega(M - X).
+   On an SVT_CONSTRAINT_INEQUALITY handle, the multiplier update of
+   eq. (3.10) instead (Y+- = [Y+- + delta (+-(B - X) - E)]_+, Y = Y+ - Y-),
+   returning the squared violation ||[|P_Omega(X - B)| - E]_+||_F^2. */
 svt_status svt_sample_update(svt_problem *h, int32_t r, const double *U,
                              const double *V, double delta, double *res2);
 

@@ -159,10 +159,22 @@ hipError_t launch_ritz(hipStream_t s, const T *Q, int64_t ldq, int nrows, int k,
 // rs: row stride of both factors, a multiple of 16 / sizeof(T) (>= r), rows
 // zero padded.  With part_out non-null, workgroup b writes its sum of e^2 to
 // part_out[b] (sample_blocks() workgroups).
+// With Yp and Ym (the Dantzig selector's multipliers, same order as Y): Yp[t]
+// = max(Yp[t] + delta (e - E), 0), Ym[t] = max(Ym[t] + delta (-e - E), 0),
+// Y[t] = Yp[t] - Ym[t], and the partials sum max(|e| - E, 0)^2 instead;
+// part2_out (may be null) then receives the partial sums of e^2.
+// hipErrorInvalidValue for a bad stride, one multiplier array without the
+// other, or E < 0.
 template <typename T>
 hipError_t launch_sample_update(hipStream_t s, int lanes, const int32_t *ptr, const int32_t *idx,
                                 const T *M, T *Y, int nrows, const T *Fu, const T *Fv, int r, int rs,
-                                bool row_side_is_u, double delta, double *part_out);
+                                bool row_side_is_u, double delta, double *part_out, T *Yp = nullptr,
+                                T *Ym = nullptr, double E = 0.0, double *part2_out = nullptr);
+
+// The Dantzig selector's start: Yp = a max(B - E, 0), Ym = a max(-B - E, 0),
+// Y = Yp - Ym; with Yp = Ym = null, Y = S_E(B) = sign(B) max(|B| - E, 0).
+template <typename T>
+hipError_t launch_ds_init(hipStream_t s, const T *B, int64_t n, double E, double a, T *Yp, T *Ym, T *Y);
 int sample_blocks(int nrows, int lanes);
 
 // Allocation-free sampled pass: a fixed device array of

@@ -1298,19 +1298,25 @@ __device__ __forceinline__ T sampled_dot(const T *__restrict__ urow, const T *__
 // RB == 0: any r, both factors read from memory.  rs: a multiple of
 // 16 / sizeof(T), rows zero padded (the gathered rows are read 16 bytes at a
 // time).
-template <typename T, int L, int RB>
+// DS (the Dantzig-selector iteration for |X - B| <= E on Omega, Section
+// 3.3): with d = B - x, the two nonnegative multipliers take
+// Y+ = max(Y+ + delta (d - E), 0) and Y- = max(Y- + delta (-d - E), 0), the
+// iterate is Y = Y+ - Y-, and the partial sums are of the squared
+// violation max(|d| - E, 0)^2; with part2_out the sums of d^2 go there too.
+template <typename T, int L, int RB, bool DS>
 __global__ __launch_bounds__(kBlock) void k_sample_update(
     const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx, const T *__restrict__ M,
     T *__restrict__ Y, int nrows, int rows_per_blk,
     const T *__restrict__ Fu, const T *__restrict__ Fv, int r, int rs, int row_side_is_u, T delta,
-    double *__restrict__ part_out) {
+    double *__restrict__ part_out, T *__restrict__ Yp, T *__restrict__ Ym, T E, double *__restrict__ part2_out) {
   __shared__ double sbuf[kWaves];
   const int r0 = blockIdx.x * rows_per_blk;
   const int r1 = min(nrows, r0 + rows_per_blk);
   const int lane = threadIdx.x % L, grp = threadIdx.x / L;
   constexpr int kGroups = kBlock / L;
   const T *other = row_side_is_u ? Fv : Fu;
-  T sum = (T)0, comp = (T)0;  // compensated sum of e^2
+  T sum = (T)0, comp = (T)0;    // compensated sum of e^2 (DS: of the violation^2)
+  T sum2 = (T)0, comp2 = (T)0;  // DS: compensated sum of e^2
   for (int row = r0 + grp; row < r1; row += kGroups) {
     const int beg = ptr[row], end = ptr[row + 1];
     const T *fixed = (row_side_is_u ? Fu : Fv) + (size_t)row * rs;
@@ -1325,14 +1331,19 @@ __global__ __launch_bounds__(kBlock) void k_sample_update(
     constexpr int kBatch = (RB > 0 && RB <= 16) ? 4 : ((RB > 0 && RB <= 32) ? 2 : 1);
     for (int t0 = beg + lane; t0 < end; t0 += kBatch * L) {
       int jj[kBatch];
-      T mv[kBatch], yv[kBatch];
+      T mv[kBatch], yv[kBatch], ymv[kBatch];
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
         const int t = t0 + q * L;
         const bool in = t < end;
         jj[q] = in ? idx[t] : 0;
         mv[q] = in ? M[t] : (T)0;
-        yv[q] = in ? Y[t] : (T)0;
+        if constexpr (DS) {
+          yv[q] = in ? Yp[t] : (T)0;
+          ymv[q] = in ? Ym[t] : (T)0;
+        } else {
+          yv[q] = in ? Y[t] : (T)0;
+        }
       }
       T x[kBatch];
       if constexpr (RB > 0) {
@@ -1374,11 +1385,27 @@ __global__ __launch_bounds__(kBlock) void k_sample_update(
         const int t = t0 + q * L;
         if (t < end) {
           const T e = mv[q] - x[q];
-          Y[t] = fma(delta, e, yv[q]);
-          const T yk = fma(e, e, -comp);
+          T g = e;  // the term whose square is summed
+          if constexpr (DS) {
+            const T yp2 = fmax(fma(delta, e - E, yv[q]), (T)0);
+            const T ym2 = fmax(fma(delta, -e - E, ymv[q]), (T)0);
+            Yp[t] = yp2;
+            Ym[t] = ym2;
+            Y[t] = yp2 - ym2;
+            g = fmax(fabs(e) - E, (T)0);
+          } else {
+            Y[t] = fma(delta, e, yv[q]);
+          }
+          const T yk = fma(g, g, -comp);
           const T tk = sum + yk;
           comp = (tk - sum) - yk;
           sum = tk;
+          if constexpr (DS) {
+            const T y2 = fma(e, e, -comp2);
+            const T t2 = sum2 + y2;
+            comp2 = (t2 - sum2) - y2;
+            sum2 = t2;
+          }
         }
       }
     }
@@ -1386,6 +1413,13 @@ __global__ __launch_bounds__(kBlock) void k_sample_update(
   if (part_out == nullptr) return;  // uniform: no residual wanted
   const double tot = block_sum((double)sum - (double)comp, sbuf);
   if (threadIdx.x == 0) part_out[blockIdx.x] = tot;
+  if constexpr (DS) {
+    if (part2_out != nullptr) {
+      __syncthreads();  // sbuf is reused
+      const double tot2 = block_sum((double)sum2 - (double)comp2, sbuf);
+      if (threadIdx.x == 0) part2_out[blockIdx.x] = tot2;
+    }
+  }
 }
 
 template <typename T>
@@ -1705,16 +1739,15 @@ int sample_blocks(int nrows, int lanes) {
       .nblk;
 }
 
-template <typename T>
-hipError_t launch_sample_update(hipStream_t s, int lanes, const int32_t *ptr, const int32_t *idx,
-                                const T *M, T *Y, int nrows, const T *Fu, const T *Fv, int r, int rs,
-                                bool row_side_is_u, double delta, double *part_out) {
-  if (rs % (16 / (int)sizeof(T)) != 0 || rs < r) return hipErrorInvalidValue;
+template <typename T, bool DS>
+static void sample_update_variant(hipStream_t s, int lanes, const int32_t *ptr, const int32_t *idx, const T *M,
+                                  T *Y, int nrows, const T *Fu, const T *Fv, int r, int rs, bool row_side_is_u,
+                                  double delta, double *part_out, T *Yp, T *Ym, double E, double *part2_out) {
   const RowChunks ch =
       row_chunks(nrows, std::max((kBlock / lanes) * 4, (nrows + kSampleMaxBlocks - 1) / kSampleMaxBlocks));
-#define SVT_SU2(LN, RB)                                                                          \
-  SVT_LAUNCH((k_sample_update<T, LN, RB>), dim3(ch.nblk), dim3(kBlock), 0, s, ptr, idx, M, Y, nrows, \
-             ch.rows_per_blk, Fu, Fv, r, rs, row_side_is_u ? 1 : 0, (T)delta, part_out)
+#define SVT_SU2(LN, RB)                                                                              \
+  SVT_LAUNCH((k_sample_update<T, LN, RB, DS>), dim3(ch.nblk), dim3(kBlock), 0, s, ptr, idx, M, Y, nrows, \
+             ch.rows_per_blk, Fu, Fv, r, rs, row_side_is_u ? 1 : 0, (T)delta, part_out, Yp, Ym, (T)E, part2_out)
 #define SVT_SU(LN)                         \
   do {                                     \
     if (r <= 8) SVT_SU2(LN, 8);            \
@@ -1732,6 +1765,46 @@ hipError_t launch_sample_update(hipStream_t s, int lanes, const int32_t *ptr, co
   }
 #undef SVT_SU
 #undef SVT_SU2
+}
+
+template <typename T>
+hipError_t launch_sample_update(hipStream_t s, int lanes, const int32_t *ptr, const int32_t *idx,
+                                const T *M, T *Y, int nrows, const T *Fu, const T *Fv, int r, int rs,
+                                bool row_side_is_u, double delta, double *part_out, T *Yp, T *Ym, double E,
+                                double *part2_out) {
+  if (rs % (16 / (int)sizeof(T)) != 0 || rs < r) return hipErrorInvalidValue;
+  if ((Yp == nullptr) != (Ym == nullptr) || !(E >= 0.0)) return hipErrorInvalidValue;
+  if (Yp) sample_update_variant<T, true>(s, lanes, ptr, idx, M, Y, nrows, Fu, Fv, r, rs, row_side_is_u, delta,
+                                         part_out, Yp, Ym, E, part2_out);
+  else sample_update_variant<T, false>(s, lanes, ptr, idx, M, Y, nrows, Fu, Fv, r, rs, row_side_is_u, delta,
+                                       part_out, nullptr, nullptr, 0.0, nullptr);
+  return hipGetLastError();
+}
+
+// The Dantzig-selector kick: Y+ = a max(B - E, 0), Y- = a max(-B - E, 0),
+// Y = Y+ - Y- (= a S_E(B)); with Yp null only Y = S_E(B) (a ignored).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ds_init(const T *__restrict__ B, int64_t n, double E, double a,
+                                                    T *__restrict__ Yp, T *__restrict__ Ym, T *__restrict__ Y) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    const double b = (double)B[i];
+    const double p = fmax(b - E, 0.0), q = fmax(-b - E, 0.0);
+    if (Yp) {
+      const T yp = (T)(a * p), ym = (T)(a * q);
+      Yp[i] = yp;
+      Ym[i] = ym;
+      Y[i] = yp - ym;
+    } else {
+      Y[i] = (T)(p - q);
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_ds_init(hipStream_t s, const T *B, int64_t n, double E, double a, T *Yp, T *Ym, T *Y) {
+  if (n <= 0) return hipSuccess;
+  if ((Yp == nullptr) != (Ym == nullptr) || !(E >= 0.0)) return hipErrorInvalidValue;
+  SVT_LAUNCH((k_ds_init<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, B, n, E, a, Yp, Ym, Y);
   return hipGetLastError();
 }
 
@@ -1776,7 +1849,8 @@ hipError_t launch_gather(hipStream_t s, const T *x, const int32_t *map, T *y, in
                                      const double *, int, T *, int);                                \
   template hipError_t launch_sample_update<T>(hipStream_t, int, const int32_t *, const int32_t *,  \
                                               const T *, T *, int, const T *, const T *, int, int,  \
-                                              bool, double, double *);                              \
+                                              bool, double, double *, T *, T *, double, double *);  \
+  template hipError_t launch_ds_init<T>(hipStream_t, const T *, int64_t, double, double, T *, T *, T *); \
   template hipError_t launch_axpby<T>(hipStream_t, const T *, T *, int64_t, double);               \
   template hipError_t launch_gather<T>(hipStream_t, const T *, const int32_t *, T *, int64_t);
 

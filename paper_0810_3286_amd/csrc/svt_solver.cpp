@@ -256,6 +256,9 @@ struct ProblemBase {
   virtual void factors(int32_t *rank, double *U, double *w, double *V) const = 0;
   virtual void set_iterate(const double *y) = 0;
   virtual void get_iterate(int which, double *y) const = 0;
+  virtual void set_multipliers(const double *yp, const double *ym) = 0;
+  virtual void get_multipliers(double *yp, double *ym) const = 0;
+  bool ds_soft_nonzero = false;  // some |B_ij| > E (the Dantzig selector's kick exists)
   virtual void apply(int trans, const double *x, double *out) = 0;
   virtual int partial_svd(int count, double *sigma, double *U, double *V) = 0;
   virtual double sample_update(int r, const double *U, const double *V, double delta) = 0;
@@ -286,6 +289,7 @@ struct Problem final : ProblemBase {
   DevMem seg_r, seg_c;                // their segment starts (when nseg > 1)
   DevMem colidx16, rowidx16;          // 16-bit copies of colidx / rowidx (n, m <= 65536)
   DevMem Mr, Mc, Yr, Yc;          // values, T
+  DevMem Yp, Ym;                  // Dantzig selector: the two multipliers (row order), T
   DevMem Ub, Vb;                  // bases, T, column-major
   int kcap = 0;                   // columns available in Ub (Vb has kcap + 1)
   DevMem pbuf_u, pbuf_v;          // unnormalised new vectors of each side, T
@@ -319,6 +323,10 @@ struct Problem final : ProblemBase {
   int prereduce_min = 64;
   int passes_now = 2;          // Gram-Schmidt passes per vector right now
   int64_t reorth_restarts = 0; // bidiagonalisations restarted with two passes
+
+  // the Dantzig-selector iteration (Section 3.3) instead of Algorithm 1's
+  // equality-constrained one
+  bool ds() const { return prm.constraint == SVT_CONSTRAINT_INEQUALITY; }
 
   // ----------------------------------------------------------------- setup
   void setup(const svt_params &p) {
@@ -399,9 +407,17 @@ struct Problem final : ProblemBase {
     upload_values(ix.vals_csr.data(), Mr.as<T>(), Mc.as<T>());
     HIP_CHECK(hipMemsetAsync(Yr.p, 0, sizeof(T) * nnz, stream));
     HIP_CHECK(hipMemsetAsync(Yc.p, 0, sizeof(T) * nnz, stream));
+    if (ds()) {
+      Yp.alloc(sizeof(T) * nnz);
+      Ym.alloc(sizeof(T) * nnz);
+      HIP_CHECK(hipMemsetAsync(Yp.p, 0, sizeof(T) * nnz, stream));
+      HIP_CHECK(hipMemsetAsync(Ym.p, 0, sizeof(T) * nnz, stream));
+    }
 
-    sample_part.alloc(sizeof(double) * (kSampleMaxBlocks + 8));
-    sample_host.ensure(sizeof(double) * (kSampleMaxBlocks + 8));
+    // residual partials; the Dantzig selector's second sum (of the plain
+    // residual) in the upper half
+    sample_part.alloc(sizeof(double) * 2 * (kSampleMaxBlocks + 8));
+    sample_host.ensure(sizeof(double) * 2 * (kSampleMaxBlocks + 8));
     // the allocation-free pass's scratch address on this device (looked up
     // once per device, with the device current)
     HIP_CHECK(noalloc_scratch(device, &noalloc_part));
@@ -509,7 +525,7 @@ struct Problem final : ProblemBase {
   // are both live.
   size_t device_bytes() const {
     const DevMem *all[] = {&rowptr, &colidx, &colptr, &rowidx, &csr_of_csc, &seg_r, &seg_c, &colidx16, &rowidx16,
-                           &Mr, &Mc, &Yr, &Yc, &Ub, &Vb, &pbuf_u, &pbuf_v, &coef, &gs1, &gs2, &gs3, &gsr,
+                           &Mr, &Mc, &Yr, &Yc, &Yp, &Ym, &Ub, &Vb, &pbuf_u, &pbuf_v, &coef, &gs1, &gs2, &gs3, &gsr,
                            &sample_part, &ritzd, &Fu, &Fv};
     size_t b = 0;
     for (const DevMem *d : all) b += d->bytes;
@@ -952,13 +968,19 @@ struct Problem final : ProblemBase {
   // row-compressed order, then the column copy gathered from it through
   // csr_of_csc; returns residual^2 (workgroup partials added on the host in
   // order, compensated).
-  double sample_pass(int r, double delta, bool want_res) {
-    return sample_pass_on(Fu.as<T>(), Fv.as<T>(), fstride, r, delta, want_res ? sample_part.as<double>() : nullptr);
+  // Dantzig selector: the violation^2 is returned and ||P_Omega(X - B)||^2
+  // goes to *plain2 (when not null).
+  double sample_pass(int r, double delta, bool want_res, double *plain2 = nullptr) {
+    double *part2 = (want_res && ds()) ? sample_part.as<double>() + kSampleMaxBlocks + 8 : nullptr;
+    return sample_pass_on(Fu.as<T>(), Fv.as<T>(), fstride, r, delta, want_res ? sample_part.as<double>() : nullptr,
+                          part2, plain2);
   }
 
-  // The same pass with the factors (row stride rs) and the partials' buffer
-  // given; part null: no residual.
-  double sample_pass_on(const T *fu, const T *fv, int rs, int r, double delta, double *part) {
+  // The same pass with the factors (row stride rs) and the partials' buffers
+  // given; part null: no residual; part2 (Dantzig selector, may be null):
+  // the partials of ||P_Omega(X - B)||^2, summed into *plain2.
+  double sample_pass_on(const T *fu, const T *fv, int rs, int r, double delta, double *part,
+                        double *part2 = nullptr, double *plain2 = nullptr) {
     const bool want_res = part != nullptr;
     const double vb = sizeof(T);
     // algorithmic bytes of the sampled pass: index, M and Y read, Y written,
@@ -966,7 +988,9 @@ struct Problem final : ProblemBase {
     const double pass_bytes = (double)ix.nnz * (4.0 + 3.0 * vb) + vb * (double)(ix.m + ix.n) * r;
     prof.begin();
     HIP_CHECK(launch_sample_update<T>(stream, lanes_r, rowptr.as<int32_t>(), colidx.as<int32_t>(), Mr.as<T>(),
-                                      Yr.as<T>(), (int)ix.m, fu, fv, r, rs, true, delta, part));
+                                      Yr.as<T>(), (int)ix.m, fu, fv, r, rs, true, delta, part,
+                                      ds() ? Yp.as<T>() : nullptr, ds() ? Ym.as<T>() : nullptr,
+                                      ds() ? prm.ineq_tol : 0.0, part2));
     prof.end(kSample, pass_bytes + 4.0 * (ix.m + 1));
     // the column copy: the map read, one value gathered and one written per entry
     prof.begin();
@@ -975,19 +999,27 @@ struct Problem final : ProblemBase {
     if (!want_res) return 0.0;
     const int nb = sample_blocks((int)ix.m, lanes_r);
     HIP_CHECK(hipMemcpyAsync(sample_host.p, part, sizeof(double) * nb, hipMemcpyDeviceToHost, stream));
+    if (part2)
+      HIP_CHECK(hipMemcpyAsync(sample_host.as<double>() + kSampleMaxBlocks + 8, part2, sizeof(double) * nb,
+                               hipMemcpyDeviceToHost, stream));
     HIP_CHECK(hipStreamSynchronize(stream));
-    double sum = 0.0, comp = 0.0;
-    for (int b = 0; b < nb; ++b) {
-      const double y = sample_host.as<double>()[b] - comp;
-      const double t = sum + y;
-      comp = (t - sum) - y;
-      sum = t;
-    }
-    return sum;
+    auto total = [&](const double *v) {
+      double sum = 0.0, comp = 0.0;
+      for (int b = 0; b < nb; ++b) {
+        const double y = v[b] - comp;
+        const double t = sum + y;
+        comp = (t - sum) - y;
+        sum = t;
+      }
+      return sum;
+    };
+    if (part2 && plain2) *plain2 = total(sample_host.as<double>() + kSampleMaxBlocks + 8);
+    return total(sample_host.as<double>());
   }
 
   // --------------------------------------------------------------- kick (a2)
   void do_kick(double *sigma1, int32_t *k0_out) {
+    if (ds()) return do_kick_ds(sigma1, k0_out);
     Gkl g;
     BidiagSVD sv;
     int r = 0;
@@ -1004,6 +1036,40 @@ struct Problem final : ProblemBase {
     const double a = (double)k0 * prm.delta;
     HIP_CHECK(launch_axpby<T>(stream, Mr.as<T>(), Yr.as<T>(), ix.nnz, a));
     HIP_CHECK(launch_axpby<T>(stream, Mc.as<T>(), Yc.as<T>(), ix.nnz, a));
+    HIP_CHECK(hipStreamSynchronize(stream));
+    *sigma1 = s1;
+    *k0_out = k0;
+  }
+
+  // The Dantzig selector's kick.  While X = 0 the multipliers grow
+  // linearly, Y+ = k delta max(B - E, 0) and Y- = k delta max(-B - E, 0), so
+  // Y = k delta S_E(B); X stays 0 up to k0 = ceil(tau / (delta ||S_E(P_Omega
+  // B)||_2)) (eq. (5.3) with S_E(B) in place of M).  With S_E(B) = 0 X = 0 is
+  // feasible: k0 = 0 and the iteration starts from zero multipliers.
+  void do_kick_ds(double *sigma1, int32_t *k0_out) {
+    const double E = prm.ineq_tol;
+    *sigma1 = 0.0;
+    *k0_out = 0;
+    if (!ds_soft_nonzero) return;
+    // S_E(B) in both copies of Y, then its largest singular value
+    HIP_CHECK(launch_ds_init<T>(stream, Mr.as<T>(), ix.nnz, E, 0.0, nullptr, nullptr, Yr.as<T>()));
+    HIP_CHECK(launch_gather<T>(stream, Yr.as<T>(), csr_of_csc.as<int32_t>(), Yc.as<T>(), ix.nnz));
+    Gkl g;
+    BidiagSVD sv;
+    int r = 0;
+    const int saved_hint = k_hint;
+    k_hint = 0;
+    const T *yr = a_is_y ? Yr.as<T>() : Yc.as<T>();
+    const T *yc = a_is_y ? Yc.as<T>() : Yr.as<T>();
+    gkl_run(yr, yc, 1, 1, 0.0, g, sv, r);
+    k_hint = saved_hint;
+    const double s1 = sv.sigma.empty() ? 0.0 : sv.sigma[0];
+    if (!(s1 > 0.0)) return;
+    const int32_t k0 = prm.k0_override > 0 ? prm.k0_override
+                                           : (int32_t)std::max(1.0, std::ceil(prm.tau / (prm.delta * s1)));
+    const double a = (double)k0 * prm.delta;
+    HIP_CHECK(launch_ds_init<T>(stream, Mr.as<T>(), ix.nnz, E, a, Yp.as<T>(), Ym.as<T>(), Yr.as<T>()));
+    HIP_CHECK(launch_gather<T>(stream, Yr.as<T>(), csr_of_csc.as<int32_t>(), Yc.as<T>(), ix.nnz));
     HIP_CHECK(hipStreamSynchronize(stream));
     *sigma1 = s1;
     *k0_out = k0;
@@ -1050,6 +1116,10 @@ struct Problem final : ProblemBase {
       int32_t k0 = 0;
       HIP_CHECK(hipMemsetAsync(Yr.p, 0, sizeof(T) * ix.nnz, stream));
       HIP_CHECK(hipMemsetAsync(Yc.p, 0, sizeof(T) * ix.nnz, stream));
+      if (ds()) {
+        HIP_CHECK(hipMemsetAsync(Yp.p, 0, sizeof(T) * ix.nnz, stream));
+        HIP_CHECK(hipMemsetAsync(Ym.p, 0, sizeof(T) * ix.nnz, stream));
+      }
       if (prm.kick) do_kick(&s1, &k0);
       HIP_CHECK(hipStreamSynchronize(stream));
       t1 = now_s();
@@ -1070,7 +1140,8 @@ struct Problem final : ProblemBase {
         for (int i = 0; i < r; ++i) ws[i] = sv.sigma[i] - prm.tau;
         form_factors(g, sv, r, ws.data());
         w.assign(ws.begin(), ws.begin() + r);
-        const double res2 = sample_pass(r, prm.delta, true);
+        double plain2 = 0.0;  // Dantzig selector: ||P_Omega(X - B)||^2 beside the violation
+        const double res2 = sample_pass(r, prm.delta, true, &plain2);
         res = std::sqrt(res2) / norm_pm;
         history.push_back({r, s, steps, res});
         if (log_level > 0)
@@ -1078,7 +1149,7 @@ struct Problem final : ProblemBase {
         if (!std::isfinite(res)) { st = SVT_EDIVERGED; break; }
         bool stop;
         if (prm.stop_rule == SVT_STOP_NOISY)
-          stop = res2 <= (1.0 + prm.eps) * (double)ix.nnz * prm.noise_sigma * prm.noise_sigma;
+          stop = (ds() ? plain2 : res2) <= (1.0 + prm.eps) * (double)ix.nnz * prm.noise_sigma * prm.noise_sigma;
         else
           stop = res <= prm.eps;
         if (stop) { st = SVT_OK; break; }
@@ -1118,6 +1189,39 @@ struct Problem final : ProblemBase {
     std::vector<double> csr((size_t)ix.nnz);
     for (int64_t t = 0; t < ix.nnz; ++t) csr[(size_t)ix.csr_of_input[(size_t)t]] = y[t];
     upload_values(csr.data(), Yr.as<T>(), Yc.as<T>());
+  }
+
+  // Dantzig selector: Y+ and Y- given in the order of the input triplets;
+  // the iterate becomes Y = Y+ - Y- (both compressed copies).
+  void set_multipliers(const double *yp, const double *ym) override {
+    if (!ds()) throw Error(SVT_ESTATE, "the handle does not run the Dantzig-selector iteration");
+    const int64_t nnz = ix.nnz;
+    std::vector<T> hp((size_t)nnz), hm((size_t)nnz), hy((size_t)nnz);
+    for (int64_t t = 0; t < nnz; ++t) {
+      const size_t c = (size_t)ix.csr_of_input[(size_t)t];
+      hp[c] = (T)yp[t];
+      hm[c] = (T)ym[t];
+      hy[c] = hp[c] - hm[c];
+    }
+    HIP_CHECK(hipMemcpyAsync(Yp.p, hp.data(), sizeof(T) * nnz, hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(Ym.p, hm.data(), sizeof(T) * nnz, hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(Yr.p, hy.data(), sizeof(T) * nnz, hipMemcpyHostToDevice, stream));
+    HIP_CHECK(launch_gather<T>(stream, Yr.as<T>(), csr_of_csc.as<int32_t>(), Yc.as<T>(), nnz));
+    HIP_CHECK(hipStreamSynchronize(stream));
+  }
+
+  void get_multipliers(double *yp, double *ym) const override {
+    if (!ds()) throw Error(SVT_ESTATE, "the handle does not run the Dantzig-selector iteration");
+    const int64_t nnz = ix.nnz;
+    std::vector<T> hp((size_t)nnz), hm((size_t)nnz);
+    HIP_CHECK(hipMemcpyAsync(hp.data(), Yp.p, sizeof(T) * nnz, hipMemcpyDeviceToHost, stream));
+    HIP_CHECK(hipMemcpyAsync(hm.data(), Ym.p, sizeof(T) * nnz, hipMemcpyDeviceToHost, stream));
+    HIP_CHECK(hipStreamSynchronize(stream));
+    for (int64_t t = 0; t < nnz; ++t) {
+      const size_t c = (size_t)ix.csr_of_input[(size_t)t];
+      if (yp) yp[t] = (double)hp[c];
+      if (ym) ym[t] = (double)hm[c];
+    }
   }
 
   void get_iterate(int which, double *y) const override {
@@ -1233,6 +1337,10 @@ static void validate_params(const svt_params &p) {
   if (p.stop_rule != SVT_STOP_RELRES && p.stop_rule != SVT_STOP_NOISY) throw Error(SVT_EINVAL, "unknown stop rule");
   if (!finite(p.noise_sigma) || p.noise_sigma < 0) throw Error(SVT_EINVAL, "noise_sigma must be finite and >= 0");
   if (p.stop_rule == SVT_STOP_NOISY && p.noise_sigma <= 0) throw Error(SVT_EINVAL, "the noisy stop rule needs noise_sigma > 0");
+  if (p.constraint != SVT_CONSTRAINT_EQUALITY && p.constraint != SVT_CONSTRAINT_INEQUALITY)
+    throw Error(SVT_EINVAL, "unknown constraint kind");
+  if (!finite(p.ineq_tol) || p.ineq_tol < 0) throw Error(SVT_EINVAL, "ineq_tol must be finite and >= 0");
+
   if (!finite(p.lanczos_tol) || p.lanczos_tol < 0 || p.lanczos_tol >= 1) throw Error(SVT_EINVAL, "lanczos_tol must be in [0, 1)");
   if (p.lanczos_maxsteps < 0) throw Error(SVT_EINVAL, "lanczos_maxsteps must be >= 0");
   if (p.reorth_passes < 0 || p.reorth_passes > 2) throw Error(SVT_EINVAL, "reorth_passes must be 0, 1 or 2");
@@ -1284,6 +1392,8 @@ svt_status svt_params_default(int64_t m, int64_t n, int64_t nnz, svt_params *out
   out->k0_override = 0;
   out->precision = SVT_FP64;
   out->stop_rule = SVT_STOP_RELRES;
+  out->constraint = SVT_CONSTRAINT_EQUALITY;
+  out->ineq_tol = 0.0;
   out->noise_sigma = 0.0;
   out->lanczos_tol = 0.0;  // auto: 1e-12 (FP64) or 1e-6 (MIXED)
   out->lanczos_maxsteps = 0;
@@ -1354,6 +1464,8 @@ svt_status svt_create(int64_t m, int64_t n, int64_t nnz, int32_t fmt, const void
       }
       impl->norm_pm = std::sqrt(s);
     }
+    for (int64_t t = 0; t < nnz && !impl->ds_soft_nonzero; ++t)
+      impl->ds_soft_nonzero = std::fabs(vals[t]) > prm.ineq_tol;
     if (prm.precision == SVT_MIXED) static_cast<svt::Problem<float> *>(impl.get())->setup(prm);
     else static_cast<svt::Problem<double> *>(impl.get())->setup(prm);
     impl->t_setup = svt::now_s() - t0;
@@ -1450,6 +1562,25 @@ svt_status svt_set_iterate(svt_problem *h, const double *y) {
     for (int64_t t = 0; t < h->impl->ix.nnz; ++t)
       if (!std::isfinite(y[t])) throw Error(SVT_EINVAL, "non-finite iterate value");
     h->impl->set_iterate(y);
+    return SVT_OK;
+  });
+}
+
+svt_status svt_set_multipliers(svt_problem *h, const double *yp, const double *ym) {
+  if (!h || !h->impl || !yp || !ym) return SVT_EINVAL;
+  return guarded(h, [&] {
+    for (int64_t t = 0; t < h->impl->ix.nnz; ++t)
+      if (!std::isfinite(yp[t]) || !std::isfinite(ym[t]) || yp[t] < 0 || ym[t] < 0)
+        throw Error(SVT_EINVAL, "multipliers must be finite and >= 0");
+    h->impl->set_multipliers(yp, ym);
+    return SVT_OK;
+  });
+}
+
+svt_status svt_get_multipliers(const svt_problem *h, double *yp, double *ym) {
+  if (!h || !h->impl) return SVT_EINVAL;
+  return guarded(h, [&] {
+    h->impl->get_multipliers(yp, ym);
     return SVT_OK;
   });
 }

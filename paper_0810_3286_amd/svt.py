@@ -30,6 +30,8 @@ SVT_COO = 0
 SVT_CSR = 1
 SVT_STOP_RELRES = 0
 SVT_STOP_NOISY = 1
+SVT_CONSTRAINT_EQUALITY = 0
+SVT_CONSTRAINT_INEQUALITY = 1
 
 KERNEL_KINDS = {0: "k_spmv", 1: "k_gather", 2: "k_gs_update_pass1", 3: "k_ritz", 4: "k_sample_update",
                 5: "k_gs_update_pass2", 6: "k_pending_reduce"}
@@ -55,6 +57,9 @@ class svt_params(ctypes.Structure):
         ("profile", ctypes.c_int32),
         ("spmv_mode", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
+        ("ineq_tol", ctypes.c_double),
+        ("constraint", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -107,6 +112,8 @@ def _signatures(lib):
         "svt_last_error": (ctypes.c_char_p, [h]),
         "svt_set_iterate": (ctypes.c_int32, [h, _dp]),
         "svt_get_iterate": (ctypes.c_int32, [h, ctypes.c_int32, _dp]),
+        "svt_set_multipliers": (ctypes.c_int32, [h, _dp, _dp]),
+        "svt_get_multipliers": (ctypes.c_int32, [h, _dp, _dp]),
         "svt_apply": (ctypes.c_int32, [h, ctypes.c_int32, _dp, _dp]),
         "svt_partial_svd": (ctypes.c_int32, [h, ctypes.c_int32, _dp, _dp, _dp, _ip]),
         "svt_sample_update": (ctypes.c_int32, [h, ctypes.c_int32, _dp, _dp, ctypes.c_double, _dp]),
@@ -264,6 +271,19 @@ def svt_get_iterate(h, nnz: int, which: int = 0):
     y = np.zeros(nnz)
     _check(load().svt_get_iterate(h, which, _p(y)), h)
     return y
+
+
+def svt_set_multipliers(h, yp, ym):
+    yp = _f64(yp)
+    ym = _f64(ym, yp.shape[0])
+    _check(load().svt_set_multipliers(h, _p(yp), _p(ym)), h)
+
+
+def svt_get_multipliers(h, nnz: int):
+    yp = np.zeros(nnz)
+    ym = np.zeros(nnz)
+    _check(load().svt_get_multipliers(h, _p(yp), _p(ym)), h)
+    return yp, ym
 
 
 def svt_apply(h, x, out_len: int, trans: int = 0):

@@ -10,6 +10,7 @@ compare against the stored files.  Run from the repository root:
     python tests/golden/make_oracle_goldens.py 3 C    # the same, complete run: tier C (library partial SVD)
     python tests/golden/make_oracle_goldens.py 4 C    # 30000 x 30000, rank 10: tier C, complete run,
                                                       # plus X at iterations 20 and 60
+    python tests/golden/make_oracle_goldens.py dantzig  # Figure 3's workload, the Dantzig selector
 
 With a second argument k the run stops after k iterations with eps = 0, and
 the file holds X^k: a fixed-iteration comparison point for trajectories
@@ -46,6 +47,25 @@ def _save(path, U, w, V, iters, k0, sigma1, ranks, s_hist, residuals, seconds, t
                         ranks=np.array(ranks), s_hist=np.array(s_hist),
                         residuals=np.array(residuals), seconds=seconds, tier=tier, **extra)
     print(f"wrote {path}: tier {tier}, {iters} iterations, k0 {k0}", flush=True)
+
+
+# the Dantzig-selector run of Figure 3's workload: half the paper's step
+# (with delta = 1.2 / p the two-multiplier iteration oscillates there) and
+# the eq. (5.10) consistency stop
+DANTZIG_STEP_SCALE = 0.5
+
+
+def dantzig():
+    from oracle.dantzig import svt_dantzig
+    p = workload.dantzig_fig3(seed=0)
+    t = time.time()
+    out = svt_dantzig(p.m, p.n, p.rows, p.cols, p.vals, p.noise_sigma, p.tau, DANTZIG_STEP_SCALE * p.delta,
+                      p.eps, p.maxiter, p.incr, partial="sparse", stop="noisy", noise_sigma=p.noise_sigma,
+                      progress=lambda k, r, res: print(f"  iteration {k}: rank {r}, violation {res:.3e}",
+                                                       flush=True))
+    _save(os.path.join(HERE, "oracle_dantzig_fig3.npz"), out["U"], out["w"], out["V"], out["iters"], out["k0"],
+          out["sigma1"], out["ranks"], out["s_hist"], out["residuals"], time.time() - t, "C",
+          delta=DANTZIG_STEP_SCALE * p.delta, E=p.noise_sigma, status=out["status"])
 
 
 def main(cfg: int, arg: str = "0"):
@@ -99,4 +119,7 @@ def main(cfg: int, arg: str = "0"):
 
 
 if __name__ == "__main__":
-    main(int(sys.argv[1]) if len(sys.argv) > 1 else 1, sys.argv[2] if len(sys.argv) > 2 else "0")
+    if len(sys.argv) > 1 and sys.argv[1] == "dantzig":
+        dantzig()
+    else:
+        main(int(sys.argv[1]) if len(sys.argv) > 1 else 1, sys.argv[2] if len(sys.argv) > 2 else "0")

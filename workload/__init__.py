@@ -35,6 +35,7 @@ __all__ = [
     "TABLE1_RANK_OVERSAMPLING",
     "full_observation",
     "dense_random_iterate",
+    "dantzig_fig3",
 ]
 
 
@@ -170,6 +171,34 @@ def noisy_lowrank(n: int, r: int, c: float, noise_ratio: float, seed: int = 0, *
     p = Problem(m=n, n=n, r=r, rows=rows, cols=cols, vals=vals, ML=ML, MR=MR,
                 tau=5.0 * float(n), delta=1.2 * float(n) * float(n) / float(nnz), eps=float(eps),
                 maxiter=int(maxiter), incr=5, name=f"svt-noisy-{n}sq-r{r}-nr{noise_ratio:g}",
+                noise_sigma=float(sigma))
+    p.clean = clean
+    return p
+
+
+def dantzig_fig3(n: int = 1000, r: int = 10, c: float = 5.0, seed: int = 0, *,
+                 eps: float = 1e-4, maxiter: int = 500) -> Problem:
+    """The linear-inequality experiment of Section 5.2.2 (Figure 3): a
+    Gaussian rank-r n x n truth on a uniform random Omega of c d_r entries,
+    observed as B = M + Z with white Gaussian Z of standard deviation
+    sigma = 0.1 sum_{Omega} |M_ij| / |Omega| (one tenth of a typical observed
+    entry), tau = 5n, delta = 1.2 n^2 / |Omega|.  ``vals`` holds B,
+    ``clean`` holds P_Omega M, ``noise_sigma`` holds sigma (the tolerance E
+    of every constraint |X_ij - B_ij| <= E).  Draw order: M_L, M_R, Omega,
+    noise."""
+    nnz = int(round(c * degrees_of_freedom(n, n, r)))
+    rng = np.random.default_rng(seed)
+    ML = rng.standard_normal((n, r))
+    MR = rng.standard_normal((n, r))
+    lin = sample_omega(rng, n, n, nnz)
+    rows = (lin // n).astype(np.int32)
+    cols = (lin % n).astype(np.int32)
+    clean = _observed_values(ML, MR, rows, cols)
+    sigma = 0.1 * float(np.mean(np.abs(clean)))
+    vals = clean + sigma * rng.standard_normal(nnz)
+    p = Problem(m=n, n=n, r=r, rows=rows, cols=cols, vals=vals, ML=ML, MR=MR,
+                tau=5.0 * float(n), delta=1.2 * float(n) * float(n) / float(nnz), eps=float(eps),
+                maxiter=int(maxiter), incr=5, name=f"svt-dantzig-{n}sq-r{r}-{c:g}dr",
                 noise_sigma=float(sigma))
     p.clean = clean
     return p
