@@ -107,7 +107,11 @@ typedef struct {
   double ineq_tol;       /* E of SVT_CONSTRAINT_INEQUALITY (one tolerance for
                             every observed entry), >= 0                        */
   int32_t constraint;    /* svt_constraint; default SVT_CONSTRAINT_EQUALITY   */
-  int32_t reserved;      /* set to 0                                          */
+  int32_t warm_start;    /* 0: start from the kick (or Y = 0); 1: start from the
+                            handle's current iterate Y (and multipliers), e.g.
+                            the last solve's final Y or one set with
+                            svt_set_iterate: the warm start of Section 6's tau
+                            continuation; no kick is applied                 */
 } svt_params;
 
 typedef struct {
@@ -147,12 +151,43 @@ svt_status svt_create(int64_t m, int64_t n, int64_t nnz, int32_t fmt,
                       const void *idx0, const int32_t *idx1, const double *vals,
                       const svt_params *params, svt_problem **out);
 
+/*
+ * Create a problem with a general linear operator (Section 3.1): p
+ * measurements b = A(M) of an m x n matrix through its entries on a support
+ * S of ns distinct positions (srows[s], scols[s]; host int32, any order):
+ * b_i = sum_t gval[t] M[srows[gidx[t]], scols[gidx[t]]] over t in
+ * [gptr[i], gptr[i+1]) (CSR over the measurements: gptr int64[p+1], gidx
+ * int32 into S, gval double).  svt_solve then runs eq. (3.3):
+ * X^k = D_tau(A*(y^{k-1})), y^k = y^{k-1} + delta (b - A(X^k)), with the
+ * kick of eq. (5.3) taken with A*(b) in place of P_Omega M and the stop test
+ * ||b - A(X^k)|| / ||b|| <= eps; completion is the case gval = 1, one term
+ * per measurement.  The handle's "iterate" (svt_get_iterate) is A*(y) on S.
+ * params (may be NULL: defaults for p samples) must keep the equality
+ * constraint and the relative-residual stop.  Errors (EINVAL, checked
+ * before any device work): bad sizes, an index out of range, a repeated
+ * support position, gptr not starting at 0 or decreasing, non-finite
+ * weights or measurements, all measurements zero.
+ */
+svt_status svt_create_sensing(int64_t m, int64_t n, int64_t ns, const int32_t *srows, const int32_t *scols,
+                              int64_t p, const int64_t *gptr, const int32_t *gidx, const double *gval,
+                              const double *b, const svt_params *params, svt_problem **out);
+
 /* Run Algorithm 1 from the kick (each call starts over).  Returns SVT_OK,
    SVT_NOT_CONVERGED (maxiter reached; the factors hold X^{maxiter}), or an
    error; after an error raised inside the iteration (e.g. SVT_ELANCZOS when
    the bidiagonalisation reaches lanczos_maxsteps) info still reports the
    iterations completed and their last residual.  info may be NULL. */
 svt_status svt_solve(svt_problem *h, svt_info *info);
+
+/* tau continuation with warm starts (Section 6): Algorithm 1 for each of the
+   count values taus[0..count-1] (finite, > 0; normally increasing), the
+   first stage as the handle's warm_start says, every later one from the
+   previous stage's final iterate Y (the dual iterate is carried, so Y stays
+   supported on Omega).  infos (may be NULL) receives count records; the
+   handle's factors and history are the last stage's.  Returns the last
+   stage's status, or the first error (infos then holds the stages done).
+   The handle's tau is left as it was. */
+svt_status svt_solve_path(svt_problem *h, const double *taus, int32_t count, svt_info *infos);
 
 /* Per-iteration record of the last solve, k = 1..len: rank r_k, the number
    s_k of triplets Algorithm 1 computes (Section 5.1.1's rule for s_k), the

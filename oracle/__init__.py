@@ -13,6 +13,7 @@ Contents (each function cites the passage of the paper it writes out):
 * ``apply_sparse``     Y x and Y^T x for Y supported on Omega (Section 2.2)
 * ``sampled_entries``  X_ij = sum_l U_il V_jl on Omega
 * ``svt_dense``        Algorithm 1 (Section 5.1.5), tier A: dense Y, full SVD
+* ``svt_continuation`` tau continuation with warm starts (Section 6)
 * ``gram_triplets``    singular triplets above tau of a sparse Y from its Gram
                        matrix's eigendecomposition (LAPACK, FP64)
 * ``svt_sparse``       Algorithm 1, tier B: sparse Y, Gram-matrix triplets
@@ -27,6 +28,7 @@ from .svt import (  # noqa: F401
     apply_sparse,
     sampled_entries,
     svt_dense,
+    svt_continuation,
     top_triplets_dense,
     gram_triplets,
     svt_sparse,

@@ -131,7 +131,7 @@ def _fro(vec) -> float:
 def svt_dense(m: int, n: int, rows, cols, vals, tau: float, delta: float,
               eps: float, maxiter: int, incr: int, kick: bool = True,
               k0: int | None = None, stop: str = "relres", noise_sigma: float = 0.0,
-              keep_iterates: bool = False):
+              keep_iterates: bool = False, y0=None):
     """Algorithm 1 (Section 5.1.5) with a dense iterate and a full Jacobi SVD.
 
     Steps, in the paper's order:
@@ -151,6 +151,10 @@ def svt_dense(m: int, n: int, rows, cols, vals, tau: float, delta: float,
     break, not counting the k0 skipped steps), k0, and the histories of s_k,
     r_k and the relative residual, and X^opt as factors (U scaled by the
     weights sigma_j - tau, and V).
+    ``y0`` (values on Omega, in the input order): start from Y^0 = y0 instead
+    (no kick: a warm start); ``y_last`` in the result is the last iterate
+    with the final update of eq. (2.7) applied, Y^{k} = Y^{k-1} + delta
+    P_Omega(M - X^k), the state a following warm start continues from.
     """
     rows = np.asarray(rows, dtype=np.int64)
     cols = np.asarray(cols, dtype=np.int64)
@@ -161,6 +165,9 @@ def svt_dense(m: int, n: int, rows, cols, vals, tau: float, delta: float,
 
     Y = np.zeros((m, n), dtype=np.float64)
     sigma1 = None
+    if y0 is not None:
+        Y[rows, cols] = np.asarray(y0, dtype=np.float64)
+        kick, k0 = False, 0
     if kick:
         PM = np.zeros((m, n), dtype=np.float64)
         PM[rows, cols] = vals
@@ -168,7 +175,7 @@ def svt_dense(m: int, n: int, rows, cols, vals, tau: float, delta: float,
         if k0 is None:
             k0 = k0_kick(tau, delta, sigma1)
         Y[rows, cols] = k0 * delta * vals
-    else:
+    elif y0 is None:
         k0 = 0
 
     ranks, s_hist, res_hist = [], [], []
@@ -207,14 +214,31 @@ def svt_dense(m: int, n: int, rows, cols, vals, tau: float, delta: float,
         if keep_iterates:
             y_hist.append(Y[rows, cols].copy())
         r_prev = r_k
+    y_last = Y[rows, cols] + (delta * e if status == "ok" else 0.0)
     out = dict(iters=k, k0=k0, sigma1=sigma1, ranks=ranks, s_hist=s_hist,
                residuals=res_hist, U=Uw, w=w, V=Vr, status=status,
-               norm_pm=norm_pm)
+               norm_pm=norm_pm, y_last=y_last)
     if keep_iterates:
         out["iterates"] = iterates
         out["y_hist"] = y_hist
         out["Y"] = Y
     return out
+
+
+def svt_continuation(m: int, n: int, rows, cols, vals, taus, delta: float, eps: float,
+                     maxiter: int, incr: int):
+    """tau continuation with warm starts (Section 6): Algorithm 1 for each
+    tau_i of an increasing schedule, the first from the kick, each later one
+    from the previous one's last iterate Y (``svt_dense``'s y0).  The dual
+    iterate is carried rather than a primal guess, so Y stays supported on
+    Omega.  Returns the list of the stages' results."""
+    stages = []
+    y = None
+    for t in taus:
+        out = svt_dense(m, n, rows, cols, vals, float(t), delta, eps, maxiter, incr, y0=y)
+        stages.append(out)
+        y = out["y_last"]
+    return stages
 
 
 def gram_triplets(Ys, tau: float):

@@ -171,6 +171,20 @@ hipError_t launch_sample_update(hipStream_t s, int lanes, const int32_t *ptr, co
                                 bool row_side_is_u, double delta, double *part_out, T *Yp = nullptr,
                                 T *Ym = nullptr, double E = 0.0, double *part2_out = nullptr);
 
+// General linear operator A(X) = G x_S (measurements; G in CSR over the p
+// measurements, gidx into the support's row-compressed order):
+// launch_measure: r_i = b_i - (G x)_i, y_i += delta r_i, and the partial
+// sums of r_i^2 into part_out (measure_blocks(p) <= kSampleMaxBlocks
+// entries).  launch_adjoint: Y = G^T y on the support (GT in CSR over the
+// support entries, tidx the measurement of each term).
+int measure_blocks(int64_t p);
+template <typename T>
+hipError_t launch_measure(hipStream_t s, const int64_t *gptr, const int32_t *gidx, const T *gval, const T *x,
+                          const T *b, T *y, int64_t p, double delta, double *part_out);
+template <typename T>
+hipError_t launch_adjoint(hipStream_t s, const int64_t *tptr, const int32_t *tidx, const T *tval, const T *y, T *Y,
+                          int64_t ns);
+
 // The Dantzig selector's start: Yp = a max(B - E, 0), Ym = a max(-B - E, 0),
 // Y = Yp - Ym; with Yp = Ym = null, Y = S_E(B) = sign(B) max(|B| - E, 0).
 template <typename T>

@@ -1800,6 +1800,60 @@ __global__ __launch_bounds__(kBlock) void k_ds_init(const T *__restrict__ B, int
   }
 }
 
+// General linear operator (measurements b = G x_S): each thread takes
+// measurements i, r_i = b_i - sum_t G[i, t] x[gidx[t]] (fma chain in t
+// order), y_i += delta r_i, and its sum of r_i^2 (FP64) joins the
+// workgroup's partial in part_out.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_measure(const int64_t *__restrict__ gptr, const int32_t *__restrict__ gidx,
+                                                    const T *__restrict__ gval, const T *__restrict__ x,
+                                                    const T *__restrict__ b, T *__restrict__ y, int64_t p, T delta,
+                                                    double *__restrict__ part_out) {
+  __shared__ double sbuf[kWaves];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < p; i += (int64_t)gridDim.x * kBlock) {
+    T v = (T)0;
+    for (int64_t t = gptr[i]; t < gptr[i + 1]; ++t) v = fma(gval[t], x[gidx[t]], v);
+    const T r = b[i] - v;
+    y[i] = fma(delta, r, y[i]);
+    acc = fma((double)r, (double)r, acc);
+  }
+  const double tot = block_sum(acc, sbuf);
+  if (threadIdx.x == 0) part_out[blockIdx.x] = tot;
+}
+
+// The adjoint onto the support: Y[s] = sum_t GT[s, t] y[tidx[t]] for each
+// support entry s (fma chain in t order).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_adjoint(const int64_t *__restrict__ tptr, const int32_t *__restrict__ tidx,
+                                                    const T *__restrict__ tval, const T *__restrict__ y,
+                                                    T *__restrict__ Y, int64_t ns) {
+  for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < ns; s += (int64_t)gridDim.x * kBlock) {
+    T v = (T)0;
+    for (int64_t t = tptr[s]; t < tptr[s + 1]; ++t) v = fma(tval[t], y[tidx[t]], v);
+    Y[s] = v;
+  }
+}
+
+int measure_blocks(int64_t p) { return (int)std::min<int64_t>(kSampleMaxBlocks, std::max<int64_t>(1, (p + kBlock - 1) / kBlock)); }
+
+template <typename T>
+hipError_t launch_measure(hipStream_t s, const int64_t *gptr, const int32_t *gidx, const T *gval, const T *x,
+                          const T *b, T *y, int64_t p, double delta, double *part_out) {
+  if (p <= 0 || part_out == nullptr) return hipErrorInvalidValue;
+  SVT_LAUNCH((k_measure<T>), dim3(measure_blocks(p)), dim3(kBlock), 0, s, gptr, gidx, gval, x, b, y, p, (T)delta,
+             part_out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adjoint(hipStream_t s, const int64_t *tptr, const int32_t *tidx, const T *tval, const T *y, T *Y,
+                          int64_t ns) {
+  if (ns <= 0) return hipSuccess;
+  SVT_LAUNCH((k_adjoint<T>), dim3(grid_for(ns)), dim3(kBlock), 0, s, tptr, tidx, tval, y, Y, ns);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_ds_init(hipStream_t s, const T *B, int64_t n, double E, double a, T *Yp, T *Ym, T *Y) {
   if (n <= 0) return hipSuccess;
@@ -1851,6 +1905,10 @@ hipError_t launch_gather(hipStream_t s, const T *x, const int32_t *map, T *y, in
                                               const T *, T *, int, const T *, const T *, int, int,  \
                                               bool, double, double *, T *, T *, double, double *);  \
   template hipError_t launch_ds_init<T>(hipStream_t, const T *, int64_t, double, double, T *, T *, T *); \
+  template hipError_t launch_measure<T>(hipStream_t, const int64_t *, const int32_t *, const T *, const T *, \
+                                        const T *, T *, int64_t, double, double *);                  \
+  template hipError_t launch_adjoint<T>(hipStream_t, const int64_t *, const int32_t *, const T *, const T *, \
+                                        T *, int64_t);                                                \
   template hipError_t launch_axpby<T>(hipStream_t, const T *, T *, int64_t, double);               \
   template hipError_t launch_gather<T>(hipStream_t, const T *, const int32_t *, T *, int64_t);
 

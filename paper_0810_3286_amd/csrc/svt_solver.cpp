@@ -257,6 +257,8 @@ struct ProblemBase {
   virtual void set_iterate(const double *y) = 0;
   virtual void get_iterate(int which, double *y) const = 0;
   virtual void set_multipliers(const double *yp, const double *ym) = 0;
+  virtual void setup_sensing(int64_t p, const int64_t *gptr, const int32_t *gidx, const double *gval,
+                             const double *b) = 0;
   virtual void get_multipliers(double *yp, double *ym) const = 0;
   bool ds_soft_nonzero = false;  // some |B_ij| > E (the Dantzig selector's kick exists)
   virtual void apply(int trans, const double *x, double *out) = 0;
@@ -290,6 +292,12 @@ struct Problem final : ProblemBase {
   DevMem colidx16, rowidx16;          // 16-bit copies of colidx / rowidx (n, m <= 65536)
   DevMem Mr, Mc, Yr, Yc;          // values, T
   DevMem Yp, Ym;                  // Dantzig selector: the two multipliers (row order), T
+  // general linear operator A(X) = G x_S (svt_create_sensing): G and G^T in
+  // compressed form over the measurements and the support, b, the dual
+  // iterate y, and X on the support
+  bool sensing = false;
+  int64_t pmeas = 0;
+  DevMem g_ptr, g_idx, g_val, gt_ptr, gt_idx, gt_val, b_d, y_d, xs_d;
   DevMem Ub, Vb;                  // bases, T, column-major
   int kcap = 0;                   // columns available in Ub (Vb has kcap + 1)
   DevMem pbuf_u, pbuf_v;          // unnormalised new vectors of each side, T
@@ -525,7 +533,8 @@ struct Problem final : ProblemBase {
   // are both live.
   size_t device_bytes() const {
     const DevMem *all[] = {&rowptr, &colidx, &colptr, &rowidx, &csr_of_csc, &seg_r, &seg_c, &colidx16, &rowidx16,
-                           &Mr, &Mc, &Yr, &Yc, &Yp, &Ym, &Ub, &Vb, &pbuf_u, &pbuf_v, &coef, &gs1, &gs2, &gs3, &gsr,
+                           &Mr, &Mc, &Yr, &Yc, &Yp, &Ym, &g_ptr, &g_idx, &g_val, &gt_ptr,
+                           &gt_idx, &gt_val, &b_d, &y_d, &xs_d, &Ub, &Vb, &pbuf_u, &pbuf_v, &coef, &gs1, &gs2, &gs3, &gsr,
                            &sample_part, &ritzd, &Fu, &Fv};
     size_t b = 0;
     for (const DevMem *d : all) b += d->bytes;
@@ -1017,8 +1026,115 @@ struct Problem final : ProblemBase {
     return total(sample_host.as<double>());
   }
 
+  // ------------------------------------------- general linear operator
+  // Section 3.1: measurements b = A(M) = G M_S on a support S (this
+  // handle's Omega).  gidx refers to S in the order given to
+  // svt_create_sensing; here it is mapped to the row-compressed order, and
+  // G^T is built over that order with its terms in measurement order.
+  void setup_sensing(int64_t p, const int64_t *gptr, const int32_t *gidx, const double *gval,
+                     const double *b) override {
+    sensing = true;
+    pmeas = p;
+    const int64_t ns = ix.nnz, ng = gptr[p];
+    std::vector<int32_t> gi((size_t)ng);
+    std::vector<T> gv((size_t)ng), bv((size_t)p);
+    for (int64_t t = 0; t < ng; ++t) {
+      gi[(size_t)t] = ix.csr_of_input[(size_t)gidx[t]];
+      gv[(size_t)t] = (T)gval[t];
+    }
+    for (int64_t i = 0; i < p; ++i) bv[(size_t)i] = (T)b[i];
+    std::vector<int64_t> tp((size_t)ns + 1, 0);
+    for (int64_t t = 0; t < ng; ++t) tp[(size_t)gi[(size_t)t] + 1]++;
+    for (int64_t s2 = 0; s2 < ns; ++s2) tp[(size_t)s2 + 1] += tp[(size_t)s2];
+    std::vector<int64_t> fill(tp.begin(), tp.end() - 1);
+    std::vector<int32_t> ti((size_t)std::max<int64_t>(ng, 1));
+    std::vector<T> tv((size_t)std::max<int64_t>(ng, 1));
+    for (int64_t i = 0; i < p; ++i)
+      for (int64_t t = gptr[i]; t < gptr[i + 1]; ++t) {
+        const int64_t pos = fill[(size_t)gi[(size_t)t]]++;
+        ti[(size_t)pos] = (int32_t)i;
+        tv[(size_t)pos] = gv[(size_t)t];
+      }
+    g_ptr.alloc(sizeof(int64_t) * (p + 1));
+    g_idx.alloc(sizeof(int32_t) * std::max<int64_t>(ng, 1));
+    g_val.alloc(sizeof(T) * std::max<int64_t>(ng, 1));
+    gt_ptr.alloc(sizeof(int64_t) * (ns + 1));
+    gt_idx.alloc(sizeof(int32_t) * std::max<int64_t>(ng, 1));
+    gt_val.alloc(sizeof(T) * std::max<int64_t>(ng, 1));
+    b_d.alloc(sizeof(T) * p);
+    y_d.alloc(sizeof(T) * p);
+    xs_d.alloc(sizeof(T) * ns);
+    HIP_CHECK(hipMemcpyAsync(g_ptr.p, gptr, sizeof(int64_t) * (p + 1), hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(g_idx.p, gi.data(), sizeof(int32_t) * ng, hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(g_val.p, gv.data(), sizeof(T) * ng, hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(gt_ptr.p, tp.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(gt_idx.p, ti.data(), sizeof(int32_t) * ng, hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(gt_val.p, tv.data(), sizeof(T) * ng, hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(b_d.p, bv.data(), sizeof(T) * p, hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemsetAsync(y_d.p, 0, sizeof(T) * p, stream));
+    HIP_CHECK(hipStreamSynchronize(stream));
+    note_peak(0);
+  }
+
+  // Y = A*(y): G^T y on the support, both compressed copies
+  void sensing_adjoint(const T *y) {
+    HIP_CHECK(launch_adjoint<T>(stream, gt_ptr.as<int64_t>(), gt_idx.as<int32_t>(), gt_val.as<T>(), y, Yr.as<T>(),
+                                ix.nnz));
+    HIP_CHECK(launch_gather<T>(stream, Yr.as<T>(), csr_of_csc.as<int32_t>(), Yc.as<T>(), ix.nnz));
+  }
+
+  // One pass of eq. (3.3)'s second line: x_S = X on the support (the sampled
+  // product with M = 0 into a cleared buffer and delta = -1, so the "update"
+  // writes x itself), r = b - G x_S, y += delta r, Y = A*(y); returns |r|^2.
+  double sensing_pass(int r, double delta) {
+    HIP_CHECK(hipMemsetAsync(xs_d.p, 0, sizeof(T) * ix.nnz, stream));
+    HIP_CHECK(launch_sample_update<T>(stream, lanes_r, rowptr.as<int32_t>(), colidx.as<int32_t>(), Mr.as<T>(),
+                                      xs_d.as<T>(), (int)ix.m, Fu.as<T>(), Fv.as<T>(), r, fstride, true, -1.0,
+                                      nullptr));
+    HIP_CHECK(launch_measure<T>(stream, g_ptr.as<int64_t>(), g_idx.as<int32_t>(), g_val.as<T>(), xs_d.as<T>(),
+                                b_d.as<T>(), y_d.as<T>(), pmeas, delta, sample_part.as<double>()));
+    sensing_adjoint(y_d.as<T>());
+    const int nb = measure_blocks(pmeas);
+    HIP_CHECK(hipMemcpyAsync(sample_host.p, sample_part.p, sizeof(double) * nb, hipMemcpyDeviceToHost, stream));
+    HIP_CHECK(hipStreamSynchronize(stream));
+    double sum = 0.0, comp = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      const double y = sample_host.as<double>()[b] - comp;
+      const double t = sum + y;
+      comp = (t - sum) - y;
+      sum = t;
+    }
+    return sum;
+  }
+
+  // The kick for a general operator: while X = 0, y^k = k delta b, so X
+  // stays 0 up to k0 = ceil(tau / (delta ||A*(b)||_2)) (eq. (5.3) with A*(b)
+  // in place of P_Omega M).
+  void do_kick_sensing(double *sigma1, int32_t *k0_out) {
+    sensing_adjoint(b_d.as<T>());
+    Gkl g;
+    BidiagSVD sv;
+    int r = 0;
+    const int saved_hint = k_hint;
+    k_hint = 0;
+    const T *yr = a_is_y ? Yr.as<T>() : Yc.as<T>();
+    const T *yc = a_is_y ? Yc.as<T>() : Yr.as<T>();
+    gkl_run(yr, yc, 1, 1, 0.0, g, sv, r);
+    k_hint = saved_hint;
+    const double s1 = sv.sigma.empty() ? 0.0 : sv.sigma[0];
+    if (!(s1 > 0.0)) throw Error(SVT_EINVAL, "||A*(b)||_2 is zero");
+    const int32_t k0 = prm.k0_override > 0 ? prm.k0_override
+                                           : (int32_t)std::max(1.0, std::ceil(prm.tau / (prm.delta * s1)));
+    HIP_CHECK(launch_axpby<T>(stream, b_d.as<T>(), y_d.as<T>(), pmeas, (double)k0 * prm.delta));
+    sensing_adjoint(y_d.as<T>());
+    HIP_CHECK(hipStreamSynchronize(stream));
+    *sigma1 = s1;
+    *k0_out = k0;
+  }
+
   // --------------------------------------------------------------- kick (a2)
   void do_kick(double *sigma1, int32_t *k0_out) {
+    if (sensing) return do_kick_sensing(sigma1, k0_out);
     if (ds()) return do_kick_ds(sigma1, k0_out);
     Gkl g;
     BidiagSVD sv;
@@ -1114,13 +1230,18 @@ struct Problem final : ProblemBase {
     try {
       double s1 = 0.0;
       int32_t k0 = 0;
-      HIP_CHECK(hipMemsetAsync(Yr.p, 0, sizeof(T) * ix.nnz, stream));
-      HIP_CHECK(hipMemsetAsync(Yc.p, 0, sizeof(T) * ix.nnz, stream));
-      if (ds()) {
-        HIP_CHECK(hipMemsetAsync(Yp.p, 0, sizeof(T) * ix.nnz, stream));
-        HIP_CHECK(hipMemsetAsync(Ym.p, 0, sizeof(T) * ix.nnz, stream));
+      if (!prm.warm_start) {
+        // a cold start: Y = 0, then the kick; a warm start keeps the
+        // handle's iterate (Section 6's continuation)
+        HIP_CHECK(hipMemsetAsync(Yr.p, 0, sizeof(T) * ix.nnz, stream));
+        HIP_CHECK(hipMemsetAsync(Yc.p, 0, sizeof(T) * ix.nnz, stream));
+        if (ds()) {
+          HIP_CHECK(hipMemsetAsync(Yp.p, 0, sizeof(T) * ix.nnz, stream));
+          HIP_CHECK(hipMemsetAsync(Ym.p, 0, sizeof(T) * ix.nnz, stream));
+        }
+        if (sensing) HIP_CHECK(hipMemsetAsync(y_d.p, 0, sizeof(T) * pmeas, stream));
+        if (prm.kick) do_kick(&s1, &k0);
       }
-      if (prm.kick) do_kick(&s1, &k0);
       HIP_CHECK(hipStreamSynchronize(stream));
       t1 = now_s();
       inf.t_kick_s = t1 - t0;
@@ -1141,7 +1262,7 @@ struct Problem final : ProblemBase {
         form_factors(g, sv, r, ws.data());
         w.assign(ws.begin(), ws.begin() + r);
         double plain2 = 0.0;  // Dantzig selector: ||P_Omega(X - B)||^2 beside the violation
-        const double res2 = sample_pass(r, prm.delta, true, &plain2);
+        const double res2 = sensing ? sensing_pass(r, prm.delta) : sample_pass(r, prm.delta, true, &plain2);
         res = std::sqrt(res2) / norm_pm;
         history.push_back({r, s, steps, res});
         if (log_level > 0)
@@ -1340,6 +1461,7 @@ static void validate_params(const svt_params &p) {
   if (p.constraint != SVT_CONSTRAINT_EQUALITY && p.constraint != SVT_CONSTRAINT_INEQUALITY)
     throw Error(SVT_EINVAL, "unknown constraint kind");
   if (!finite(p.ineq_tol) || p.ineq_tol < 0) throw Error(SVT_EINVAL, "ineq_tol must be finite and >= 0");
+  if (p.warm_start != 0 && p.warm_start != 1) throw Error(SVT_EINVAL, "warm_start must be 0 or 1");
 
   if (!finite(p.lanczos_tol) || p.lanczos_tol < 0 || p.lanczos_tol >= 1) throw Error(SVT_EINVAL, "lanczos_tol must be in [0, 1)");
   if (p.lanczos_maxsteps < 0) throw Error(SVT_EINVAL, "lanczos_maxsteps must be >= 0");
@@ -1485,9 +1607,100 @@ svt_status svt_create(int64_t m, int64_t n, int64_t nnz, int32_t fmt, const void
   }
 }
 
+svt_status svt_create_sensing(int64_t m, int64_t n, int64_t ns, const int32_t *srows, const int32_t *scols,
+                              int64_t p, const int64_t *gptr, const int32_t *gidx, const double *gval,
+                              const double *b, const svt_params *params, svt_problem **out) {
+  if (out) *out = nullptr;
+  svt::g_create_error.clear();
+  try {
+    if (!out) throw Error(SVT_EINVAL, "out is NULL");
+    if (m < 1 || n < 1 || m > INT32_MAX - 1 || n > INT32_MAX - 1) throw Error(SVT_EINVAL, "bad dimensions");
+    if (ns < 1 || (double)ns > (double)m * (double)n || ns > INT32_MAX) throw Error(SVT_EINVAL, "bad support size");
+    if (p < 1 || p > INT32_MAX) throw Error(SVT_EINVAL, "bad measurement count");
+    if (!srows || !scols || !gptr || !gidx || !gval || !b) throw Error(SVT_EINVAL, "NULL array");
+    if (gptr[0] != 0) throw Error(SVT_EINVAL, "gptr must start at 0");
+    for (int64_t i = 0; i < p; ++i)
+      if (gptr[i + 1] < gptr[i]) throw Error(SVT_EINVAL, "gptr must be non-decreasing");
+    const int64_t ng = gptr[p];
+    if (ng > INT32_MAX) throw Error(SVT_EINVAL, "too many measurement terms");
+    for (int64_t t = 0; t < ng; ++t) {
+      if (gidx[t] < 0 || gidx[t] >= ns) throw Error(SVT_EINVAL, "gidx out of range at term " + std::to_string(t));
+      if (!std::isfinite(gval[t])) throw Error(SVT_EINVAL, "non-finite weight at term " + std::to_string(t));
+    }
+    bool any = false;
+    for (int64_t i = 0; i < p; ++i) {
+      if (!std::isfinite(b[i])) throw Error(SVT_EINVAL, "non-finite measurement");
+      any |= b[i] != 0.0;
+    }
+    if (!any) throw Error(SVT_EINVAL, "all measurements are zero: the stop test is undefined");
+    for (int64_t t = 0; t < ns; ++t)
+      if (srows[t] < 0 || srows[t] >= m || scols[t] < 0 || scols[t] >= n)
+        throw Error(SVT_EINVAL, "support index out of range at entry " + std::to_string(t));
+    svt_params prm;
+    if (params) prm = *params;
+    else svt_params_default(m, n, p, &prm);
+    svt::validate_params(prm);
+    if (prm.constraint != SVT_CONSTRAINT_EQUALITY || prm.stop_rule != SVT_STOP_RELRES)
+      throw Error(SVT_EINVAL, "a general operator takes equality constraints and the relative-residual stop");
+    if (prm.lanczos_tol == 0.0) prm.lanczos_tol = (prm.precision == SVT_MIXED) ? 1e-6 : 1e-12;
+    const double t0 = svt::now_s();
+    std::unique_ptr<svt::ProblemBase> impl;
+    if (prm.precision == SVT_MIXED) impl.reset(new svt::Problem<float>());
+    else impl.reset(new svt::Problem<double>());
+    std::vector<double> zeros((size_t)ns, 0.0);
+    svt::build_index(m, n, ns, srows, scols, zeros.data(), impl->ix);
+    {
+      double s2 = 0.0, c = 0.0;
+      for (int64_t i = 0; i < p; ++i) {
+        const double y = b[i] * b[i] - c;
+        const double tt = s2 + y;
+        c = (tt - s2) - y;
+        s2 = tt;
+      }
+      impl->norm_pm = std::sqrt(s2);
+    }
+    if (prm.precision == SVT_MIXED) static_cast<svt::Problem<float> *>(impl.get())->setup(prm);
+    else static_cast<svt::Problem<double> *>(impl.get())->setup(prm);
+    impl->setup_sensing(p, gptr, gidx, gval, b);
+    impl->t_setup = svt::now_s() - t0;
+    svt_problem *h = new svt_problem();
+    h->impl = std::move(impl);
+    *out = h;
+    return SVT_OK;
+  } catch (const Error &e) {
+    svt::g_create_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    svt::g_create_error = "host allocation failed";
+    return SVT_ENOMEM;
+  } catch (const std::exception &e) {
+    svt::g_create_error = e.what();
+    return SVT_EDEVICE;
+  }
+}
+
 svt_status svt_solve(svt_problem *h, svt_info *info) {
   if (!h || !h->impl) return SVT_EINVAL;
   return guarded(h, [&] { return h->impl->solve(info); });
+}
+
+svt_status svt_solve_path(svt_problem *h, const double *taus, int32_t count, svt_info *infos) {
+  if (!h || !h->impl || !taus || count < 1) return SVT_EINVAL;
+  for (int32_t i = 0; i < count; ++i)
+    if (!std::isfinite(taus[i]) || taus[i] <= 0) return SVT_EINVAL;
+  auto &prm = h->impl->prm;
+  const double tau0 = prm.tau;
+  const int32_t warm0 = prm.warm_start;
+  svt_status st = SVT_OK;
+  for (int32_t i = 0; i < count; ++i) {
+    prm.tau = taus[i];
+    prm.warm_start = i == 0 ? warm0 : 1;
+    st = guarded(h, [&] { return h->impl->solve(infos ? infos + i : nullptr); });
+    if (st != SVT_OK && st != SVT_NOT_CONVERGED) break;
+  }
+  prm.tau = tau0;
+  prm.warm_start = warm0;
+  return st;
 }
 
 svt_status svt_history(const svt_problem *h, int32_t cap, int32_t *ranks, int32_t *s_hist,

@@ -59,7 +59,7 @@ class svt_params(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("ineq_tol", ctypes.c_double),
         ("constraint", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("warm_start", ctypes.c_int32),
     ]
 
 
@@ -103,7 +103,11 @@ def _signatures(lib):
         "svt_create": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                         ctypes.c_void_p, _ip, _dp, ctypes.POINTER(svt_params),
                                         ctypes.POINTER(ctypes.c_void_p)]),
+        "svt_create_sensing": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _ip, _ip,
+                                                ctypes.c_int64, _lp, _ip, _dp, _dp, ctypes.POINTER(svt_params),
+                                                ctypes.POINTER(ctypes.c_void_p)]),
         "svt_solve": (ctypes.c_int32, [h, ctypes.POINTER(svt_info)]),
+        "svt_solve_path": (ctypes.c_int32, [h, _dp, ctypes.c_int32, ctypes.POINTER(svt_info)]),
         "svt_history": (ctypes.c_int32, [h, ctypes.c_int32, _ip, _ip, _dp, _ip, _ip]),
         "svt_factors": (ctypes.c_int32, [h, _ip, _dp, _dp, _dp]),
         "svt_predict": (ctypes.c_int32, [h, ctypes.c_int64, _ip, _ip, _dp]),
@@ -208,6 +212,24 @@ def svt_create(m: int, n: int, rows, cols, vals, params: svt_params | None = Non
     return h
 
 
+def svt_create_sensing(m: int, n: int, srows, scols, gptr, gidx, gval, b, params: svt_params | None = None):
+    """Create a problem with a general linear operator: support positions
+    (srows, scols) and the measurement matrix in CSR form (gptr int64[p+1],
+    gidx into the support, gval), measurements b."""
+    srows = _i32(srows)
+    scols = _i32(scols)
+    gptr = np.ascontiguousarray(gptr, dtype=np.int64)
+    gidx = _i32(gidx)
+    gval = _f64(gval)
+    b = _f64(b)
+    h = ctypes.c_void_p()
+    st = load().svt_create_sensing(m, n, srows.shape[0], _p(srows, _ip), _p(scols, _ip), b.shape[0],
+                                   _p(gptr, _lp), _p(gidx, _ip), _p(gval), _p(b),
+                                   ctypes.byref(params) if params is not None else None, ctypes.byref(h))
+    _check(st, None)
+    return h
+
+
 def svt_destroy(h) -> None:
     if h is not None:
         load().svt_destroy(h)
@@ -224,6 +246,20 @@ def svt_solve(h):
         e.info = info
         raise
     return st, info
+
+
+def svt_solve_path(h, taus):
+    """tau continuation: returns (status, [info per stage]); raises SvtError
+    on an error, with the stages done as ``.info``."""
+    taus = _f64(taus)
+    infos = (svt_info * taus.shape[0])()
+    st = load().svt_solve_path(h, _p(taus), taus.shape[0], infos)
+    try:
+        _check(st, h, allow=(SVT_OK, SVT_NOT_CONVERGED))
+    except SvtError as e:
+        e.info = list(infos)
+        raise
+    return st, list(infos)
 
 
 def svt_history(h):

@@ -36,6 +36,8 @@ __all__ = [
     "full_observation",
     "dense_random_iterate",
     "dantzig_fig3",
+    "SensingProblem",
+    "sparse_sensing",
 ]
 
 
@@ -202,6 +204,71 @@ def dantzig_fig3(n: int = 1000, r: int = 10, c: float = 5.0, seed: int = 0, *,
                 noise_sigma=float(sigma))
     p.clean = clean
     return p
+
+
+@dataclasses.dataclass
+class SensingProblem:
+    """Linear measurements b = A(M) of a rank-r matrix (Section 3.1): entry
+    positions of the support S (srows, scols, row-major, distinct) and the
+    p x |S| measurement matrix G in CSR form (gptr, gidx into S, gval), so
+    that b_i = sum_s G[i, s] M[srows[s], scols[s]]."""
+
+    m: int
+    n: int
+    r: int
+    srows: np.ndarray
+    scols: np.ndarray
+    gptr: np.ndarray
+    gidx: np.ndarray
+    gval: np.ndarray
+    b: np.ndarray
+    ML: np.ndarray
+    MR: np.ndarray
+    tau: float
+    delta: float
+    eps: float
+    maxiter: int
+    incr: int
+    name: str = ""
+
+    @property
+    def p(self) -> int:
+        return int(self.b.shape[0])
+
+    def G(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.gval, self.gidx, self.gptr), shape=(self.p, self.srows.shape[0]))
+
+
+def sparse_sensing(m: int, n: int, r: int, p: int, c: int = 4, seed: int = 0, *,
+                   eps: float = 1e-4, maxiter: int = 500) -> SensingProblem:
+    """A Gaussian rank-r m x n truth seen through p measurements, each a
+    random combination of c distinct entries at uniform positions with
+    N(0, 1/c) weights (so E[A* A] = p / (m n) I, as E[P_Omega] = |Omega| /
+    (m n) I for sampling).  tau = 5 sqrt(m n) and delta = 1.2 m n / p carry
+    the completion choices over (Section 5.2.1).  Draw order: M_L, M_R, the
+    positions, the weights."""
+    rng = np.random.default_rng(seed)
+    ML = rng.standard_normal((m, r))
+    MR = rng.standard_normal((n, r))
+    pos = np.empty((p, c), dtype=np.int64)
+    for i in range(p):
+        pos[i] = rng.choice(m * n, size=c, replace=False)
+    wts = rng.standard_normal((p, c)) / math.sqrt(c)
+    support, inv = np.unique(pos.ravel(), return_inverse=True)
+    srows = (support // n).astype(np.int32)
+    scols = (support % n).astype(np.int32)
+    gidx = inv.reshape(p, c).astype(np.int32)
+    order = np.argsort(gidx, axis=1)
+    gidx = np.take_along_axis(gidx, order, axis=1)
+    gval = np.take_along_axis(wts, order, axis=1)
+    gptr = np.arange(0, p * c + 1, c, dtype=np.int64)
+    ms = _observed_values(ML, MR, srows, scols)
+    b = (gval * ms[gidx]).sum(axis=1)
+    return SensingProblem(m=m, n=n, r=r, srows=srows, scols=scols, gptr=gptr, gidx=gidx.ravel(),
+                          gval=gval.ravel(), b=b, ML=ML, MR=MR, tau=5.0 * math.sqrt(float(m) * float(n)),
+                          delta=1.2 * float(m) * float(n) / float(p), eps=float(eps), maxiter=int(maxiter),
+                          incr=5, name=f"sensing-{m}x{n}-r{r}-p{p}-c{c}")
 
 
 def config(idx: int, seed: int = 0) -> Problem:
