@@ -11,6 +11,7 @@ compare against the stored files.  Run from the repository root:
     python tests/golden/make_oracle_goldens.py 4 C    # 30000 x 30000, rank 10: tier C, complete run,
                                                       # plus X at iterations 20 and 60
     python tests/golden/make_oracle_goldens.py dantzig  # Figure 3's workload, the Dantzig selector
+    python tests/golden/make_oracle_goldens.py serving  # four serving-stream requests, X at iteration 30
 
 With a second argument k the run stops after k iterations with eps = 0, and
 the file holds X^k: a fixed-iteration comparison point for trajectories
@@ -68,6 +69,32 @@ def dantzig():
           delta=DANTZIG_STEP_SCALE * p.delta, E=p.noise_sigma, status=out["status"])
 
 
+# requests of the serving stream (workload.serving_trace, seed 0) compared at
+# a fixed iteration: square-ish, wide and tall members inside the method's regime
+SERVING_REQUESTS = (5, 8, 15, 17)
+SERVING_K = 30
+
+
+def serving():
+    trace = workload.serving_trace(32, seed=0, rate=1.0)
+    out = {}
+    for i in SERVING_REQUESTS:
+        sp_ = trace[i][1]
+        p = workload.gaussian_lowrank(sp_["m"], sp_["n"], sp_["r"], sp_["nnz"], sp_["seed"],
+                                      noise_sigma=sp_["noise_sigma"], maxiter=500)
+        t = time.time()
+        o = svt_krylov(p.m, p.n, p.rows, p.cols, p.vals, p.tau, p.delta, 0.0, SERVING_K, p.incr)
+        print(f"request {i}: {p.m} x {p.n}, r {p.r}, |Omega| {p.nnz}: {time.time() - t:.0f} s, ranks {o['ranks'][-3:]}",
+              flush=True)
+        for key in ("U", "w", "V"):
+            out[f"r{i}_{key}"] = o[key]
+        out[f"r{i}_ranks"] = np.array(o["ranks"])
+        out[f"r{i}_residuals"] = np.array(o["residuals"])
+        out[f"r{i}_k0"] = o["k0"]
+    np.savez_compressed(os.path.join(HERE, f"oracle_serving_k{SERVING_K}.npz"), requests=np.array(SERVING_REQUESTS),
+                        k=SERVING_K, tier="C", **out)
+
+
 def main(cfg: int, arg: str = "0"):
     p = workload.config(cfg, seed=0)
     t = time.time()
@@ -121,5 +148,7 @@ def main(cfg: int, arg: str = "0"):
 if __name__ == "__main__":
     if len(sys.argv) > 1 and sys.argv[1] == "dantzig":
         dantzig()
+    elif len(sys.argv) > 1 and sys.argv[1] == "serving":
+        serving()
     else:
         main(int(sys.argv[1]) if len(sys.argv) > 1 else 1, sys.argv[2] if len(sys.argv) > 2 else "0")

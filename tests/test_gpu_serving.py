@@ -153,3 +153,38 @@ def test_footprint_bounds_the_device_bytes(precision):
             B.svt_destroy(h)
         fp = B.svt_footprint(p.m, p.n, p.nnz, precision)
         assert 0 < cur <= peak <= fp, (c, cur, peak, fp)
+
+
+def test_serving_stream_members_match_stored_oracle():
+    # four requests drawn by the serving stream's own generator (seed 0,
+    # sizes 622 to 7506, ranks 10 and 20), submitted together and solved in
+    # the mix in the served (mixed) precision, each stopped at iteration 30
+    # and compared with the stored oracle X^30 at the mixed form's 5e-4
+    import os
+    gpu_case("serving stream members vs stored oracle at iteration 30")
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "oracle_serving_k30.npz"))
+    k = int(g["k"])
+    trace = workload.serving_trace(32, seed=0, rate=1.0)
+    probs = []
+    for i in g["requests"]:
+        spec = trace[int(i)][1]
+        probs.append((int(i), workload.gaussian_lowrank(spec["m"], spec["n"], spec["r"], spec["nnz"], spec["seed"],
+                                                        noise_sigma=spec["noise_sigma"], maxiter=500)))
+    srv = B.svt_server_create(64 << 30, 4)
+    try:
+        tickets = []
+        for i, p in probs:
+            prm = B.svt_params_default(p.m, p.n, p.nnz)
+            prm.tau, prm.delta, prm.incr = p.tau, p.delta, p.incr
+            prm.eps, prm.maxiter = 0.0, k
+            prm.precision = B.SVT_MIXED
+            tickets.append(B.svt_submit(srv, p.m, p.n, p.rows, p.cols, p.vals, prm))
+        for (i, p), t in zip(probs, tickets):
+            st, info = B.svt_wait(srv, t)
+            st2, U, w, V, times = B.svt_result(srv, t, p.m, p.n)
+            assert st == B.SVT_NOT_CONVERGED and info.iters == k and info.k0 == int(g[f"r{i}_k0"])
+            assert info.rank == int(g[f"r{i}_ranks"][-1])
+            assert rel_diff_factored(U, V, g[f"r{i}_U"], g[f"r{i}_V"]) <= 5e-4, i
+        assert B.svt_server_stats(srv)["max_running"] >= 2
+    finally:
+        B.svt_server_destroy(srv)
