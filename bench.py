@@ -244,6 +244,84 @@ def table2_runs(precisions=("fp64", "mixed"), seed: int = 7) -> dict:
     return {"table2": out}
 
 
+def _timed_solve(B, h):
+    B.svt_solve(h)   # warm-up: the library's first-call costs
+    t0 = time.perf_counter()
+    st, info = B.svt_solve(h)
+    return st, info, time.perf_counter() - t0
+
+
+def dantzig_runs(seed: int = 0) -> dict:
+    """Section 5.2.2 (Figure 3): n = 1000, r = 10, |Omega| = 5 d_r, noise
+    sigma = 0.1 x the mean |M_ij| on Omega, constraints |X_ij - B_ij| <= sigma
+    on Omega (the Dantzig-selector iteration, eq. (3.10)).  Runs: the paper's
+    step delta = 1.2 / p (300 iterations), half that step with the eq. (5.10)
+    stop, in both precisions, and Algorithm 1 on the noiseless data."""
+    import numpy as np
+    import workload
+    from paper_0810_3286_amd import svt as B
+    from tests.helpers import rel_diff_factored
+    p = workload.dantzig_fig3(seed=seed)
+    out = {"noise_ratio": float(np.linalg.norm(p.vals - p.clean) / np.linalg.norm(p.clean)), "runs": []}
+
+    def run(label, vals, precision, delta, ds, maxiter, noisy):
+        prm = B.svt_params_default(p.m, p.n, p.nnz)
+        prm.tau, prm.delta, prm.eps, prm.maxiter, prm.incr = p.tau, delta, p.eps, maxiter, p.incr
+        prm.precision = precision
+        if ds:
+            prm.constraint = B.SVT_CONSTRAINT_INEQUALITY
+            prm.ineq_tol = p.noise_sigma
+        if noisy:
+            prm.stop_rule = B.SVT_STOP_NOISY
+            prm.noise_sigma = p.noise_sigma
+        h = B.svt_create(p.m, p.n, p.rows, p.cols, vals, prm)
+        try:
+            st, info, dt = _timed_solve(B, h)
+            U, w, V = B.svt_factors(h, p.m, p.n)
+            hist = B.svt_history(h)
+        finally:
+            B.svt_destroy(h)
+        rec = {"run": label, "precision": "fp64" if precision == B.SVT_FP64 else "mixed",
+               "status": B.svt_status_string(st), "iters": int(info.iters), "seconds": dt,
+               "final_rank": int(info.rank), "max_rank": int(max(hist["ranks"])) if len(hist["ranks"]) else 0,
+               "rel_error_vs_truth": rel_diff_factored(U, V, p.ML, p.MR)}
+        out["runs"].append(rec)
+        log(f"[bench] dantzig {rec}")
+
+    for prec in (B.SVT_FP64, B.SVT_MIXED):
+        run("inequality, delta = 0.6 / p, eq. (5.10) stop", p.vals, prec, 0.5 * p.delta, True, p.maxiter, True)
+    run("inequality, delta = 1.2 / p (the paper's step)", p.vals, B.SVT_FP64, p.delta, True, 300, False)
+    run("equality, noiseless data", p.clean, B.SVT_FP64, p.delta, False, p.maxiter, False)
+    return {"dantzig_fig3": out}
+
+
+def sensing_runs(seed: int = 0) -> dict:
+    """A general linear operator (Section 3.1): 3000 x 3000, rank 10, p =
+    8 d_r measurements of 4 entries each; both precisions."""
+    import workload
+    from paper_0810_3286_amd import svt as B
+    from tests.helpers import rel_diff_factored
+    q = workload.sparse_sensing(3000, 3000, 10, 8 * 10 * (6000 - 10), 4, seed=seed)
+    out = []
+    for prec in (B.SVT_FP64, B.SVT_MIXED):
+        prm = B.svt_params_default(q.m, q.n, q.p)
+        prm.tau, prm.delta, prm.eps, prm.maxiter, prm.incr = q.tau, q.delta, q.eps, q.maxiter, q.incr
+        prm.precision = prec
+        h = B.svt_create_sensing(q.m, q.n, q.srows, q.scols, q.gptr, q.gidx, q.gval, q.b, prm)
+        try:
+            st, info, dt = _timed_solve(B, h)
+            U, w, V = B.svt_factors(h, q.m, q.n)
+        finally:
+            B.svt_destroy(h)
+        rec = {"precision": "fp64" if prec == B.SVT_FP64 else "mixed", "status": B.svt_status_string(st),
+               "iters": int(info.iters), "seconds": dt, "svt_iters_per_s": info.iters / dt,
+               "final_rank": int(info.rank), "rel_error_vs_truth": rel_diff_factored(U, V, q.ML, q.MR),
+               "measurements": q.p, "support": int(q.srows.shape[0])}
+        out.append(rec)
+        log(f"[bench] sensing {rec}")
+    return {"sensing": out}
+
+
 def copy_calibration(mib: int, reps: int = 3):
     """Device-to-device copies of a known size through the HIP runtime's copy
     kernel: under rocprofv3 --pmc its FETCH_SIZE / WRITE_SIZE per dispatch,
@@ -409,6 +487,10 @@ def main():
                          "needs --traffic-mib and --traffic-bench-json")
     ap.add_argument("--table2", action="store_true",
                     help="run Table 2's noisy-data shapes (n = 1000) and print their results instead")
+    ap.add_argument("--dantzig", action="store_true",
+                    help="run Figure 3's inequality-constrained (Dantzig selector) workload and print its results")
+    ap.add_argument("--sensing", action="store_true",
+                    help="run a general-linear-operator (sparse measurement) workload and print its results")
     ap.add_argument("--traffic-mib", type=int, default=256)
     ap.add_argument("--traffic-bench-json", help="the JSON line of the counted bench run")
     args = ap.parse_args()
@@ -425,6 +507,12 @@ def main():
 
     if args.table2:
         print(json.dumps(table2_runs()), flush=True)
+        return
+    if args.dantzig:
+        print(json.dumps(dantzig_runs()), flush=True)
+        return
+    if args.sensing:
+        print(json.dumps(sensing_runs()), flush=True)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:

@@ -65,22 +65,29 @@ static double now_s() {
 // ---------------------------------------------------------------------------
 // device memory
 
+// Stream-ordered device memory: allocated and freed in the order of the
+// handle's stream (hipMallocAsync / hipFreeAsync from the device's pool), so
+// freeing a buffer never waits for the whole device -- a served solve that
+// ends or grows its bases does not stall the solves on other streams.  The
+// owner releases every buffer before its stream is destroyed.
 struct DevMem {
   void *p = nullptr;
   size_t bytes = 0;
+  hipStream_t s = nullptr;
   DevMem() = default;
   DevMem(const DevMem &) = delete;
   DevMem &operator=(const DevMem &) = delete;
   ~DevMem() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) (void)hipFreeAsync(p, s);
     p = nullptr;
     bytes = 0;
   }
-  void alloc(size_t b) {
+  void alloc(hipStream_t st, size_t b) {
     release();
     if (b == 0) b = 8;
-    HIP_CHECK(hipMalloc(&p, b));
+    s = st;
+    HIP_CHECK(hipMallocAsync(&p, b, st));
     bytes = b;
   }
   template <typename T>
@@ -362,16 +369,16 @@ struct Problem final : ProblemBase {
     lanes_r = lanes_for((double)nnz / (double)m);
     lanes_c = lanes_for((double)nnz / (double)n);
 
-    rowptr.alloc(sizeof(int32_t) * (m + 1));
-    colidx.alloc(sizeof(int32_t) * nnz);
-    colptr.alloc(sizeof(int32_t) * (n + 1));
-    rowidx.alloc(sizeof(int32_t) * nnz);
-    Mr.alloc(sizeof(T) * nnz);
-    Mc.alloc(sizeof(T) * nnz);
-    Yr.alloc(sizeof(T) * nnz);
-    Yc.alloc(sizeof(T) * nnz);
-    pbuf_u.alloc(sizeof(T) * arows);
-    pbuf_v.alloc(sizeof(T) * acols);
+    rowptr.alloc(stream, sizeof(int32_t) * (m + 1));
+    colidx.alloc(stream, sizeof(int32_t) * nnz);
+    colptr.alloc(stream, sizeof(int32_t) * (n + 1));
+    rowidx.alloc(stream, sizeof(int32_t) * nnz);
+    Mr.alloc(stream, sizeof(T) * nnz);
+    Mc.alloc(stream, sizeof(T) * nnz);
+    Yr.alloc(stream, sizeof(T) * nnz);
+    Yc.alloc(stream, sizeof(T) * nnz);
+    pbuf_u.alloc(stream, sizeof(T) * arows);
+    pbuf_v.alloc(stream, sizeof(T) * acols);
     HIP_CHECK(hipMemcpyAsync(rowptr.p, ix.rowptr.data(), sizeof(int32_t) * (m + 1), hipMemcpyHostToDevice, stream));
     HIP_CHECK(hipMemcpyAsync(colidx.p, ix.colidx.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, stream));
     HIP_CHECK(hipMemcpyAsync(colptr.p, ix.colptr.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, stream));
@@ -380,19 +387,19 @@ struct Problem final : ProblemBase {
     // the row copy after each sampled pass
     std::vector<int32_t> inv((size_t)nnz);
     for (int64_t t = 0; t < nnz; ++t) inv[(size_t)ix.csc_of_csr[(size_t)t]] = (int32_t)t;
-    csr_of_csc.alloc(sizeof(int32_t) * std::max<int64_t>(nnz, 1));
+    csr_of_csc.alloc(stream, sizeof(int32_t) * std::max<int64_t>(nnz, 1));
     HIP_CHECK(hipMemcpyAsync(csr_of_csc.p, inv.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, stream));
     // 16-bit column indices where they fit: the sparse product streams 6
     // instead of 8 bytes per FP32 entry
     std::vector<uint16_t> c16, r16;
     if (n <= 65536) {
       c16.assign(ix.colidx.begin(), ix.colidx.end());
-      colidx16.alloc(sizeof(uint16_t) * std::max<int64_t>(nnz, 1));
+      colidx16.alloc(stream, sizeof(uint16_t) * std::max<int64_t>(nnz, 1));
       HIP_CHECK(hipMemcpyAsync(colidx16.p, c16.data(), sizeof(uint16_t) * nnz, hipMemcpyHostToDevice, stream));
     }
     if (m <= 65536) {
       r16.assign(ix.rowidx.begin(), ix.rowidx.end());
-      rowidx16.alloc(sizeof(uint16_t) * std::max<int64_t>(nnz, 1));
+      rowidx16.alloc(stream, sizeof(uint16_t) * std::max<int64_t>(nnz, 1));
       HIP_CHECK(hipMemcpyAsync(rowidx16.p, r16.data(), sizeof(uint16_t) * nnz, hipMemcpyHostToDevice, stream));
     }
     {
@@ -403,28 +410,30 @@ struct Problem final : ProblemBase {
       plan_c = spmv_plan((int)n, (int)m, (int)sizeof(T), lds_limit, prm.spmv_mode);
       if (plan_r.nseg > 1) {
         const auto sr = segment_starts(ix.rowptr, ix.colidx, (int)m, plan_r);
-        seg_r.alloc(sizeof(int32_t) * sr.size());
-        HIP_CHECK(hipMemcpy(seg_r.p, sr.data(), sizeof(int32_t) * sr.size(), hipMemcpyHostToDevice));
+        seg_r.alloc(stream, sizeof(int32_t) * sr.size());
+        HIP_CHECK(hipMemcpyAsync(seg_r.p, sr.data(), sizeof(int32_t) * sr.size(), hipMemcpyHostToDevice, stream));
+        HIP_CHECK(hipStreamSynchronize(stream));
       }
       if (plan_c.nseg > 1) {
         const auto sc = segment_starts(ix.colptr, ix.rowidx, (int)n, plan_c);
-        seg_c.alloc(sizeof(int32_t) * sc.size());
-        HIP_CHECK(hipMemcpy(seg_c.p, sc.data(), sizeof(int32_t) * sc.size(), hipMemcpyHostToDevice));
+        seg_c.alloc(stream, sizeof(int32_t) * sc.size());
+        HIP_CHECK(hipMemcpyAsync(seg_c.p, sc.data(), sizeof(int32_t) * sc.size(), hipMemcpyHostToDevice, stream));
+        HIP_CHECK(hipStreamSynchronize(stream));
       }
     }
     upload_values(ix.vals_csr.data(), Mr.as<T>(), Mc.as<T>());
     HIP_CHECK(hipMemsetAsync(Yr.p, 0, sizeof(T) * nnz, stream));
     HIP_CHECK(hipMemsetAsync(Yc.p, 0, sizeof(T) * nnz, stream));
     if (ds()) {
-      Yp.alloc(sizeof(T) * nnz);
-      Ym.alloc(sizeof(T) * nnz);
+      Yp.alloc(stream, sizeof(T) * nnz);
+      Ym.alloc(stream, sizeof(T) * nnz);
       HIP_CHECK(hipMemsetAsync(Yp.p, 0, sizeof(T) * nnz, stream));
       HIP_CHECK(hipMemsetAsync(Ym.p, 0, sizeof(T) * nnz, stream));
     }
 
     // residual partials; the Dantzig selector's second sum (of the plain
     // residual) in the upper half
-    sample_part.alloc(sizeof(double) * 2 * (kSampleMaxBlocks + 8));
+    sample_part.alloc(stream, sizeof(double) * 2 * (kSampleMaxBlocks + 8));
     sample_host.ensure(sizeof(double) * 2 * (kSampleMaxBlocks + 8));
     // the allocation-free pass's scratch address on this device (looked up
     // once per device, with the device current)
@@ -456,15 +465,15 @@ struct Problem final : ProblemBase {
     int newcap = std::max(cap, std::min<int>((int)acols, std::max(kcap * 2, 16)));
     newcap = std::min(newcap, step_cap());
     DevMem nU, nV, ncoef, n1, n2, n3, nr;
-    nU.alloc(sizeof(T) * (size_t)arows * (size_t)(newcap + 1));
-    nV.alloc(sizeof(T) * (size_t)acols * (size_t)(newcap + 2));
-    ncoef.alloc(sizeof(double) * 4 * (size_t)(newcap + 4));
+    nU.alloc(stream, sizeof(T) * (size_t)arows * (size_t)(newcap + 1));
+    nV.alloc(stream, sizeof(T) * (size_t)acols * (size_t)(newcap + 2));
+    ncoef.alloc(stream, sizeof(double) * 4 * (size_t)(newcap + 4));
     const int cols = newcap + 4;
     const int blocks = std::max(row_plan((int)arows).nblk, row_plan((int)acols).nblk);
-    n1.alloc(sizeof(double) * (size_t)cols * blocks);
-    n2.alloc(sizeof(double) * (size_t)cols * blocks);
-    n3.alloc(sizeof(double) * (size_t)blocks);
-    nr.alloc(sizeof(double) * (size_t)cols);
+    n1.alloc(stream, sizeof(double) * (size_t)cols * blocks);
+    n2.alloc(stream, sizeof(double) * (size_t)cols * blocks);
+    n3.alloc(stream, sizeof(double) * (size_t)blocks);
+    nr.alloc(stream, sizeof(double) * (size_t)cols);
     // old and new bases are both live until the copies below complete
     note_peak(nU.bytes + nV.bytes + ncoef.bytes + n1.bytes + n2.bytes + n3.bytes + nr.bytes);
     HIP_CHECK(hipMemsetAsync(ncoef.p, 0, ncoef.bytes, stream));
@@ -519,11 +528,11 @@ struct Problem final : ProblemBase {
       constexpr int al = 16 / (int)sizeof(T);
       fstride = std::max(al, (cap + al - 1) / al * al);
       fcap = cap;
-      Fu.alloc(sizeof(T) * (size_t)ix.m * fstride);
-      Fv.alloc(sizeof(T) * (size_t)ix.n * fstride);
+      Fu.alloc(stream, sizeof(T) * (size_t)ix.m * fstride);
+      Fv.alloc(stream, sizeof(T) * (size_t)ix.n * fstride);
     }
     const size_t need = sizeof(double) * (2 * (size_t)std::max(k, 1) * (size_t)std::max(r, 1) + (size_t)r);
-    if (ritzd.bytes < need) ritzd.alloc(need * 2);
+    if (ritzd.bytes < need) ritzd.alloc(stream, need * 2);
     ritz_host.ensure(need * 2);
     note_peak(0);
   }
@@ -531,13 +540,15 @@ struct Problem final : ProblemBase {
   // Device bytes held now (every buffer of the handle) and the most held at
   // once, including the moments when a growing buffer's old and new copies
   // are both live.
+  std::vector<DevMem *> all_mem() {
+    return {&rowptr, &colidx, &colptr, &rowidx, &csr_of_csc, &seg_r, &seg_c, &colidx16, &rowidx16,
+            &Mr, &Mc, &Yr, &Yc, &Yp, &Ym, &g_ptr, &g_idx, &g_val, &gt_ptr,
+            &gt_idx, &gt_val, &b_d, &y_d, &xs_d, &Ub, &Vb, &pbuf_u, &pbuf_v, &coef, &gs1, &gs2, &gs3, &gsr,
+            &sample_part, &ritzd, &Fu, &Fv};
+  }
   size_t device_bytes() const {
-    const DevMem *all[] = {&rowptr, &colidx, &colptr, &rowidx, &csr_of_csc, &seg_r, &seg_c, &colidx16, &rowidx16,
-                           &Mr, &Mc, &Yr, &Yc, &Yp, &Ym, &g_ptr, &g_idx, &g_val, &gt_ptr,
-                           &gt_idx, &gt_val, &b_d, &y_d, &xs_d, &Ub, &Vb, &pbuf_u, &pbuf_v, &coef, &gs1, &gs2, &gs3, &gsr,
-                           &sample_part, &ritzd, &Fu, &Fv};
     size_t b = 0;
-    for (const DevMem *d : all) b += d->bytes;
+    for (const DevMem *d : const_cast<Problem *>(this)->all_mem()) b += d->bytes;
     return b;
   }
   void note_peak(size_t extra) { peak_bytes = std::max(peak_bytes, device_bytes() + extra); }
@@ -1055,15 +1066,15 @@ struct Problem final : ProblemBase {
         ti[(size_t)pos] = (int32_t)i;
         tv[(size_t)pos] = gv[(size_t)t];
       }
-    g_ptr.alloc(sizeof(int64_t) * (p + 1));
-    g_idx.alloc(sizeof(int32_t) * std::max<int64_t>(ng, 1));
-    g_val.alloc(sizeof(T) * std::max<int64_t>(ng, 1));
-    gt_ptr.alloc(sizeof(int64_t) * (ns + 1));
-    gt_idx.alloc(sizeof(int32_t) * std::max<int64_t>(ng, 1));
-    gt_val.alloc(sizeof(T) * std::max<int64_t>(ng, 1));
-    b_d.alloc(sizeof(T) * p);
-    y_d.alloc(sizeof(T) * p);
-    xs_d.alloc(sizeof(T) * ns);
+    g_ptr.alloc(stream, sizeof(int64_t) * (p + 1));
+    g_idx.alloc(stream, sizeof(int32_t) * std::max<int64_t>(ng, 1));
+    g_val.alloc(stream, sizeof(T) * std::max<int64_t>(ng, 1));
+    gt_ptr.alloc(stream, sizeof(int64_t) * (ns + 1));
+    gt_idx.alloc(stream, sizeof(int32_t) * std::max<int64_t>(ng, 1));
+    gt_val.alloc(stream, sizeof(T) * std::max<int64_t>(ng, 1));
+    b_d.alloc(stream, sizeof(T) * p);
+    y_d.alloc(stream, sizeof(T) * p);
+    xs_d.alloc(stream, sizeof(T) * ns);
     HIP_CHECK(hipMemcpyAsync(g_ptr.p, gptr, sizeof(int64_t) * (p + 1), hipMemcpyHostToDevice, stream));
     HIP_CHECK(hipMemcpyAsync(g_idx.p, gi.data(), sizeof(int32_t) * ng, hipMemcpyHostToDevice, stream));
     HIP_CHECK(hipMemcpyAsync(g_val.p, gv.data(), sizeof(T) * ng, hipMemcpyHostToDevice, stream));
@@ -1361,8 +1372,8 @@ struct Problem final : ProblemBase {
     std::vector<T> hx((size_t)nin);
     for (int64_t i = 0; i < nin; ++i) hx[(size_t)i] = (T)x[i];
     DevMem dx, dout;
-    dx.alloc(sizeof(T) * nin);
-    dout.alloc(sizeof(T) * nout);
+    dx.alloc(stream, sizeof(T) * nin);
+    dout.alloc(stream, sizeof(T) * nout);
     note_peak(dx.bytes + dout.bytes);
     HIP_CHECK(hipMemcpyAsync(dx.p, hx.data(), sizeof(T) * nin, hipMemcpyHostToDevice, stream));
     const Csx c = trans ? csc_struct() : csr_struct();
@@ -1436,6 +1447,9 @@ struct Problem final : ProblemBase {
   }
 
   ~Problem() override {
+    if (stream) (void)hipStreamSynchronize(stream);
+    // every buffer goes back to the pool on its stream before the stream ends
+    for (DevMem *d : all_mem()) d->release();
     if (stream) (void)hipStreamSynchronize(stream);
     if (fetch_ev) (void)hipEventDestroy(fetch_ev);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
