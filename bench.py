@@ -351,8 +351,10 @@ def serving_bench(n_req: int, slots: int, budget_gib: float, precision: int, see
     (r, c) drawn from Table 1's pairs (10, 6), (50, 5), (100, 4).
     Both: tau = 5 sqrt(m n), delta = 1.2 m n / |Omega|, eps = 1e-4, maxiter
     500, noise off; each request's bidiagonalisation is capped at step_cap
-    steps (a request that needs more ends with SVT_ELANCZOS), so a request
-    outside the method's regime holds its slot for a bounded time.
+    steps (a request that needs more ends with SVT_ELANCZOS), and the server's
+    stall bound ends a request whose residual sets no new minimum for 20
+    iterations (SVT_STALLED), so a request outside the method's regime holds
+    its slot for a bounded time.
     Closed loop (all requests at t = 0) gives the capacity C in requests/s;
     an open loop with Poisson arrivals at load_frac * C gives the latency
     (arrival to completion).  Solves/s and the latency percentiles count

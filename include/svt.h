@@ -36,6 +36,8 @@ extern "C" {
 typedef enum {
   SVT_OK = 0,
   SVT_NOT_CONVERGED = 1, /* maxiter reached; the result is the last iterate  */
+  SVT_STALLED = 2,       /* stall_window iterations without a new residual
+                            minimum; the result is the last iterate         */
   SVT_EINVAL = -1,       /* invalid argument (checked before any device work) */
   SVT_ENOMEM = -2,       /* host or device allocation failed                   */
   SVT_EDEVICE = -3,      /* a HIP runtime call failed                          */
@@ -112,6 +114,13 @@ typedef struct {
                             the last solve's final Y or one set with
                             svt_set_iterate: the warm start of Section 6's tau
                             continuation; no kick is applied                 */
+  int32_t stall_window;  /* > 0: stop with SVT_STALLED once this many
+                            consecutive iterations set no new minimum of the
+                            recorded residual (a bound on runs that oscillate
+                            without converging, which Algorithm 1 itself does
+                            not stop before maxiter); <= 0 (default): off.
+                            The server applies 20 to requests that leave it
+                            0; < 0 turns it off there too                   */
 } svt_params;
 
 typedef struct {
@@ -173,7 +182,8 @@ svt_status svt_create_sensing(int64_t m, int64_t n, int64_t ns, const int32_t *s
                               const double *b, const svt_params *params, svt_problem **out);
 
 /* Run Algorithm 1 from the kick (each call starts over).  Returns SVT_OK,
-   SVT_NOT_CONVERGED (maxiter reached; the factors hold X^{maxiter}), or an
+   SVT_NOT_CONVERGED (maxiter reached; the factors hold X^{maxiter}),
+   SVT_STALLED (with stall_window > 0; the factors hold the last iterate), or an
    error; after an error raised inside the iteration (e.g. SVT_ELANCZOS when
    the bidiagonalisation reaches lanczos_maxsteps) info still reports the
    iterations completed and their last residual.  info may be NULL. */
@@ -219,7 +229,8 @@ void svt_destroy(svt_problem *h);
 
 /* Short text of a status code, including the two ends of Algorithm 1's loop
    (Section 5.1.5): SVT_OK (the stop test of eq. (5.5) or (5.10) passed) and
-   SVT_NOT_CONVERGED (k_max reached).  Never NULL; unknown codes give
+   SVT_NOT_CONVERGED (k_max reached), and SVT_STALLED (the stall bound of
+   stall_window).  Never NULL; unknown codes give
    "unknown status". */
 const char *svt_status_string(int32_t status);
 
@@ -367,7 +378,7 @@ svt_status svt_submit(svt_server *s, int64_t m, int64_t n, int64_t nnz, const in
 svt_status svt_poll(svt_server *s, uint64_t ticket, int32_t *state);
 
 /* Block until the request is done; returns its solve status (SVT_OK,
-   SVT_NOT_CONVERGED or the error of svt_create / svt_solve). */
+   SVT_NOT_CONVERGED, SVT_STALLED or the error of svt_create / svt_solve). */
 svt_status svt_wait(svt_server *s, uint64_t ticket, svt_info *info);
 
 /* Copy out a finished request's factors (as svt_factors: U m x r scaled by

@@ -1211,72 +1211,123 @@ __global__ __launch_bounds__(kBlock) void k_randn(T *__restrict__ out, int n, ui
 // Ritz vectors: out[i, l] = w[l] sum_c Q[i, c] P[c, l] for l < r, zero for
 // r <= l < rs: a tall-skinny product (rows x k) times (k x r), on the FP64
 // matrix cores (v_mfma_f64_16x16x4f64; FP32 bases are widened on load, so the
-// sums are FP64 in both precisions).  A workgroup owns 64 rows (one
-// wavefront per 16) and up to 64 output columns (four 16-column tiles; wider
-// factors take more workgroups along y), so every basis entry is read once
-// per 64 output columns.  P is staged in LDS kRitzKc rows at a time; each
-// stage's basis loads are issued before the staging barrier.  Operand
-// layouts of the 16x16x4 FP64 instruction, lane l: A[l % 16][l / 16] (row,
-// c), B[l / 16][l % 16] (c, column), and element v of the result holds
+// sums are FP64 in both precisions).  A workgroup owns kRitzRT 16-row tiles
+// and up to 64 output columns (four 16-column tiles; wider factors take more
+// workgroups along y), so every basis entry is read once per 64 output
+// columns.  The k basis columns are cut into 16-column chunks dealt round
+// robin to the four wavefronts (wave w takes chunks w, w + 4, ...); each wave
+// accumulates its chunks for all the workgroup's rows and columns, reading
+// the P entries it multiplies straight from memory (P is small and stays in
+// L2), and issues the next chunk's loads before the current chunk's matrix
+// operations, so no barrier sits in the loop.  The four partial products are
+// added through LDS in wave order at the end.  Loads use clamped addresses;
+// a P entry outside (c < k, l < r) is taken as zero, which also cancels the
+// clamped basis columns; rows past the end are computed but not stored.
+// Operand layouts of the 16x16x4 FP64 instruction, lane l: A[l % 16][l / 16]
+// (row, c), B[l / 16][l % 16] (c, column), and element v of the result holds
 // D[l / 16 + 4 v][l % 16] (rows interleaved by four; checked on the device).
-constexpr int kRitzRows = 64;
-constexpr int kRitzCols = 64;
-constexpr int kRitzKc = 64;
-constexpr int kRitzThreads = 256;
+constexpr int kRitzRT = 1;         // 16-row tiles per workgroup
+constexpr int kRitzCols = 64;      // output columns per workgroup
+constexpr int kRitzKc = 16;        // basis columns per chunk (4 matrix steps)
+constexpr int kRitzWaves = 4;
+constexpr int kRitzThreads = kRitzWaves * kWave;
 using d4_t = __attribute__((ext_vector_type(4))) double;
+
+template <typename T, int NT>
+struct RitzChunk {
+  T a[kRitzRT][kRitzKc / 4];  // basis values, as loaded
+  double b[kRitzKc / 4][NT];  // P values, as loaded (masked where used)
+};
+
+template <typename T, int NT>
+__device__ __forceinline__ void ritz_load(RitzChunk<T, NT> &ch, const T *const (&qrow)[kRitzRT], int64_t ldq,
+                                          const double *__restrict__ P, int r, int k, int c0, int kq, int pcol0,
+                                          int lane16) {
+#pragma unroll
+  for (int st = 0; st < kRitzKc / 4; ++st) {
+    const int c = c0 + 4 * st + kq;
+    const int cc = min(c, k - 1);
+#pragma unroll
+    for (int rt = 0; rt < kRitzRT; ++rt) ch.a[rt][st] = qrow[rt][(size_t)cc * ldq];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) ch.b[st][t] = P[(size_t)cc * r + min(pcol0 + t * 16 + lane16, r - 1)];
+  }
+}
 
 template <typename T, int NT>
 __global__ __launch_bounds__(kRitzThreads) void k_ritz(const T *__restrict__ Q, int64_t ldq, int nrows, int k,
                                                        const double *__restrict__ P, const double *__restrict__ w,
                                                        int r, T *__restrict__ out, int rs) {
-  __shared__ double ps[kRitzKc * kRitzCols];
+  // the partial products of waves 1..3: [wave - 1][rt][t][v][lane]
+  __shared__ double red[(kRitzWaves - 1) * kRitzRT * NT * 4 * kWave];
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-  const int row0 = blockIdx.x * kRitzRows + wave * 16;
+  const int kq = lane / 16, lane16 = lane % 16;
+  const int row0 = blockIdx.x * (16 * kRitzRT);
   const int l0 = blockIdx.y * kRitzCols;
-  const int arow = row0 + lane % 16;
-  const bool avalid = arow < nrows;
-  const T *qrow = Q + (avalid ? arow : 0);
-  const int kq = lane / 16;
-  d4_t acc[NT];
+  const T *qrow[kRitzRT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = d4_t{0.0, 0.0, 0.0, 0.0};
-  for (int c0 = 0; c0 < k; c0 += kRitzKc) {
-    const int kc = min(kRitzKc, k - c0);
-    // this stage's A operands: column c0 + 4 s + kq of the lane's row
-    // (unconditional loads from clamped addresses, masked afterwards)
-    double a[kRitzKc / 4];
+  for (int rt = 0; rt < kRitzRT; ++rt) qrow[rt] = Q + min(row0 + rt * 16 + lane16, nrows - 1);
+  d4_t acc[kRitzRT][NT];
 #pragma unroll
-    for (int st = 0; st < kRitzKc / 4; ++st) {
-      const int c = 4 * st + kq;
-      const double v = (double)qrow[(size_t)min(c0 + c, k - 1) * ldq];
-      a[st] = (c < kc && avalid) ? v : 0.0;
-    }
-    __syncthreads();  // the previous stage's reads of ps are done
-    for (int e = threadIdx.x; e < kRitzKc * kRitzCols; e += kRitzThreads) {
-      const int c = e / kRitzCols, col = l0 + e % kRitzCols;
-      ps[e] = (c < kc && col < r) ? P[(size_t)(c0 + c) * r + col] : 0.0;
-    }
-    __syncthreads();
+  for (int rt = 0; rt < kRitzRT; ++rt)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[rt][t] = d4_t{0.0, 0.0, 0.0, 0.0};
+  const int nchunks = (k + kRitzKc - 1) / kRitzKc;
+  // the P entries outside l < r (the same for every chunk)
+  bool colok[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) colok[t] = l0 + t * 16 + lane16 < r;
+  auto mma = [&](const RitzChunk<T, NT> &ch, int jc, bool use) {
 #pragma unroll
     for (int st = 0; st < kRitzKc / 4; ++st) {
+      const bool cok = use && jc * kRitzKc + 4 * st + kq < k;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const double bv = ps[(4 * st + kq) * kRitzCols + t * 16 + lane % 16];
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], bv, acc[t], 0, 0, 0);
+      for (int rt = 0; rt < kRitzRT; ++rt)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const double b = (cok && colok[t]) ? ch.b[st][t] : 0.0;
+          acc[rt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)ch.a[rt][st], b, acc[rt][t], 0, 0, 0);
+        }
+    }
+  };
+  // two chunks per round: both chunks' loads are issued before the first
+  // chunk's matrix operations, which then wait only for their own operands
+  // while the second chunk's are in flight.  Past the wave's last chunk the
+  // second load repeats the first (already in cache) and its P operands are
+  // taken as zero (an unconditional use keeps the loads where they are).
+  RitzChunk<T, NT> c0, c1;
+  for (int j = wave; j < nchunks; j += 2 * kRitzWaves) {
+    const int j1 = j + kRitzWaves < nchunks ? j + kRitzWaves : j;
+    ritz_load(c0, qrow, ldq, P, r, k, j * kRitzKc, kq, l0, lane16);
+    ritz_load(c1, qrow, ldq, P, r, k, j1 * kRitzKc, kq, l0, lane16);
+    mma(c0, j, true);
+    mma(c1, j1, j1 != j);
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int rt = 0; rt < kRitzRT; ++rt)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[((((wave - 1) * kRitzRT + rt) * NT + t) * 4 + v) * kWave + lane] = acc[rt][t][v];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int rt = 0; rt < kRitzRT; ++rt)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int col = l0 + t * 16 + lane16;
+      const double scale = col < r ? (w ? w[col] : 1.0) : 0.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double x = acc[rt][t][v];
+#pragma unroll
+        for (int ww = 1; ww < kRitzWaves; ++ww) x += red[((((ww - 1) * kRitzRT + rt) * NT + t) * 4 + v) * kWave + lane];
+        const int row = row0 + rt * 16 + kq + 4 * v;
+        if (row < nrows && col < rs) out[(size_t)row * rs + col] = (T)(x * scale);
       }
     }
-  }
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int col = l0 + t * 16 + lane % 16;
-    if (col >= rs) continue;
-    const double scale = col < r ? (w ? w[col] : 1.0) : 0.0;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = row0 + kq + 4 * v;
-      if (row < nrows) out[(size_t)row * rs + col] = (T)(acc[t][v] * scale);
-    }
-  }
 }
 
 // Sampled product, residual and iterate update in one pass over a compressed
@@ -1695,7 +1746,7 @@ hipError_t launch_ritz(hipStream_t s, const T *Q, int64_t ldq, int nrows, int k,
                        const double *w, int r, T *out, int rs) {
   if (rs < 1 || nrows < 1) return hipSuccess;
   if (k < 1 || r > rs || ldq < nrows) return hipErrorInvalidValue;
-  const dim3 grid((nrows + kRitzRows - 1) / kRitzRows, (rs + kRitzCols - 1) / kRitzCols);
+  const dim3 grid((nrows + 16 * kRitzRT - 1) / (16 * kRitzRT), (rs + kRitzCols - 1) / kRitzCols);
   // 16-column tiles per workgroup: enough for the first kRitzCols columns
   const int nt = std::min(kRitzCols, rs + 15) / 16;
   switch (nt) {

@@ -93,6 +93,17 @@ double request_cap(const svt_params &p) {
   return p.lanczos_maxsteps > 0 ? (double)p.lanczos_maxsteps : kDefaultStepCap;
 }
 
+// A served request that leaves stall_window 0 stops once 20 consecutive
+// iterations set no new minimum of its residual (SVT_STALLED): requests
+// outside the method's regime oscillate for hundreds of iterations and
+// would otherwise hold a slot up to maxiter; converging runs set a new
+// minimum at every iteration.  A negative window turns the bound off.
+constexpr int32_t kDefaultStallWindow = 20;
+
+int32_t request_stall(const svt_params &p) {
+  return p.stall_window == 0 ? kDefaultStallWindow : p.stall_window;
+}
+
 
 }  // namespace
 
@@ -155,6 +166,7 @@ struct svt_server {
     p.stream = stream;  // the slot's own stream (library-owned when null)
     // the step cap the admission footprint assumed
     p.lanczos_maxsteps = (int32_t)request_cap(p);
+    p.stall_window = request_stall(p);
     svt_problem *h = nullptr;
     svt_status st = svt_create(r->m, r->n, r->nnz, SVT_COO, r->rows.data(), r->cols.data(), r->vals.data(), &p, &h);
     if (st != SVT_OK) {
@@ -164,7 +176,7 @@ struct svt_server {
     }
     st = svt_solve(h, &r->info);
     r->status = st;
-    if (st == SVT_OK || st == SVT_NOT_CONVERGED) {
+    if (st == SVT_OK || st == SVT_NOT_CONVERGED || st == SVT_STALLED) {
       int32_t rank = 0;
       svt_factors(h, &rank, nullptr, nullptr, nullptr);
       r->rank = rank;

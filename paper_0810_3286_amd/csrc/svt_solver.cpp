@@ -1228,6 +1228,9 @@ struct Problem final : ProblemBase {
     svt_status st = SVT_NOT_CONVERGED;
     int k = 0;
     double res = 1.0;
+    // the stall bound: the smallest residual so far and its iteration
+    double best_res = std::numeric_limits<double>::infinity();
+    int best_k = 0;
     // an error in the kick or the loop still reports the iterations completed
     auto report = [&](int iters, svt_status status) {
       inf.t_solve_s = now_s() - t1;
@@ -1285,6 +1288,15 @@ struct Problem final : ProblemBase {
         else
           stop = res <= prm.eps;
         if (stop) { st = SVT_OK; break; }
+        if (prm.stall_window > 0) {
+          if (res < best_res) {
+            best_res = res;
+            best_k = k;
+          } else if (k - best_k >= prm.stall_window) {
+            st = SVT_STALLED;
+            break;
+          }
+        }
         r_prev = r;
       }
     } catch (const Error &e) {
@@ -1710,7 +1722,7 @@ svt_status svt_solve_path(svt_problem *h, const double *taus, int32_t count, svt
     prm.tau = taus[i];
     prm.warm_start = i == 0 ? warm0 : 1;
     st = guarded(h, [&] { return h->impl->solve(infos ? infos + i : nullptr); });
-    if (st != SVT_OK && st != SVT_NOT_CONVERGED) break;
+    if (st != SVT_OK && st != SVT_NOT_CONVERGED && st != SVT_STALLED) break;
   }
   prm.tau = tau0;
   prm.warm_start = warm0;
@@ -1767,6 +1779,7 @@ const char *svt_status_string(int32_t s) {
   switch (s) {
     case SVT_OK: return "ok";
     case SVT_NOT_CONVERGED: return "not converged (maxiter reached)";
+    case SVT_STALLED: return "stalled (no new residual minimum within stall_window iterations)";
     case SVT_EINVAL: return "invalid argument";
     case SVT_ENOMEM: return "out of memory";
     case SVT_EDEVICE: return "device error";

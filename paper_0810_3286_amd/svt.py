@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "_build", "libsvt.so")
 
 SVT_OK = 0
 SVT_NOT_CONVERGED = 1
+SVT_STALLED = 2
 SVT_EINVAL = -1
 SVT_ENOMEM = -2
 SVT_EDEVICE = -3
@@ -60,6 +61,7 @@ class svt_params(ctypes.Structure):
         ("ineq_tol", ctypes.c_double),
         ("constraint", ctypes.c_int32),
         ("warm_start", ctypes.c_int32),
+        ("stall_window", ctypes.c_int32),
     ]
 
 
@@ -236,12 +238,12 @@ def svt_destroy(h) -> None:
 
 
 def svt_solve(h):
-    """Returns (status, info) for SVT_OK / SVT_NOT_CONVERGED; raises SvtError
+    """Returns (status, info) for SVT_OK / SVT_NOT_CONVERGED / SVT_STALLED; raises SvtError
     otherwise, with the info of the iterations completed as ``.info``."""
     info = svt_info()
     st = load().svt_solve(h, ctypes.byref(info))
     try:
-        _check(st, h, allow=(SVT_OK, SVT_NOT_CONVERGED))
+        _check(st, h, allow=(SVT_OK, SVT_NOT_CONVERGED, SVT_STALLED))
     except SvtError as e:
         e.info = info
         raise
@@ -255,7 +257,7 @@ def svt_solve_path(h, taus):
     infos = (svt_info * taus.shape[0])()
     st = load().svt_solve_path(h, _p(taus), taus.shape[0], infos)
     try:
-        _check(st, h, allow=(SVT_OK, SVT_NOT_CONVERGED))
+        _check(st, h, allow=(SVT_OK, SVT_NOT_CONVERGED, SVT_STALLED))
     except SvtError as e:
         e.info = list(infos)
         raise
@@ -436,7 +438,7 @@ def svt_result(server, ticket: int, m: int, n: int):
     if st == SVT_EINVAL or st == SVT_EBUSY:
         raise SvtError(st, svt_status_string(st))
     # a failed solve still carries its timestamps (and rank 0)
-    r = r.value if st in (SVT_OK, SVT_NOT_CONVERGED) else 0
+    r = r.value if st in (SVT_OK, SVT_NOT_CONVERGED, SVT_STALLED) else 0
     U = np.zeros((m, r))
     V = np.zeros((n, r))
     w = np.zeros(r)

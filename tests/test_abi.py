@@ -40,8 +40,8 @@ def test_binding_covers_every_declared_symbol():
 
 def test_struct_layout_matches_header():
     # svt_params: 3 doubles, 6 int32, 2 doubles, 2 int32, double, uint64, 2 int32, pointer,
-    # double, 2 int32
-    assert ctypes.sizeof(B.svt_params) == 3 * 8 + 6 * 4 + 2 * 8 + 2 * 4 + 8 + 8 + 2 * 4 + 8 + 8 + 2 * 4
+    # double, 3 int32 (and 4 bytes of tail padding)
+    assert ctypes.sizeof(B.svt_params) == 3 * 8 + 6 * 4 + 2 * 8 + 2 * 4 + 8 + 8 + 2 * 4 + 8 + 8 + 2 * 4 + 8
     assert ctypes.sizeof(B.svt_info) == 4 * 4 + 6 * 8 + 8
 
 

@@ -178,6 +178,7 @@ def test_serving_stream_members_match_stored_oracle():
             prm.tau, prm.delta, prm.incr = p.tau, p.delta, p.incr
             prm.eps, prm.maxiter = 0.0, k
             prm.precision = B.SVT_MIXED
+            prm.stall_window = -1       # a fixed iteration count: no stall bound
             tickets.append(B.svt_submit(srv, p.m, p.n, p.rows, p.cols, p.vals, prm))
         for (i, p), t in zip(probs, tickets):
             st, info = B.svt_wait(srv, t)
