@@ -105,7 +105,12 @@ typedef struct {
                             LDS, in column segments when it does not fit
                             whole (up to 8 of >= 1024 entries; otherwise it
                             is gathered from memory); 1 always gather        */
-  void *stream;          /* hipStream_t to run on; NULL = library-owned stream */
+  void *stream;          /* hipStream_t to run on; NULL = library-owned stream.
+                            It must come from the HIP runtime this library
+                            links (libamdhip64.so.7): a second runtime in the
+                            process (PyTorch bundles its own) has stream
+                            handles that are not valid here.  The library
+                            never destroys a caller's stream               */
   double ineq_tol;       /* E of SVT_CONSTRAINT_INEQUALITY (one tolerance for
                             every observed entry), >= 0                        */
   int32_t constraint;    /* svt_constraint; default SVT_CONSTRAINT_EQUALITY   */

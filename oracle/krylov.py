@@ -61,7 +61,9 @@ def svt_krylov(m: int, n: int, rows, cols, vals, tau: float, delta: float,
     Y += delta P_Omega(M - X^k) (eq. (2.7)).  ``keep_iterates_at``: loop
     counters whose X^k (U scaled by w, w, V) is returned in ``snapshots``.
     ``max_seconds``: end the loop (status "time_limit") once it has run that
-    long, for bounded timings.
+    long, for bounded timings.  ``y_last``: the iterate after the last update
+    (in the input order of the samples), the Y that the next iteration would
+    take its triplets of.
     """
     import time
 
@@ -124,4 +126,4 @@ def svt_krylov(m: int, n: int, rows, cols, vals, tau: float, delta: float,
             break
     return dict(iters=k, k0=k0, sigma1=sigma1, ranks=ranks, s_hist=s_hist,
                 residuals=res_hist, U=Uw, w=w, V=Vr, status=status, norm_pm=norm_pm,
-                seconds=seconds, snapshots=snapshots)
+                seconds=seconds, snapshots=snapshots, y_last=y)
