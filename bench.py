@@ -342,7 +342,8 @@ def copy_calibration(mib: int, reps: int = 3):
 
 
 def serving_bench(n_req: int, slots: int, budget_gib: float, precision: int, seed: int = 0,
-                  load_frac: float = 0.7, mix: str = "baseline", step_cap: int = 512):
+                  load_fracs=(0.7, 0.9), mix: str = "baseline", step_cap: int = 512,
+                  noise_frac: float = 0.0, open_loop: bool = True):
     """Serving form on a stream of mixed completion requests.
 
     mix "baseline": m, n uniform in [500, 8000] (rectangular), r in
@@ -350,63 +351,57 @@ def serving_bench(n_req: int, slots: int, budget_gib: float, precision: int, see
     mix "table1": m, n uniform in [1000, 8000] (aspect ratio at most 1.5),
     (r, c) drawn from Table 1's pairs (10, 6), (50, 5), (100, 4).
     Both: tau = 5 sqrt(m n), delta = 1.2 m n / |Omega|, eps = 1e-4, maxiter
-    500, noise off; each request's bidiagonalisation is capped at step_cap
-    steps (a request that needs more ends with SVT_ELANCZOS), and the server's
-    stall bound ends a request whose residual sets no new minimum for 20
-    iterations (SVT_STALLED), so a request outside the method's regime holds
-    its slot for a bounded time.
+    500; each request's bidiagonalisation is capped at step_cap steps (a
+    request that needs more ends with SVT_ELANCZOS), and the server's stall
+    bound ends a request whose residual sets no new minimum for 20 iterations
+    (SVT_STALLED), so a request outside the method's regime holds its slot
+    for a bounded time.  noise_frac: that share of the requests carries
+    N(0, 0.01^2) noise on its observations and stops by eq. (5.10) with
+    sigma = 0.01 and eps = 0.1 (the others as above).
     Closed loop (all requests at t = 0) gives the capacity C in requests/s;
-    an open loop with Poisson arrivals at load_frac * C gives the latency
-    (arrival to completion).  Solves/s and the latency percentiles count
-    converged solves (SVT_OK) only; the status split and the latencies of the
-    other requests are reported beside them."""
+    open loops with Poisson arrivals at each of load_fracs times C (fresh
+    requests of the same stream for each) give the latency (arrival to
+    completion).  Solves/s and the latency percentiles count converged solves
+    (SVT_OK) only; the status split and the latencies of the other requests
+    are reported beside them."""
     import threading
     import workload
     from paper_0810_3286_amd import svt as B
+    nruns = 1 + (len(load_fracs) if open_loop else 0)
     if mix == "table1":
-        trace = workload.serving_trace(2 * n_req, seed=seed, rate=1.0, mn_range=(1000, 8000),
-                                       pairs=workload.TABLE1_RANK_OVERSAMPLING, max_aspect=1.5)
+        trace = workload.serving_trace(nruns * n_req, seed=seed, rate=1.0, mn_range=(1000, 8000),
+                                       pairs=workload.TABLE1_RANK_OVERSAMPLING, max_aspect=1.5,
+                                       noise_frac=noise_frac)
     else:
-        trace = workload.serving_trace(2 * n_req, seed=seed, rate=1.0)
+        trace = workload.serving_trace(nruns * n_req, seed=seed, rate=1.0, noise_frac=noise_frac)
     probs = []
     for _, sp in trace:
         probs.append(workload.gaussian_lowrank(sp["m"], sp["n"], sp["r"], sp["nnz"], sp["seed"],
                                                noise_sigma=sp["noise_sigma"], maxiter=500))
         log(f"[bench] serving request {len(probs) - 1} generated ({sp['m']} x {sp['n']}, r {sp['r']}, "
-            f"|Omega| {sp['nnz']})")
+            f"|Omega| {sp['nnz']}{', noisy' if sp['noise_sigma'] > 0 else ''})")
 
     def params(p):
         prm = B.svt_params_default(p.m, p.n, p.nnz)
         prm.tau, prm.delta, prm.eps, prm.maxiter, prm.incr = p.tau, p.delta, p.eps, p.maxiter, p.incr
         prm.precision = precision
         prm.lanczos_maxsteps = step_cap
+        if p.noise_sigma > 0:
+            prm.stop_rule = B.SVT_STOP_NOISY
+            prm.noise_sigma = p.noise_sigma
+            prm.eps = 0.1
         return prm
 
+    pct = (lambda a, q: float(np.percentile(a, q)) if len(a) else None)
     budget = int(budget_gib * (1 << 30))
     srv = B.svt_server_create(budget, slots)
     statuses = []
-    try:
-        closed = probs[:n_req]
-        t0 = time.perf_counter()
-        tickets = [B.svt_submit(srv, p.m, p.n, p.rows, p.cols, p.vals, params(p)) for p in closed]
-        iters = 0
-        closed_ok = 0
-        for i, t in enumerate(tickets):
-            st, info = B.svt_wait(srv, t)
-            iters += info.iters
-            statuses.append(st)
-            closed_ok += int(st == B.SVT_OK)
-            B.svt_release(srv, t)
-            log(f"[bench] serving closed loop: request {i} done (status {st}, {info.iters} iterations)")
-        t_closed = time.perf_counter() - t0
-        capacity = n_req / t_closed
-        log(f"[bench] serving closed loop: {n_req} requests ({closed_ok} converged) in {t_closed:.2f} s")
-        # open loop: Poisson arrivals at load_frac * capacity
-        rate = load_frac * capacity
-        rng = np.random.default_rng(seed + 1)
-        arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
-        openp = probs[n_req:2 * n_req]
-        tix = [None] * n_req
+
+    def run_open(frac, openp, capacity, rseed):
+        rate = frac * capacity
+        rng = np.random.default_rng(rseed)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, len(openp)))
+        tix = [None] * len(openp)
 
         def submitter():
             base = time.perf_counter()
@@ -415,7 +410,7 @@ def serving_bench(n_req: int, slots: int, budget_gib: float, precision: int, see
                 if dt > 0:
                     time.sleep(dt)
                 tix[i] = B.svt_submit(srv, p.m, p.n, p.rows, p.cols, p.vals, params(p))
-                log(f"[bench] serving open loop: request {i} submitted")
+                log(f"[bench] serving open loop {frac}: request {i} submitted")
 
         t1 = time.perf_counter()
         th = threading.Thread(target=submitter)
@@ -429,33 +424,60 @@ def serving_bench(n_req: int, slots: int, budget_gib: float, precision: int, see
             (lat if st == B.SVT_OK else lat_failed).append(li)
             statuses.append(st)
             B.svt_release(srv, tix[i])
-            log(f"[bench] serving open loop: request {i} done (status {st}, latency {li:.2f} s)")
+            log(f"[bench] serving open loop {frac}: request {i} done (status {st}, latency {li:.2f} s)")
         t_open = time.perf_counter() - t1
+        return {"load_frac": frac, "rate_per_s": rate, "solves_per_s": len(lat) / t_open,
+                "converged": len(lat), "p50_latency_s": pct(lat, 50), "p99_latency_s": pct(lat, 99),
+                "failed_latency_s": sorted(float(x) for x in lat_failed)}
+
+    try:
+        closed = probs[:n_req]
+        t0 = time.perf_counter()
+        tickets = [B.svt_submit(srv, p.m, p.n, p.rows, p.cols, p.vals, params(p)) for p in closed]
+        iters = 0
+        entries = 0
+        closed_ok = 0
+        for i, t in enumerate(tickets):
+            st, info = B.svt_wait(srv, t)
+            iters += info.iters
+            entries += info.iters * closed[i].nnz
+            statuses.append(st)
+            closed_ok += int(st == B.SVT_OK)
+            B.svt_release(srv, t)
+            log(f"[bench] serving closed loop: request {i} done (status {st}, {info.iters} iterations)")
+        t_closed = time.perf_counter() - t0
+        capacity = n_req / t_closed
+        log(f"[bench] serving closed loop: {n_req} requests ({closed_ok} converged) in {t_closed:.2f} s")
+        opens = []
+        if open_loop:
+            for q, frac in enumerate(load_fracs):
+                opens.append(run_open(frac, probs[(q + 1) * n_req:(q + 2) * n_req], capacity, seed + 1 + q))
         stats = B.svt_server_stats(srv)
     finally:
         B.svt_server_destroy(srv)
-    lat = np.array(lat)
-    pct = (lambda a, q: float(np.percentile(a, q)) if len(a) else None)
-    open_ok = len(lat)
-    return {
+    out = {
         "requests_per_run": n_req, "slots": slots, "budget_gib": budget_gib,
         "precision": "mixed" if precision == B.SVT_MIXED else "fp64",
+        "noisy_share": noise_frac,
         # converged solves (SVT_OK) only; requests that ended otherwise are
         # counted apart
         "closed_loop_solves_per_s": closed_ok / t_closed,
         "closed_loop_converged": closed_ok,
         "closed_loop_requests_per_s": capacity,
         "closed_loop_svt_iters_per_s": iters / t_closed,
+        "closed_loop_sampled_entries_per_s": entries / t_closed,
         "mix": mix, "step_cap": step_cap,
         "status_counts": {B.svt_status_string(k): int(v) for k, v in
                           zip(*np.unique(np.array(statuses), return_counts=True))},
-        "open_loop_rate_per_s": rate,
-        "open_loop_solves_per_s": open_ok / t_open,
-        "open_loop_converged": open_ok,
-        "p50_latency_s": pct(lat, 50), "p99_latency_s": pct(lat, 99),
-        "failed_latency_s": sorted(float(x) for x in lat_failed),
         "max_running": stats["max_running"], "peak_admitted_gib": stats["peak_bytes"] / (1 << 30),
     }
+    if opens:
+        o = opens[0]
+        out.update({"open_loop_rate_per_s": o["rate_per_s"], "open_loop_solves_per_s": o["solves_per_s"],
+                    "open_loop_converged": o["converged"], "p50_latency_s": o["p50_latency_s"],
+                    "p99_latency_s": o["p99_latency_s"], "failed_latency_s": o["failed_latency_s"],
+                    "open_loops": opens})
+    return out
 
 
 def main():
@@ -658,6 +680,11 @@ def main():
         # converged solves only (the status split is in "serving")
         out["solves_per_s"] = out["serving"]["closed_loop_solves_per_s"]
         out["p99_latency_s"] = out["serving"]["p99_latency_s"]
+        # the same stream with half of the requests noisy (eq. (5.10) stop),
+        # closed loop
+        out["serving_noisy"] = serving_bench(args.serving_requests, args.serving_slots, 64.0, B.SVT_MIXED,
+                                             mix=args.serving_mix, step_cap=args.serving_step_cap,
+                                             noise_frac=0.5, open_loop=False)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
