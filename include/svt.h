@@ -213,9 +213,9 @@ svt_status svt_history(const svt_problem *h, int32_t cap, int32_t *ranks,
                        int32_t *s_hist, double *residuals, int32_t *gkl_steps,
                        int32_t *len_out);
 
-/* X^opt = U diag(w) V^T as factors (Algorithm 1's output): U is m x r
-   row-major and already multiplied by w (w_j = sigma_j - tau), V is n x r
-   row-major with orthonormal columns.  Pass U = w = V = NULL to query r
+/* X^opt as factors (Algorithm 1's output), X = U V^T: U is m x r row-major,
+   the left singular vectors already multiplied by w (w_j = sigma_j - tau,
+   also returned in w), V is n x r row-major with orthonormal columns.  Pass U = w = V = NULL to query r
    first; buffers are caller-owned and at least m r, r, n r doubles. */
 svt_status svt_factors(const svt_problem *h, int32_t *rank_out, double *U,
                        double *w, double *V);
