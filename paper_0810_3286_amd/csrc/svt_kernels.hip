@@ -709,16 +709,23 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
   constexpr int kGroups = kRowBlock / L;
   const int r0 = blockIdx.x * rows_per_blk;
   const int r1 = min(nrows, r0 + rows_per_blk);
-  // x staged in one segment and at most one row per lane group: the row's
-  // bounds are loaded first, its first half batch of entries right after the
-  // other independent loads, so both round trips overlap the staging of x
-  // and the pending update (a full batch held that long would spill)
-  const bool early = STAGE && L >= 8 && nseg == 1 && rows_per_blk <= kGroups;
+  // x staged in LDS and at most one row per lane group: the row's bounds in
+  // the first segment are loaded first, its first half batch of entries
+  // right after the other independent loads, so both round trips overlap
+  // the staging of x and the pending update (a full batch held that long
+  // would spill; loading a later segment's bounds during its staging, too,
+  // made the FP64 kernel spill and measured slower)
+  const bool early = STAGE && L >= 8 && rows_per_blk <= kGroups;
   const int erow = r0 + grp;
   int ebeg = 0, eend = 0;
   if (early && erow < r1) {
-    ebeg = ptr[erow];
-    eend = ptr[erow + 1];
+    if (nseg == 1) {
+      ebeg = ptr[erow];
+      eend = ptr[erow + 1];
+    } else {
+      ebeg = segptr[(size_t)erow * (nseg + 1)];
+      eend = segptr[(size_t)erow * (nseg + 1) + 1];
+    }
   }
   // this thread's Q values and prev for the epilogue (rows of at most
   // kRowLanes per workgroup and nq < kColsPerPass)
@@ -810,7 +817,11 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
     }
     for (int row = r0 + grp; row < r1; row += kGroups) {
       int beg, end;
-      if (!STAGE || nseg == 1) {
+      const bool pre = early && sgm == 0;  // the first segment's batch was loaded early
+      if (pre) {
+        beg = ebeg;  // row == erow: one row per lane group
+        end = eend;
+      } else if (!STAGE || nseg == 1) {
         beg = ptr[row];
         end = ptr[row + 1];
       } else {
@@ -819,7 +830,7 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
       }
       T acc = (T)0;
       int t = beg + lane;
-      if (early) {
+      if (pre) {
         // the first batch arrived with the early loads (same order)
 #pragma unroll
         for (int j = 0; j < kEarly; ++j)
