@@ -108,7 +108,7 @@ def test_sparse_products_full_size_30000(precision, mode):
 
 
 @pytest.mark.parametrize("case", SMALL + [(400, 400, 10, 47400, 0)])
-@pytest.mark.parametrize("rank", [0, 1, 7, 12, 20, 40, 70, 100])
+@pytest.mark.parametrize("rank", [0, 1, 7, 10, 12, 16, 20, 40, 70, 100])
 def test_sample_update(case, rank):
     m, n, r, nnz, seed = case
     gpu_case(f"sample_update {case} rank {rank}")
@@ -134,7 +134,7 @@ def test_sample_update(case, rank):
 
 
 @pytest.mark.parametrize("case", SMALL + [(400, 400, 10, 47400, 0)])
-@pytest.mark.parametrize("rank", [1, 12, 20, 40, 70, 100])
+@pytest.mark.parametrize("rank", [1, 10, 12, 16, 20, 40, 70, 100])
 def test_sample_update_mixed(case, rank):
     # the mixed form's pass (FP32 factors, values and products; compensated
     # FP32 sum of e^2 promoted to FP64): every kernel variant (factor rows in
