@@ -343,7 +343,7 @@ def copy_calibration(mib: int, reps: int = 3):
 
 def serving_bench(n_req: int, slots: int, budget_gib: float, precision: int, seed: int = 0,
                   load_fracs=(0.7, 0.9), mix: str = "baseline", step_cap: int = 512,
-                  noise_frac: float = 0.0, open_loop: bool = True):
+                  noise_frac: float = 0.0, open_loop: bool = True, min_rows: int = 0):
     """Serving form on a stream of mixed completion requests.
 
     mix "baseline": m, n uniform in [500, 8000] (rectangular), r in
@@ -386,6 +386,7 @@ def serving_bench(n_req: int, slots: int, budget_gib: float, precision: int, see
         prm.tau, prm.delta, prm.eps, prm.maxiter, prm.incr = p.tau, p.delta, p.eps, p.maxiter, p.incr
         prm.precision = precision
         prm.lanczos_maxsteps = step_cap
+        prm.min_block_rows = min_rows      # 0: the server's choice
         if p.noise_sigma > 0:
             prm.stop_rule = B.SVT_STOP_NOISY
             prm.noise_sigma = p.noise_sigma
@@ -499,6 +500,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-mix", choices=["baseline", "table1"], default="baseline")
     ap.add_argument("--serving-step-cap", type=int, default=512)
+    ap.add_argument("--serving-min-rows", type=int, default=0,
+                    help="min_block_rows of the served requests (0: the server's default)")
     ap.add_argument("--no-other", action="store_true",
                     help="skip the run of the other precision (mixed beside an fp64 headline, or fp64 "
                          "beside a mixed one)")
@@ -676,7 +679,8 @@ def main():
         log("[bench] serving stream")
         # the serving form runs mixed-precision solves (its workload's definition)
         out["serving"] = serving_bench(args.serving_requests, args.serving_slots, 64.0, B.SVT_MIXED,
-                                       mix=args.serving_mix, step_cap=args.serving_step_cap)
+                                       mix=args.serving_mix, step_cap=args.serving_step_cap,
+                                       min_rows=args.serving_min_rows)
         # converged solves only (the status split is in "serving")
         out["solves_per_s"] = out["serving"]["closed_loop_solves_per_s"]
         out["p99_latency_s"] = out["serving"]["p99_latency_s"]
@@ -684,7 +688,7 @@ def main():
         # closed loop
         out["serving_noisy"] = serving_bench(args.serving_requests, args.serving_slots, 64.0, B.SVT_MIXED,
                                              mix=args.serving_mix, step_cap=args.serving_step_cap,
-                                             noise_frac=0.5, open_loop=False)
+                                             noise_frac=0.5, open_loop=False, min_rows=args.serving_min_rows)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)

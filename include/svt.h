@@ -126,6 +126,14 @@ typedef struct {
                             not stop before maxiter); <= 0 (default): off.
                             The server applies 20 to requests that leave it
                             0; < 0 turns it off there too                   */
+  int32_t min_block_rows;/* the bidiagonalisation's vectors are cut into at
+                            most 256 row blocks (one workgroup each) of at
+                            least this many rows; 0 (default) = 8, at most
+                            2048.  Fewer, fuller blocks leave compute units to
+                            solves running at the same time; the server uses
+                            64 for requests that leave it 0.  The partial
+                            sums follow the blocks, so results depend on it
+                            at rounding level                               */
 } svt_params;
 
 typedef struct {

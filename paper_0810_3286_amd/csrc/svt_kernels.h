@@ -31,11 +31,14 @@ constexpr int kSampleMaxBlocks = 1024;
 // Partition of a vector of nrows entries into nblk contiguous row ranges of
 // rows_per_blk (the last one shorter), shared by the sparse product, the
 // Gram-Schmidt kernels and the norm kernels: the partial sums they exchange
-// have one entry per range.
+// have one entry per range.  At most kMaxRowBlocks ranges of at least
+// min_rows rows (kDefaultMinRows unless a solve asks for more: fewer, fuller
+// workgroups leave compute units to other solves running at the same time).
+constexpr int kDefaultMinRows = 8;
 struct RowPlan {
   int nblk, rows_per_blk;
 };
-RowPlan row_plan(int nrows);
+RowPlan row_plan(int nrows, int min_rows = kDefaultMinRows);
 
 // Partial-sum buffers of the bidiagonalisation (device memory owned by the
 // solver): part1 and part2 hold max_cols columns of max_blocks partials,
@@ -62,8 +65,10 @@ int lanes_for(double mean_per_row);
 struct SpmvPlan {
   int nblk, rows_per_blk, lanes, nseg, segcols;
   size_t lds;  // dynamic LDS bytes of a launch
+  int min_rows;  // of row_plan
 };
-SpmvPlan spmv_plan(int nrows, int ncols, int elem_bytes, int lds_bytes, int mode);
+SpmvPlan spmv_plan(int nrows, int ncols, int elem_bytes, int lds_bytes, int mode,
+                   int min_rows = kDefaultMinRows);
 
 // The input of a sparse product: the other side's new vector x (ncols
 // entries) as the previous half-step left it, with its one-pass
@@ -130,16 +135,18 @@ hipError_t launch_pending_reduce(hipStream_t s, const double *pend, int np, int 
 // null): receives |h|^2 / |p|^2.
 template <typename T>
 hipError_t launch_gs_update(hipStream_t s, T *p, int nrows, const T *Q, int64_t ldq, int nq,
-                            const double *part_in, double *part_out, bool second, double *removed);
+                            const double *part_in, double *part_out, bool second, double *removed,
+                            int min_rows = kDefaultMinRows);
 
 // |p|^2 partials (one column).
 template <typename T>
-hipError_t launch_sumsq(hipStream_t s, const T *p, int nrows, double *part_out);
+hipError_t launch_sumsq(hipStream_t s, const T *p, int nrows, double *part_out,
+                       int min_rows = kDefaultMinRows);
 
 // out = p / |p| with |p|^2 the sum of the partials in part; *coef_out = |p|.
 template <typename T>
 hipError_t launch_finalize(hipStream_t s, const T *p, int nrows, const double *part, T *out,
-                           double *coef_out);
+                           double *coef_out, int min_rows = kDefaultMinRows);
 
 // out[i] = standard normal draw i of stream (seed, ctr); counter-based.
 template <typename T>

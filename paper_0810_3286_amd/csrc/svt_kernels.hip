@@ -1558,9 +1558,10 @@ int lanes_for(double mean) {
   return 64;
 }
 
-RowPlan row_plan(int nrows) {
+RowPlan row_plan(int nrows, int min_rows) {
   RowPlan rp;
-  rp.nblk = std::max(1, std::min(kMaxRowBlocks, (nrows + 7) / 8));
+  min_rows = std::max(1, min_rows);
+  rp.nblk = std::max(1, std::min(kMaxRowBlocks, (nrows + min_rows - 1) / min_rows));
   // very long vectors: more workgroups rather than more rows each
   rp.nblk = std::max(rp.nblk, (nrows + kMaxRowsPerBlock - 1) / kMaxRowsPerBlock);
   rp.rows_per_blk = std::max(1, (nrows + rp.nblk - 1) / rp.nblk);
@@ -1595,9 +1596,10 @@ hipError_t allow_dynamic_lds(const void *kern, size_t bytes) {
   return hipSuccess;
 }
 
-SpmvPlan spmv_plan(int nrows, int ncols, int elem_bytes, int lds_bytes, int mode) {
+SpmvPlan spmv_plan(int nrows, int ncols, int elem_bytes, int lds_bytes, int mode, int min_rows) {
   SpmvPlan pl{};
-  const RowPlan rp = row_plan(nrows);
+  const RowPlan rp = row_plan(nrows, min_rows);
+  pl.min_rows = min_rows;
   pl.nblk = rp.nblk;
   pl.rows_per_blk = rp.rows_per_blk;
   // lanes per row: the widest power of two that still runs all of a
@@ -1679,7 +1681,7 @@ hipError_t launch_spmv(hipStream_t s, const SpmvPlan &pl, const int32_t *ptr, co
     if (in.x_out != nullptr && in.ldqx < ncols) return hipErrorInvalidValue;
   }
   if (in.pend != nullptr && in.np < 1) return hipErrorInvalidValue;
-  const RowPlan rp = row_plan(nrows);
+  const RowPlan rp = row_plan(nrows, pl.min_rows);
   if (rp.nblk != pl.nblk || rp.rows_per_blk != pl.rows_per_blk) return hipErrorInvalidValue;
   if (idx16 != nullptr)
     return launch_spmv_i<T, uint16_t>(s, pl, ptr, idx16, val, segptr, in, ncols, prev, p, nrows, Q, ldq, nq,
@@ -1695,8 +1697,9 @@ size_t gs_update_lds(int nq, int rows_per_blk) {
 
 template <typename T>
 hipError_t launch_gs_update(hipStream_t s, T *p, int nrows, const T *Q, int64_t ldq, int nq,
-                            const double *part_in, double *part_out, bool second, double *removed) {
-  const RowPlan rp = row_plan(nrows);
+                            const double *part_in, double *part_out, bool second, double *removed,
+                            int min_rows) {
+  const RowPlan rp = row_plan(nrows, min_rows);
   if (nq < 1 || Q == nullptr) return hipErrorInvalidValue;
   const size_t lds = gs_update_lds(nq, rp.rows_per_blk);
   if (!second) {
@@ -1716,16 +1719,16 @@ hipError_t launch_gs_update(hipStream_t s, T *p, int nrows, const T *Q, int64_t 
 }
 
 template <typename T>
-hipError_t launch_sumsq(hipStream_t s, const T *p, int nrows, double *part_out) {
-  const RowPlan rp = row_plan(nrows);
+hipError_t launch_sumsq(hipStream_t s, const T *p, int nrows, double *part_out, int min_rows) {
+  const RowPlan rp = row_plan(nrows, min_rows);
   SVT_LAUNCH((k_sumsq<T>), dim3(rp.nblk), dim3(kRowBlock), 0, s, p, nrows, rp.rows_per_blk, part_out);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_finalize(hipStream_t s, const T *p, int nrows, const double *part, T *out,
-                           double *coef_out) {
-  const RowPlan rp = row_plan(nrows);
+                           double *coef_out, int min_rows) {
+  const RowPlan rp = row_plan(nrows, min_rows);
   SVT_LAUNCH((k_gs_scale<T>), dim3(rp.nblk), dim3(kRowBlock), 0, s, p, nrows, part, rp.nblk, out, coef_out);
   return hipGetLastError();
 }
@@ -1957,9 +1960,10 @@ hipError_t launch_gather(hipStream_t s, const T *x, const int32_t *map, T *y, in
                                      const uint16_t *, const T *, const int32_t *, const SpmvInput<T> &, \
                                      int, const T *, T *, int, const T *, int64_t, int, double *);     \
   template hipError_t launch_gs_update<T>(hipStream_t, T *, int, const T *, int64_t, int, const double *, \
-                                          double *, bool, double *);                                   \
-  template hipError_t launch_sumsq<T>(hipStream_t, const T *, int, double *);                          \
-  template hipError_t launch_finalize<T>(hipStream_t, const T *, int, const double *, T *, double *);   \
+                                          double *, bool, double *, int);                              \
+  template hipError_t launch_sumsq<T>(hipStream_t, const T *, int, double *, int);                     \
+  template hipError_t launch_finalize<T>(hipStream_t, const T *, int, const double *, T *, double *,   \
+                                         int);                                                         \
   template hipError_t launch_randn<T>(hipStream_t, T *, int, uint64_t, uint64_t);                  \
   template hipError_t launch_ritz<T>(hipStream_t, const T *, int64_t, int, int, const double *,    \
                                      const double *, int, T *, int);                                \

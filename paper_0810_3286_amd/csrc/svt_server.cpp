@@ -104,6 +104,17 @@ int32_t request_stall(const svt_params &p) {
   return p.stall_window == 0 ? kDefaultStallWindow : p.stall_window;
 }
 
+// A served request that leaves min_block_rows 0 cuts its vectors into row
+// blocks of at least 64 rows: a request of a few thousand rows then runs its
+// half-steps on a few dozen compute units instead of all of them, so that
+// the solves of other slots find free units (a block of 64 rows still
+// takes one workgroup pass).
+constexpr int32_t kServedMinBlockRows = 64;
+
+int32_t request_min_rows(const svt_params &p) {
+  return p.min_block_rows == 0 ? kServedMinBlockRows : p.min_block_rows;
+}
+
 
 }  // namespace
 
@@ -167,6 +178,7 @@ struct svt_server {
     // the step cap the admission footprint assumed
     p.lanczos_maxsteps = (int32_t)request_cap(p);
     p.stall_window = request_stall(p);
+    p.min_block_rows = request_min_rows(p);
     svt_problem *h = nullptr;
     svt_status st = svt_create(r->m, r->n, r->nnz, SVT_COO, r->rows.data(), r->cols.data(), r->vals.data(), &p, &h);
     if (st != SVT_OK) {

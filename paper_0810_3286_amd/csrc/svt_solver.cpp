@@ -406,8 +406,8 @@ struct Problem final : ProblemBase {
       int lds = 0;
       HIP_CHECK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
       lds_limit = std::min(lds, 160 * 1024);
-      plan_r = spmv_plan((int)m, (int)n, (int)sizeof(T), lds_limit, prm.spmv_mode);
-      plan_c = spmv_plan((int)n, (int)m, (int)sizeof(T), lds_limit, prm.spmv_mode);
+      plan_r = spmv_plan((int)m, (int)n, (int)sizeof(T), lds_limit, prm.spmv_mode, mrows());
+      plan_c = spmv_plan((int)n, (int)m, (int)sizeof(T), lds_limit, prm.spmv_mode, mrows());
       if (plan_r.nseg > 1) {
         const auto sr = segment_starts(ix.rowptr, ix.colidx, (int)m, plan_r);
         seg_r.alloc(stream, sizeof(int32_t) * sr.size());
@@ -469,7 +469,7 @@ struct Problem final : ProblemBase {
     nV.alloc(stream, sizeof(T) * (size_t)acols * (size_t)(newcap + 2));
     ncoef.alloc(stream, sizeof(double) * 4 * (size_t)(newcap + 4));
     const int cols = newcap + 4;
-    const int blocks = std::max(row_plan((int)arows).nblk, row_plan((int)acols).nblk);
+    const int blocks = std::max(row_plan((int)arows, mrows()).nblk, row_plan((int)acols, mrows()).nblk);
     n1.alloc(stream, sizeof(double) * (size_t)cols * blocks);
     n2.alloc(stream, sizeof(double) * (size_t)cols * blocks);
     n3.alloc(stream, sizeof(double) * (size_t)blocks);
@@ -575,6 +575,8 @@ struct Problem final : ProblemBase {
             seg_c.as<int32_t>()};
   }
   int spmv_segments(int which) const override { return (which == 0 ? plan_r : plan_c).nseg; }
+  // rows per row block of the vector partition: at least this many
+  int mrows() const { return prm.min_block_rows > 0 ? (int)prm.min_block_rows : kDefaultMinRows; }
   Csx a_rows_struct() { return a_is_y ? csr_struct() : csc_struct(); }
   Csx a_cols_struct() { return a_is_y ? csc_struct() : csr_struct(); }
 
@@ -588,7 +590,7 @@ struct Problem final : ProblemBase {
     if (e == hipErrorInvalidValue && c.plan->nseg > 0) {
       // the device refused the LDS size: gather x from memory from now on
       (void)hipGetLastError();
-      *c.plan = spmv_plan(c.nrows, c.ncols, (int)sizeof(T), lds_limit, 1);
+      *c.plan = spmv_plan(c.nrows, c.ncols, (int)sizeof(T), lds_limit, 1, mrows());
       e = launch_spmv<T>(stream, *c.plan, c.ptr, c.idx, c.idx16, vals, nullptr, in, c.ncols, prev, out, c.nrows,
                          Q, ldq, nq, dots);
     }
@@ -659,7 +661,7 @@ struct Problem final : ProblemBase {
         // too wide to fuse: x's update runs first, in place
         prof.begin();
         HIP_CHECK(launch_gs_update<T>(stream, x_raw, c.ncols, Qx, ldqx, xp.nq, part_buf(xp.buf), gs.part3, true,
-                                      x_removed));
+                                      x_removed, mrows()));
         prof.end(kGsUpdate2, vb * c.ncols * (xp.nq + 2.0));
         xp = PendingVec{3, 0};
       }
@@ -694,16 +696,16 @@ struct Problem final : ProblemBase {
     spmv(c, vals, in, prev, p, Q, ldq, nq, nq > 0 ? gs.part1 : nullptr);
     prof.end(kSpmv, spmv_bytes(c, c.ncols, prev != nullptr) + vb * c.ncols + vb * len * nq);
     if (nq == 0) {
-      HIP_CHECK(launch_sumsq<T>(stream, p, c.nrows, gs.part3));
+      HIP_CHECK(launch_sumsq<T>(stream, p, c.nrows, gs.part3, mrows()));
       return PendingVec{3, 0};
     }
     // each update: Q read once, p read and written (the fused dot products
     // and norms reuse the same rows)
     prof.begin();
-    HIP_CHECK(launch_gs_update<T>(stream, p, c.nrows, Q, ldq, nq, gs.part1, gs.part2, false, nullptr));
+    HIP_CHECK(launch_gs_update<T>(stream, p, c.nrows, Q, ldq, nq, gs.part1, gs.part2, false, nullptr, mrows()));
     prof.end(kGsUpdate1, vb * len * (nq + 2.0));
     prof.begin();
-    HIP_CHECK(launch_gs_update<T>(stream, p, c.nrows, Q, ldq, nq, gs.part2, gs.part3, true, nullptr));
+    HIP_CHECK(launch_gs_update<T>(stream, p, c.nrows, Q, ldq, nq, gs.part2, gs.part3, true, nullptr, mrows()));
     prof.end(kGsUpdate2, vb * len * (nq + 2.0));
     return PendingVec{3, 0};
   }
@@ -717,7 +719,7 @@ struct Problem final : ProblemBase {
     PendingVec pu, pv;        // the raw vectors in pbuf_u and pbuf_v
   };
 
-  int xnp_of(int nrows) const { return row_plan(nrows).nblk; }
+  int xnp_of(int nrows) const { return row_plan(nrows, mrows()).nblk; }
 
   // Start: v_1 random unit, u_1 = A v_1 / alpha_1, then v_2, beta_2.  The
   // removed fraction of the vector made by half-step j goes to slot j (it is
@@ -726,7 +728,7 @@ struct Problem final : ProblemBase {
     ensure_basis(std::min<int64_t>(acols, 8));
     const Csx R = a_rows_struct(), C = a_cols_struct();
     HIP_CHECK(launch_randn<T>(stream, pbuf_v.as<T>(), (int)acols, prm.seed, rng_ctr++));
-    HIP_CHECK(launch_sumsq<T>(stream, pbuf_v.as<T>(), (int)acols, gs.part3));
+    HIP_CHECK(launch_sumsq<T>(stream, pbuf_v.as<T>(), (int)acols, gs.part3, mrows()));
     g.pv = PendingVec{3, 0};
     // u_1 = A v_1 / alpha_1 (v_1 = the normalised start vector)
     g.pu = half_step(R, vr, pbuf_v.as<T>(), g.pv, Vb.as<T>(), acols, vcol(0), beta_d(), nullptr, nullptr,
@@ -770,10 +772,11 @@ struct Problem final : ProblemBase {
         if (g.pv.nq > 0) {
           // an update too wide to fuse runs here, as the next step would
           HIP_CHECK(launch_gs_update<T>(stream, pbuf_v.as<T>(), (int)acols, Vb.as<T>(), acols, g.pv.nq,
-                                        part_buf(g.pv.buf), gs.part3, true, removed_d() + 2 * k - 1));
+                                        part_buf(g.pv.buf), gs.part3, true, removed_d() + 2 * k - 1, mrows()));
           g.pv = PendingVec{3, 0};
         }
-        HIP_CHECK(launch_finalize<T>(stream, pbuf_v.as<T>(), (int)acols, gs.part3, vcol(k), beta_d() + k));
+        HIP_CHECK(launch_finalize<T>(stream, pbuf_v.as<T>(), (int)acols, gs.part3, vcol(k), beta_d() + k,
+                                     mrows()));
       }
       g.finalized = true;
     }
@@ -1488,6 +1491,8 @@ static void validate_params(const svt_params &p) {
     throw Error(SVT_EINVAL, "unknown constraint kind");
   if (!finite(p.ineq_tol) || p.ineq_tol < 0) throw Error(SVT_EINVAL, "ineq_tol must be finite and >= 0");
   if (p.warm_start != 0 && p.warm_start != 1) throw Error(SVT_EINVAL, "warm_start must be 0 or 1");
+  if (p.min_block_rows < 0 || p.min_block_rows > kMaxRowsPerBlock)
+    throw Error(SVT_EINVAL, "min_block_rows must be in [0, 2048]");
 
   if (!finite(p.lanczos_tol) || p.lanczos_tol < 0 || p.lanczos_tol >= 1) throw Error(SVT_EINVAL, "lanczos_tol must be in [0, 1)");
   if (p.lanczos_maxsteps < 0) throw Error(SVT_EINVAL, "lanczos_maxsteps must be >= 0");

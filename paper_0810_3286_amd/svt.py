@@ -62,6 +62,7 @@ class svt_params(ctypes.Structure):
         ("constraint", ctypes.c_int32),
         ("warm_start", ctypes.c_int32),
         ("stall_window", ctypes.c_int32),
+        ("min_block_rows", ctypes.c_int32),
     ]
 
 

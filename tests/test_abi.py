@@ -40,8 +40,8 @@ def test_binding_covers_every_declared_symbol():
 
 def test_struct_layout_matches_header():
     # svt_params: 3 doubles, 6 int32, 2 doubles, 2 int32, double, uint64, 2 int32, pointer,
-    # double, 3 int32 (and 4 bytes of tail padding)
-    assert ctypes.sizeof(B.svt_params) == 3 * 8 + 6 * 4 + 2 * 8 + 2 * 4 + 8 + 8 + 2 * 4 + 8 + 8 + 2 * 4 + 8
+    # double, 4 int32
+    assert ctypes.sizeof(B.svt_params) == 3 * 8 + 6 * 4 + 2 * 8 + 2 * 4 + 8 + 8 + 2 * 4 + 8 + 8 + 4 * 4
     assert ctypes.sizeof(B.svt_info) == 4 * 4 + 6 * 8 + 8
 
 
@@ -91,7 +91,8 @@ def test_rejects_bad_parameters():
     for field, bad in [("tau", 0.0), ("tau", float("inf")), ("delta", -1.0), ("eps", -1e-3),
                        ("maxiter", 0), ("incr", 0), ("kick", 2), ("precision", 5),
                        ("stop_rule", 3), ("lanczos_tol", 1.5), ("reorth_passes", 3),
-                       ("decide_margin", -0.1), ("spmv_mode", 3)]:
+                       ("decide_margin", -0.1), ("spmv_mode", 3), ("min_block_rows", -1),
+                       ("min_block_rows", 2049)]:
         p = B.svt_params_default(2, 2, 2)
         setattr(p, field, bad)
         _expect_einval(2, 2, rows, cols, vals, p)

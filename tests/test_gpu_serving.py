@@ -43,11 +43,18 @@ def _alone(p, prm):
     return st, info, U, w, V
 
 
+def _prm_alone(p, precision):
+    # a request served with min_block_rows left 0 runs with the server's 64
+    prm = _prm(p, precision)
+    prm.min_block_rows = 64
+    return prm
+
+
 @pytest.mark.parametrize("precision", [B.SVT_FP64, B.SVT_MIXED])
 def test_alone_equals_mix(precision):
     gpu_case(f"serving alone vs mix precision {precision}")
     probs = [workload.gaussian_lowrank(*c, shuffle=True) for c in REQS]
-    alone = [_alone(p, _prm(p, precision)) for p in probs]
+    alone = [_alone(p, _prm_alone(p, precision)) for p in probs]
     srv = B.svt_server_create(64 << 30, 4)
     try:
         tickets = [B.svt_submit(srv, p.m, p.n, p.rows, p.cols, p.vals, _prm(p, precision)) for p in probs]

@@ -93,6 +93,7 @@ def test_server_default_window():
             prm.tau, prm.delta, prm.eps, prm.incr, prm.maxiter = p.tau, p.delta, p.eps, p.incr, 150
             prm.precision = B.SVT_MIXED
             prm.stall_window = window
+            prm.min_block_rows = 8      # the free run's row blocks: the same residuals
             tickets.append(B.svt_submit(srv, p.m, p.n, p.rows, p.cols, p.vals, prm))
         st0, info0 = B.svt_wait(srv, tickets[0])
         st1, info1 = B.svt_wait(srv, tickets[1])
