@@ -495,6 +495,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=1)
     ap.add_argument("--spmv-mode", type=int, default=0,
                     help="0 or 2: x staged in LDS (column segments when needed), 1: gathered")
+    ap.add_argument("--min-rows", type=int, default=0,
+                    help="min_block_rows of the headline solve (0: the library default)")
     ap.add_argument("--serving-requests", type=int, default=16)
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--no-serving", action="store_true")
@@ -562,6 +564,7 @@ def main():
         prm.precision = prec
         prm.profile = 1 if profile else 0
         prm.spmv_mode = args.spmv_mode
+        prm.min_block_rows = args.min_rows
         return B.svt_create(p.m, p.n, p.rows, p.cols, p.vals, prm)
 
     log("[bench] svt_create")
@@ -656,6 +659,7 @@ def main():
         prm.tau, prm.delta, prm.eps, prm.maxiter, prm.incr = p.tau, p.delta, p.eps, p.maxiter, p.incr
         prm.precision = B.SVT_MIXED if other == "mixed" else B.SVT_FP64
         prm.spmv_mode = args.spmv_mode
+        prm.min_block_rows = args.min_rows
         ho = B.svt_create(p.m, p.n, p.rows, p.cols, p.vals, prm)
         try:
             log(f"[bench] {other} solves")
