@@ -322,6 +322,39 @@ def sensing_runs(seed: int = 0) -> dict:
     return {"sensing": out}
 
 
+def randomized_runs(maxiter: int = 200) -> dict:
+    """D_tau by the randomised range finder (Section 6) against the
+    Lanczos partial SVD on 400^2 (rank 10, 6 d_r) and 5000^2 (rank 10,
+    5 d_r), FP64: status, iterations, the smallest residual reached and the
+    error against the truth, for 1, 2 and 4 power iterations."""
+    import workload
+    from paper_0810_3286_amd import svt as B
+    from tests.helpers import rel_diff_factored
+    out = []
+    for cfg in (1, 2):
+        p = workload.config(cfg)
+        for method, power in ((B.SVT_SVD_LANCZOS, 0), (B.SVT_SVD_RANDOMIZED, 1), (B.SVT_SVD_RANDOMIZED, 2),
+                              (B.SVT_SVD_RANDOMIZED, 4)):
+            prm = B.svt_params_default(p.m, p.n, p.nnz)
+            prm.tau, prm.delta, prm.eps, prm.maxiter, prm.incr = p.tau, p.delta, p.eps, maxiter, p.incr
+            prm.svd_method = method
+            prm.rsvd_power = power
+            h = B.svt_create(p.m, p.n, p.rows, p.cols, p.vals, prm)
+            try:
+                st, info, dt = _timed_solve(B, h)
+                U, w, V = B.svt_factors(h, p.m, p.n)
+                hist = B.svt_history(h)
+            finally:
+                B.svt_destroy(h)
+            rec = {"config": f"{p.m}x{p.n} r{p.r}", "method": "lanczos" if method == B.SVT_SVD_LANCZOS else
+                   f"randomized q={power}", "status": B.svt_status_string(st), "iters": int(info.iters),
+                   "seconds": dt, "svt_iters_per_s": info.iters / dt, "min_residual": float(np.min(hist["residuals"])),
+                   "rel_error_vs_truth": rel_diff_factored(U, V, p.ML, p.MR), "final_rank": int(info.rank)}
+            out.append(rec)
+            log(f"[bench] randomized {rec}")
+    return {"randomized_svd": out}
+
+
 def copy_calibration(mib: int, reps: int = 3):
     """Device-to-device copies of a known size through the HIP runtime's copy
     kernel: under rocprofv3 --pmc its FETCH_SIZE / WRITE_SIZE per dispatch,
@@ -520,6 +553,8 @@ def main():
                     help="run Figure 3's inequality-constrained (Dantzig selector) workload and print its results")
     ap.add_argument("--sensing", action="store_true",
                     help="run a general-linear-operator (sparse measurement) workload and print its results")
+    ap.add_argument("--randomized", action="store_true",
+                    help="compare the randomised partial SVD with the Lanczos one and print the results")
     ap.add_argument("--traffic-mib", type=int, default=256)
     ap.add_argument("--traffic-bench-json", help="the JSON line of the counted bench run")
     args = ap.parse_args()
@@ -542,6 +577,9 @@ def main():
         return
     if args.sensing:
         print(json.dumps(sensing_runs()), flush=True)
+        return
+    if args.randomized:
+        print(json.dumps(randomized_runs()), flush=True)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:

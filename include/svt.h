@@ -50,6 +50,17 @@ typedef enum {
 typedef enum { SVT_FP64 = 0, SVT_MIXED = 1 } svt_precision;
 typedef enum { SVT_COO = 0, SVT_CSR = 1 } svt_index_format;
 typedef enum { SVT_STOP_RELRES = 0, SVT_STOP_NOISY = 1 } svt_stop_rule;
+/* How D_tau finds the singular triplets of Y above tau:
+   SVT_SVD_LANCZOS: Golub-Kahan-Lanczos bidiagonalisation until the rank
+   decision is certain (Section 5.1.1), the default;
+   SVT_SVD_RANDOMIZED: the randomised range finder with power iterations
+   that Section 6 proposes (Halko, Martinsson and Tropp, 2011): for each s_k
+   of Algorithm 1's repeat loop, l = min(m, n, s_k + rsvd_oversample)
+   Gaussian test vectors, rsvd_power power iterations, and the SVD of the
+   projected matrix.  Approximate: with a fixed number of power iterations
+   the values near tau carry an error that can stall the iteration above
+   eps.  Matrix completion with equality constraints only. */
+typedef enum { SVT_SVD_LANCZOS = 0, SVT_SVD_RANDOMIZED = 1 } svt_svd_method;
 /* SVT_CONSTRAINT_EQUALITY: X = M on Omega in the limit (Algorithm 1).
    SVT_CONSTRAINT_INEQUALITY: the matrix Dantzig selector of Section 3.3 for
    completion, |X_ij - B_ij| <= E on Omega (eq. (3.8) with A = P_Omega),
@@ -134,6 +145,10 @@ typedef struct {
                             64 for requests that leave it 0.  The partial
                             sums follow the blocks, so results depend on it
                             at rounding level                               */
+  int32_t svd_method;    /* svt_svd_method; default SVT_SVD_LANCZOS          */
+  int32_t rsvd_oversample; /* extra test vectors of the randomised SVD, >= 0
+                              (default 10)                                   */
+  int32_t rsvd_power;    /* its power iterations, 0..64 (default 2)          */
 } svt_params;
 
 typedef struct {

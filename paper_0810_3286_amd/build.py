@@ -25,6 +25,7 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 SOURCES = [
     ("svt_kernels.hip", True),
     ("bidiag.cpp", False),
+    ("dense_host.cpp", False),
     ("svt_solver.cpp", False),
     ("svt_server.cpp", False),
 ]

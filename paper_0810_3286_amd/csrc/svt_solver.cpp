@@ -36,6 +36,7 @@
 #include <vector>
 
 #include "bidiag.h"
+#include "dense_host.h"
 #include "svt_kernels.h"
 
 namespace svt {
@@ -327,6 +328,8 @@ struct Problem final : ProblemBase {
   int rank = 0;
   std::vector<double> w;          // sigma - tau
   uint64_t rng_ctr = 0;
+  uint64_t rs_ctr = 0;            // test matrices drawn by the randomised partial SVD in a solve
+  DevMem rs_a, rs_b;              // its device blocks (rows x l, column-major, T)
   int k_hint = 0;
   int log_level = 0;
   int64_t steps_total = 0;
@@ -544,7 +547,7 @@ struct Problem final : ProblemBase {
     return {&rowptr, &colidx, &colptr, &rowidx, &csr_of_csc, &seg_r, &seg_c, &colidx16, &rowidx16,
             &Mr, &Mc, &Yr, &Yc, &Yp, &Ym, &g_ptr, &g_idx, &g_val, &gt_ptr,
             &gt_idx, &gt_val, &b_d, &y_d, &xs_d, &Ub, &Vb, &pbuf_u, &pbuf_v, &coef, &gs1, &gs2, &gs3, &gsr,
-            &sample_part, &ritzd, &Fu, &Fv};
+            &sample_part, &ritzd, &Fu, &Fv, &rs_a, &rs_b};
   }
   size_t device_bytes() const {
     size_t b = 0;
@@ -954,6 +957,124 @@ struct Problem final : ProblemBase {
     }
   }
 
+  // ------------------------------------------- randomised partial SVD
+  // p = Y x (trans 0, rows m) or Y^T x (trans 1, rows n), x and p on the
+  // device: the sparse product with nothing pending and no previous vector.
+  void plain_product(int trans, const T *x, T *out) {
+    SpmvInput<T> in;
+    in.x = x;
+    const Csx c = trans == 0 ? csr_struct() : csc_struct();
+    spmv(c, trans == 0 ? Yr.as<T>() : Yc.as<T>(), in, nullptr, out);
+  }
+
+  // out (rows x l, device) = Y or Y^T times the l columns of x (device).
+  void block_product(int trans, const T *x, int l, T *out) {
+    const int64_t xr = trans == 0 ? ix.n : ix.m, orows = trans == 0 ? ix.m : ix.n;
+    for (int j = 0; j < l; ++j) plain_product(trans, x + (size_t)j * xr, out + (size_t)j * orows);
+  }
+
+  void to_host(const DevMem &d, int64_t count, std::vector<double> &h) {
+    std::vector<T> t((size_t)count);
+    HIP_CHECK(hipMemcpyAsync(t.data(), d.p, sizeof(T) * count, hipMemcpyDeviceToHost, stream));
+    HIP_CHECK(hipStreamSynchronize(stream));
+    h.assign(t.begin(), t.end());
+  }
+  void to_device(const std::vector<double> &h, DevMem &d) {
+    std::vector<T> t(h.begin(), h.end());
+    HIP_CHECK(hipMemcpyAsync(d.p, t.data(), sizeof(T) * t.size(), hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipStreamSynchronize(stream));
+  }
+
+  // The s largest singular triplets of Y, approximated by the randomised
+  // range finder with power iterations (Section 6 proposes randomised
+  // low-rank SVDs for D_tau; the method is that of Halko, Martinsson and
+  // Tropp, 2011): l = min(m, n, s + oversample) Gaussian columns Omega
+  // (the counter-based generator of the start vectors, one counter per
+  // matrix drawn in a solve), Q = orth(Y Omega), then `power` times
+  // P = orth(Y^T Q), Q = orth(Y P); W = Y^T Q = Vw S Uw^T; U = Q Uw, V = Vw.
+  // The sparse products run on the device, one vector at a time; the
+  // orthonormalisations and the small SVD on the host.  Returns the number
+  // of sparse products.
+  int randomized_triplets(int s, std::vector<double> &sigma, std::vector<double> &U, std::vector<double> &V) {
+    const int64_t m = ix.m, n = ix.n;
+    const int64_t cap = std::min(m, n);
+    const int l = (int)std::min<int64_t>(cap, (int64_t)s + prm.rsvd_oversample);
+    const int64_t big = std::max(m, n);
+    if (rs_a.bytes < sizeof(T) * (size_t)big * l) {
+      rs_a.alloc(stream, sizeof(T) * (size_t)big * l);
+      rs_b.alloc(stream, sizeof(T) * (size_t)big * l);
+      note_peak(0);
+    }
+    T *a = rs_a.as<T>(), *b = rs_b.as<T>();
+    int products = 0;
+    HIP_CHECK(launch_randn<T>(stream, a, (int)(n * l), prm.seed, rs_ctr++));   // Omega, n x l
+    block_product(0, a, l, b);                                                 // Y Omega, m x l
+    products += l;
+    std::vector<double> Q, P, W;
+    to_host(rs_b, m * l, Q);
+    orth_columns(Q.data(), m, l);
+    for (int it = 0; it < prm.rsvd_power; ++it) {
+      to_device(Q, rs_a);
+      block_product(1, a, l, b);      // Y^T Q, n x l
+      to_host(rs_b, n * l, P);
+      orth_columns(P.data(), n, l);
+      to_device(P, rs_a);
+      block_product(0, a, l, b);      // Y P, m x l
+      to_host(rs_b, m * l, Q);
+      orth_columns(Q.data(), m, l);
+      products += 2 * l;
+    }
+    to_device(Q, rs_a);
+    block_product(1, a, l, b);        // W = Y^T Q, n x l
+    products += l;
+    to_host(rs_b, n * l, W);
+    std::vector<double> Vw, Uw;
+    if (!jacobi_svd_tall(W.data(), n, l, sigma, Vw, Uw))
+      throw Error(SVT_ELANCZOS, "randomised partial SVD: the small SVD did not settle");
+    U.assign((size_t)m * l, 0.0);     // Q Uw
+    for (int c = 0; c < l; ++c)
+      for (int j = 0; j < l; ++j) {
+        const double f = Uw[(size_t)c * l + j];
+        const double *qj = Q.data() + (size_t)j * m;
+        double *uc = U.data() + (size_t)c * m;
+        for (int64_t i = 0; i < m; ++i) uc[i] += qj[i] * f;
+      }
+    V.swap(Vw);
+    return products;
+  }
+
+  // One SVT iteration's D_tau by the randomised triplets, with Algorithm 1's
+  // repeat loop over s_k (Section 5.1.1) and the factors of X^k into Fu, Fv.
+  void randomized_iteration(int r_prev, int &r, int &s, int &steps, std::vector<double> &ws) {
+    const int64_t m = ix.m, n = ix.n;
+    const int cap = (int)std::min(m, n);
+    s = std::min(r_prev + 1, cap);
+    std::vector<double> sigma, U, V;
+    int products = 0;
+    for (;;) {
+      products += randomized_triplets(s, sigma, U, V);
+      if (sigma[(size_t)s - 1] <= prm.tau || s >= cap) break;
+      s = std::min(s + (int)prm.incr, cap);
+    }
+    r = 0;
+    while (r < s && sigma[(size_t)r] > prm.tau) ++r;
+    steps = (products + 1) / 2;
+    steps_total += steps;
+    ws.assign(std::max(r, 1), 0.0);
+    for (int i = 0; i < r; ++i) ws[(size_t)i] = sigma[(size_t)i] - prm.tau;
+    ensure_factors(std::max(r, 1), 1);
+    rank = r;
+    if (r == 0) return;
+    std::vector<T> fu((size_t)m * fstride, (T)0), fv((size_t)n * fstride, (T)0);
+    for (int c = 0; c < r; ++c) {
+      for (int64_t i = 0; i < m; ++i) fu[(size_t)i * fstride + c] = (T)(U[(size_t)c * m + i] * ws[(size_t)c]);
+      for (int64_t j = 0; j < n; ++j) fv[(size_t)j * fstride + c] = (T)V[(size_t)c * n + j];
+    }
+    HIP_CHECK(hipMemcpyAsync(Fu.p, fu.data(), sizeof(T) * fu.size(), hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipMemcpyAsync(Fv.p, fv.data(), sizeof(T) * fv.size(), hipMemcpyHostToDevice, stream));
+    HIP_CHECK(hipStreamSynchronize(stream));
+  }
+
   // Ritz vectors for the first r triplets; ws scales the left factor of Y.
   void form_factors(const Gkl &g, const BidiagSVD &sv, int r, const double *ws) {
     const int k = g.k;
@@ -1217,6 +1338,7 @@ struct Problem final : ProblemBase {
     prof.reset();
     steps_total = 0;
     rng_ctr = 0;
+    rs_ctr = 0;
     k_hint = 0;
     rank = 0;
     w.clear();
@@ -1266,17 +1388,22 @@ struct Problem final : ProblemBase {
       inf.k0 = k0;
 
       for (k = 1; k <= prm.maxiter; ++k) {
-        Gkl g;
-        BidiagSVD sv;
-        int r = 0;
-        const int steps = gkl_run(yr, yc, 0, 0, prm.tau, g, sv, r);
-        k_hint = steps;
-        // s_k bookkeeping of Algorithm 1's repeat loop (Section 5.1.1)
-        int s = std::min<int64_t>(r_prev + 1, acols);
-        while (s <= r && s < acols) s = (int)std::min<int64_t>(s + prm.incr, acols);
-        std::vector<double> ws(std::max(r, 1));
-        for (int i = 0; i < r; ++i) ws[i] = sv.sigma[i] - prm.tau;
-        form_factors(g, sv, r, ws.data());
+        int r = 0, s = 0, steps = 0;
+        std::vector<double> ws;
+        if (prm.svd_method == SVT_SVD_RANDOMIZED) {
+          randomized_iteration(r_prev, r, s, steps, ws);
+        } else {
+          Gkl g;
+          BidiagSVD sv;
+          steps = gkl_run(yr, yc, 0, 0, prm.tau, g, sv, r);
+          k_hint = steps;
+          // s_k bookkeeping of Algorithm 1's repeat loop (Section 5.1.1)
+          s = std::min<int64_t>(r_prev + 1, acols);
+          while (s <= r && s < acols) s = (int)std::min<int64_t>(s + prm.incr, acols);
+          ws.assign(std::max(r, 1), 0.0);
+          for (int i = 0; i < r; ++i) ws[i] = sv.sigma[i] - prm.tau;
+          form_factors(g, sv, r, ws.data());
+        }
         w.assign(ws.begin(), ws.begin() + r);
         double plain2 = 0.0;  // Dantzig selector: ||P_Omega(X - B)||^2 beside the violation
         const double res2 = sensing ? sensing_pass(r, prm.delta) : sample_pass(r, prm.delta, true, &plain2);
@@ -1493,6 +1620,12 @@ static void validate_params(const svt_params &p) {
   if (p.warm_start != 0 && p.warm_start != 1) throw Error(SVT_EINVAL, "warm_start must be 0 or 1");
   if (p.min_block_rows < 0 || p.min_block_rows > kMaxRowsPerBlock)
     throw Error(SVT_EINVAL, "min_block_rows must be in [0, 2048]");
+  if (p.svd_method != SVT_SVD_LANCZOS && p.svd_method != SVT_SVD_RANDOMIZED)
+    throw Error(SVT_EINVAL, "unknown svd_method");
+  if (p.rsvd_oversample < 0 || p.rsvd_power < 0 || p.rsvd_power > 64)
+    throw Error(SVT_EINVAL, "rsvd_oversample must be >= 0 and rsvd_power in [0, 64]");
+  if (p.svd_method == SVT_SVD_RANDOMIZED && p.constraint != SVT_CONSTRAINT_EQUALITY)
+    throw Error(SVT_EINVAL, "the randomised partial SVD serves the equality form only");
 
   if (!finite(p.lanczos_tol) || p.lanczos_tol < 0 || p.lanczos_tol >= 1) throw Error(SVT_EINVAL, "lanczos_tol must be in [0, 1)");
   if (p.lanczos_maxsteps < 0) throw Error(SVT_EINVAL, "lanczos_maxsteps must be >= 0");
@@ -1552,6 +1685,9 @@ svt_status svt_params_default(int64_t m, int64_t n, int64_t nnz, svt_params *out
   out->lanczos_maxsteps = 0;
   out->reorth_passes = 0;
   out->decide_margin = 0.05;
+  out->svd_method = SVT_SVD_LANCZOS;
+  out->rsvd_oversample = 10;
+  out->rsvd_power = 2;
   out->seed = 0x5EEDull;
   out->profile = 0;
   out->stream = nullptr;
@@ -1649,6 +1785,8 @@ svt_status svt_create_sensing(int64_t m, int64_t n, int64_t ns, const int32_t *s
     if (ns < 1 || (double)ns > (double)m * (double)n || ns > INT32_MAX) throw Error(SVT_EINVAL, "bad support size");
     if (p < 1 || p > INT32_MAX) throw Error(SVT_EINVAL, "bad measurement count");
     if (!srows || !scols || !gptr || !gidx || !gval || !b) throw Error(SVT_EINVAL, "NULL array");
+    if (params && params->svd_method != SVT_SVD_LANCZOS)
+      throw Error(SVT_EINVAL, "the randomised partial SVD serves matrix completion only");
     if (gptr[0] != 0) throw Error(SVT_EINVAL, "gptr must start at 0");
     for (int64_t i = 0; i < p; ++i)
       if (gptr[i + 1] < gptr[i]) throw Error(SVT_EINVAL, "gptr must be non-decreasing");

@@ -33,6 +33,8 @@ SVT_STOP_RELRES = 0
 SVT_STOP_NOISY = 1
 SVT_CONSTRAINT_EQUALITY = 0
 SVT_CONSTRAINT_INEQUALITY = 1
+SVT_SVD_LANCZOS = 0
+SVT_SVD_RANDOMIZED = 1
 
 KERNEL_KINDS = {0: "k_spmv", 1: "k_gather", 2: "k_gs_update_pass1", 3: "k_ritz", 4: "k_sample_update",
                 5: "k_gs_update_pass2", 6: "k_pending_reduce"}
@@ -63,6 +65,9 @@ class svt_params(ctypes.Structure):
         ("warm_start", ctypes.c_int32),
         ("stall_window", ctypes.c_int32),
         ("min_block_rows", ctypes.c_int32),
+        ("svd_method", ctypes.c_int32),
+        ("rsvd_oversample", ctypes.c_int32),
+        ("rsvd_power", ctypes.c_int32),
     ]
 
 

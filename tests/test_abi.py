@@ -38,10 +38,20 @@ def test_binding_covers_every_declared_symbol():
     assert all(hasattr(B, n) for n in names), sorted(n for n in names if not hasattr(B, n))
 
 
+def test_randomized_svd_refused_outside_completion():
+    rows = np.array([0, 1], dtype=np.int32)
+    cols = np.array([0, 1], dtype=np.int32)
+    vals = np.array([1.0, 2.0])
+    p = B.svt_params_default(2, 2, 2)
+    p.svd_method = B.SVT_SVD_RANDOMIZED
+    p.constraint = B.SVT_CONSTRAINT_INEQUALITY
+    _expect_einval(2, 2, rows, cols, vals, p)
+
+
 def test_struct_layout_matches_header():
     # svt_params: 3 doubles, 6 int32, 2 doubles, 2 int32, double, uint64, 2 int32, pointer,
-    # double, 4 int32
-    assert ctypes.sizeof(B.svt_params) == 3 * 8 + 6 * 4 + 2 * 8 + 2 * 4 + 8 + 8 + 2 * 4 + 8 + 8 + 4 * 4
+    # double, 7 int32 (and 4 bytes of tail padding)
+    assert ctypes.sizeof(B.svt_params) == 3 * 8 + 6 * 4 + 2 * 8 + 2 * 4 + 8 + 8 + 2 * 4 + 8 + 8 + 7 * 4 + 4
     assert ctypes.sizeof(B.svt_info) == 4 * 4 + 6 * 8 + 8
 
 
@@ -92,7 +102,8 @@ def test_rejects_bad_parameters():
                        ("maxiter", 0), ("incr", 0), ("kick", 2), ("precision", 5),
                        ("stop_rule", 3), ("lanczos_tol", 1.5), ("reorth_passes", 3),
                        ("decide_margin", -0.1), ("spmv_mode", 3), ("min_block_rows", -1),
-                       ("min_block_rows", 2049)]:
+                       ("min_block_rows", 2049), ("svd_method", 2), ("rsvd_oversample", -1),
+                       ("rsvd_power", 65)]:
         p = B.svt_params_default(2, 2, 2)
         setattr(p, field, bad)
         _expect_einval(2, 2, rows, cols, vals, p)
