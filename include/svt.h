@@ -96,7 +96,8 @@ typedef struct {
   double lanczos_tol;    /* Ritz residual bound, relative to the largest Ritz
                             value; 0 = automatic: 1e-12 FP64, 1e-6 MIXED       */
   int32_t lanczos_maxsteps; /* cap on bidiagonalisation steps per SVT step
-                               (0 = min(m, n))                                 */
+                               (0 = min(m, n)); with the randomised SVD the
+                               cap on s_k                                      */
   int32_t reorth_passes; /* classical Gram-Schmidt against the whole basis:
                             0 (default) one pass per vector, recording the
                             fraction of the vector's |.|^2 it removes; if a

@@ -61,7 +61,8 @@ struct Request {
 // (the handle's step cap: its bases never grow past it, and the rank of X,
 // hence the factor width, cannot exceed it).  Counts every buffer a handle
 // allocates, with a growing buffer's old and new copies both live.
-size_t footprint_bytes(int64_t m, int64_t n, int64_t nnz, int32_t precision, double kmax, bool ds = false) {
+size_t footprint_bytes(int64_t m, int64_t n, int64_t nnz, int32_t precision, double kmax, bool ds = false,
+                       int rsvd_oversample = -1) {
   const double vb = precision == SVT_MIXED ? 4.0 : 8.0;
   const double big = (double)std::max(m, n), small = (double)std::min(m, n);
   const double kcap = std::min(small, kmax);
@@ -73,6 +74,8 @@ size_t footprint_bytes(int64_t m, int64_t n, int64_t nnz, int32_t precision, dou
   b += 4.0 * 9.0 * (double)(m + n);                        // LDS plan segment starts (up to 8 segments)
   b += 4.0 * vb * (double)nnz;                             // M and Y, both orders
   if (ds) b += 2.0 * vb * (double)nnz;                     // the Dantzig selector's two multipliers
+  if (rsvd_oversample >= 0)                                // the randomised SVD's two blocks
+    b += 2.0 * vb * big * std::min(small, kmax + (double)rsvd_oversample);
   double grow = 0.0;                                       // buffers that grow with the basis
   grow += vb * (big * (kcap + 1) + small * (kcap + 2));    // Lanczos bases
   grow += 8.0 * (kcap + 4) * (4.0 + 2.0 * nblk + 1.0) + 8.0 * nblk;  // coefficients and partials
@@ -242,7 +245,8 @@ svt_status svt_submit(svt_server *s, int64_t m, int64_t n, int64_t nnz, const in
   if (params) r->prm = *params;
   else svt_params_default(m, n, nnz, &r->prm);
   r->footprint = footprint_bytes(m, n, nnz, r->prm.precision, request_cap(r->prm),
-                                 r->prm.constraint == SVT_CONSTRAINT_INEQUALITY);
+                                 r->prm.constraint == SVT_CONSTRAINT_INEQUALITY,
+                                 r->prm.svd_method == SVT_SVD_RANDOMIZED ? r->prm.rsvd_oversample : -1);
   r->rows.assign(rows, rows + nnz);
   r->cols.assign(cols, cols + nnz);
   r->vals.assign(vals, vals + nnz);

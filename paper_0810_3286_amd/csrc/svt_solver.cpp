@@ -1048,12 +1048,16 @@ struct Problem final : ProblemBase {
   void randomized_iteration(int r_prev, int &r, int &s, int &steps, std::vector<double> &ws) {
     const int64_t m = ix.m, n = ix.n;
     const int cap = (int)std::min(m, n);
+    const int scap = step_cap();   // lanczos_maxsteps, when given, bounds s_k here too
     s = std::min(r_prev + 1, cap);
     std::vector<double> sigma, U, V;
     int products = 0;
     for (;;) {
       products += randomized_triplets(s, sigma, U, V);
       if (sigma[(size_t)s - 1] <= prm.tau || s >= cap) break;
+      if (s >= scap)
+        throw Error(SVT_ELANCZOS, "randomised partial SVD: s_k reached the step cap (" + std::to_string(scap) +
+                                      ") with its last value above tau");
       s = std::min(s + (int)prm.incr, cap);
     }
     r = 0;

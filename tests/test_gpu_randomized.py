@@ -74,3 +74,31 @@ def test_refused_for_the_dantzig_selector():
     with pytest.raises(B.SvtError):
         solve(p.m, p.n, p.rows, p.cols, p.vals, svd_method=B.SVT_SVD_RANDOMIZED,
               constraint=B.SVT_CONSTRAINT_INEQUALITY, ineq_tol=0.1)
+
+
+def test_step_cap_bounds_s():
+    # lanczos_maxsteps caps s_k: a rank above it ends with SVT_ELANCZOS.  No
+    # kick, so that the cap meets the randomised SVD, not the kick's
+    # bidiagonalisation
+    gpu_case("randomised SVD step cap")
+    p = workload.config(1)
+    with pytest.raises(B.SvtError) as e:
+        _gpu_capped(p, 4, 20)
+    assert e.value.status == B.SVT_ELANCZOS and "randomised" in str(e.value)
+    assert e.value.info.iters >= 1
+    g = _gpu_capped(p, 16, 5)
+    assert g[0] == B.SVT_NOT_CONVERGED and g[1].iters == 5
+
+
+def _gpu_capped(p, cap, maxiter):
+    prm = B.svt_params_default(p.m, p.n, p.nnz)
+    prm.tau, prm.delta, prm.eps, prm.maxiter, prm.incr = p.tau, p.delta, 0.0, maxiter, p.incr
+    prm.kick = 0
+    prm.svd_method = B.SVT_SVD_RANDOMIZED
+    prm.seed = SEED
+    prm.lanczos_maxsteps = cap
+    h = B.svt_create(p.m, p.n, p.rows, p.cols, p.vals, prm)
+    try:
+        return B.svt_solve(h)
+    finally:
+        B.svt_destroy(h)
