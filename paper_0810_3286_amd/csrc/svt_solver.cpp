@@ -1000,6 +1000,8 @@ struct Problem final : ProblemBase {
     const int64_t cap = std::min(m, n);
     const int l = (int)std::min<int64_t>(cap, (int64_t)s + prm.rsvd_oversample);
     const int64_t big = std::max(m, n);
+    if (big * (int64_t)l > INT32_MAX)
+      throw Error(SVT_EINVAL, "randomised partial SVD: max(m, n) x (s_k + oversample) exceeds 2^31 entries");
     if (rs_a.bytes < sizeof(T) * (size_t)big * l) {
       rs_a.alloc(stream, sizeof(T) * (size_t)big * l);
       rs_b.alloc(stream, sizeof(T) * (size_t)big * l);
