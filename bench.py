@@ -470,11 +470,16 @@ def serving_bench(n_req: int, slots: int, budget_gib: float, precision: int, see
         tickets = [B.svt_submit(srv, p.m, p.n, p.rows, p.cols, p.vals, params(p)) for p in closed]
         iters = 0
         entries = 0
+        spmv_bytes = 0.0
+        vbytes = 4.0 if precision == B.SVT_MIXED else 8.0
         closed_ok = 0
         for i, t in enumerate(tickets):
             st, info = B.svt_wait(srv, t)
             iters += info.iters
             entries += info.iters * closed[i].nnz
+            # the sparse products' algorithmic bytes: two per bidiagonalisation
+            # step, each streaming every stored entry (value and 16-bit index)
+            spmv_bytes += 2.0 * info.gkl_steps * closed[i].nnz * (vbytes + 2.0)
             statuses.append(st)
             closed_ok += int(st == B.SVT_OK)
             B.svt_release(srv, t)
@@ -500,6 +505,9 @@ def serving_bench(n_req: int, slots: int, budget_gib: float, precision: int, see
         "closed_loop_requests_per_s": capacity,
         "closed_loop_svt_iters_per_s": iters / t_closed,
         "closed_loop_sampled_entries_per_s": entries / t_closed,
+        # aggregate HBM rate of the sparse products over the closed loop
+        # (their stored entries only), as a fraction of the 8 TB/s peak
+        "closed_loop_spmv_hbm_frac": spmv_bytes / t_closed / 8e12,
         "mix": mix, "step_cap": step_cap,
         "status_counts": {B.svt_status_string(k): int(v) for k, v in
                           zip(*np.unique(np.array(statuses), return_counts=True))},
