@@ -536,6 +536,9 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=1)
     ap.add_argument("--spmv-mode", type=int, default=0,
                     help="0 or 2: x staged in LDS (column segments when needed), 1: gathered")
+    ap.add_argument("--reorth-eta", type=float, default=None,
+                    help="partial reorthogonalisation level of the FP64 solves (0: full; "
+                         "default: the library's)")
     ap.add_argument("--min-rows", type=int, default=0,
                     help="min_block_rows of the headline solve (0: the library default)")
     ap.add_argument("--serving-requests", type=int, default=16)
@@ -604,6 +607,8 @@ def main():
     prec = B.SVT_MIXED if args.precision == "mixed" else B.SVT_FP64
     wl_name = p.name
 
+    eta_used = [0.0]
+
     def make(profile):
         prm = B.svt_params_default(p.m, p.n, p.nnz)
         prm.tau, prm.delta, prm.eps, prm.maxiter, prm.incr = p.tau, p.delta, p.eps, p.maxiter, p.incr
@@ -611,6 +616,9 @@ def main():
         prm.profile = 1 if profile else 0
         prm.spmv_mode = args.spmv_mode
         prm.min_block_rows = args.min_rows
+        if prec == B.SVT_FP64 and args.reorth_eta is not None:
+            prm.reorth_eta = args.reorth_eta
+        eta_used[0] = prm.reorth_eta
         return B.svt_create(p.m, p.n, p.rows, p.cols, p.vals, prm)
 
     log("[bench] svt_create")
@@ -630,6 +638,7 @@ def main():
         t_total = time.perf_counter() - t0
         U, w, V = B.svt_factors(h, p.m, p.n)
         hist = B.svt_history(h)
+        reorth = B.svt_reorth_stats(h)
     finally:
         B.svt_destroy(h)
 
@@ -687,6 +696,9 @@ def main():
         "rel_error_vs_truth": relerr,
         "final_rank": int(hist["ranks"][-1]) if len(hist["ranks"]) else 0,
         "gkl_steps_per_iter": float(np.mean(hist["gkl_steps"])) if len(hist["gkl_steps"]) else 0.0,
+        "reorth": {"eta": eta_used[0], "vectors": reorth[0],
+                   "orthogonalised": reorth[1], "two_pass_restarts": reorth[2],
+                   "partial_fallbacks": reorth[3]},
         "kernels": {KIND_NAMES[k]: {"launches": v[0], "ms": v[1],
                                     "avg_us": v[1] * 1e3 / max(v[0], 1),
                                     "bytes_per_launch": v[2] / max(v[0], 1),
@@ -704,6 +716,8 @@ def main():
         prm = B.svt_params_default(p.m, p.n, p.nnz)
         prm.tau, prm.delta, prm.eps, prm.maxiter, prm.incr = p.tau, p.delta, p.eps, p.maxiter, p.incr
         prm.precision = B.SVT_MIXED if other == "mixed" else B.SVT_FP64
+        if prm.precision == B.SVT_FP64 and args.reorth_eta is not None:
+            prm.reorth_eta = args.reorth_eta
         prm.spmv_mode = args.spmv_mode
         prm.min_block_rows = args.min_rows
         ho = B.svt_create(p.m, p.n, p.rows, p.cols, p.vals, prm)

@@ -150,6 +150,26 @@ typedef struct {
   int32_t rsvd_oversample; /* extra test vectors of the randomised SVD, >= 0
                               (default 10)                                   */
   int32_t rsvd_power;    /* its power iterations, 0..64 (default 2)          */
+  double reorth_eta;     /* In (0, 1e-4] (default 1e-10): partial
+                            reorthogonalisation (Section 5.1.1): the loss of
+                            orthogonality of each new vector of the
+                            bidiagonalisation is estimated from the
+                            bidiagonal coefficients alone (the recurrences
+                            of Simon and Larsen), and a vector is
+                            orthogonalised against its whole basis, with the
+                            next vector of the other side, only once its
+                            predicted estimate passes reorth_eta.  With the
+                            MIXED form's FP32 vectors the rounding of a new
+                            vector alone exceeds 1e-10, so at the default
+                            every vector is orthogonalised there.  0: every
+                            new vector is orthogonalised.
+                            The estimates are checked as the coefficients
+                            reach the host; if one of a vector left alone
+                            passed sqrt(unit roundoff) the bidiagonalisation
+                            starts again with full reorthogonalisation, kept
+                            for the rest of the solve.  Applies with one
+                            Gram-Schmidt pass per vector (reorth_passes 0 or
+                            1); svt_reorth_stats reports what it did       */
 } svt_params;
 
 typedef struct {
@@ -366,6 +386,18 @@ svt_status svt_device_bytes(const svt_problem *h, size_t *current, size_t *peak)
    Any output pointer may be NULL; EINVAL for a kind outside 0..6. */
 svt_status svt_kernel_stats(const svt_problem *h, int32_t kind, int64_t *launches,
                             double *total_ms, double *total_bytes);
+
+/* Reorthogonalisation of the bidiagonalisation (Section 5.1.1) over the
+   handle's last solve (svt_solve, svt_solve_path's last solve, or
+   svt_partial_svd / svt_kick): the number of vectors the bidiagonalisation
+   made (every half-step, including steps taken ahead of a check and then
+   discarded), how many of them were orthogonalised against their basis (all
+   but the first without reorth_eta), how many bidiagonalisations restarted
+   with two Gram-Schmidt passes (reorth_passes 0), and how many times partial
+   reorthogonalisation fell back to full.  Any output pointer may be NULL;
+   EINVAL for a NULL handle. */
+svt_status svt_reorth_stats(const svt_problem *h, int64_t *vectors, int64_t *orthogonalised,
+                            int64_t *two_pass_restarts, int64_t *partial_fallbacks);
 
 /* ---------------------------------------------------------------------
  * Serving form: continuous batching of completion requests on one GPU.

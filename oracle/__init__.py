@@ -20,6 +20,12 @@ Contents (each function cites the passage of the paper it writes out):
 * ``krylov.svt_krylov`` Algorithm 1, tier C: sparse Y, the s_k largest
                        triplets from a library partial SVD (SciPy / ARPACK),
                        the repeat loop over s_k as printed
+
+Modules beside the package's exports: ``general`` (linear measurements,
+Section 3.1), ``dantzig`` (the matrix Dantzig selector, Section 3.3),
+``randomized`` (the randomised partial SVD, Section 6), ``block_krylov``
+(block bidiagonalisation, an experiment) and ``partial_reorth``
+(bidiagonalisation with partial reorthogonalisation, Section 5.1.1).
 """
 from .svt import (  # noqa: F401
     jacobi_svd,

@@ -27,6 +27,7 @@ def solve(m, n, rows, cols, vals, **params):
         status, info = svt_solve(h)
         U, w, V = svt_factors(h, m, n)
         hist = svt_history(h)
+        reorth = svt.svt_reorth_stats(h)
     finally:
         svt_destroy(h)
-    return dict(status=status, info=info.as_dict(), U=U, w=w, V=V, **hist)
+    return dict(status=status, info=info.as_dict(), U=U, w=w, V=V, reorth=reorth, **hist)

@@ -26,6 +26,7 @@ SOURCES = [
     ("svt_kernels.hip", True),
     ("bidiag.cpp", False),
     ("dense_host.cpp", False),
+    ("orth_estimate.cpp", False),
     ("svt_solver.cpp", False),
     ("svt_server.cpp", False),
 ]

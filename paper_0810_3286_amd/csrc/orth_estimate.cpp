@@ -1,0 +1,137 @@
+#include "orth_estimate.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace svt {
+
+void OrthEstimate::reset(double unit, int64_t dim) {
+  unit_ = unit;
+  root_ = std::sqrt((double)dim);
+  anorm_ = 0.0;
+  alpha_.clear();
+  beta_.assign(1, 0.0);
+  mu_.clear();
+  nu_.clear();
+}
+
+double OrthEstimate::push_u(double a, bool reorth) {
+  const int j = (int)alpha_.size() + 1;  // u_j
+  anorm_ = std::max(anorm_, a + beta_[(size_t)j - 1]);
+  const double noise = unit_ * root_ * anorm_ / a;
+  row_.assign((size_t)j - 1, 0.0);
+  double top = 0.0;
+  for (int i = 1; i < j; ++i) {
+    // nu_ holds nu_{j,1..j-1}; mu_ holds mu_{j-1,1..j-2}
+    const double nu_next = (i + 1 == j) ? 1.0 : nu_[(size_t)i];
+    double t = beta_[(size_t)i] * nu_next + alpha_[(size_t)i - 1] * nu_[(size_t)i - 1];
+    const double mu_old = (i == j - 1) ? 1.0 : mu_[(size_t)i - 1];
+    t = (t - beta_[(size_t)j - 1] * mu_old) / a;
+    t += std::copysign(noise, t);
+    row_[(size_t)i - 1] = t;
+    top = std::max(top, std::fabs(t));
+  }
+  alpha_.push_back(a);
+  if (reorth) std::fill(row_.begin(), row_.end(), unit_);
+  mu_.swap(row_);
+  return top;
+}
+
+double OrthEstimate::push_v(double b, bool reorth) {
+  const int j = (int)alpha_.size();  // v_{j+1}
+  anorm_ = std::max(anorm_, alpha_[(size_t)j - 1] + b);
+  const double noise = unit_ * root_ * anorm_ / b;
+  row_.assign((size_t)j, 0.0);
+  double top = 0.0;
+  for (int i = 1; i <= j; ++i) {
+    // mu_ holds mu_{j,1..j-1}; nu_ holds nu_{j,1..j-1}
+    double t = alpha_[(size_t)i - 1] * ((i == j) ? 1.0 : mu_[(size_t)i - 1]);
+    if (i >= 2) t += beta_[(size_t)i - 1] * mu_[(size_t)i - 2];
+    t -= alpha_[(size_t)j - 1] * ((i == j) ? 1.0 : nu_[(size_t)i - 1]);
+    t /= b;
+    t += std::copysign(noise, t);
+    row_[(size_t)i - 1] = t;
+    top = std::max(top, std::fabs(t));
+  }
+  beta_.push_back(b);
+  if (reorth) std::fill(row_.begin(), row_.end(), unit_);
+  nu_.swap(row_);
+  return top;
+}
+
+void ReorthSchedule::start(double eta, double unit, int64_t dim, double growth_prior) {
+  eta_ = eta;
+  unit_ = unit;
+  verify_ = std::sqrt(unit);
+  prior_ = std::max(growth_prior, kGrowthFloor);
+  seen_ = 0.0;
+  growth_ = prior_;
+  // the rounding term alone, with |Y|_est / divisor taken as 2
+  reset_level_ = unit * std::sqrt((double)dim) * 2.0;
+  est_.reset(unit, dim);
+  logs_.assign(kWindow, 0.0);
+  nlogs_ = 0;
+  sched_.clear();
+  trig_.clear();
+  level_.clear();
+}
+
+bool ReorthSchedule::decide(int h) {
+  // vectors are decided in order, each once
+  if (h != (int)sched_.size()) return true;
+  bool r = false, trig = false;
+  double lev = reset_level_;
+  if (h >= 1) {  // u_1 has no basis to be orthogonalised against
+    const double pred = level_[(size_t)h - 1] * growth_;
+    trig = pred > eta_;
+    r = trig || trig_[(size_t)h - 1];
+    lev = r ? reset_level_ : pred;
+  }
+  sched_.push_back(r ? 1 : 0);
+  trig_.push_back(trig ? 1 : 0);
+  level_.push_back(lev);
+  return r;
+}
+
+void ReorthSchedule::repredict(int from) {
+  for (int h = std::max(from, 2); h < (int)level_.size(); ++h)
+    level_[(size_t)h] = sched_[(size_t)h] ? reset_level_ : level_[(size_t)h - 1] * growth_;
+}
+
+bool ReorthSchedule::advance(const double *alpha, const double *beta, int k) {
+  bool ok = true;
+  // only vectors already decided can be checked
+  k = std::min(k, (int)sched_.size() / 2);
+  while (est_.steps() < k) {
+    const int j = est_.steps() + 1;
+    for (int side = 0; side < 2; ++side) {
+      const int h = 2 * (j - 1) + side;
+      const bool r = sched_[(size_t)h] != 0;
+      const double e = side == 0 ? est_.push_u(alpha[j - 1], r) : est_.push_v(beta[j], r);
+      if (!r && e > verify_) ok = false;
+      if (!r && h >= 2) {
+        if (sched_[(size_t)h - 1]) {
+          // the first vector after a reorthogonalised one: where levels restart
+          reset_level_ = std::max(reset_level_, e / growth_);
+        } else if (level_[(size_t)h - 1] > 0.0) {
+          const double g = std::max(e, unit_) / level_[(size_t)h - 1];
+          seen_ = std::max(seen_, g);
+          logs_[(size_t)(nlogs_ % kWindow)] = std::log(std::max(g, 1.0));
+          ++nlogs_;
+        }
+      }
+      level_[(size_t)h] = r ? reset_level_ : std::max(e, unit_);
+    }
+  }
+  if (nlogs_ >= kWindow) {
+    double mean = 0.0;
+    for (int i = 0; i < kWindow; ++i) mean += logs_[(size_t)i];
+    growth_ = std::max(kGrowthFloor, kSafety * std::exp(mean / kWindow));
+  } else {
+    growth_ = std::max(prior_, seen_);
+  }
+  repredict(2 * est_.steps());
+  return ok;
+}
+
+}  // namespace svt

@@ -104,14 +104,15 @@ struct SpmvInput {
 // = nqx + side basis columns of p's side.  Column indices: idx16 (16-bit,
 // ncols <= 65536: a quarter less streamed per entry) when not null, else
 // idx.  segptr: nrows x (nseg + 1) segment starts (null unless nseg > 1).  With dots_out non-null the kernel
-// also writes the partial dot products of p with the nq columns of Q and
-// |p|^2 (column nq): nq + 1 columns, p's own pending update.  Returns
+// also writes the partial dot products of p with the first ndots columns of
+// Q (ndots = nq, or 0 when p is left unorthogonalised) and |p|^2 (column
+// ndots): ndots + 1 columns, p's own pending update.  Returns
 // hipErrorInvalidValue for inconsistent arguments (nqx > 0 with a missing
-// pointer, nq != nqx + side, or nq > kSpmvAuxCols).
+// pointer, nq != nqx + side, nq > kSpmvAuxCols, or ndots not 0 or nq).
 template <typename T>
 hipError_t launch_spmv(hipStream_t s, const SpmvPlan &pl, const int32_t *ptr, const int32_t *idx,
                        const uint16_t *idx16, const T *val, const int32_t *segptr, const SpmvInput<T> &in,
-                       int ncols, const T *prev, T *p, int nrows, const T *Q, int64_t ldq, int nq,
+                       int ncols, const T *prev, T *p, int nrows, const T *Q, int64_t ldq, int nq, int ndots,
                        double *dots_out);
 
 // s (and |h|^2 / |x|^2) of a pending vector, exactly as the sparse product

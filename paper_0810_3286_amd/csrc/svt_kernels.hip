@@ -452,7 +452,8 @@ __device__ __forceinline__ void load_q8(T (&q)[8], const T *__restrict__ Q, int6
 // kSpmvUnroll entries in flight, accumulating them in index order (the
 // result does not depend on the unrolling).  With part_out, the partial dot
 // products of p with the nq columns of Q and |p|^2 follow in the same kernel
-// (row_dots): p's own pending one-pass update.
+// (row_dots) with its first ndots columns (nq, or 0 for |p|^2 alone: a vector
+// that partial reorthogonalisation leaves alone): p's own pending update.
 //
 // Order of work: the loads that depend on nothing are issued first (this
 // thread's rows of Q and prev, this workgroup's slice of x and Q_x, x's first
@@ -690,7 +691,7 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
     const int32_t *__restrict__ ptr, const I *__restrict__ idx, const T *__restrict__ val,
     const int32_t *__restrict__ segptr, int nseg, int segcols, const SpmvInput<T> in, int ncols,
     const T *__restrict__ prev, T *__restrict__ p, int nrows, int rows_per_blk, const T *__restrict__ Q,
-    int64_t ldq, int nq, double *__restrict__ part_out) {
+    int64_t ldq, int nq, int ndots, double *__restrict__ part_out) {
   extern __shared__ double smem_d[];
   __shared__ double sred[kRowWaves][8];
   T *racc = reinterpret_cast<T *>(smem_d);  // rows_per_blk row sums, then the rows of p
@@ -988,14 +989,14 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
   }
   if (part_out == nullptr) return;  // uniform
   if (fast) {
-    row_dots_lds<T>(q8, fvalid ? (double)racc[frow - r0] : 0.0, fvalid, nq, part_out,
+    row_dots_lds<T>(q8, fvalid ? (double)racc[frow - r0] : 0.0, fvalid, ndots, part_out,
                     reinterpret_cast<double *>(region));
   } else if (rows_per_blk <= kNarrowLanes) {
-    row_dots_passes_narrow<T>(racc, r0, r1, Q, ldq, nq, in.x, part_out, reinterpret_cast<double *>(region));
+    row_dots_passes_narrow<T>(racc, r0, r1, Q, ldq, ndots, in.x, part_out, reinterpret_cast<double *>(region));
   } else if (rows_per_blk <= kRowLanes) {
-    row_dots_passes<T>(racc, r0, r1, Q, ldq, nq, in.x, part_out, reinterpret_cast<double *>(region));
+    row_dots_passes<T>(racc, r0, r1, Q, ldq, ndots, in.x, part_out, reinterpret_cast<double *>(region));
   } else {
-    row_dots<T>([&](int row) { return (double)racc[row - r0]; }, r0, r1, Q, ldq, nq, part_out, sred);
+    row_dots<T>([&](int row) { return (double)racc[row - r0]; }, r0, r1, Q, ldq, ndots, part_out, sred);
   }
 }
 
@@ -1635,14 +1636,14 @@ SpmvPlan spmv_plan(int nrows, int ncols, int elem_bytes, int lds_bytes, int mode
 template <typename T, typename I>
 hipError_t launch_spmv_i(hipStream_t s, const SpmvPlan &pl, const int32_t *ptr, const I *idx, const T *val,
                          const int32_t *segptr, const SpmvInput<T> &in, int ncols, const T *prev, T *p,
-                         int nrows, const T *Q, int64_t ldq, int nq, double *dots_out) {
+                         int nrows, const T *Q, int64_t ldq, int nq, int ndots, double *dots_out) {
 #define SVT_SPMVR(LN, ST)                                                                          \
   do {                                                                                            \
     auto kern = k_spmv_rows<T, I, LN, ST>;                                                        \
     hipError_t ea = allow_dynamic_lds(reinterpret_cast<const void *>(kern), pl.lds);              \
     if (ea != hipSuccess) return ea;                                                              \
     SVT_LAUNCH(kern, dim3(pl.nblk), dim3(kRowBlock), pl.lds, s, ptr, idx, val, segptr, pl.nseg,    \
-               pl.segcols, in, ncols, prev, p, nrows, pl.rows_per_blk, Q, ldq, nq, dots_out);      \
+               pl.segcols, in, ncols, prev, p, nrows, pl.rows_per_blk, Q, ldq, nq, ndots, dots_out); \
   } while (0)
 #define SVT_SPMVS(ST)                      \
   switch (pl.lanes) {                      \
@@ -1666,8 +1667,9 @@ template <typename T>
 hipError_t launch_spmv(hipStream_t s, const SpmvPlan &pl, const int32_t *ptr, const int32_t *idx,
                        const uint16_t *idx16, const T *val, const int32_t *segptr, const SpmvInput<T> &in,
                        int ncols, const T *prev, T *p, int nrows, const T *Q, int64_t ldq, int nq,
-                       double *dots_out) {
+                       int ndots, double *dots_out) {
   if (pl.nseg > 1 && segptr == nullptr) return hipErrorInvalidValue;
+  if (ndots != 0 && ndots != nq) return hipErrorInvalidValue;
   if (in.x == nullptr || p == nullptr) return hipErrorInvalidValue;
   if (idx16 != nullptr && ncols > 65536) return hipErrorInvalidValue;
   if ((dots_out != nullptr || in.nqx > 0) && nq > 0 && Q == nullptr) return hipErrorInvalidValue;
@@ -1685,10 +1687,10 @@ hipError_t launch_spmv(hipStream_t s, const SpmvPlan &pl, const int32_t *ptr, co
   if (rp.nblk != pl.nblk || rp.rows_per_blk != pl.rows_per_blk) return hipErrorInvalidValue;
   if (idx16 != nullptr)
     return launch_spmv_i<T, uint16_t>(s, pl, ptr, idx16, val, segptr, in, ncols, prev, p, nrows, Q, ldq, nq,
-                                      dots_out);
+                                      ndots, dots_out);
   if (idx == nullptr) return hipErrorInvalidValue;
   return launch_spmv_i<T, int32_t>(s, pl, ptr, idx, val, segptr, in, ncols, prev, p, nrows, Q, ldq, nq,
-                                   dots_out);
+                                   ndots, dots_out);
 }
 
 size_t gs_update_lds(int nq, int rows_per_blk) {
@@ -1958,7 +1960,7 @@ hipError_t launch_gather(hipStream_t s, const T *x, const int32_t *map, T *y, in
 #define SVT_INSTANTIATE(T)                                                                          \
   template hipError_t launch_spmv<T>(hipStream_t, const SpmvPlan &, const int32_t *, const int32_t *,      \
                                      const uint16_t *, const T *, const int32_t *, const SpmvInput<T> &, \
-                                     int, const T *, T *, int, const T *, int64_t, int, double *);     \
+                                     int, const T *, T *, int, const T *, int64_t, int, int, double *);     \
   template hipError_t launch_gs_update<T>(hipStream_t, T *, int, const T *, int64_t, int, const double *, \
                                           double *, bool, double *, int);                              \
   template hipError_t launch_sumsq<T>(hipStream_t, const T *, int, double *, int);                     \

@@ -37,6 +37,7 @@
 
 #include "bidiag.h"
 #include "dense_host.h"
+#include "orth_estimate.h"
 #include "svt_kernels.h"
 
 namespace svt {
@@ -278,6 +279,8 @@ struct ProblemBase {
   // product; 0 when that product gathers x from memory
   virtual int spmv_segments(int which) const = 0;
   virtual void mem_stats(size_t *cur, size_t *peak) const = 0;
+  virtual void reorth_stats(int64_t *vectors, int64_t *orthogonalised, int64_t *two_pass_restarts,
+                            int64_t *partial_fallbacks) const = 0;
   size_t peak_bytes = 0;
   std::vector<Record> history;
   Profiler prof;
@@ -341,6 +344,14 @@ struct Problem final : ProblemBase {
   int prereduce_min = 64;
   int passes_now = 2;          // Gram-Schmidt passes per vector right now
   int64_t reorth_restarts = 0; // bidiagonalisations restarted with two passes
+  // partial reorthogonalisation (reorth_eta > 0): the schedule of the
+  // current bidiagonalisation, whether it is still in use in this solve,
+  // the growth factor carried to the next bidiagonalisation, and counts
+  ReorthSchedule rsched;
+  bool partial_now = false;
+  bool partial_run = false;    // the current bidiagonalisation follows rsched
+  double growth_carry = 0.0;
+  int64_t vec_made = 0, vec_orth = 0, partial_fallbacks = 0;
 
   // the Dantzig-selector iteration (Section 3.3) instead of Algorithm 1's
   // equality-constrained one
@@ -587,15 +598,16 @@ struct Problem final : ProblemBase {
   // partial dot products of out with the nq columns of Q and |out|^2 follow
   // in the same kernel.
   void spmv(const Csx &c, const T *vals, const SpmvInput<T> &in, const T *prev, T *out, const T *Q = nullptr,
-            int64_t ldq = 0, int nq = 0, double *dots = nullptr) {
+            int64_t ldq = 0, int nq = 0, double *dots = nullptr, int ndots = -1) {
+    if (ndots < 0) ndots = nq;
     hipError_t e = launch_spmv<T>(stream, *c.plan, c.ptr, c.idx, c.idx16, vals, c.segptr, in, c.ncols, prev,
-                                  out, c.nrows, Q, ldq, nq, dots);
+                                  out, c.nrows, Q, ldq, nq, ndots, dots);
     if (e == hipErrorInvalidValue && c.plan->nseg > 0) {
       // the device refused the LDS size: gather x from memory from now on
       (void)hipGetLastError();
       *c.plan = spmv_plan(c.nrows, c.ncols, (int)sizeof(T), lds_limit, 1, mrows());
       e = launch_spmv<T>(stream, *c.plan, c.ptr, c.idx, c.idx16, vals, nullptr, in, c.ncols, prev, out, c.nrows,
-                         Q, ldq, nq, dots);
+                         Q, ldq, nq, ndots, dots);
     }
     HIP_CHECK(e);
   }
@@ -649,8 +661,8 @@ struct Problem final : ProblemBase {
   // vector is orthogonalised in its own half-step (the pending part is only
   // its norm, in gs.part3).
   PendingVec half_step(const Csx &c, const T *vals, T *x_raw, PendingVec xp, const T *Qx, int64_t ldqx, T *x_col,
-                       double *x_coef, double *x_removed, const T *prev, T *Q, int64_t ldq, int nq, T *p,
-                       int side) {
+                       double *x_coef, double *x_removed, const T *prev, T *Q, int64_t ldq, int nq, bool orth,
+                       T *p, int side) {
     const double vb = sizeof(T);
     const double len = (double)c.nrows;
     const int xnp = xnp_of(c.ncols);
@@ -686,13 +698,17 @@ struct Problem final : ProblemBase {
       in.beta = beta_d();
       in.side = side;
       const int out_buf = side == 0 ? 1 : 2;
+      // p's dot products with its basis when it is to be orthogonalised; the
+      // update of x (nqx > 0) needs the basis of p's side either way
+      const int ndots = orth ? nq : 0;
+      const int nq_k = xp.nq > 0 ? nq : ndots;
       // algorithmic bytes: the product's (spmv_bytes), x' written to its
       // basis column, Q_x read once for it, and Q read once for the image
       // of the update and the dot products
       prof.begin();
-      spmv(c, vals, in, prev, p, Q, ldq, nq, part_buf(out_buf));
-      prof.end(kSpmv, spmv_bytes(c, c.ncols, prev != nullptr) + vb * c.ncols * (1.0 + xp.nq) + vb * len * nq);
-      return PendingVec{out_buf, nq};
+      spmv(c, vals, in, prev, p, Q, ldq, nq_k, part_buf(out_buf), ndots);
+      prof.end(kSpmv, spmv_bytes(c, c.ncols, prev != nullptr) + vb * c.ncols * (1.0 + xp.nq) + vb * len * nq_k);
+      return PendingVec{out_buf, ndots};
     }
     in.pend = part_buf(xp.buf);  // x already orthogonal: only its norm
     prof.begin();
@@ -730,15 +746,17 @@ struct Problem final : ProblemBase {
   void gkl_start(const T *vr, const T *vc, Gkl &g) {
     ensure_basis(std::min<int64_t>(acols, 8));
     const Csx R = a_rows_struct(), C = a_cols_struct();
+    partial_run = partial_now && passes_now == 1;
+    if (partial_run) rsched.start(prm.reorth_eta, kUnit, arows + acols, growth_carry);
     HIP_CHECK(launch_randn<T>(stream, pbuf_v.as<T>(), (int)acols, prm.seed, rng_ctr++));
     HIP_CHECK(launch_sumsq<T>(stream, pbuf_v.as<T>(), (int)acols, gs.part3, mrows()));
     g.pv = PendingVec{3, 0};
     // u_1 = A v_1 / alpha_1 (v_1 = the normalised start vector)
     g.pu = half_step(R, vr, pbuf_v.as<T>(), g.pv, Vb.as<T>(), acols, vcol(0), beta_d(), nullptr, nullptr,
-                     Ub.as<T>(), arows, 0, pbuf_u.as<T>(), 0);
+                     Ub.as<T>(), arows, 0, orth_vec(0, 0), pbuf_u.as<T>(), 0);
     // v_2 = A^T u_1 - alpha_1 v_1, orthogonal to v_1
     g.pv = half_step(C, vc, pbuf_u.as<T>(), g.pu, Ub.as<T>(), arows, ucol(0), alpha_d(), removed_d(), vcol(0),
-                     Vb.as<T>(), acols, 1, pbuf_v.as<T>(), 1);
+                     Vb.as<T>(), acols, 1, orth_vec(1, 1), pbuf_v.as<T>(), 1);
     g.k = 1;
     g.finalized = false;
     steps_total += 1;
@@ -751,10 +769,10 @@ struct Problem final : ProblemBase {
     const Csx R = a_rows_struct(), C = a_cols_struct();
     // u_{k+1} = A v_{k+1} - beta_{k+1} u_k, orthogonal to u_1..u_k
     g.pu = half_step(R, vr, pbuf_v.as<T>(), g.pv, Vb.as<T>(), acols, vcol(k), beta_d() + k, removed_d() + 2 * k - 1,
-                     ucol(k - 1), Ub.as<T>(), arows, k, pbuf_u.as<T>(), 0);
+                     ucol(k - 1), Ub.as<T>(), arows, k, orth_vec(2 * k, k), pbuf_u.as<T>(), 0);
     // v_{k+2} = A^T u_{k+1} - alpha_{k+1} v_{k+1}, orthogonal to v_1..v_{k+1}
     g.pv = half_step(C, vc, pbuf_u.as<T>(), g.pu, Ub.as<T>(), arows, ucol(k), alpha_d() + k, removed_d() + 2 * k,
-                     vcol(k), Vb.as<T>(), acols, k + 1, pbuf_v.as<T>(), 1);
+                     vcol(k), Vb.as<T>(), acols, k + 1, orth_vec(2 * k + 1, k + 1), pbuf_v.as<T>(), 1);
     g.k = k + 1;
     g.finalized = false;
     steps_total += 1;
@@ -778,8 +796,8 @@ struct Problem final : ProblemBase {
                                         part_buf(g.pv.buf), gs.part3, true, removed_d() + 2 * k - 1, mrows()));
           g.pv = PendingVec{3, 0};
         }
-        HIP_CHECK(launch_finalize<T>(stream, pbuf_v.as<T>(), (int)acols, gs.part3, vcol(k), beta_d() + k,
-                                     mrows()));
+        HIP_CHECK(launch_finalize<T>(stream, pbuf_v.as<T>(), (int)acols, part_buf(g.pv.buf), vcol(k),
+                                     beta_d() + k, mrows()));
       }
       g.finalized = true;
     }
@@ -871,6 +889,20 @@ struct Problem final : ProblemBase {
       gkl_fetch_begin(g);
       for (int a = 0; a < kAheadSteps && g.k < cap; ++a) gkl_step(vr, vc, g);
       gkl_fetch_end(snap);
+      if (partial_run && !rsched.advance(snap.alpha.data(), snap.beta.data(), snap.k)) {
+        // a vector left alone lost more orthogonality than semi-orthogonality
+        // allows (the prediction fell short of the estimate): start again
+        // with every vector orthogonalised, for the rest of the solve
+        partial_now = false;
+        ++partial_fallbacks;
+        if (log_level > 0)
+          std::fprintf(stderr, "[svt] partial reorthogonalisation: an estimate passed %.2e by step %d "
+                               "(growth %.2f): restarting with full reorthogonalisation\n",
+                       rsched.verify(), snap.k, rsched.growth());
+        gkl_start(vr, vc, g);
+        next_check = first_check;
+        continue;
+      }
       if (prm.reorth_passes == 0 && passes_now == 1) {
         // one pass per vector is enough while no pass removes a large part
         // of its vector (the vector then already was nearly orthogonal, as
@@ -881,6 +913,7 @@ struct Problem final : ProblemBase {
         double worst = 0.0;
         bool bad = false;
         for (int j = 1; j < 2 * snap.k; ++j) {
+          if (partial_run && !rsched.reorthogonalised(j)) continue;  // no pass made: no fraction
           const double f = snap.removed[(size_t)j];
           if (!(f <= reorth_trigger)) bad = true;  // also a non-finite value
           if (f > worst) worst = f;
@@ -943,6 +976,9 @@ struct Problem final : ProblemBase {
         bidiag_of(snap, d, e);
         bidiag_vectors(d, e, mode == 1 ? std::min(count, k) : r, chk);
         sv = std::move(chk);
+        // the next bidiagonalisation starts from this one's growth (half of
+        // the carried value decays away when a run measures less)
+        if (partial_run) growth_carry = std::max(rsched.growth_seen(), 0.5 * growth_carry);
         // the factors are formed from the first k columns of the bases
         g.k = k;
         g.alpha = snap.alpha;
@@ -1336,6 +1372,35 @@ struct Problem final : ProblemBase {
   void reset_passes() {
     passes_now = prm.reorth_passes == 2 ? 2 : 1;
     reorth_restarts = 0;
+    partial_now = prm.reorth_eta > 0.0 && passes_now == 1;
+    partial_run = false;
+    growth_carry = kFirstGrowth;
+    vec_made = vec_orth = partial_fallbacks = 0;
+  }
+
+  // the growth per half-step assumed by the first partially reorthogonalised
+  // bidiagonalisation of a solve, before any has been measured (the largest
+  // measured on the completion workloads is about 6.5)
+  static constexpr double kFirstGrowth = 8.0;
+  static constexpr double kUnit = sizeof(T) == 8 ? 0x1p-53 : 0x1p-24;
+
+  // Whether the vector made by half-step h is orthogonalised against the nq
+  // columns of its basis (always, unless partial reorthogonalisation leaves
+  // it alone).
+  bool orth_vec(int h, int nq) {
+    bool r = nq > 0;
+    if (partial_run) r = rsched.decide(h) && r;  // every vector is decided, in order
+    ++vec_made;
+    if (r) ++vec_orth;
+    return r;
+  }
+
+  void reorth_stats(int64_t *vectors, int64_t *orthogonalised, int64_t *two_pass_restarts,
+                    int64_t *fallbacks) const override {
+    if (vectors) *vectors = vec_made;
+    if (orthogonalised) *orthogonalised = vec_orth;
+    if (two_pass_restarts) *two_pass_restarts = reorth_restarts;
+    if (fallbacks) *fallbacks = partial_fallbacks;
   }
 
   svt_status solve(svt_info *info) override {
@@ -1636,6 +1701,8 @@ static void validate_params(const svt_params &p) {
   if (!finite(p.lanczos_tol) || p.lanczos_tol < 0 || p.lanczos_tol >= 1) throw Error(SVT_EINVAL, "lanczos_tol must be in [0, 1)");
   if (p.lanczos_maxsteps < 0) throw Error(SVT_EINVAL, "lanczos_maxsteps must be >= 0");
   if (p.reorth_passes < 0 || p.reorth_passes > 2) throw Error(SVT_EINVAL, "reorth_passes must be 0, 1 or 2");
+  if (!finite(p.reorth_eta) || p.reorth_eta < 0 || p.reorth_eta > 1e-4)
+    throw Error(SVT_EINVAL, "reorth_eta must be in [0, 1e-4]");
   if (!finite(p.decide_margin) || p.decide_margin < 0) throw Error(SVT_EINVAL, "decide_margin must be finite and >= 0");
   if (p.spmv_mode < 0 || p.spmv_mode > 2) throw Error(SVT_EINVAL, "spmv_mode must be 0, 1 or 2");
 }
@@ -1690,6 +1757,7 @@ svt_status svt_params_default(int64_t m, int64_t n, int64_t nnz, svt_params *out
   out->lanczos_tol = 0.0;  // auto: 1e-12 (FP64) or 1e-6 (MIXED)
   out->lanczos_maxsteps = 0;
   out->reorth_passes = 0;
+  out->reorth_eta = 1e-10;
   out->decide_margin = 0.05;
   out->svd_method = SVT_SVD_LANCZOS;
   out->rsvd_oversample = 10;
@@ -2041,6 +2109,13 @@ svt_status svt_spmv_plan(const svt_problem *h, int32_t which, int32_t *segments)
 svt_status svt_device_bytes(const svt_problem *h, size_t *current, size_t *peak) {
   if (!h || !h->impl) return SVT_EINVAL;
   h->impl->mem_stats(current, peak);
+  return SVT_OK;
+}
+
+svt_status svt_reorth_stats(const svt_problem *h, int64_t *vectors, int64_t *orthogonalised,
+                            int64_t *two_pass_restarts, int64_t *partial_fallbacks) {
+  if (!h || !h->impl) return SVT_EINVAL;
+  h->impl->reorth_stats(vectors, orthogonalised, two_pass_restarts, partial_fallbacks);
   return SVT_OK;
 }
 

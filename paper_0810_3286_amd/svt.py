@@ -68,6 +68,7 @@ class svt_params(ctypes.Structure):
         ("svd_method", ctypes.c_int32),
         ("rsvd_oversample", ctypes.c_int32),
         ("rsvd_power", ctypes.c_int32),
+        ("reorth_eta", ctypes.c_double),
     ]
 
 
@@ -133,6 +134,7 @@ def _signatures(lib):
         "svt_sample_update_noalloc": (ctypes.c_int32, [h, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                                        ctypes.c_int64, ctypes.c_double, _dp]),
         "svt_kernel_stats": (ctypes.c_int32, [h, ctypes.c_int32, _lp, _dp, _dp]),
+        "svt_reorth_stats": (ctypes.c_int32, [h, _lp, _lp, _lp, _lp]),
         "svt_spmv_plan": (ctypes.c_int32, [h, ctypes.c_int32, _ip]),
         "svt_device_bytes": (ctypes.c_int32, [h, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
         "svt_footprint": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
@@ -378,6 +380,15 @@ def svt_kernel_stats(h, kind: int):
     b = ctypes.c_double()
     _check(load().svt_kernel_stats(h, kind, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(b)), h)
     return n.value, ms.value, b.value
+
+
+def svt_reorth_stats(h):
+    """(vectors made, vectors orthogonalised against their basis, restarts
+    with two Gram-Schmidt passes, fallbacks from partial to full
+    reorthogonalisation) of the handle's last solve."""
+    v = [ctypes.c_int64() for _ in range(4)]
+    _check(load().svt_reorth_stats(h, *[ctypes.byref(x) for x in v]), h)
+    return tuple(x.value for x in v)
 
 
 def svt_spmv_plan(h, which: int) -> int:

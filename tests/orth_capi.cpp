@@ -1,0 +1,31 @@
+// A C interface to the library's partial-reorthogonalisation estimate and
+// schedule (orth_estimate.cpp), for CPU tests through ctypes.
+#include <cstdint>
+
+#include "orth_estimate.h"
+
+extern "C" {
+
+void *est_new(double unit, int64_t dim) {
+  auto *e = new svt::OrthEstimate();
+  e->reset(unit, dim);
+  return e;
+}
+double est_push_u(void *e, double a, int reorth) { return static_cast<svt::OrthEstimate *>(e)->push_u(a, reorth != 0); }
+double est_push_v(void *e, double b, int reorth) { return static_cast<svt::OrthEstimate *>(e)->push_v(b, reorth != 0); }
+void est_free(void *e) { delete static_cast<svt::OrthEstimate *>(e); }
+
+void *sched_new(double eta, double unit, int64_t dim, double prior) {
+  auto *s = new svt::ReorthSchedule();
+  s->start(eta, unit, dim, prior);
+  return s;
+}
+int sched_decide(void *s, int h) { return static_cast<svt::ReorthSchedule *>(s)->decide(h) ? 1 : 0; }
+int sched_advance(void *s, const double *alpha, const double *beta, int k) {
+  return static_cast<svt::ReorthSchedule *>(s)->advance(alpha, beta, k) ? 1 : 0;
+}
+double sched_growth(void *s) { return static_cast<svt::ReorthSchedule *>(s)->growth(); }
+double sched_growth_seen(void *s) { return static_cast<svt::ReorthSchedule *>(s)->growth_seen(); }
+void sched_free(void *s) { delete static_cast<svt::ReorthSchedule *>(s); }
+
+}  // extern "C"

@@ -50,8 +50,9 @@ def test_randomized_svd_refused_outside_completion():
 
 def test_struct_layout_matches_header():
     # svt_params: 3 doubles, 6 int32, 2 doubles, 2 int32, double, uint64, 2 int32, pointer,
-    # double, 7 int32 (and 4 bytes of tail padding)
-    assert ctypes.sizeof(B.svt_params) == 3 * 8 + 6 * 4 + 2 * 8 + 2 * 4 + 8 + 8 + 2 * 4 + 8 + 8 + 7 * 4 + 4
+    # double, 7 int32 (and 4 bytes of padding), double
+    assert ctypes.sizeof(B.svt_params) == 3 * 8 + 6 * 4 + 2 * 8 + 2 * 4 + 8 + 8 + 2 * 4 + 8 + 8 + 7 * 4 + 4 + 8
+    assert B.svt_params.reorth_eta.offset == ctypes.sizeof(B.svt_params) - 8
     assert ctypes.sizeof(B.svt_info) == 4 * 4 + 6 * 8 + 8
 
 
@@ -60,6 +61,8 @@ def test_params_default_is_the_papers_choice():
     assert p.tau == pytest.approx(2000.0)
     assert p.delta == pytest.approx(1.2 * 400 * 400 / 47400)
     assert p.eps == 1e-4 and p.maxiter == 500 and p.incr == 5 and p.kick == 1
+    # partial reorthogonalisation, as the paper's PROPACK runs (Section 5.1.1)
+    assert p.reorth_eta == 1e-10
     q = B.svt_params_default(300, 1200, 1000)
     assert q.tau == pytest.approx(5.0 * np.sqrt(300 * 1200))
     with pytest.raises(B.SvtError):
@@ -103,7 +106,8 @@ def test_rejects_bad_parameters():
                        ("stop_rule", 3), ("lanczos_tol", 1.5), ("reorth_passes", 3),
                        ("decide_margin", -0.1), ("spmv_mode", 3), ("min_block_rows", -1),
                        ("min_block_rows", 2049), ("svd_method", 2), ("rsvd_oversample", -1),
-                       ("rsvd_power", 65)]:
+                       ("rsvd_power", 65), ("reorth_eta", -1e-12), ("reorth_eta", 1e-3),
+                       ("reorth_eta", float("nan"))]:
         p = B.svt_params_default(2, 2, 2)
         setattr(p, field, bad)
         _expect_einval(2, 2, rows, cols, vals, p)
