@@ -537,8 +537,8 @@ def main():
     ap.add_argument("--spmv-mode", type=int, default=0,
                     help="0 or 2: x staged in LDS (column segments when needed), 1: gathered")
     ap.add_argument("--reorth-eta", type=float, default=None,
-                    help="partial reorthogonalisation level of the FP64 solves (0: full; "
-                         "default: the library's)")
+                    help="partial reorthogonalisation level, a multiple of sqrt(unit roundoff) "
+                         "(0: every vector orthogonalised; default: the library's)")
     ap.add_argument("--min-rows", type=int, default=0,
                     help="min_block_rows of the headline solve (0: the library default)")
     ap.add_argument("--serving-requests", type=int, default=16)
@@ -616,7 +616,7 @@ def main():
         prm.profile = 1 if profile else 0
         prm.spmv_mode = args.spmv_mode
         prm.min_block_rows = args.min_rows
-        if prec == B.SVT_FP64 and args.reorth_eta is not None:
+        if args.reorth_eta is not None:
             prm.reorth_eta = args.reorth_eta
         eta_used[0] = prm.reorth_eta
         return B.svt_create(p.m, p.n, p.rows, p.cols, p.vals, prm)
@@ -716,7 +716,7 @@ def main():
         prm = B.svt_params_default(p.m, p.n, p.nnz)
         prm.tau, prm.delta, prm.eps, prm.maxiter, prm.incr = p.tau, p.delta, p.eps, p.maxiter, p.incr
         prm.precision = B.SVT_MIXED if other == "mixed" else B.SVT_FP64
-        if prm.precision == B.SVT_FP64 and args.reorth_eta is not None:
+        if args.reorth_eta is not None:
             prm.reorth_eta = args.reorth_eta
         prm.spmv_mode = args.spmv_mode
         prm.min_block_rows = args.min_rows
@@ -732,13 +732,16 @@ def main():
                 ito += inf.iters
             to = time.perf_counter() - t0
             Uo, _, Vo = B.svt_factors(ho, p.m, p.n)
+            ro = B.svt_reorth_stats(ho)
         finally:
             B.svt_destroy(ho)
         out[other] = {"svt_iters_per_s": ito / to, "sampled_entries_per_s": ito / to * p.nnz,
                       "iters_per_solve": ito / args.steps, "ms_per_step": to / args.steps * 1e3,
                       "dtype": "f64" if other == "fp64" else "f32+f64",
                       "rel_error_vs_truth": rel_diff_factored(Uo, Vo, p.ML, p.MR),
-                      "rel_diff_vs_headline": rel_diff_factored(Uo, Vo, U, V)}
+                      "rel_diff_vs_headline": rel_diff_factored(Uo, Vo, U, V),
+                      "reorth": {"eta": prm.reorth_eta, "vectors": ro[0], "orthogonalised": ro[1],
+                                 "partial_fallbacks": ro[3]}}
     if not args.no_serving:
         log("[bench] serving stream")
         # the serving form runs mixed-precision solves (its workload's definition)

@@ -150,26 +150,27 @@ typedef struct {
   int32_t rsvd_oversample; /* extra test vectors of the randomised SVD, >= 0
                               (default 10)                                   */
   int32_t rsvd_power;    /* its power iterations, 0..64 (default 2)          */
-  double reorth_eta;     /* In (0, 1e-4] (default 1e-10): partial
-                            reorthogonalisation (Section 5.1.1): the loss of
-                            orthogonality of each new vector of the
-                            bidiagonalisation is estimated from the
-                            bidiagonal coefficients alone (the recurrences
-                            of Simon and Larsen), and a vector is
-                            orthogonalised against its whole basis, with the
-                            next vector of the other side, only once its
-                            predicted estimate passes reorth_eta.  With the
-                            MIXED form's FP32 vectors the rounding of a new
-                            vector alone exceeds 1e-10, so at the default
-                            every vector is orthogonalised there.  0: every
-                            new vector is orthogonalised.
+  double reorth_eta;     /* Partial reorthogonalisation (Section 5.1.1), the
+                            level as a multiple of sqrt(u), u the unit
+                            roundoff of the bidiagonalisation's vectors
+                            (FP64: sqrt(u) = 1.05e-8; MIXED, FP32 vectors:
+                            2.44e-4).  In (0, 100] (default 0.01): the loss
+                            of orthogonality of each new vector is estimated
+                            from the bidiagonal coefficients alone (the
+                            recurrences of Simon and Larsen), and a vector
+                            is orthogonalised against its whole basis, with
+                            the next vector of the other side, only once its
+                            predicted estimate passes reorth_eta sqrt(u).
                             The estimates are checked as the coefficients
                             reach the host; if one of a vector left alone
-                            passed sqrt(unit roundoff) the bidiagonalisation
-                            starts again with full reorthogonalisation, kept
-                            for the rest of the solve.  Applies with one
-                            Gram-Schmidt pass per vector (reorth_passes 0 or
-                            1); svt_reorth_stats reports what it did       */
+                            passed sqrt(u) (semi-orthogonality) the
+                            bidiagonalisation starts again with full
+                            reorthogonalisation, kept for the rest of the
+                            solve (levels of 1 and above make that happen).
+                            0: every new vector is orthogonalised.  Applies
+                            with one Gram-Schmidt pass per vector
+                            (reorth_passes 0 or 1); svt_reorth_stats reports
+                            what it did                                    */
 } svt_params;
 
 typedef struct {

@@ -30,9 +30,13 @@ Y v_i = alpha_i u_i + beta_i u_{i-1}:
 
 exactly for the computed vectors, up to the rounding of the step itself.
 The estimate runs these recurrences on the coefficients alone and adds that
-rounding as a term of size eps * sqrt(m + n) * ||Y||_est / (the divisor),
-with the sign of the value it is added to (so the estimate only grows);
-||Y||_est is the largest alpha_i + beta_i seen so far.  A vector that is
+rounding as a term of size eps * c * ||Y||_est / (the divisor), with the
+sign of the value it is added to (so the estimate only grows); ||Y||_est is
+the largest alpha_i + beta_i seen so far, eps the unit roundoff of the
+stored vectors, and c = sqrt(m + n) for vectors in FP64.  Vectors stored in
+FP32 (with FP32 products, the rest in FP64, as the mixed form computes)
+take c = 1: their rounding is dominated by that of their storage, which
+has no systematic direction (the tests pin both choices).  A vector that is
 reorthogonalised (twice against all earlier vectors of its side: classical
 Gram-Schmidt applied twice) has its row of estimates set to eps.  The
 policy: once the largest estimate of a new vector passes eta, that vector
@@ -47,6 +51,7 @@ from __future__ import annotations
 import numpy as np
 
 EPS64 = np.finfo(np.float64).eps / 2  # unit roundoff of FP64
+EPS32 = 2.0 ** -24                     # unit roundoff of FP32
 
 
 def _cgs2(z, Q):
@@ -62,14 +67,15 @@ def _cgs2(z, Q):
 class OmegaEstimate:
     """The estimates mu_{j, .} and nu_{j, .} of the module docstring, one row
     per vector, advanced with each new coefficient.  ``unit`` is the unit
-    roundoff the new vectors are stored in, ``dim`` = m + n.  ``row_u`` /
+    roundoff the new vectors are stored in, ``dim`` = m + n, ``root`` the
+    factor c of the rounding term (default sqrt(dim)).  ``row_u`` /
     ``row_v`` give the row of the next vector from its norm before it is
     reorthogonalised; ``push_u`` / ``push_v`` then record its coefficient and
     its row (that row, or eps if the vector was reorthogonalised)."""
 
-    def __init__(self, unit: float = EPS64, dim: int = 2):
+    def __init__(self, unit: float = EPS64, dim: int = 2, root=None):
         self.unit = unit
-        self.root = np.sqrt(dim)
+        self.root = np.sqrt(dim) if root is None else root
         self.alpha = []          # alpha[j - 1] = alpha_j
         self.beta = [0.0]        # beta[j - 1] = beta_j (beta_1 multiplies u_0 = 0)
         self.mu = []             # mu[j - 1] = estimates of u_j against u_1 .. u_{j-1}
@@ -127,14 +133,17 @@ class OmegaEstimate:
 
 
 def gkl(Y, k: int, policy: str = "full", eta: float = 1e-10, seed: int = 0, v1=None,
-        decide=None, on_step=None):
+        decide=None, on_step=None, store: str = "f64"):
     """k steps of the bidiagonalisation of the module docstring on Y (a
     SciPy sparse matrix or a dense array).  policy: "full" (every new vector
     orthogonalised twice against its basis), "partial" (only those the
     estimates name, see the module docstring), "none", or "given": vector h
     (h = 2(j - 1) for u_j, 2j - 1 for v_{j+1}) is orthogonalised iff
     decide(h) is true, asked before the vector is formed; on_step(j, alpha,
-    beta) is called after step j with the coefficients so far.
+    beta) is called after step j with the coefficients so far (a true
+    return ends the run there).  store="f32":
+    products with FP32 values and vectors, vectors stored in FP32, the rest in
+    FP64, and the estimate with FP32's unit roundoff and c = 1.
 
     Returns dict(alpha[k], beta[k + 1] (beta[0] = 0 for beta_1 u_0, beta[j]
     = beta_{j+1}), U (m x k), V (n x (k + 1)), reorth_u, reorth_v (bool per
@@ -142,20 +151,30 @@ def gkl(Y, k: int, policy: str = "full", eta: float = 1e-10, seed: int = 0, v1=N
     / v_{j+1} before any reorthogonalisation of it), loss_u[j] / loss_v[j]
     (the largest |u_j^T u_i| / |v_{j+1}^T v_i| actually left)."""
     m, n = Y.shape
-    Yt = Y.T
+    f32 = store == "f32"
+    vt = np.float32 if f32 else np.float64
+    Ys = Y.astype(np.float32) if f32 else Y
+    Yt = Ys.T
+
+    def prod(A, x):
+        return np.asarray(A @ x, dtype=np.float64)
+
+    def f64(B):
+        return np.asarray(B, dtype=np.float64)
+
     if v1 is None:
         v1 = np.random.default_rng(seed).standard_normal(n)
-    U = np.zeros((m, k))
-    V = np.zeros((n, k + 1))
+    U = np.zeros((m, k), vt)
+    V = np.zeros((n, k + 1), vt)
     V[:, 0] = v1 / np.linalg.norm(v1)
     alpha = np.zeros(k)
     beta = np.zeros(k + 1)
-    est = OmegaEstimate(EPS64, m + n)
+    est = OmegaEstimate(EPS32, m + n, 1.0) if f32 else OmegaEstimate(EPS64, m + n)
     out = dict(reorth_u=[], reorth_v=[], est_u=[], est_v=[], loss_u=[], loss_v=[])
     force_u = force_v = False
     for j in range(k):
         # alpha_{j+1} u_{j+1} = Y v_{j+1} - beta_{j+1} u_j
-        z = Y @ V[:, j]
+        z = prod(Ys, V[:, j])
         if j > 0:
             z = z - beta[j] * U[:, j - 1]
         row = est.row_u(np.linalg.norm(z))
@@ -166,16 +185,16 @@ def gkl(Y, k: int, policy: str = "full", eta: float = 1e-10, seed: int = 0, v1=N
             do = j > 0 and (policy == "full" or (policy == "partial" and (e_u > eta or force_u)))
         force_u = False
         if do:
-            z = _cgs2(z, U[:, :j])
+            z = _cgs2(z, f64(U[:, :j]))
             force_v = policy == "partial" and e_u > eta
         alpha[j] = np.linalg.norm(z)
         U[:, j] = z / alpha[j]
         est.push_u(alpha[j], row, do)
         out["reorth_u"].append(do)
         out["est_u"].append(e_u)
-        out["loss_u"].append(float(np.max(np.abs(U[:, :j].T @ U[:, j]))) if j else 0.0)
+        out["loss_u"].append(float(np.max(np.abs(f64(U[:, :j]).T @ U[:, j]))) if j else 0.0)
         # beta_{j+2} v_{j+2} = Y^T u_{j+1} - alpha_{j+1} v_{j+1}
-        z = Yt @ U[:, j] - alpha[j] * V[:, j]
+        z = prod(Yt, U[:, j]) - alpha[j] * V[:, j]
         row = est.row_v(np.linalg.norm(z))
         e_v = float(np.max(np.abs(row)))
         if policy == "given":
@@ -184,17 +203,18 @@ def gkl(Y, k: int, policy: str = "full", eta: float = 1e-10, seed: int = 0, v1=N
             do = policy == "full" or (policy == "partial" and (e_v > eta or force_v))
         force_v = False
         if do:
-            z = _cgs2(z, V[:, :j + 1])
+            z = _cgs2(z, f64(V[:, :j + 1]))
             force_u = policy == "partial" and e_v > eta
         beta[j + 1] = np.linalg.norm(z)
         V[:, j + 1] = z / beta[j + 1]
         est.push_v(beta[j + 1], row, do)
         out["reorth_v"].append(do)
         out["est_v"].append(e_v)
-        out["loss_v"].append(float(np.max(np.abs(V[:, :j + 1].T @ V[:, j + 1]))))
-        if on_step is not None:
-            on_step(j + 1, alpha[:j + 1], beta[:j + 2])
-    out.update(alpha=alpha, beta=beta, U=U, V=V)
+        out["loss_v"].append(float(np.max(np.abs(f64(V[:, :j + 1]).T @ V[:, j + 1]))))
+        if on_step is not None and on_step(j + 1, alpha[:j + 1], beta[:j + 2]):
+            k = j + 1                                 # the caller stops here
+            break
+    out.update(alpha=alpha[:k], beta=beta[:k + 1], U=U[:, :k], V=V[:, :k + 1])
     for key in ("reorth_u", "reorth_v"):
         out[key] = np.array(out[key], dtype=bool)
     for key in ("est_u", "est_v", "loss_u", "loss_v"):
@@ -223,17 +243,24 @@ def decide(Y, tau: float, tol: float = 1e-12, kmax: int = 1000, policy: str = "f
     (strict, as ``block_krylov.block_gkl`` with b = 1) is certain.  Returns
     dict(steps, rank, sigma (Ritz values through the first at or below tau),
     resid, reorth (the number of vectors reorthogonalised), vectors (2
-    steps), U, V (the Ritz vectors of the values above tau)) or None."""
+    steps), U, V (the Ritz vectors of the values above tau), run) or None."""
     m, n = Y.shape
     kmax = min(kmax, m, n)
-    run = gkl(Y, kmax, policy=policy, eta=eta, seed=seed)
-    for k in range(1, kmax + 1):
-        s, res, P, Q = ritz(run["alpha"], run["beta"], k)
-        atol = tol * s[0]
+    found = {}
+
+    def check(k, alpha, beta):
+        s, res, P, Q = ritz(alpha, beta, k)
         r = int(np.count_nonzero(s > tau))
-        if k == min(m, n) or (r < k and np.all(res[:r + 1] <= atol)):
-            nre = int(run["reorth_u"][:k].sum() + run["reorth_v"][:k].sum())
-            return dict(steps=k, rank=r, sigma=s[:r + 1], resid=res[:r + 1], reorth=nre,
-                        vectors=2 * k, U=run["U"][:, :k] @ P[:, :r], V=run["V"][:, :k] @ Q[:, :r],
-                        run=run)
-    return None
+        if k == min(m, n) or (r < k and np.all(res[:r + 1] <= tol * s[0])):
+            found.update(k=k, s=s, res=res, P=P, Q=Q, r=r)
+            return True
+        return False
+
+    run = gkl(Y, kmax, policy=policy, eta=eta, seed=seed, on_step=check)
+    if not found:
+        return None
+    k, r, P, Q = found["k"], found["r"], found["P"], found["Q"]
+    nre = int(run["reorth_u"][:k].sum() + run["reorth_v"][:k].sum())
+    return dict(steps=k, rank=r, sigma=found["s"][:r + 1], resid=found["res"][:r + 1], reorth=nre,
+                vectors=2 * k, U=np.asarray(run["U"][:, :k], dtype=np.float64) @ P[:, :r],
+                V=np.asarray(run["V"][:, :k], dtype=np.float64) @ Q[:, :r], run=run)

@@ -5,9 +5,9 @@
 
 namespace svt {
 
-void OrthEstimate::reset(double unit, int64_t dim) {
+void OrthEstimate::reset(double unit, double root) {
   unit_ = unit;
-  root_ = std::sqrt((double)dim);
+  root_ = root;
   anorm_ = 0.0;
   alpha_.clear();
   beta_.assign(1, 0.0);
@@ -59,7 +59,7 @@ double OrthEstimate::push_v(double b, bool reorth) {
   return top;
 }
 
-void ReorthSchedule::start(double eta, double unit, int64_t dim, double growth_prior) {
+void ReorthSchedule::start(double eta, double unit, double root, double growth_prior) {
   eta_ = eta;
   unit_ = unit;
   verify_ = std::sqrt(unit);
@@ -67,8 +67,8 @@ void ReorthSchedule::start(double eta, double unit, int64_t dim, double growth_p
   seen_ = 0.0;
   growth_ = prior_;
   // the rounding term alone, with |Y|_est / divisor taken as 2
-  reset_level_ = unit * std::sqrt((double)dim) * 2.0;
-  est_.reset(unit, dim);
+  reset_level_ = unit * root * 2.0;
+  est_.reset(unit, root);
   logs_.assign(kWindow, 0.0);
   nlogs_ = 0;
   sched_.clear();

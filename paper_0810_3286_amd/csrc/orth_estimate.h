@@ -13,10 +13,12 @@
 //
 // up to the rounding of step j.  OrthEstimate runs these on the coefficients
 // alone (the recurrences of Simon for symmetric Lanczos and of Larsen for
-// bidiagonalisation), adding the rounding as u sqrt(m + n) |Y|_est / divisor
-// with the sign of the value (u: the unit roundoff of the stored vectors;
-// |Y|_est: the largest alpha_i + beta_i so far).  A vector orthogonalised
-// against its whole basis has its row set to u.
+// bidiagonalisation), adding the rounding as u c |Y|_est / divisor with the
+// sign of the value (u: the unit roundoff of the stored vectors; |Y|_est: the
+// largest alpha_i + beta_i so far; c: sqrt(m + n) for FP64 vectors, 1 for
+// FP32 vectors, whose rounding is dominated by that of their storage, which
+// has no systematic direction).  A vector orthogonalised against its whole
+// basis has its row set to u.
 #pragma once
 
 #include <cstddef>
@@ -27,7 +29,7 @@ namespace svt {
 
 class OrthEstimate {
  public:
-  void reset(double unit, int64_t dim);
+  void reset(double unit, double root);
   // u_j (j = steps() + 1) with coefficient alpha_j: returns the largest
   // |mu_{j,i}|, i < j, as the recurrence gives it; reorth: u_j was then
   // orthogonalised against u_1 .. u_{j-1} (its row becomes u).
@@ -64,7 +66,7 @@ class OrthEstimate {
 // can start again with full reorthogonalisation.
 class ReorthSchedule {
  public:
-  void start(double eta, double unit, int64_t dim, double growth_prior);
+  void start(double eta, double unit, double root, double growth_prior);
   bool decide(int h);
   // alpha_1..alpha_k and beta_1..beta_{k+1} (beta[0] = beta_1, unused):
   // returns false if an unreorthogonalised vector passed `verify`.

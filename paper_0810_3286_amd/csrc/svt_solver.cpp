@@ -747,7 +747,12 @@ struct Problem final : ProblemBase {
     ensure_basis(std::min<int64_t>(acols, 8));
     const Csx R = a_rows_struct(), C = a_cols_struct();
     partial_run = partial_now && passes_now == 1;
-    if (partial_run) rsched.start(prm.reorth_eta, kUnit, arows + acols, growth_carry);
+    if (partial_run) {
+      // the level is a multiple of sqrt(u), semi-orthogonality in the
+      // vectors' precision; the rounding term's factor as OrthEstimate states
+      const double root = sizeof(T) == 8 ? std::sqrt((double)(arows + acols)) : 1.0;
+      rsched.start(prm.reorth_eta * std::sqrt(kUnit), kUnit, root, growth_carry);
+    }
     HIP_CHECK(launch_randn<T>(stream, pbuf_v.as<T>(), (int)acols, prm.seed, rng_ctr++));
     HIP_CHECK(launch_sumsq<T>(stream, pbuf_v.as<T>(), (int)acols, gs.part3, mrows()));
     g.pv = PendingVec{3, 0};
@@ -1701,8 +1706,8 @@ static void validate_params(const svt_params &p) {
   if (!finite(p.lanczos_tol) || p.lanczos_tol < 0 || p.lanczos_tol >= 1) throw Error(SVT_EINVAL, "lanczos_tol must be in [0, 1)");
   if (p.lanczos_maxsteps < 0) throw Error(SVT_EINVAL, "lanczos_maxsteps must be >= 0");
   if (p.reorth_passes < 0 || p.reorth_passes > 2) throw Error(SVT_EINVAL, "reorth_passes must be 0, 1 or 2");
-  if (!finite(p.reorth_eta) || p.reorth_eta < 0 || p.reorth_eta > 1e-4)
-    throw Error(SVT_EINVAL, "reorth_eta must be in [0, 1e-4]");
+  if (!finite(p.reorth_eta) || p.reorth_eta < 0 || p.reorth_eta > 100)
+    throw Error(SVT_EINVAL, "reorth_eta must be in [0, 100]");
   if (!finite(p.decide_margin) || p.decide_margin < 0) throw Error(SVT_EINVAL, "decide_margin must be finite and >= 0");
   if (p.spmv_mode < 0 || p.spmv_mode > 2) throw Error(SVT_EINVAL, "spmv_mode must be 0, 1 or 2");
 }
@@ -1757,7 +1762,7 @@ svt_status svt_params_default(int64_t m, int64_t n, int64_t nnz, svt_params *out
   out->lanczos_tol = 0.0;  // auto: 1e-12 (FP64) or 1e-6 (MIXED)
   out->lanczos_maxsteps = 0;
   out->reorth_passes = 0;
-  out->reorth_eta = 1e-10;
+  out->reorth_eta = 0.01;
   out->decide_margin = 0.05;
   out->svd_method = SVT_SVD_LANCZOS;
   out->rsvd_oversample = 10;

@@ -6,18 +6,18 @@
 
 extern "C" {
 
-void *est_new(double unit, int64_t dim) {
+void *est_new(double unit, double root) {
   auto *e = new svt::OrthEstimate();
-  e->reset(unit, dim);
+  e->reset(unit, root);
   return e;
 }
 double est_push_u(void *e, double a, int reorth) { return static_cast<svt::OrthEstimate *>(e)->push_u(a, reorth != 0); }
 double est_push_v(void *e, double b, int reorth) { return static_cast<svt::OrthEstimate *>(e)->push_v(b, reorth != 0); }
 void est_free(void *e) { delete static_cast<svt::OrthEstimate *>(e); }
 
-void *sched_new(double eta, double unit, int64_t dim, double prior) {
+void *sched_new(double eta, double unit, double root, double prior) {
   auto *s = new svt::ReorthSchedule();
-  s->start(eta, unit, dim, prior);
+  s->start(eta, unit, root, prior);
   return s;
 }
 int sched_decide(void *s, int h) { return static_cast<svt::ReorthSchedule *>(s)->decide(h) ? 1 : 0; }

@@ -53,6 +53,32 @@ def _kick_iterate(idx):
     return (k0 * p.delta) * P, p.tau
 
 
+_LATER = {}
+
+
+def _later_iterate(idx, iters):
+    """The iterate after `iters` SVT iterations of the tier-C oracle (the
+    bidiagonalisations of later iterations run longer: 55 steps at 400^2,
+    111 at 5000^2, where orthogonality is lost fast)."""
+    key = (idx, iters)
+    if key not in _LATER:
+        from oracle import krylov
+        p = workload.config(idx)
+        o = krylov.svt_krylov(p.m, p.n, p.rows, p.cols, p.vals, p.tau, p.delta, 0.0, iters, p.incr)
+        _LATER[key] = (sp.csr_matrix((o["y_last"], (p.rows, p.cols)), shape=(p.m, p.n)), p.tau)
+    return _LATER[key]
+
+
+def _case(case):
+    if case == "dense":
+        return None
+    if case == "later1":
+        return _later_iterate(1, 5)
+    if case == "later2":
+        return _later_iterate(2, 3)
+    return _kick_iterate(1 if case == "config1" else 2)
+
+
 def _actual(run, k):
     U, V = run["U"][:, :k], run["V"][:, :k + 1]
     return U.T @ U, V.T @ V
@@ -89,6 +115,47 @@ def test_estimate_bounds_the_loss():
         assert np.all(est[live] >= loss[live])
 
 
+def _min_ratio(run):
+    est = np.r_[run["est_u"][1:], run["est_v"]]
+    loss = np.r_[run["loss_u"][1:], run["loss_v"]]
+    live = (loss < 1e-3) & (loss > 0)                   # before the loss saturates
+    return float(np.min(est[live] / loss[live])), int(live.sum())
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_fp32_storage_estimate_bounds_the_loss(seed):
+    # vectors stored in FP32 (the mixed form): the rounding term with c = 1
+    ratio, n = _min_ratio(pr.gkl(_dense_problem(seed=seed), 60, policy="none", store="f32"))
+    assert n > 10 and ratio >= 1.0
+
+
+@pytest.mark.parametrize("case", ["config1", "later1"])
+def test_fp32_storage_on_a_completion_iterate(case):
+    Y, _ = _case(case)
+    ratio, n = _min_ratio(pr.gkl(Y, 50, policy="none", store="f32"))
+    assert n > 10 and ratio >= 1.0
+
+
+def test_fp64_needs_the_dimension_factor():
+    # in FP64 the same term without sqrt(m + n) falls below the loss: the
+    # estimate keeps the factor there
+    run = pr.gkl(_dense_problem(seed=1), 60, policy="none")
+    m, n = 300, 200
+    est = pr.OmegaEstimate(pr.EPS64, m + n, root=1.0)
+    low = []
+    for j in range(60):
+        r = est.row_u(run["alpha"][j])
+        est.push_u(run["alpha"][j], r, False)
+        if j and 0 < run["loss_u"][j] < 1e-3:
+            low.append(np.max(np.abs(r)) / run["loss_u"][j])
+        r = est.row_v(run["beta"][j + 1])
+        est.push_v(run["beta"][j + 1], r, False)
+        if 0 < run["loss_v"][j] < 1e-3:
+            low.append(np.max(np.abs(r)) / run["loss_v"][j])
+    assert min(low) < 1.0
+    assert _min_ratio(run)[0] >= 1.0
+
+
 def test_ghosts_without_reorthogonalisation():
     A = _dense_problem(seed=3)
     k = 120
@@ -102,14 +169,14 @@ def test_ghosts_without_reorthogonalisation():
     assert counts["partial"] == counts["full"] == 1
 
 
-@pytest.mark.parametrize("case", ["dense", "config1", "config2"])
+@pytest.mark.parametrize("case", ["dense", "config1", "config2", "later1", "later2"])
 def test_partial_matches_full(case):
     if case == "dense":
         Y = _dense_problem(seed=4)
         sv = np.linalg.svd(Y, compute_uv=False)
         tau = 0.5 * (sv[5] + sv[6])
     else:
-        Y, tau = _kick_iterate(1 if case == "config1" else 2)
+        Y, tau = _case(case)
     full = pr.decide(Y, tau, policy="full")
     part = pr.decide(Y, tau, policy="partial", eta=1e-10)
     assert full is not None and part is not None
@@ -137,10 +204,10 @@ def capi(tmp_path_factory):
                     os.path.join(ROOT, "tests", "orth_capi.cpp"), os.path.join(CSRC, "orth_estimate.cpp"),
                     "-o", so], check=True)
     lib = ctypes.CDLL(so)
-    vp, d, i64, i = ctypes.c_void_p, ctypes.c_double, ctypes.c_int64, ctypes.c_int
+    vp, d, i = ctypes.c_void_p, ctypes.c_double, ctypes.c_int
     dp = ctypes.POINTER(ctypes.c_double)
-    for name, res, args in [("est_new", vp, [d, i64]), ("est_push_u", d, [vp, d, i]), ("est_push_v", d, [vp, d, i]),
-                            ("est_free", None, [vp]), ("sched_new", vp, [d, d, i64, d]),
+    for name, res, args in [("est_new", vp, [d, d]), ("est_push_u", d, [vp, d, i]), ("est_push_v", d, [vp, d, i]),
+                            ("est_free", None, [vp]), ("sched_new", vp, [d, d, d, d]),
                             ("sched_decide", i, [vp, i]), ("sched_advance", i, [vp, dp, dp, i]),
                             ("sched_growth", d, [vp]), ("sched_growth_seen", d, [vp]), ("sched_free", None, [vp])]:
         fn = getattr(lib, name)
@@ -153,7 +220,7 @@ def test_host_estimate_equals_oracle(capi):
     Y, _ = _kick_iterate(1)
     m, n = Y.shape
     run = pr.gkl(Y, 60, policy="partial", eta=1e-10)
-    e = capi.est_new(pr.EPS64, m + n)
+    e = capi.est_new(pr.EPS64, np.sqrt(m + n))
     try:
         for j in range(60):
             got_u = capi.est_push_u(e, run["alpha"][j], int(run["reorth_u"][j]))
@@ -164,7 +231,8 @@ def test_host_estimate_equals_oracle(capi):
         capi.est_free(e)
 
 
-@pytest.mark.parametrize("case,lag", [("dense", 8), ("config1", 8), ("config2", 8), ("config2", 3)])
+@pytest.mark.parametrize("case,lag", [("dense", 8), ("config1", 8), ("config2", 8), ("later1", 8), ("later2", 8),
+                                      ("later2", 3)])
 def test_host_schedule_in_closed_loop(capi, case, lag):
     # the solver checks the coefficients of every snapshot before its rank
     # decision; here every `lag` steps (two steps behind, as the device runs
@@ -174,11 +242,11 @@ def test_host_schedule_in_closed_loop(capi, case, lag):
         sv = np.linalg.svd(Y, compute_uv=False)
         tau = 0.5 * (sv[5] + sv[6])
     else:
-        Y, tau = _kick_iterate(1 if case == "config1" else 2)
+        Y, tau = _case(case)
     m, n = Y.shape
     full = pr.decide(Y, tau, policy="full")
     k = full["steps"]
-    s = capi.sched_new(1e-10, pr.EPS64, m + n, 8.0)
+    s = capi.sched_new(1e-10, pr.EPS64, np.sqrt(m + n), 8.0)
     dp = ctypes.POINTER(ctypes.c_double)
     verdicts = []
 
@@ -213,3 +281,33 @@ def test_host_schedule_in_closed_loop(capi, case, lag):
     r = full["rank"]
     np.testing.assert_allclose(sig[:r + 1], full["sigma"], rtol=1e-12)
     assert 1.0 < growth < 50.0
+
+
+@pytest.mark.parametrize("case", ["config2", "later1", "later2"])
+def test_host_schedule_fp32_in_closed_loop(capi, case):
+    # the mixed form's setting: FP32 vectors, level 0.01 sqrt(u), c = 1
+    Y, tau = _case(case)
+    m, n = Y.shape
+    full = pr.decide(Y, tau, policy="full")
+    k = full["steps"]
+    s = capi.sched_new(0.01 * np.sqrt(pr.EPS32), pr.EPS32, 1.0, 8.0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    verdicts = []
+
+    def check(alpha, beta, j):
+        a = np.ascontiguousarray(alpha, dtype=np.float64)
+        b = np.ascontiguousarray(beta, dtype=np.float64)
+        verdicts.append(capi.sched_advance(s, a.ctypes.data_as(dp), b.ctypes.data_as(dp), j))
+
+    try:
+        run = pr.gkl(Y, k, policy="given", store="f32", decide=lambda h: capi.sched_decide(s, h),
+                     on_step=lambda j, a, b: check(a, b, j - 2) if j % 8 == 0 else None)
+        check(run["alpha"], run["beta"], k)
+    finally:
+        capi.sched_free(s)
+    assert all(verdicts)
+    assert max(run["loss_u"].max(), run["loss_v"].max()) < np.sqrt(pr.EPS32)
+    assert int(run["reorth_u"].sum() + run["reorth_v"].sum()) < 0.9 * 2 * k
+    sig = pr.ritz(run["alpha"], run["beta"], k)[0]
+    r = full["rank"]
+    np.testing.assert_allclose(sig[:r + 1], full["sigma"], rtol=1e-5)
