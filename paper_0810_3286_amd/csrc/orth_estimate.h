@@ -58,10 +58,11 @@ class OrthEstimate {
 // successor restarts from the rounding term, not from u: its predicted level
 // is a restart level times the growth.  When coefficients arrive, advance()
 // runs OrthEstimate on them with the schedule that was applied: levels up to
-// there become exact, the growth factor becomes the largest ratio seen
-// between consecutive levels of vectors left alone (never below the floor,
-// nor below the value carried from the previous run), the restart level the
-// largest seen (divided by the growth), and a vector left alone whose level
+// there become exact, the growth factor becomes 1.25 times the geometric mean
+// of the last 8 ratios between consecutive levels of vectors left alone
+// (before 8 are seen, the largest ratio seen, and at least the value carried
+// from the previous run), the restart level the largest seen (divided by the
+// growth), and a vector left alone whose level
 // passed `verify` (semi-orthogonality, sqrt(u)) is reported so the caller
 // can start again with full reorthogonalisation.
 class ReorthSchedule {
