@@ -18,9 +18,10 @@ The library's host code for it (``orth_estimate.cpp``: the same estimate and
 the schedule the solver uses, which decides each vector before its
 coefficients reach the host) is compiled here with g++ and checked against
 the oracle: its estimates equal the oracle's, and driving the oracle's
-bidiagonalisation with its decisions, the coefficients arriving 8 steps
-late, keeps the bases semi-orthogonal with the full method's result.
-Nothing runs on a GPU.
+bidiagonalisation with its decisions, the coefficients arriving 2 to 10
+steps late, keeps the bases semi-orthogonal with the full method's result
+(FP64 and FP32 vectors), while a level above sqrt(u) is reported by its
+check.  Nothing runs on a GPU.
 """
 import ctypes
 import os
@@ -311,3 +312,28 @@ def test_host_schedule_fp32_in_closed_loop(capi, case):
     sig = pr.ritz(run["alpha"], run["beta"], k)[0]
     r = full["rank"]
     np.testing.assert_allclose(sig[:r + 1], full["sigma"], rtol=1e-5)
+
+
+def test_host_schedule_reports_a_level_past_semi_orthogonality(capi):
+    # a level above sqrt(u) lets the schedule leave vectors alone past
+    # semi-orthogonality: its check must say so (the solver then starts
+    # again with every vector orthogonalised)
+    Y, tau = _case("later2")
+    m, n = Y.shape
+    s = capi.sched_new(100.0 * np.sqrt(pr.EPS64), pr.EPS64, np.sqrt(m + n), 8.0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    verdicts = []
+
+    def check(alpha, beta, j):
+        a = np.ascontiguousarray(alpha, dtype=np.float64)
+        b = np.ascontiguousarray(beta, dtype=np.float64)
+        verdicts.append(capi.sched_advance(s, a.ctypes.data_as(dp), b.ctypes.data_as(dp), j))
+
+    try:
+        run = pr.gkl(Y, 111, policy="given", decide=lambda h: capi.sched_decide(s, h),
+                     on_step=lambda j, a, b: check(a, b, j - 2) if j % 8 == 0 else None)
+        check(run["alpha"], run["beta"], 111)
+    finally:
+        capi.sched_free(s)
+    assert not all(verdicts)
+    assert max(run["loss_u"].max(), run["loss_v"].max()) > np.sqrt(pr.EPS64) * 1e-3
