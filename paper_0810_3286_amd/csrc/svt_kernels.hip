@@ -883,7 +883,7 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv_rows(
     }
   }
   if (!kEarlyX) {
-    load_q8<T>(qx8, in.Qx, in.ldqx, in.nqx, xrow, xvalid, in.x);
+    if constexpr (!PLAIN) load_q8<T>(qx8, in.Qx, in.ldqx, in.nqx, xrow, xvalid, in.x);
     xv0 = in.x[xvalid ? xrow : 0];
   }
   __syncthreads();  // racc complete, s published; the region is free again
