@@ -15,13 +15,18 @@ void OrthEstimate::reset(double unit, double root) {
   nu_.clear();
 }
 
+// A coefficient that is not positive and finite (a breakdown of the
+// recurrence) leaves nothing to divide by: the new vector is taken as having
+// lost its orthogonality entirely (level 1), never as NaN.
+static bool usable(double c) { return c > 0.0 && std::isfinite(c); }
+
 double OrthEstimate::push_u(double a, bool reorth) {
   const int j = (int)alpha_.size() + 1;  // u_j
-  anorm_ = std::max(anorm_, a + beta_[(size_t)j - 1]);
-  const double noise = unit_ * root_ * anorm_ / a;
-  row_.assign((size_t)j - 1, 0.0);
-  double top = 0.0;
-  for (int i = 1; i < j; ++i) {
+  if (usable(a)) anorm_ = std::max(anorm_, a + beta_[(size_t)j - 1]);
+  const double noise = usable(a) ? unit_ * root_ * anorm_ / a : 0.0;
+  row_.assign((size_t)j - 1, usable(a) ? 0.0 : 1.0);
+  double top = (usable(a) || j == 1) ? 0.0 : 1.0;
+  for (int i = 1; i < j && usable(a); ++i) {
     // nu_ holds nu_{j,1..j-1}; mu_ holds mu_{j-1,1..j-2}
     const double nu_next = (i + 1 == j) ? 1.0 : nu_[(size_t)i];
     double t = beta_[(size_t)i] * nu_next + alpha_[(size_t)i - 1] * nu_[(size_t)i - 1];
@@ -31,7 +36,7 @@ double OrthEstimate::push_u(double a, bool reorth) {
     row_[(size_t)i - 1] = t;
     top = std::max(top, std::fabs(t));
   }
-  alpha_.push_back(a);
+  alpha_.push_back(usable(a) ? a : 0.0);
   if (reorth) std::fill(row_.begin(), row_.end(), unit_);
   mu_.swap(row_);
   return top;
@@ -39,11 +44,11 @@ double OrthEstimate::push_u(double a, bool reorth) {
 
 double OrthEstimate::push_v(double b, bool reorth) {
   const int j = (int)alpha_.size();  // v_{j+1}
-  anorm_ = std::max(anorm_, alpha_[(size_t)j - 1] + b);
-  const double noise = unit_ * root_ * anorm_ / b;
-  row_.assign((size_t)j, 0.0);
-  double top = 0.0;
-  for (int i = 1; i <= j; ++i) {
+  if (usable(b)) anorm_ = std::max(anorm_, alpha_[(size_t)j - 1] + b);
+  const double noise = usable(b) ? unit_ * root_ * anorm_ / b : 0.0;
+  row_.assign((size_t)j, usable(b) ? 0.0 : 1.0);
+  double top = usable(b) ? 0.0 : 1.0;
+  for (int i = 1; i <= j && usable(b); ++i) {
     // mu_ holds mu_{j,1..j-1}; nu_ holds nu_{j,1..j-1}
     double t = alpha_[(size_t)i - 1] * ((i == j) ? 1.0 : mu_[(size_t)i - 1]);
     if (i >= 2) t += beta_[(size_t)i - 1] * mu_[(size_t)i - 2];
@@ -53,7 +58,7 @@ double OrthEstimate::push_v(double b, bool reorth) {
     row_[(size_t)i - 1] = t;
     top = std::max(top, std::fabs(t));
   }
-  beta_.push_back(b);
+  beta_.push_back(usable(b) ? b : 0.0);
   if (reorth) std::fill(row_.begin(), row_.end(), unit_);
   nu_.swap(row_);
   return top;

@@ -337,3 +337,24 @@ def test_host_schedule_reports_a_level_past_semi_orthogonality(capi):
         capi.sched_free(s)
     assert not all(verdicts)
     assert max(run["loss_u"].max(), run["loss_v"].max()) > np.sqrt(pr.EPS64) * 1e-3
+
+
+def test_host_estimate_at_a_breakdown(capi):
+    # a zero or non-finite coefficient (the recurrence broke down) counts as
+    # total loss of orthogonality, and later estimates stay finite
+    Y, _ = _kick_iterate(1)
+    m, n = Y.shape
+    run = pr.gkl(Y, 12, policy="full")
+    for bad in (0.0, float("nan"), float("inf")):
+        e = capi.est_new(pr.EPS64, np.sqrt(m + n))
+        try:
+            for j in range(5):
+                capi.est_push_u(e, run["alpha"][j], 1)
+                capi.est_push_v(e, run["beta"][j + 1], 1)
+            assert capi.est_push_u(e, bad, 0) == 1.0
+            assert capi.est_push_v(e, bad, 0) == 1.0
+            for j in range(6, 10):
+                for got in (capi.est_push_u(e, run["alpha"][j], 0), capi.est_push_v(e, run["beta"][j + 1], 0)):
+                    assert np.isfinite(got) and got >= 0.0
+        finally:
+            capi.est_free(e)
