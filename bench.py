@@ -538,7 +538,8 @@ def main():
                     help="0 or 2: x staged in LDS (column segments when needed), 1: gathered")
     ap.add_argument("--reorth-eta", type=float, default=None,
                     help="partial reorthogonalisation level, a multiple of sqrt(unit roundoff) "
-                         "(0: every vector orthogonalised; default: the library's)")
+                         "(0: every vector orthogonalised; default: the library's automatic level, "
+                         "reported as -1)")
     ap.add_argument("--min-rows", type=int, default=0,
                     help="min_block_rows of the headline solve (0: the library default)")
     ap.add_argument("--serving-requests", type=int, default=16)

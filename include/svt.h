@@ -154,23 +154,24 @@ typedef struct {
                             level as a multiple of sqrt(u), u the unit
                             roundoff of the bidiagonalisation's vectors
                             (FP64: sqrt(u) = 1.05e-8; MIXED, FP32 vectors:
-                            2.44e-4).  In (0, 100] (default 0.01): the loss
-                            of orthogonality of each new vector is estimated
-                            from the bidiagonal coefficients alone (the
-                            recurrences of Simon and Larsen), and a vector
-                            is orthogonalised against its whole basis, with
-                            the next vector of the other side, only once its
-                            predicted estimate passes reorth_eta sqrt(u).
-                            The estimates are checked as the coefficients
-                            reach the host; if one of a vector left alone
-                            passed sqrt(u) (semi-orthogonality) the
-                            bidiagonalisation starts again with full
-                            reorthogonalisation, kept for the rest of the
-                            solve (levels of 1 and above make that happen).
-                            0: every new vector is orthogonalised.  Applies
-                            with one Gram-Schmidt pass per vector
-                            (reorth_passes 0 or 1); svt_reorth_stats reports
-                            what it did                                    */
+                            2.44e-4).  The loss of orthogonality of each new
+                            vector is estimated from the bidiagonal
+                            coefficients alone (the recurrences of Simon and
+                            Larsen), and a vector is orthogonalised against
+                            its whole basis, with the next vector of the
+                            other side, only once its predicted estimate
+                            passes reorth_eta sqrt(u).  The estimates are
+                            checked as the coefficients reach the host; if
+                            one of a vector left alone passed sqrt(u)
+                            (semi-orthogonality) the bidiagonalisation
+                            starts again with full reorthogonalisation, kept
+                            for the rest of the solve (levels of 1 and above
+                            make that happen).  Negative (default):
+                            automatic, 0.01 with FP64 vectors and 0.1 with
+                            FP32 vectors; 0: every new vector is
+                            orthogonalised; at most 100.  Applies with one
+                            Gram-Schmidt pass per vector (reorth_passes 0 or
+                            1); svt_reorth_stats reports what it did       */
 } svt_params;
 
 typedef struct {

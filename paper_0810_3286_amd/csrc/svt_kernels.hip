@@ -447,8 +447,8 @@ __device__ __forceinline__ void load_q8(T (&q)[8], const T *__restrict__ Q, int6
 // PLAIN (a half-step with nothing to orthogonalise: nq = nqx = 0, so no
 // update of x and no dot products beyond |p|^2): the same arithmetic without
 // the basis loads, whose registers the general kernel holds through the
-// product; measured 16.5 -> 16.3 us per half-step at 30000^2 (FP64) and
-// 18.1 -> 17.1 us at 10000^2.
+// product; measured, on average over all half-steps, 16.5 -> 16.1 us at
+// 30000^2 (FP64) and 18.1 -> 17.0 us at 10000^2, rank 50.
 //
 // STAGE: x_raw is copied into LDS in nseg column segments of segcols entries
 // (coalesced, every thread's loads issued before its stores) and the

@@ -751,7 +751,7 @@ struct Problem final : ProblemBase {
       // the level is a multiple of sqrt(u), semi-orthogonality in the
       // vectors' precision; the rounding term's factor as OrthEstimate states
       const double root = sizeof(T) == 8 ? std::sqrt((double)(arows + acols)) : 1.0;
-      rsched.start(prm.reorth_eta * std::sqrt(kUnit), kUnit, root, growth_carry);
+      rsched.start(reorth_level() * std::sqrt(kUnit), kUnit, root, growth_carry);
     }
     HIP_CHECK(launch_randn<T>(stream, pbuf_v.as<T>(), (int)acols, prm.seed, rng_ctr++));
     HIP_CHECK(launch_sumsq<T>(stream, pbuf_v.as<T>(), (int)acols, gs.part3, mrows()));
@@ -1377,10 +1377,19 @@ struct Problem final : ProblemBase {
   void reset_passes() {
     passes_now = prm.reorth_passes == 2 ? 2 : 1;
     reorth_restarts = 0;
-    partial_now = prm.reorth_eta > 0.0 && passes_now == 1;
+    partial_now = reorth_level() > 0.0 && passes_now == 1;
     partial_run = false;
     growth_carry = kFirstGrowth;
     vec_made = vec_orth = partial_fallbacks = 0;
+  }
+
+  // The partial-reorthogonalisation level as a multiple of sqrt(u): the
+  // caller's, or (negative) 0.01 for FP64 vectors and 0.1 for FP32 vectors,
+  // whose rounding term sits closer to semi-orthogonality (a shorter horizon
+  // for the prediction; 0.1 in FP64 fails the check, measured on the CPU).
+  double reorth_level() const {
+    if (prm.reorth_eta >= 0.0) return prm.reorth_eta;
+    return sizeof(T) == 8 ? 0.01 : 0.1;
   }
 
   // the growth per half-step assumed by the first partially reorthogonalised
@@ -1706,8 +1715,8 @@ static void validate_params(const svt_params &p) {
   if (!finite(p.lanczos_tol) || p.lanczos_tol < 0 || p.lanczos_tol >= 1) throw Error(SVT_EINVAL, "lanczos_tol must be in [0, 1)");
   if (p.lanczos_maxsteps < 0) throw Error(SVT_EINVAL, "lanczos_maxsteps must be >= 0");
   if (p.reorth_passes < 0 || p.reorth_passes > 2) throw Error(SVT_EINVAL, "reorth_passes must be 0, 1 or 2");
-  if (!finite(p.reorth_eta) || p.reorth_eta < 0 || p.reorth_eta > 100)
-    throw Error(SVT_EINVAL, "reorth_eta must be in [0, 100]");
+  if (!finite(p.reorth_eta) || p.reorth_eta > 100)
+    throw Error(SVT_EINVAL, "reorth_eta must be finite and at most 100");
   if (!finite(p.decide_margin) || p.decide_margin < 0) throw Error(SVT_EINVAL, "decide_margin must be finite and >= 0");
   if (p.spmv_mode < 0 || p.spmv_mode > 2) throw Error(SVT_EINVAL, "spmv_mode must be 0, 1 or 2");
 }
@@ -1762,7 +1771,7 @@ svt_status svt_params_default(int64_t m, int64_t n, int64_t nnz, svt_params *out
   out->lanczos_tol = 0.0;  // auto: 1e-12 (FP64) or 1e-6 (MIXED)
   out->lanczos_maxsteps = 0;
   out->reorth_passes = 0;
-  out->reorth_eta = 0.01;
+  out->reorth_eta = -1.0;  // automatic: 0.01 (FP64 vectors), 0.1 (FP32 vectors)
   out->decide_margin = 0.05;
   out->svd_method = SVT_SVD_LANCZOS;
   out->rsvd_oversample = 10;

@@ -62,7 +62,7 @@ def test_params_default_is_the_papers_choice():
     assert p.delta == pytest.approx(1.2 * 400 * 400 / 47400)
     assert p.eps == 1e-4 and p.maxiter == 500 and p.incr == 5 and p.kick == 1
     # partial reorthogonalisation, as the paper's PROPACK runs (Section 5.1.1)
-    assert p.reorth_eta == 0.01
+    assert p.reorth_eta < 0          # automatic: 0.01 sqrt(u) FP64, 0.1 sqrt(u) FP32
     q = B.svt_params_default(300, 1200, 1000)
     assert q.tau == pytest.approx(5.0 * np.sqrt(300 * 1200))
     with pytest.raises(B.SvtError):
@@ -106,7 +106,7 @@ def test_rejects_bad_parameters():
                        ("stop_rule", 3), ("lanczos_tol", 1.5), ("reorth_passes", 3),
                        ("decide_margin", -0.1), ("spmv_mode", 3), ("min_block_rows", -1),
                        ("min_block_rows", 2049), ("svd_method", 2), ("rsvd_oversample", -1),
-                       ("rsvd_power", 65), ("reorth_eta", -1e-12), ("reorth_eta", 101.0),
+                       ("rsvd_power", 65), ("reorth_eta", 101.0),
                        ("reorth_eta", float("nan"))]:
         p = B.svt_params_default(2, 2, 2)
         setattr(p, field, bad)

@@ -13,8 +13,9 @@ tolerances as with full reorthogonalisation:
 * the stored oracle runs at full size: 5000^2 X^60, 10000^2 rank 50 X^40
   and its complete run, 30000^2 X^20 and its complete run: FP64 within 1e-8
   with the same ranks, while fewer than half of the vectors are
-  orthogonalised; the mixed form (FP32 vectors) within 5e-4 while
-  orthogonalising fewer vectors than with reorth_eta = 0;
+  orthogonalised; the mixed form (FP32 vectors, the automatic level 0.1)
+  within 5e-4 while orthogonalising fewer vectors than with reorth_eta = 0;
+  the automatic level is 0.01 (FP64) and 0.1 (FP32) bit for bit;
 * the fall-back: reorth_eta = 100 lets predictions pass sqrt(u), the check
   of the estimates must then restart with full reorthogonalisation, and the
   solve still matches the oracle;
@@ -40,9 +41,12 @@ ETA = 0.01
 
 
 def _run(p, precision=B.SVT_FP64, eta=ETA, k=None, **kw):
+    # eta None: the library's automatic level
+    if eta is not None:
+        kw["reorth_eta"] = eta
     return solve(p.m, p.n, p.rows, p.cols, p.vals, tau=p.tau, delta=p.delta,
                  eps=0.0 if k else p.eps, maxiter=k or p.maxiter, incr=p.incr,
-                 precision=precision, reorth_eta=eta, **kw)
+                 precision=precision, **kw)
 
 
 def _stats(g):
@@ -110,7 +114,7 @@ def test_mixed_matches_stored_oracle(cfg, k):
     gpu_case(f"partial reorth: config {cfg} mixed, {k} iterations vs stored oracle")
     p = workload.config(cfg)
     o = _gold(f"{cfg}_k{k}")
-    g = _run(p, precision=B.SVT_MIXED, k=k)
+    g = _run(p, precision=B.SVT_MIXED, eta=None, k=k)
     assert list(g["ranks"]) == o["ranks"]
     np.testing.assert_allclose(g["residuals"], o["residuals"], rtol=5e-4)
     assert rel_diff_factored(g["U"], g["V"], o["U"], o["V"]) <= 5e-4
@@ -135,13 +139,26 @@ def test_mixed_default_orthogonalises_fewer(cfg):
     gpu_case(f"partial reorth: config {cfg} mixed, default vs level 0")
     p = workload.config(cfg)
     k = 30
-    a = _run(p, precision=B.SVT_MIXED, k=k)
+    a = _run(p, precision=B.SVT_MIXED, eta=None, k=k)
     b = _run(p, precision=B.SVT_MIXED, eta=0.0, k=k)
     fa, fall = _stats(a)
     fb, _ = _stats(b)
     assert fall == 0 and fa < 0.9 * fb
     assert list(a["ranks"]) == list(b["ranks"])
     assert rel_diff_factored(a["U"], a["V"], b["U"], b["V"]) <= 5e-4
+
+
+@pytest.mark.parametrize("precision,level", [(B.SVT_FP64, 0.01), (B.SVT_MIXED, 0.1)])
+def test_automatic_level(precision, level):
+    # the default (negative) level: 0.01 sqrt(u) for FP64 vectors, 0.1 sqrt(u)
+    # for FP32 vectors, bit for bit
+    gpu_case(f"partial reorth: automatic level, precision {precision}")
+    p = workload.config(1)
+    a = _run(p, precision=precision, eta=None, k=40)
+    b = _run(p, precision=precision, eta=level, k=40)
+    np.testing.assert_array_equal(a["U"], b["U"])
+    np.testing.assert_array_equal(a["V"], b["V"])
+    assert a["reorth"] == b["reorth"]
 
 
 def test_two_passes_keep_full_reorthogonalisation():
