@@ -163,10 +163,13 @@ typedef struct {
                             passes reorth_eta sqrt(u).  The estimates are
                             checked as the coefficients reach the host; if
                             one of a vector left alone passed sqrt(u)
-                            (semi-orthogonality) the bidiagonalisation
-                            starts again with full reorthogonalisation, kept
-                            for the rest of the solve (levels of 1 and above
-                            make that happen).  Negative (default):
+                            (semi-orthogonality) that bidiagonalisation
+                            starts again with full reorthogonalisation
+                            (levels of 1 and above make that happen).  The
+                            bidiagonalisation of an SVT step orthogonalises
+                            on a prediction no earlier than a few steps
+                            before where the previous step's coefficients
+                            show the first vector needed it.  Negative (default):
                             automatic, 0.01 with FP64 vectors and 0.1 with
                             FP32 vectors; 0: every new vector is
                             orthogonalised; at most 100.  Applies with one

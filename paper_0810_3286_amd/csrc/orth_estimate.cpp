@@ -64,8 +64,9 @@ double OrthEstimate::push_v(double b, bool reorth) {
   return top;
 }
 
-void ReorthSchedule::start(double eta, double unit, double root, double growth_prior) {
+void ReorthSchedule::start(double eta, double unit, double root, double growth_prior, int hold) {
   eta_ = eta;
+  hold_ = hold;
   unit_ = unit;
   verify_ = std::sqrt(unit);
   prior_ = std::max(growth_prior, kGrowthFloor);
@@ -88,7 +89,7 @@ bool ReorthSchedule::decide(int h) {
   double lev = reset_level_;
   if (h >= 1) {  // u_1 has no basis to be orthogonalised against
     const double pred = level_[(size_t)h - 1] * growth_;
-    trig = pred > eta_;
+    trig = pred > eta_ && h >= hold_;
     r = trig || trig_[(size_t)h - 1];
     lev = r ? reset_level_ : pred;
   }
@@ -137,6 +138,16 @@ bool ReorthSchedule::advance(const double *alpha, const double *beta, int k) {
   }
   repredict(2 * est_.steps());
   return ok;
+}
+
+int first_trigger(const double *alpha, const double *beta, int k, double eta, double unit, double root) {
+  OrthEstimate est;
+  est.reset(unit, root);
+  for (int j = 1; j <= k; ++j) {
+    if (est.push_u(alpha[j - 1], false) > eta) return 2 * (j - 1);
+    if (est.push_v(beta[j], false) > eta) return 2 * j - 1;
+  }
+  return 2 * k;
 }
 
 }  // namespace svt

@@ -67,7 +67,10 @@ class OrthEstimate {
 // can start again with full reorthogonalisation.
 class ReorthSchedule {
  public:
-  void start(double eta, double unit, double root, double growth_prior);
+  // hold: no vector before this half-step is orthogonalised on a prediction
+  // (the replayed first trigger of the previous bidiagonalisation, less a
+  // margin; 0: none)
+  void start(double eta, double unit, double root, double growth_prior, int hold = 0);
   bool decide(int h);
   // alpha_1..alpha_k and beta_1..beta_{k+1} (beta[0] = beta_1, unused):
   // returns false if an unreorthogonalised vector passed `verify`.
@@ -86,6 +89,7 @@ class ReorthSchedule {
   void repredict(int from);
   OrthEstimate est_;
   double eta_ = 0.0, verify_ = 0.0, unit_ = 0.0;
+  int hold_ = 0;
   double growth_ = kGrowthFloor, seen_ = 0.0, prior_ = 0.0;
   double reset_level_ = 0.0;    // predicted level of a vector just orthogonalised
   std::vector<double> logs_;    // logs of the last kWindow ratios
@@ -94,5 +98,12 @@ class ReorthSchedule {
   std::vector<uint8_t> trig_;   // ... because its own prediction passed eta
   std::vector<double> level_;   // level after vector h (exact below exact_vectors())
 };
+
+// The exact policy replayed on the coefficients of a finished
+// bidiagonalisation (alpha_1..alpha_k, beta[j] = beta_{j+1}): the first
+// half-step at which the estimate of a vector, with nothing orthogonalised
+// before it, passes eta; 2k if none does.  Consecutive SVT iterates put it
+// within a few half-steps of each other.
+int first_trigger(const double *alpha, const double *beta, int k, double eta, double unit, double root);
 
 }  // namespace svt

@@ -350,7 +350,9 @@ struct Problem final : ProblemBase {
   ReorthSchedule rsched;
   bool partial_now = false;
   bool partial_run = false;    // the current bidiagonalisation follows rsched
+  bool full_this_run = false;  // ... unless its check failed: then all vectors
   double growth_carry = 0.0;
+  int hold_hint = 0;           // no predicted trigger before this half-step
   int64_t vec_made = 0, vec_orth = 0, partial_fallbacks = 0;
 
   // the Dantzig-selector iteration (Section 3.3) instead of Algorithm 1's
@@ -746,13 +748,8 @@ struct Problem final : ProblemBase {
   void gkl_start(const T *vr, const T *vc, Gkl &g) {
     ensure_basis(std::min<int64_t>(acols, 8));
     const Csx R = a_rows_struct(), C = a_cols_struct();
-    partial_run = partial_now && passes_now == 1;
-    if (partial_run) {
-      // the level is a multiple of sqrt(u), semi-orthogonality in the
-      // vectors' precision; the rounding term's factor as OrthEstimate states
-      const double root = sizeof(T) == 8 ? std::sqrt((double)(arows + acols)) : 1.0;
-      rsched.start(reorth_level() * std::sqrt(kUnit), kUnit, root, growth_carry);
-    }
+    partial_run = partial_now && passes_now == 1 && !full_this_run;
+    if (partial_run) rsched.start(orth_eta(), kUnit, orth_root(), growth_carry, hold_hint);
     HIP_CHECK(launch_randn<T>(stream, pbuf_v.as<T>(), (int)acols, prm.seed, rng_ctr++));
     HIP_CHECK(launch_sumsq<T>(stream, pbuf_v.as<T>(), (int)acols, gs.part3, mrows()));
     g.pv = PendingVec{3, 0};
@@ -874,6 +871,7 @@ struct Problem final : ProblemBase {
               int &r_out) {
     const double tol = prm.lanczos_tol;
     const int cap = step_cap();
+    full_this_run = false;
     gkl_start(vr, vc, g);
     // the first check: where the previous iteration stopped, less 2 on
     // small bases (a check there costs about two steps, so probing below is
@@ -896,9 +894,11 @@ struct Problem final : ProblemBase {
       gkl_fetch_end(snap);
       if (partial_run && !rsched.advance(snap.alpha.data(), snap.beta.data(), snap.k)) {
         // a vector left alone lost more orthogonality than semi-orthogonality
-        // allows (the prediction fell short of the estimate): start again
-        // with every vector orthogonalised, for the rest of the solve
-        partial_now = false;
+        // allows (the prediction fell short of the estimate): this
+        // bidiagonalisation starts again with every vector orthogonalised,
+        // and the next one takes no hold
+        full_this_run = true;
+        hold_hint = 0;
         ++partial_fallbacks;
         if (log_level > 0)
           std::fprintf(stderr, "[svt] partial reorthogonalisation: an estimate passed %.2e by step %d "
@@ -983,7 +983,14 @@ struct Problem final : ProblemBase {
         sv = std::move(chk);
         // the next bidiagonalisation starts from this one's growth (half of
         // the carried value decays away when a run measures less)
-        if (partial_run) growth_carry = std::max(rsched.growth_seen(), 0.5 * growth_carry);
+        if (partial_run) {
+          growth_carry = std::max(rsched.growth_seen(), 0.5 * growth_carry);
+          // an SVT step's bidiagonalisation: where the next one may start
+          // orthogonalising (the exact policy replayed on these coefficients)
+          if (mode == 0)
+            hold_hint = std::max(0, first_trigger(snap.alpha.data(), snap.beta.data(), k, orth_eta(), kUnit,
+                                                  orth_root()) - kHoldMargin);
+        }
         // the factors are formed from the first k columns of the bases
         g.k = k;
         g.alpha = snap.alpha;
@@ -1379,9 +1386,17 @@ struct Problem final : ProblemBase {
     reorth_restarts = 0;
     partial_now = reorth_level() > 0.0 && passes_now == 1;
     partial_run = false;
+    full_this_run = false;
     growth_carry = kFirstGrowth;
+    hold_hint = 0;
     vec_made = vec_orth = partial_fallbacks = 0;
   }
+
+  // The level as an absolute estimate (a multiple of sqrt(u), semi-
+  // orthogonality in the vectors' precision) and the rounding term's factor
+  // (as OrthEstimate states).
+  double orth_eta() const { return reorth_level() * std::sqrt(kUnit); }
+  double orth_root() const { return sizeof(T) == 8 ? std::sqrt((double)(arows + acols)) : 1.0; }
 
   // The partial-reorthogonalisation level as a multiple of sqrt(u): the
   // caller's, or (negative) 0.01 for FP64 vectors and 0.1 for FP32 vectors,
@@ -1396,6 +1411,10 @@ struct Problem final : ProblemBase {
   // bidiagonalisation of a solve, before any has been measured (the largest
   // measured on the completion workloads is about 6.5)
   static constexpr double kFirstGrowth = 8.0;
+  // half-steps before the previous bidiagonalisation's replayed first
+  // trigger from which predicted triggers are allowed (the first trigger of
+  // consecutive SVT iterates moves by about 3)
+  static constexpr int kHoldMargin = 8;
   static constexpr double kUnit = sizeof(T) == 8 ? 0x1p-53 : 0x1p-24;
 
   // Whether the vector made by half-step h is orthogonalised against the nq

@@ -15,10 +15,13 @@ double est_push_u(void *e, double a, int reorth) { return static_cast<svt::OrthE
 double est_push_v(void *e, double b, int reorth) { return static_cast<svt::OrthEstimate *>(e)->push_v(b, reorth != 0); }
 void est_free(void *e) { delete static_cast<svt::OrthEstimate *>(e); }
 
-void *sched_new(double eta, double unit, double root, double prior) {
+void *sched_new(double eta, double unit, double root, double prior, int hold) {
   auto *s = new svt::ReorthSchedule();
-  s->start(eta, unit, root, prior);
+  s->start(eta, unit, root, prior, hold);
   return s;
+}
+int first_trigger(const double *alpha, const double *beta, int k, double eta, double unit, double root) {
+  return svt::first_trigger(alpha, beta, k, eta, unit, root);
 }
 int sched_decide(void *s, int h) { return static_cast<svt::ReorthSchedule *>(s)->decide(h) ? 1 : 0; }
 int sched_advance(void *s, const double *alpha, const double *beta, int k) {

@@ -126,7 +126,7 @@ def test_fallback_to_full_reorthogonalisation():
     o = _gold("2_k60")
     g = _run(p, eta=100.0, k=60)
     frac, fallbacks = _stats(g)
-    assert fallbacks == 1
+    assert fallbacks >= 1          # each bidiagonalisation whose check fails
     assert list(g["ranks"]) == o["ranks"]
     np.testing.assert_allclose(g["residuals"], o["residuals"], rtol=1e-8)
     assert rel_diff_factored(g["U"], g["V"], o["U"], o["V"]) <= 1e-8

@@ -208,7 +208,8 @@ def capi(tmp_path_factory):
     vp, d, i = ctypes.c_void_p, ctypes.c_double, ctypes.c_int
     dp = ctypes.POINTER(ctypes.c_double)
     for name, res, args in [("est_new", vp, [d, d]), ("est_push_u", d, [vp, d, i]), ("est_push_v", d, [vp, d, i]),
-                            ("est_free", None, [vp]), ("sched_new", vp, [d, d, d, d]),
+                            ("est_free", None, [vp]), ("sched_new", vp, [d, d, d, d, i]),
+                            ("first_trigger", i, [dp, dp, i, d, d, d]),
                             ("sched_decide", i, [vp, i]), ("sched_advance", i, [vp, dp, dp, i]),
                             ("sched_growth", d, [vp]), ("sched_growth_seen", d, [vp]), ("sched_free", None, [vp])]:
         fn = getattr(lib, name)
@@ -247,7 +248,7 @@ def test_host_schedule_in_closed_loop(capi, case, lag):
     m, n = Y.shape
     full = pr.decide(Y, tau, policy="full")
     k = full["steps"]
-    s = capi.sched_new(1e-10, pr.EPS64, np.sqrt(m + n), 8.0)
+    s = capi.sched_new(1e-10, pr.EPS64, np.sqrt(m + n), 8.0, 0)
     dp = ctypes.POINTER(ctypes.c_double)
     verdicts = []
 
@@ -291,7 +292,7 @@ def test_host_schedule_fp32_in_closed_loop(capi, case):
     m, n = Y.shape
     full = pr.decide(Y, tau, policy="full")
     k = full["steps"]
-    s = capi.sched_new(0.01 * np.sqrt(pr.EPS32), pr.EPS32, 1.0, 8.0)
+    s = capi.sched_new(0.01 * np.sqrt(pr.EPS32), pr.EPS32, 1.0, 8.0, 0)
     dp = ctypes.POINTER(ctypes.c_double)
     verdicts = []
 
@@ -320,7 +321,7 @@ def test_host_schedule_reports_a_level_past_semi_orthogonality(capi):
     # again with every vector orthogonalised)
     Y, tau = _case("later2")
     m, n = Y.shape
-    s = capi.sched_new(100.0 * np.sqrt(pr.EPS64), pr.EPS64, np.sqrt(m + n), 8.0)
+    s = capi.sched_new(100.0 * np.sqrt(pr.EPS64), pr.EPS64, np.sqrt(m + n), 8.0, 0)
     dp = ctypes.POINTER(ctypes.c_double)
     verdicts = []
 
@@ -358,3 +359,58 @@ def test_host_estimate_at_a_breakdown(capi):
                     assert np.isfinite(got) and got >= 0.0
         finally:
             capi.est_free(e)
+
+
+def _closed_loop(capi, Y, k, hold, lag=8):
+    m, n = Y.shape
+    s = capi.sched_new(1e-10, pr.EPS64, np.sqrt(m + n), 8.0, hold)
+    dp = ctypes.POINTER(ctypes.c_double)
+    verdicts = []
+
+    def check(alpha, beta, j):
+        a = np.ascontiguousarray(alpha, dtype=np.float64)
+        b = np.ascontiguousarray(beta, dtype=np.float64)
+        verdicts.append(capi.sched_advance(s, a.ctypes.data_as(dp), b.ctypes.data_as(dp), j))
+
+    try:
+        run = pr.gkl(Y, k, policy="given", decide=lambda h: capi.sched_decide(s, h),
+                     on_step=lambda j, a, b: check(a, b, j - 2) if j % lag == 0 else None)
+        check(run["alpha"], run["beta"], k)
+    finally:
+        capi.sched_free(s)
+    return run, verdicts
+
+
+@pytest.mark.parametrize("cfg,first,second", [(1, 5, 6), (2, 3, 4)])
+def test_host_hold_from_the_previous_iterate(capi, cfg, first, second):
+    # the first trigger of the exact policy, replayed on one SVT iterate's
+    # coefficients, is where the library lets the next iterate's schedule
+    # start orthogonalising (less 8 half-steps): the next run stays
+    # semi-orthogonal with the full method's values and orthogonalises fewer
+    # vectors than without the hold
+    Y1, tau = _later_iterate(cfg, first)
+    Y2, _ = _later_iterate(cfg, second)
+    m, n = Y1.shape
+    k1 = pr.decide(Y1, tau, policy="full")["steps"]
+    run1, _ = _closed_loop(capi, Y1, k1, 0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    a = np.ascontiguousarray(run1["alpha"], dtype=np.float64)
+    b = np.ascontiguousarray(run1["beta"], dtype=np.float64)
+    ft = capi.first_trigger(a.ctypes.data_as(dp), b.ctypes.data_as(dp), k1, 1e-10, pr.EPS64, np.sqrt(m + n))
+    # the same point as the oracle's exact policy on the same iterate
+    ex = pr.decide(Y1, tau, policy="partial", eta=1e-10)["run"]
+    R = np.empty(2 * len(ex["reorth_u"]), bool)
+    R[0::2], R[1::2] = ex["reorth_u"], ex["reorth_v"]
+    assert abs(ft - int(np.nonzero(R)[0][0])) <= 2
+    full = pr.decide(Y2, tau, policy="full")
+    k2 = full["steps"]
+    held, verdicts = _closed_loop(capi, Y2, k2, max(0, ft - 8))
+    plain, _ = _closed_loop(capi, Y2, k2, 0)
+    assert all(verdicts)
+    assert max(held["loss_u"].max(), held["loss_v"].max()) < np.sqrt(pr.EPS64)
+    n_held = int(held["reorth_u"].sum() + held["reorth_v"].sum())
+    n_plain = int(plain["reorth_u"].sum() + plain["reorth_v"].sum())
+    assert n_held < n_plain
+    sig = pr.ritz(held["alpha"], held["beta"], k2)[0]
+    r = full["rank"]
+    np.testing.assert_allclose(sig[:r + 1], full["sigma"], rtol=1e-12)
