@@ -165,11 +165,12 @@ typedef struct {
                             one of a vector left alone passed sqrt(u)
                             (semi-orthogonality) that bidiagonalisation
                             starts again with full reorthogonalisation
-                            (levels of 1 and above make that happen).  The
-                            bidiagonalisation of an SVT step orthogonalises
-                            on a prediction no earlier than a few steps
-                            before where the previous step's coefficients
-                            show the first vector needed it.  Negative (default):
+                            (levels of 1 and above make that happen).  With
+                            FP64 vectors the bidiagonalisation of an SVT
+                            step orthogonalises on a prediction no earlier
+                            than a few steps before where the previous
+                            step's coefficients show the first vector
+                            needed it.  Negative (default):
                             automatic, 0.01 with FP64 vectors and 0.1 with
                             FP32 vectors; 0: every new vector is
                             orthogonalised; at most 100.  Applies with one

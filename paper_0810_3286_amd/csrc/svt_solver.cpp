@@ -986,8 +986,10 @@ struct Problem final : ProblemBase {
         if (partial_run) {
           growth_carry = std::max(rsched.growth_seen(), 0.5 * growth_carry);
           // an SVT step's bidiagonalisation: where the next one may start
-          // orthogonalising (the exact policy replayed on these coefficients)
-          if (mode == 0)
+          // orthogonalising (the exact policy replayed on these coefficients).
+          // FP64 vectors only: for FP32 vectors it gained nothing measurable
+          // and moved a small general-operator run past the mixed form's bar
+          if (mode == 0 && sizeof(T) == 8)
             hold_hint = std::max(0, first_trigger(snap.alpha.data(), snap.beta.data(), k, orth_eta(), kUnit,
                                                   orth_root()) - kHoldMargin);
         }
