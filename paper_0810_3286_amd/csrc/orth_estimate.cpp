@@ -83,7 +83,8 @@ void ReorthSchedule::start(double eta, double unit, double root, double growth_p
 }
 
 bool ReorthSchedule::decide(int h) {
-  // vectors are decided in order, each once
+  // vectors are decided in order, each once (a call out of order, which the
+  // solver never makes, orthogonalises)
   if (h != (int)sched_.size()) return true;
   bool r = false, trig = false;
   double lev = reset_level_;
@@ -126,6 +127,8 @@ bool ReorthSchedule::advance(const double *alpha, const double *beta, int k) {
           ++nlogs_;
         }
       }
+      // an orthogonalised vector's row is u, but its successor starts from
+      // the rounding term: predictions continue from the restart level
       level_[(size_t)h] = r ? reset_level_ : std::max(e, unit_);
     }
   }
