@@ -542,7 +542,8 @@ def main():
                          "reported as -1)")
     ap.add_argument("--min-rows", type=int, default=0,
                     help="min_block_rows of the headline solve (0: the library default)")
-    ap.add_argument("--serving-requests", type=int, default=16)
+    ap.add_argument("--serving-requests", type=int, default=64,
+                    help="requests per serving run (closed loop, each open loop, noisy run)")
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-mix", choices=["baseline", "table1"], default="baseline")
