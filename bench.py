@@ -385,10 +385,12 @@ def serving_bench(n_req: int, slots: int, budget_gib: float, precision: int, see
     (r, c) drawn from Table 1's pairs (10, 6), (50, 5), (100, 4).
     Both: tau = 5 sqrt(m n), delta = 1.2 m n / |Omega|, eps = 1e-4, maxiter
     500; each request's bidiagonalisation is capped at step_cap steps (a
-    request that needs more ends with SVT_ELANCZOS), and the server's stall
+    request that needs more ends with SVT_ELANCZOS), the server's stall
     bound ends a request whose residual sets no new minimum for 20 iterations
-    (SVT_STALLED), so a request outside the method's regime holds its slot
-    for a bounded time.  noise_frac: that share of the requests carries
+    (SVT_STALLED) and its degrees-of-freedom bound one whose iterate's rank
+    has more degrees of freedom than the request has observations
+    (SVT_UNDERDETERMINED), so a request outside the method's regime holds its
+    slot for a bounded time.  noise_frac: that share of the requests carries
     N(0, 0.01^2) noise on its observations and stops by eq. (5.10) with
     sigma = 0.01 and eps = 0.1 (the others as above).
     Closed loop (all requests at t = 0) gives the capacity C in requests/s;

@@ -38,6 +38,9 @@ typedef enum {
   SVT_NOT_CONVERGED = 1, /* maxiter reached; the result is the last iterate  */
   SVT_STALLED = 2,       /* stall_window iterations without a new residual
                             minimum; the result is the last iterate         */
+  SVT_UNDERDETERMINED = 3, /* the iterate's rank has more degrees of freedom
+                            than dof_bound |Omega|; the result is the last
+                            completed iterate                               */
   SVT_EINVAL = -1,       /* invalid argument (checked before any device work) */
   SVT_ENOMEM = -2,       /* host or device allocation failed                   */
   SVT_EDEVICE = -3,      /* a HIP runtime call failed                          */
@@ -176,6 +179,19 @@ typedef struct {
                             orthogonalised; at most 100.  Applies with one
                             Gram-Schmidt pass per vector (reorth_passes 0 or
                             1); svt_reorth_stats reports what it did       */
+  double dof_bound;      /* > 0: stop with SVT_UNDERDETERMINED once an SVT
+                            step's rank r_k certainly has more degrees of
+                            freedom, r_k (m + n - r_k), than dof_bound |Omega|
+                            (Section 1.1: a rank-r matrix has r (m + n - r)
+                            degrees of freedom, and no fewer observations
+                            can determine it).  Checked as the step's
+                            bidiagonalisation runs: its Ritz values bound the
+                            singular values from below, so once more of them
+                            than the bound's rank exceed tau the step ends
+                            there, without its update (the Lanczos partial
+                            SVD only).  <= 0 (default): off.
+                            The server applies 1 to requests that leave it 0;
+                            < 0 turns it off there too                      */
 } svt_params;
 
 typedef struct {
@@ -238,8 +254,9 @@ svt_status svt_create_sensing(int64_t m, int64_t n, int64_t ns, const int32_t *s
 
 /* Run Algorithm 1 from the kick (each call starts over).  Returns SVT_OK,
    SVT_NOT_CONVERGED (maxiter reached; the factors hold X^{maxiter}),
-   SVT_STALLED (with stall_window > 0; the factors hold the last iterate), or an
-   error; after an error raised inside the iteration (e.g. SVT_ELANCZOS when
+   SVT_STALLED (with stall_window > 0; the factors hold the last iterate),
+   SVT_UNDERDETERMINED (with dof_bound > 0; the factors hold the last completed
+   iterate), or an error; after an error raised inside the iteration (e.g. SVT_ELANCZOS when
    the bidiagonalisation reaches lanczos_maxsteps) info still reports the
    iterations completed and their last residual.  info may be NULL. */
 svt_status svt_solve(svt_problem *h, svt_info *info);
@@ -284,8 +301,9 @@ void svt_destroy(svt_problem *h);
 
 /* Short text of a status code, including the two ends of Algorithm 1's loop
    (Section 5.1.5): SVT_OK (the stop test of eq. (5.5) or (5.10) passed) and
-   SVT_NOT_CONVERGED (k_max reached), and SVT_STALLED (the stall bound of
-   stall_window).  Never NULL; unknown codes give
+   SVT_NOT_CONVERGED (k_max reached), SVT_STALLED (the stall bound of
+   stall_window) and SVT_UNDERDETERMINED (the bound of dof_bound).  Never
+   NULL; unknown codes give
    "unknown status". */
 const char *svt_status_string(int32_t status);
 
@@ -445,7 +463,8 @@ svt_status svt_submit(svt_server *s, int64_t m, int64_t n, int64_t nnz, const in
 svt_status svt_poll(svt_server *s, uint64_t ticket, int32_t *state);
 
 /* Block until the request is done; returns its solve status (SVT_OK,
-   SVT_NOT_CONVERGED, SVT_STALLED or the error of svt_create / svt_solve). */
+   SVT_NOT_CONVERGED, SVT_STALLED, SVT_UNDERDETERMINED or the error of
+   svt_create / svt_solve). */
 svt_status svt_wait(svt_server *s, uint64_t ticket, svt_info *info);
 
 /* Copy out a finished request's factors (as svt_factors: U m x r scaled by

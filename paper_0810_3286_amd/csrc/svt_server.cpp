@@ -107,6 +107,16 @@ int32_t request_stall(const svt_params &p) {
   return p.stall_window == 0 ? kDefaultStallWindow : p.stall_window;
 }
 
+// A served request that leaves dof_bound 0 stops once its iterate's rank has
+// more degrees of freedom than it has observations (SVT_UNDERDETERMINED):
+// requests that far outside the method's regime would otherwise grow their
+// bidiagonalisations to the step cap.  A negative value turns it off.
+constexpr double kDefaultDofBound = 1.0;
+
+double request_dof(const svt_params &p) {
+  return p.dof_bound == 0.0 ? kDefaultDofBound : (p.dof_bound < 0.0 ? 0.0 : p.dof_bound);
+}
+
 // A served request that leaves min_block_rows 0 cuts its vectors into row
 // blocks of at least 64 rows: a request of a few thousand rows then runs its
 // half-steps on a few dozen compute units instead of all of them, so that
@@ -181,6 +191,7 @@ struct svt_server {
     // the step cap the admission footprint assumed
     p.lanczos_maxsteps = (int32_t)request_cap(p);
     p.stall_window = request_stall(p);
+    p.dof_bound = request_dof(p);
     p.min_block_rows = request_min_rows(p);
     svt_problem *h = nullptr;
     svt_status st = svt_create(r->m, r->n, r->nnz, SVT_COO, r->rows.data(), r->cols.data(), r->vals.data(), &p, &h);
@@ -191,7 +202,7 @@ struct svt_server {
     }
     st = svt_solve(h, &r->info);
     r->status = st;
-    if (st == SVT_OK || st == SVT_NOT_CONVERGED || st == SVT_STALLED) {
+    if (st == SVT_OK || st == SVT_NOT_CONVERGED || st == SVT_STALLED || st == SVT_UNDERDETERMINED) {
       int32_t rank = 0;
       svt_factors(h, &rank, nullptr, nullptr, nullptr);
       r->rank = rank;

@@ -353,6 +353,10 @@ struct Problem final : ProblemBase {
   bool full_this_run = false;  // ... unless its check failed: then all vectors
   double growth_carry = 0.0;
   int hold_hint = 0;           // no predicted trigger before this half-step
+  // the degrees-of-freedom bound (dof_bound): the largest rank it allows in
+  // this solve (-1: off), and whether the current step passed it
+  int dof_rmax = -1;
+  bool dof_hit = false;
   int64_t vec_made = 0, vec_orth = 0, partial_fallbacks = 0;
 
   // the Dantzig-selector iteration (Section 3.3) instead of Algorithm 1's
@@ -937,6 +941,17 @@ struct Problem final : ProblemBase {
       BidiagSVD chk;
       gkl_ritz(snap, chk, res);
       const int k = snap.k;
+      if (mode == 0 && dof_rmax >= 0) {
+        // Ritz values bound the singular values from below: more of them
+        // above tau than the degrees-of-freedom bound allows settles it
+        int above = 0;
+        while (above < k && chk.sigma[above] > tau) ++above;
+        if (above > dof_rmax) {
+          dof_hit = true;
+          r_out = above;
+          return k;
+        }
+      }
       const double top = chk.sigma.empty() ? 0.0 : chk.sigma[0];
       const double atol = tol * std::max(top, 1e-300);
       bool done = false;
@@ -1419,6 +1434,23 @@ struct Problem final : ProblemBase {
   static constexpr int kHoldMargin = 8;
   static constexpr double kUnit = sizeof(T) == 8 ? 0x1p-53 : 0x1p-24;
 
+  // The largest rank r with r (m + n - r) <= dof_bound * (observations), or
+  // -1 when the bound is off (Section 1.1's degrees of freedom of a rank-r
+  // matrix; observations: |Omega|, or the measurements of a general operator).
+  int dof_rank() const {
+    if (!(prm.dof_bound > 0.0)) return -1;
+    const double F = prm.dof_bound * (double)(sensing ? pmeas : ix.nnz);
+    const double sm = (double)(arows + acols);
+    const int rmax = (int)std::min<int64_t>(arows, acols);
+    const double disc = sm * sm - 4.0 * F;
+    int r = disc <= 0.0 ? rmax : (int)std::floor(0.5 * (sm - std::sqrt(disc)));
+    r = std::max(0, std::min(r, rmax));
+    auto dof = [&](int q) { return (double)q * (sm - (double)q); };
+    while (r > 0 && dof(r) > F) --r;
+    while (r < rmax && dof(r + 1) <= F) ++r;
+    return r;
+  }
+
   // Whether the vector made by half-step h is orthogonalised against the nq
   // columns of its basis (always, unless partial reorthogonalisation leaves
   // it alone).
@@ -1462,6 +1494,8 @@ struct Problem final : ProblemBase {
     // the stall bound: the smallest residual so far and its iteration
     double best_res = std::numeric_limits<double>::infinity();
     int best_k = 0;
+    dof_rmax = dof_rank();
+    dof_hit = false;
     // an error in the kick or the loop still reports the iterations completed
     auto report = [&](int iters, svt_status status) {
       inf.t_solve_s = now_s() - t1;
@@ -1503,6 +1537,12 @@ struct Problem final : ProblemBase {
           BidiagSVD sv;
           steps = gkl_run(yr, yc, 0, 0, prm.tau, g, sv, r);
           k_hint = steps;
+          if (dof_hit) {
+            // the step's rank passes the degrees-of-freedom bound: it ends
+            // without its update; the factors keep the last completed iterate
+            st = SVT_UNDERDETERMINED;
+            break;
+          }
           // s_k bookkeeping of Algorithm 1's repeat loop (Section 5.1.1)
           s = std::min<int64_t>(r_prev + 1, acols);
           while (s <= r && s < acols) s = (int)std::min<int64_t>(s + prm.incr, acols);
@@ -1540,6 +1580,7 @@ struct Problem final : ProblemBase {
       throw;
     }
     if (k > prm.maxiter) k = prm.maxiter;
+    if (st == SVT_UNDERDETERMINED) k -= 1;  // step k did not complete
     HIP_CHECK(hipStreamSynchronize(stream));
     prof.flush();
     report(k, st);
@@ -1738,6 +1779,7 @@ static void validate_params(const svt_params &p) {
   if (p.reorth_passes < 0 || p.reorth_passes > 2) throw Error(SVT_EINVAL, "reorth_passes must be 0, 1 or 2");
   if (!finite(p.reorth_eta) || p.reorth_eta > 100)
     throw Error(SVT_EINVAL, "reorth_eta must be finite and at most 100");
+  if (!finite(p.dof_bound)) throw Error(SVT_EINVAL, "dof_bound must be finite");
   if (!finite(p.decide_margin) || p.decide_margin < 0) throw Error(SVT_EINVAL, "decide_margin must be finite and >= 0");
   if (p.spmv_mode < 0 || p.spmv_mode > 2) throw Error(SVT_EINVAL, "spmv_mode must be 0, 1 or 2");
 }
@@ -1793,6 +1835,7 @@ svt_status svt_params_default(int64_t m, int64_t n, int64_t nnz, svt_params *out
   out->lanczos_maxsteps = 0;
   out->reorth_passes = 0;
   out->reorth_eta = -1.0;  // automatic: 0.01 (FP64 vectors), 0.1 (FP32 vectors)
+  out->dof_bound = 0.0;
   out->decide_margin = 0.05;
   out->svd_method = SVT_SVD_LANCZOS;
   out->rsvd_oversample = 10;
@@ -1974,7 +2017,7 @@ svt_status svt_solve_path(svt_problem *h, const double *taus, int32_t count, svt
     prm.tau = taus[i];
     prm.warm_start = i == 0 ? warm0 : 1;
     st = guarded(h, [&] { return h->impl->solve(infos ? infos + i : nullptr); });
-    if (st != SVT_OK && st != SVT_NOT_CONVERGED && st != SVT_STALLED) break;
+    if (st != SVT_OK && st != SVT_NOT_CONVERGED && st != SVT_STALLED && st != SVT_UNDERDETERMINED) break;
   }
   prm.tau = tau0;
   prm.warm_start = warm0;
@@ -2032,6 +2075,7 @@ const char *svt_status_string(int32_t s) {
     case SVT_OK: return "ok";
     case SVT_NOT_CONVERGED: return "not converged (maxiter reached)";
     case SVT_STALLED: return "stalled (no new residual minimum within stall_window iterations)";
+    case SVT_UNDERDETERMINED: return "underdetermined (the rank has more degrees of freedom than dof_bound observations)";
     case SVT_EINVAL: return "invalid argument";
     case SVT_ENOMEM: return "out of memory";
     case SVT_EDEVICE: return "device error";

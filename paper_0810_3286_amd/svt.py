@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "_build", "libsvt.so")
 SVT_OK = 0
 SVT_NOT_CONVERGED = 1
 SVT_STALLED = 2
+SVT_UNDERDETERMINED = 3
 SVT_EINVAL = -1
 SVT_ENOMEM = -2
 SVT_EDEVICE = -3
@@ -69,6 +70,7 @@ class svt_params(ctypes.Structure):
         ("rsvd_oversample", ctypes.c_int32),
         ("rsvd_power", ctypes.c_int32),
         ("reorth_eta", ctypes.c_double),
+        ("dof_bound", ctypes.c_double),
     ]
 
 
@@ -246,12 +248,13 @@ def svt_destroy(h) -> None:
 
 
 def svt_solve(h):
-    """Returns (status, info) for SVT_OK / SVT_NOT_CONVERGED / SVT_STALLED; raises SvtError
+    """Returns (status, info) for SVT_OK / SVT_NOT_CONVERGED / SVT_STALLED /
+    SVT_UNDERDETERMINED; raises SvtError
     otherwise, with the info of the iterations completed as ``.info``."""
     info = svt_info()
     st = load().svt_solve(h, ctypes.byref(info))
     try:
-        _check(st, h, allow=(SVT_OK, SVT_NOT_CONVERGED, SVT_STALLED))
+        _check(st, h, allow=(SVT_OK, SVT_NOT_CONVERGED, SVT_STALLED, SVT_UNDERDETERMINED))
     except SvtError as e:
         e.info = info
         raise
@@ -265,7 +268,7 @@ def svt_solve_path(h, taus):
     infos = (svt_info * taus.shape[0])()
     st = load().svt_solve_path(h, _p(taus), taus.shape[0], infos)
     try:
-        _check(st, h, allow=(SVT_OK, SVT_NOT_CONVERGED, SVT_STALLED))
+        _check(st, h, allow=(SVT_OK, SVT_NOT_CONVERGED, SVT_STALLED, SVT_UNDERDETERMINED))
     except SvtError as e:
         e.info = list(infos)
         raise
@@ -455,7 +458,7 @@ def svt_result(server, ticket: int, m: int, n: int):
     if st == SVT_EINVAL or st == SVT_EBUSY:
         raise SvtError(st, svt_status_string(st))
     # a failed solve still carries its timestamps (and rank 0)
-    r = r.value if st in (SVT_OK, SVT_NOT_CONVERGED, SVT_STALLED) else 0
+    r = r.value if st in (SVT_OK, SVT_NOT_CONVERGED, SVT_STALLED, SVT_UNDERDETERMINED) else 0
     U = np.zeros((m, r))
     V = np.zeros((n, r))
     w = np.zeros(r)

@@ -50,9 +50,10 @@ def test_randomized_svd_refused_outside_completion():
 
 def test_struct_layout_matches_header():
     # svt_params: 3 doubles, 6 int32, 2 doubles, 2 int32, double, uint64, 2 int32, pointer,
-    # double, 7 int32 (and 4 bytes of padding), double
-    assert ctypes.sizeof(B.svt_params) == 3 * 8 + 6 * 4 + 2 * 8 + 2 * 4 + 8 + 8 + 2 * 4 + 8 + 8 + 7 * 4 + 4 + 8
-    assert B.svt_params.reorth_eta.offset == ctypes.sizeof(B.svt_params) - 8
+    # double, 7 int32 (and 4 bytes of padding), 2 doubles
+    assert ctypes.sizeof(B.svt_params) == 3 * 8 + 6 * 4 + 2 * 8 + 2 * 4 + 8 + 8 + 2 * 4 + 8 + 8 + 7 * 4 + 4 + 16
+    assert B.svt_params.reorth_eta.offset == ctypes.sizeof(B.svt_params) - 16
+    assert B.svt_params.dof_bound.offset == ctypes.sizeof(B.svt_params) - 8
     assert ctypes.sizeof(B.svt_info) == 4 * 4 + 6 * 8 + 8
 
 
@@ -70,7 +71,7 @@ def test_params_default_is_the_papers_choice():
 
 
 def test_status_strings():
-    for s in (0, 1, -1, -2, -3, -4, -5, -6, -7):
+    for s in (0, 1, 2, 3, -1, -2, -3, -4, -5, -6, -7):
         assert B.svt_status_string(s)
     assert "unknown" in B.svt_status_string(99)
 
@@ -107,7 +108,8 @@ def test_rejects_bad_parameters():
                        ("decide_margin", -0.1), ("spmv_mode", 3), ("min_block_rows", -1),
                        ("min_block_rows", 2049), ("svd_method", 2), ("rsvd_oversample", -1),
                        ("rsvd_power", 65), ("reorth_eta", 101.0),
-                       ("reorth_eta", float("nan"))]:
+                       ("reorth_eta", float("nan")), ("dof_bound", float("nan")),
+                       ("dof_bound", float("inf"))]:
         p = B.svt_params_default(2, 2, 2)
         setattr(p, field, bad)
         _expect_einval(2, 2, rows, cols, vals, p)
