@@ -452,7 +452,12 @@ svt_status svt_footprint(int64_t m, int64_t n, int64_t nnz, int32_t precision, s
 svt_status svt_server_create(size_t hbm_budget_bytes, int32_t max_slots, svt_server **out);
 
 /* Queue one request (COO triplets in any order, host pointers, copied).
-   params may be NULL (defaults); its stream field is ignored.  Returns
+   params may be NULL (defaults); its stream field is ignored.  Fields a
+   request leaves 0 take the server's defaults: a 512-step cap
+   (lanczos_maxsteps), a stall window of 20 (stall_window), the
+   degrees-of-freedom bound at |Omega| (dof_bound 1) and row blocks of at
+   least 64 rows (min_block_rows); a negative stall_window or dof_bound
+   turns that bound off.  Returns
    EINVAL for invalid indices or values (checked here), ENOMEM if the request
    could never fit in the budget; *ticket identifies the request. */
 svt_status svt_submit(svt_server *s, int64_t m, int64_t n, int64_t nnz, const int32_t *rows,
