@@ -511,6 +511,10 @@ def serving_bench(n_req: int, slots: int, budget_gib: float, precision: int, see
         # (their stored entries only), as a fraction of the 8 TB/s peak
         "closed_loop_spmv_hbm_frac": spmv_bytes / t_closed / 8e12,
         "mix": mix, "step_cap": step_cap,
+        # the server's defaults for what the requests leave unset: the stall
+        # window, the degrees-of-freedom bound (multiples of |Omega|) and the
+        # row-block minimum (min_rows, when 0)
+        "server_defaults": {"stall_window": 20, "dof_bound": 1.0, "min_block_rows": 64},
         "status_counts": {B.svt_status_string(k): int(v) for k, v in
                           zip(*np.unique(np.array(statuses), return_counts=True))},
         "max_running": stats["max_running"], "peak_admitted_gib": stats["peak_bytes"] / (1 << 30),
