@@ -64,9 +64,19 @@ double OrthEstimate::push_v(double b, bool reorth) {
   return top;
 }
 
-void ReorthSchedule::start(double eta, double unit, double root, double growth_prior, int hold) {
+void OrthEstimate::mark_u() { std::fill(mu_.begin(), mu_.end(), unit_); }
+void OrthEstimate::mark_v() { std::fill(nu_.begin(), nu_.end(), unit_); }
+
+void ReorthSchedule::start(double eta, double unit, double root, double growth_prior, int hold,
+                           const std::vector<uint8_t> *replay, double replay_eta) {
   eta_ = eta;
   hold_ = hold;
+  replay_eta_ = replay_eta;
+  replay_.clear();
+  if (replay != nullptr && replay->size() > (size_t)kReplayLead) {
+    replay_.assign(replay->size() - (size_t)kReplayLead, 0);
+    for (size_t h = 1; h < replay_.size(); ++h) replay_[h] = (*replay)[h + (size_t)kReplayLead];
+  }
   unit_ = unit;
   verify_ = std::sqrt(unit);
   prior_ = std::max(growth_prior, kGrowthFloor);
@@ -90,8 +100,9 @@ bool ReorthSchedule::decide(int h) {
   double lev = reset_level_;
   if (h >= 1) {  // u_1 has no basis to be orthogonalised against
     const double pred = level_[(size_t)h - 1] * growth_;
-    trig = pred > eta_ && h >= hold_;
-    r = trig || trig_[(size_t)h - 1];
+    const bool replayed = h < (int)replay_.size();
+    trig = pred > (replayed ? replay_eta_ : eta_) && h >= hold_;
+    r = trig || trig_[(size_t)h - 1] || (replayed && replay_[(size_t)h]);
     lev = r ? reset_level_ : pred;
   }
   sched_.push_back(r ? 1 : 0);
@@ -151,6 +162,35 @@ int first_trigger(const double *alpha, const double *beta, int k, double eta, do
     if (est.push_v(beta[j], false) > eta) return 2 * j - 1;
   }
   return 2 * k;
+}
+
+std::vector<uint8_t> exact_pattern(const double *alpha, const double *beta, int k, double eta, double unit,
+                                   double root) {
+  std::vector<uint8_t> pat((size_t)(2 * std::max(k, 0)), 0);
+  OrthEstimate est;
+  est.reset(unit, root);
+  bool force = false;
+  for (int j = 1; j <= k; ++j) {
+    // u_j (u_1 has no basis)
+    double e = est.push_u(alpha[j - 1], false);
+    bool d = j > 1 && (e > eta || force);
+    force = false;
+    if (d) {
+      est.mark_u();
+      pat[(size_t)(2 * (j - 1))] = 1;
+      force = e > eta;
+    }
+    // v_{j+1}
+    e = est.push_v(beta[j], false);
+    d = e > eta || force;
+    force = false;
+    if (d) {
+      est.mark_v();
+      pat[(size_t)(2 * j - 1)] = 1;
+      force = e > eta;
+    }
+  }
+  return pat;
 }
 
 }  // namespace svt

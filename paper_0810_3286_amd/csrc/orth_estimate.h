@@ -37,6 +37,9 @@ class OrthEstimate {
   // v_{j+1} (j = steps()) with coefficient beta_{j+1}: the largest
   // |nu_{j+1,i}|, i <= j; reorth as for push_u.
   double push_v(double beta_next, bool reorth);
+  // the latest u (v) taken as orthogonalised after all: its row becomes u
+  void mark_u();
+  void mark_v();
   int steps() const { return (int)alpha_.size(); }
   double unit() const { return unit_; }
 
@@ -69,8 +72,12 @@ class ReorthSchedule {
  public:
   // hold: no vector before this half-step is orthogonalised on a prediction
   // (the replayed first trigger of the previous bidiagonalisation, less a
-  // margin; 0: none)
-  void start(double eta, double unit, double root, double growth_prior, int hold = 0);
+  // margin; 0: none).  replay (may be null): the vectors the exact policy
+  // orthogonalised in the previous bidiagonalisation (exact_pattern); each
+  // is orthogonalised here kReplayLead half-steps earlier, and over the
+  // pattern's length a prediction must pass replay_eta (not eta) to add one.
+  void start(double eta, double unit, double root, double growth_prior, int hold = 0,
+             const std::vector<uint8_t> *replay = nullptr, double replay_eta = 0.0);
   bool decide(int h);
   // alpha_1..alpha_k and beta_1..beta_{k+1} (beta[0] = beta_1, unused):
   // returns false if an unreorthogonalised vector passed `verify`.
@@ -84,12 +91,14 @@ class ReorthSchedule {
   static constexpr double kGrowthFloor = 1.5;
   static constexpr int kWindow = 8;         // ratios in the sustained growth
   static constexpr double kSafety = 1.25;   // on the sustained growth
+  static constexpr int kReplayLead = 2;     // half-steps ahead of the replayed pattern
 
  private:
   void repredict(int from);
   OrthEstimate est_;
-  double eta_ = 0.0, verify_ = 0.0, unit_ = 0.0;
+  double eta_ = 0.0, verify_ = 0.0, unit_ = 0.0, replay_eta_ = 0.0;
   int hold_ = 0;
+  std::vector<uint8_t> replay_; // vector h orthogonalised as the replayed pattern says
   double growth_ = kGrowthFloor, seen_ = 0.0, prior_ = 0.0;
   double reset_level_ = 0.0;    // predicted level of a vector just orthogonalised
   std::vector<double> logs_;    // logs of the last kWindow ratios
@@ -105,5 +114,11 @@ class ReorthSchedule {
 // before it, passes eta; 2k if none does.  Consecutive SVT iterates put it
 // within a few half-steps of each other.
 int first_trigger(const double *alpha, const double *beta, int k, double eta, double unit, double root);
+
+// The whole exact policy replayed the same way: pattern[h] = 1 for each
+// vector h (of 2k) it orthogonalises, a vector whose estimate passes eta and
+// the next vector after it.
+std::vector<uint8_t> exact_pattern(const double *alpha, const double *beta, int k, double eta, double unit,
+                                   double root);
 
 }  // namespace svt

@@ -353,6 +353,9 @@ struct Problem final : ProblemBase {
   bool full_this_run = false;  // ... unless its check failed: then all vectors
   double growth_carry = 0.0;
   int hold_hint = 0;           // no predicted trigger before this half-step
+  // the vectors the exact policy orthogonalises, replayed on the previous SVT
+  // step's coefficients (empty: none)
+  std::vector<uint8_t> replay_hint;
   // the degrees-of-freedom bound (dof_bound): the largest rank it allows in
   // this solve (-1: off), and whether the current step passed it
   int dof_rmax = -1;
@@ -753,7 +756,9 @@ struct Problem final : ProblemBase {
     ensure_basis(std::min<int64_t>(acols, 8));
     const Csx R = a_rows_struct(), C = a_cols_struct();
     partial_run = partial_now && passes_now == 1 && !full_this_run;
-    if (partial_run) rsched.start(orth_eta(), kUnit, orth_root(), growth_carry, hold_hint);
+    if (partial_run)
+      rsched.start(orth_eta(), kUnit, orth_root(), growth_carry, hold_hint,
+                   replay_hint.empty() ? nullptr : &replay_hint, std::sqrt(kUnit));
     HIP_CHECK(launch_randn<T>(stream, pbuf_v.as<T>(), (int)acols, prm.seed, rng_ctr++));
     HIP_CHECK(launch_sumsq<T>(stream, pbuf_v.as<T>(), (int)acols, gs.part3, mrows()));
     g.pv = PendingVec{3, 0};
@@ -900,9 +905,10 @@ struct Problem final : ProblemBase {
         // a vector left alone lost more orthogonality than semi-orthogonality
         // allows (the prediction fell short of the estimate): this
         // bidiagonalisation starts again with every vector orthogonalised,
-        // and the next one takes no hold
+        // and the next one takes no hold and no replayed pattern
         full_this_run = true;
         hold_hint = 0;
+        replay_hint.clear();
         ++partial_fallbacks;
         if (log_level > 0)
           std::fprintf(stderr, "[svt] partial reorthogonalisation: an estimate passed %.2e by step %d "
@@ -1004,9 +1010,18 @@ struct Problem final : ProblemBase {
           // orthogonalising (the exact policy replayed on these coefficients).
           // FP64 vectors only: for FP32 vectors it gained nothing measurable
           // and moved a small general-operator run past the mixed form's bar
-          if (mode == 0 && sizeof(T) == 8)
+          if (mode == 0 && sizeof(T) == 8) {
             hold_hint = std::max(0, first_trigger(snap.alpha.data(), snap.beta.data(), k, orth_eta(), kUnit,
                                                   orth_root()) - kHoldMargin);
+            // and, after a long one, the whole pattern, which the next one
+            // follows slightly ahead, its predictions then guarding only
+            // semi-orthogonality (on short bidiagonalisations consecutive
+            // SVT steps differ too much: such a schedule fell back to full)
+            if (k >= kReplayMinSteps)
+              replay_hint = exact_pattern(snap.alpha.data(), snap.beta.data(), k, orth_eta(), kUnit, orth_root());
+            else
+              replay_hint.clear();
+          }
         }
         // the factors are formed from the first k columns of the bases
         g.k = k;
@@ -1406,6 +1421,7 @@ struct Problem final : ProblemBase {
     full_this_run = false;
     growth_carry = kFirstGrowth;
     hold_hint = 0;
+    replay_hint.clear();
     vec_made = vec_orth = partial_fallbacks = 0;
   }
 
@@ -1432,6 +1448,7 @@ struct Problem final : ProblemBase {
   // trigger from which predicted triggers are allowed (the first trigger of
   // consecutive SVT iterates moves by about 3)
   static constexpr int kHoldMargin = 8;
+  static constexpr int kReplayMinSteps = 64;  // steps of a bidiagonalisation whose pattern is replayed
   static constexpr double kUnit = sizeof(T) == 8 ? 0x1p-53 : 0x1p-24;
 
   // The largest rank r with r (m + n - r) <= dof_bound * (observations), or

@@ -1,6 +1,7 @@
 // A C interface to the library's partial-reorthogonalisation estimate and
 // schedule (orth_estimate.cpp), for CPU tests through ctypes.
 #include <cstdint>
+#include <vector>
 
 #include "orth_estimate.h"
 
@@ -19,6 +20,19 @@ void *sched_new(double eta, double unit, double root, double prior, int hold) {
   auto *s = new svt::ReorthSchedule();
   s->start(eta, unit, root, prior, hold);
   return s;
+}
+void *sched_new_replay(double eta, double unit, double root, double prior, int hold, const uint8_t *pattern,
+                       int npattern, double replay_eta) {
+  auto *s = new svt::ReorthSchedule();
+  std::vector<uint8_t> pat(pattern, pattern + npattern);
+  s->start(eta, unit, root, prior, hold, &pat, replay_eta);
+  return s;
+}
+int exact_pattern(const double *alpha, const double *beta, int k, double eta, double unit, double root,
+                  uint8_t *out) {
+  const std::vector<uint8_t> p = svt::exact_pattern(alpha, beta, k, eta, unit, root);
+  for (size_t h = 0; h < p.size(); ++h) out[h] = p[h];
+  return (int)p.size();
 }
 int first_trigger(const double *alpha, const double *beta, int k, double eta, double unit, double root) {
   return svt::first_trigger(alpha, beta, k, eta, unit, root);

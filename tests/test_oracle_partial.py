@@ -210,6 +210,8 @@ def capi(tmp_path_factory):
     for name, res, args in [("est_new", vp, [d, d]), ("est_push_u", d, [vp, d, i]), ("est_push_v", d, [vp, d, i]),
                             ("est_free", None, [vp]), ("sched_new", vp, [d, d, d, d, i]),
                             ("first_trigger", i, [dp, dp, i, d, d, d]),
+                            ("exact_pattern", i, [dp, dp, i, d, d, d, ctypes.POINTER(ctypes.c_uint8)]),
+                            ("sched_new_replay", vp, [d, d, d, d, i, ctypes.POINTER(ctypes.c_uint8), i, d]),
                             ("sched_decide", i, [vp, i]), ("sched_advance", i, [vp, dp, dp, i]),
                             ("sched_growth", d, [vp]), ("sched_growth_seen", d, [vp]), ("sched_free", None, [vp])]:
         fn = getattr(lib, name)
@@ -361,9 +363,15 @@ def test_host_estimate_at_a_breakdown(capi):
             capi.est_free(e)
 
 
-def _closed_loop(capi, Y, k, hold, lag=8):
+def _closed_loop(capi, Y, k, hold, lag=8, pattern=None):
     m, n = Y.shape
-    s = capi.sched_new(1e-10, pr.EPS64, np.sqrt(m + n), 8.0, hold)
+    if pattern is None:
+        s = capi.sched_new(1e-10, pr.EPS64, np.sqrt(m + n), 8.0, hold)
+    else:
+        pat = np.ascontiguousarray(pattern, dtype=np.uint8)
+        s = capi.sched_new_replay(1e-10, pr.EPS64, np.sqrt(m + n), 8.0, hold,
+                                  pat.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), len(pat),
+                                  float(np.sqrt(pr.EPS64)))
     dp = ctypes.POINTER(ctypes.c_double)
     verdicts = []
 
@@ -412,5 +420,72 @@ def test_host_hold_from_the_previous_iterate(capi, cfg, first, second):
     n_plain = int(plain["reorth_u"].sum() + plain["reorth_v"].sum())
     assert n_held < n_plain
     sig = pr.ritz(held["alpha"], held["beta"], k2)[0]
+    r = full["rank"]
+    np.testing.assert_allclose(sig[:r + 1], full["sigma"], rtol=1e-12)
+
+
+def _pattern(run):
+    R = np.empty(2 * len(run["reorth_u"]), bool)
+    R[0::2], R[1::2] = run["reorth_u"], run["reorth_v"]
+    return R
+
+
+def _exact_pattern(capi, run, k, m, n):
+    dp = ctypes.POINTER(ctypes.c_double)
+    a = np.ascontiguousarray(run["alpha"][:k], dtype=np.float64)
+    b = np.ascontiguousarray(run["beta"][:k + 1], dtype=np.float64)
+    out = np.zeros(2 * k, np.uint8)
+    got = capi.exact_pattern(a.ctypes.data_as(dp), b.ctypes.data_as(dp), k, 1e-10, pr.EPS64, np.sqrt(m + n),
+                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    assert got == 2 * k
+    return out.astype(bool)
+
+
+@pytest.mark.parametrize("cfg,it", [(1, 5), (2, 3)])
+def test_host_exact_pattern_equals_oracle(capi, cfg, it):
+    # the exact policy replayed on a run's coefficients names the vectors the
+    # oracle's exact policy orthogonalised in that run (its estimates come
+    # from the same coefficients and the same decisions)
+    Y, tau = _later_iterate(cfg, it)
+    m, n = Y.shape
+    ex = pr.decide(Y, tau, policy="partial", eta=1e-10)
+    k = ex["steps"]
+    R = _pattern(ex["run"])[:2 * k]
+    assert R.any()
+    np.testing.assert_array_equal(_exact_pattern(capi, ex["run"], k, m, n), R)
+
+
+@pytest.mark.parametrize("cfg,first,second", [(1, 5, 6), (2, 3, 4)])
+def test_host_replay_from_the_previous_iterate(capi, cfg, first, second):
+    # the next SVT iterate's schedule follows the exact policy's pattern on
+    # the previous iterate's coefficients two half-steps ahead, its
+    # predictions guarding only semi-orthogonality: every check passes, the
+    # run stays semi-orthogonal with the full method's values, every vector
+    # the pattern names (shifted) is orthogonalised, and fewer vectors are
+    # orthogonalised than with the hold alone
+    Y1, tau = _later_iterate(cfg, first)
+    Y2, _ = _later_iterate(cfg, second)
+    m, n = Y1.shape
+    k1 = pr.decide(Y1, tau, policy="full")["steps"]
+    run1, _ = _closed_loop(capi, Y1, k1, 0)
+    pat = _exact_pattern(capi, run1, k1, m, n)
+    dp = ctypes.POINTER(ctypes.c_double)
+    a = np.ascontiguousarray(run1["alpha"], dtype=np.float64)
+    b = np.ascontiguousarray(run1["beta"], dtype=np.float64)
+    hold = max(0, capi.first_trigger(a.ctypes.data_as(dp), b.ctypes.data_as(dp), k1, 1e-10, pr.EPS64,
+                                     np.sqrt(m + n)) - 8)
+    full = pr.decide(Y2, tau, policy="full")
+    k2 = full["steps"]
+    replayed, verdicts = _closed_loop(capi, Y2, k2, hold, pattern=pat)
+    held, _ = _closed_loop(capi, Y2, k2, hold)
+    assert all(verdicts)
+    assert max(replayed["loss_u"].max(), replayed["loss_v"].max()) < np.sqrt(pr.EPS64)
+    R = _pattern(replayed)
+    lead = 2
+    for h in np.nonzero(pat)[0]:
+        if h - lead >= 1 and h - lead < len(R):
+            assert R[h - lead]
+    assert R.sum() < _pattern(held).sum()
+    sig = pr.ritz(replayed["alpha"], replayed["beta"], k2)[0]
     r = full["rank"]
     np.testing.assert_allclose(sig[:r + 1], full["sigma"], rtol=1e-12)
