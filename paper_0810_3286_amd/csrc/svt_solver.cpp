@@ -1010,9 +1010,10 @@ struct Problem final : ProblemBase {
           // orthogonalising (the exact policy replayed on these coefficients).
           // FP64 vectors only: for FP32 vectors it gained nothing measurable
           // and moved a small general-operator run past the mixed form's bar
-          if (mode == 0 && sizeof(T) == 8) {
+          if (mode == 0 && sizeof(T) == 8)
             hold_hint = std::max(0, first_trigger(snap.alpha.data(), snap.beta.data(), k, orth_eta(), kUnit,
                                                   orth_root()) - kHoldMargin);
+          if (mode == 0) {
             // and, after a long one, the whole pattern, which the next one
             // follows slightly ahead, its predictions then guarding only
             // semi-orthogonality (on short bidiagonalisations consecutive
