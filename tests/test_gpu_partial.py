@@ -12,8 +12,10 @@ tolerances as with full reorthogonalisation:
   stored run: same iterations, ranks and s_k, X within 1e-8;
 * the stored oracle runs at full size: 5000^2 X^60, 10000^2 rank 50 X^40
   and its complete run, 30000^2 X^20 and its complete run: FP64 within 1e-8
-  with the same ranks, while fewer than half of the vectors are
-  orthogonalised; the mixed form (FP32 vectors, the automatic level 0.1)
+  with the same ranks, while fewer than a quarter of the vectors are
+  orthogonalised (a third over the first 20 iterations at 30000^2, whose
+  first bidiagonalisations have no previous pattern to follow) and none
+  falls back; the mixed form (FP32 vectors, the automatic level 0.1)
   within 5e-4 while orthogonalising fewer vectors than with reorth_eta = 0;
   the automatic level is 0.01 (FP64) and 0.1 (FP32) bit for bit;
 * the fall-back: reorth_eta = 100 lets predictions pass sqrt(u), the check
@@ -77,10 +79,10 @@ def test_400_matches_stored_oracle():
     _compare_solves(g, o)
     assert list(g["s_hist"]) == list(gold["s_hist"])
     frac, fallbacks = _stats(g)
-    assert fallbacks == 0 and frac < 0.75
+    assert fallbacks == 0 and frac < 0.25
 
 
-@pytest.mark.parametrize("cfg,k,frac_max", [(2, 60, 0.6), (3, 40, 0.5), (4, 20, 0.6)])
+@pytest.mark.parametrize("cfg,k,frac_max", [(2, 60, 0.25), (3, 40, 0.25), (4, 20, 0.33)])
 def test_fixed_iteration_matches_stored_oracle(cfg, k, frac_max):
     gpu_case(f"partial reorth: config {cfg} FP64, {k} iterations vs stored oracle")
     p = workload.config(cfg)
@@ -106,7 +108,7 @@ def test_complete_run_matches_stored_oracle(cfg):
     np.testing.assert_allclose(g["residuals"], o["residuals"], rtol=1e-8)
     assert rel_diff_factored(g["U"], g["V"], o["U"], o["V"]) <= 1e-8
     frac, fallbacks = _stats(g)
-    assert fallbacks == 0 and frac < 0.5
+    assert fallbacks == 0 and frac < 0.25
 
 
 @pytest.mark.parametrize("cfg,k", [(2, 60), (4, 20)])
