@@ -17,7 +17,9 @@ definition, applied to the history of the same run without it:
   of the unbounded run stopped at that iteration;
 * a run whose rank stays within the bound is unchanged bit for bit;
 * the server applies dof_bound = 1 to a request that names none, and a
-  negative value turns it off.
+  negative value turns it off;
+* with a general operator (Section 3.1) the observations counted are the
+  measurements, not the support.
 """
 import numpy as np
 import pytest
@@ -120,3 +122,44 @@ def test_server_default_bound():
             np.testing.assert_array_equal(V, ref["V"])
     finally:
         B.svt_server_destroy(srv)
+
+
+def _sensing(q, dof_bound):
+    prm = B.svt_params_default(q.m, q.n, q.p)
+    prm.tau, prm.delta, prm.eps, prm.maxiter, prm.incr = q.tau, q.delta, q.eps, 500, q.incr
+    prm.dof_bound = dof_bound
+    h = B.svt_create_sensing(q.m, q.n, q.srows, q.scols, q.gptr, q.gidx, q.gval, q.b, prm)
+    try:
+        st, info = B.svt_solve(h)
+        U, w, V = B.svt_factors(h, q.m, q.n)
+        hist = B.svt_history(h)
+    finally:
+        B.svt_destroy(h)
+    return st, info, U, V, hist
+
+
+def test_general_operator_counts_measurements():
+    # with a general operator (Section 3.1) the observations are the
+    # measurements b, not the support: the bound's largest rank follows p
+    gpu_case("dof bound, general operator")
+    q = workload.sparse_sensing(150, 120, 4, int(5 * 4 * (150 + 120 - 4)), 3, seed=3)
+    st, info, U, V, hist = _sensing(q, 0.0)
+    assert st == B.SVT_OK
+    ranks = list(hist["ranks"])
+    dof = lambda r: r * (q.m + q.n - r)
+    if max(ranks) > ranks[0]:
+        rmax = ranks[0]
+        kt = next(i for i, r in enumerate(ranks) if r > rmax)
+        st2, info2, U2, V2, hist2 = _sensing(q, 0.5 * (dof(rmax) + dof(rmax + 1)) / q.p)
+        assert st2 == B.SVT_UNDERDETERMINED and info2.iters == kt
+        assert list(hist2["ranks"]) == ranks[:kt]
+        np.testing.assert_array_equal(hist2["residuals"], hist["residuals"][:kt])
+    # below the first iterate's rank, counted against the measurements: no
+    # iteration completes
+    r0 = ranks[0]
+    st3, info3, U3, V3, hist3 = _sensing(q, 0.5 * (dof(r0 - 1) + dof(r0)) / q.p)
+    assert st3 == B.SVT_UNDERDETERMINED and info3.iters == 0 and U3.shape == (q.m, 0)
+    # (the same bound counted against the support instead would allow rank
+    # r0, so the stop shows which count the library takes)
+    if r0 >= 2:
+        assert dof(r0) <= 0.5 * (dof(r0 - 1) + dof(r0)) / q.p * len(q.srows)
