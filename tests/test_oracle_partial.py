@@ -455,6 +455,26 @@ def test_host_exact_pattern_equals_oracle(capi, cfg, it):
     np.testing.assert_array_equal(_exact_pattern(capi, ex["run"], k, m, n), R)
 
 
+@pytest.mark.parametrize("cfg,it", [(1, 5), (2, 3)])
+def test_host_exact_pattern_fp32_equals_oracle(capi, cfg, it):
+    # the same with FP32 vectors (the mixed form): FP32's unit roundoff, no
+    # sqrt(m + n) factor, the automatic level 0.1 sqrt(u)
+    Y, tau = _later_iterate(cfg, it)
+    m, n = Y.shape
+    eta = 0.1 * np.sqrt(pr.EPS32)
+    k = pr.decide(Y, tau, policy="full")["steps"]
+    run = pr.gkl(Y, k, policy="partial", eta=eta, store="f32")
+    R = _pattern(run)[:2 * k]
+    assert R.any()
+    dp = ctypes.POINTER(ctypes.c_double)
+    a = np.ascontiguousarray(run["alpha"][:k], dtype=np.float64)
+    b = np.ascontiguousarray(run["beta"][:k + 1], dtype=np.float64)
+    out = np.zeros(2 * k, np.uint8)
+    assert capi.exact_pattern(a.ctypes.data_as(dp), b.ctypes.data_as(dp), k, eta, pr.EPS32, 1.0,
+                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))) == 2 * k
+    np.testing.assert_array_equal(out.astype(bool), R)
+
+
 @pytest.mark.parametrize("cfg,first,second", [(1, 5, 6), (2, 3, 4)])
 def test_host_replay_from_the_previous_iterate(capi, cfg, first, second):
     # the next SVT iterate's schedule follows the exact policy's pattern on
